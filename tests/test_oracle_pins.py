@@ -1,0 +1,252 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test would fail on a plausible mistake in the oracle (a dropped term, a
+sign, a misplaced conjugate, a transposed operand):
+
+  P1  brute-force intermediate-state construction (paper Eq. 4-12) in a tiny
+      Fock space -> E_MP2, singles block through 2nd order, first-order
+      coupling, zeroth-order doubles block.
+  P2  exact diagonalisation of the explicit matrix vs the oracle Davidson.
+  P3  Hermiticity, sigma linearity, matrix-free sigma == explicit matrix.
+  P4  MP2 closed form vs the textbook closed-shell RMP2 formula.
+  P5  nonrelativistic limit: real M, singlet/triplet multiplets, CIS limit
+      equal to the textbook RHF singlet and triplet CIS matrices.
+  P6  invariances: spinor phases, real rotation of the Cholesky index,
+      permutation of spinors inside a block, uniform shift of energies.
+  P8  Hellmann-Feynman gradient vs central finite differences and the
+      scaling identity.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from synth import make_system, make_spin_blocked
+from oracle import adc2 as O
+from oracle.isr_bruteforce import adc2_blocks
+
+torch.set_num_threads(min(8, torch.get_num_threads()))
+
+
+def _tensors(s):
+    return O.as_c128(s.L), O.as_f64(s.eps), O.Spaces(s.nc, s.no, s.nv)
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("shape,seed,sigma", [((1, 2, 3), 5, 0.12), ((2, 2, 3), 7, 0.15),
+                                              ((1, 3, 3), 11, 0.10)])
+def test_p1_bruteforce_isr(shape, seed, sigma):
+    nc, no, nv = shape
+    s = make_system(nc, no, nv, 8, seed=seed, sigma=sigma, core=(-3.0, -2.5))
+    bf = adc2_blocks(s.L, s.eps, nc, no, nv)
+    assert bf["fit_resid"] < 1e-11
+    L, e, sp = _tensors(s)
+    tol = 1e-9
+    # ground state: E_MP2 is the lambda^2 coefficient of E0
+    assert abs(bf["E_mp2"] - float(O.mp2_energy(L, e, sp))) < tol
+    # singles block of CVS-ADC(2) and of full ADC(2) (all occupied as holes)
+    m11 = O.m11(L, e, sp).numpy()
+    assert np.abs(m11 - bf["M11_cvs"]).max() < tol
+    spf = O.Spaces(nc + no, 0, nv)
+    assert np.abs(O.m11(L, e, spf).numpy() - bf["M11_full"]).max() < tol
+    # first-order coupling and zeroth-order doubles
+    assert np.abs(O.m21_dense(L, e, sp).numpy() - bf["M21_cvs"]).max() < tol
+    assert np.abs(np.diag(O.m22_diag(e, sp).numpy()) - bf["M22_cvs"]).max() < tol
+    # the second-order singles terms are large enough here for the pin to bite
+    t = O.m11_terms(L, e, sp)
+    for k in ("m2i", "m2ii", "m2iii"):
+        assert float(t[k].abs().max()) > 1e3 * tol
+
+
+def test_p1_orders_separate():
+    """The ISR zeroth/first orders alone equal the oracle's m0 and m1."""
+    s = make_system(1, 2, 3, 8, seed=3, sigma=0.12, core=(-3.0, -2.5))
+    bf = adc2_blocks(s.L, s.eps, 1, 2, 3)
+    M0, M1, M2 = bf["orders"]
+    L, e, sp = _tensors(s)
+    t = O.m11_terms(L, e, O.Spaces(3, 0, 3))
+    ns = 9
+    assert np.abs(M0[:ns, :ns] - t["m0"].reshape(ns, ns).numpy()).max() < 1e-9
+    assert np.abs(M1[:ns, :ns] - t["m1"].reshape(ns, ns).numpy()).max() < 1e-9
+    m2 = (t["m2i"] + t["m2ii"] + t["m2iii"]).reshape(ns, ns).numpy()
+    assert np.abs(M2[:ns, :ns] - m2).max() < 1e-9
+
+
+# ---------------------------------------------------------------- P2
+def test_p2_davidson_vs_exact():
+    s = make_system(2, 4, 14, 24, seed=21)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    assert a.dim == 2 * 14 + 2 * 4 * 91
+    w_ex, _ = a.roots_exact(4)
+    w_dv, X, info = a.roots(4, tol=1e-9)
+    assert info["converged"]
+    assert torch.max(torch.abs(w_ex - w_dv)).item() < 1e-10
+    # Ritz vectors are orthonormal eigenvectors of the explicit matrix
+    M = a.matrix()
+    R = X @ M.T - w_dv[:, None] * X
+    assert torch.linalg.vector_norm(R, dim=1).max().item() < 1e-8
+    assert torch.allclose(X.conj() @ X.T, torch.eye(4, dtype=O.C128), atol=1e-10)
+
+
+# ---------------------------------------------------------------- P3
+def test_p3_hermitian_and_sigma():
+    s = make_system(2, 3, 7, 16, seed=4)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    M = a.matrix()
+    assert torch.linalg.matrix_norm(M - M.conj().T) <= 1e-14 * torch.linalg.matrix_norm(M)
+    g = torch.Generator().manual_seed(0)
+    x = torch.randn(3, a.dim, dtype=O.C128, generator=g)
+    y = torch.randn(3, a.dim, dtype=O.C128, generator=g)
+    sx, sy = a.sigma(x), a.sigma(y)
+    assert torch.allclose(sx, x @ M.T, atol=1e-11, rtol=0)
+    # linearity and x^H sigma(y) = conj(y^H sigma(x))
+    assert torch.allclose(a.sigma(2.5 * x - 1j * y), 2.5 * sx - 1j * sy, atol=1e-11)
+    lhs = torch.sum(x.conj() * sy, dim=1)
+    rhs = torch.sum(y.conj() * sx, dim=1).conj()
+    assert torch.allclose(lhs, rhs, atol=1e-10)
+
+
+# ---------------------------------------------------------------- P4
+def test_p4_rmp2_closed_shell():
+    sb = make_spin_blocked(1, 2, 4, 12, seed=8, sigma=0.08)
+    L, e, sp = _tensors(sb)
+    e_so = float(O.mp2_energy(L, e, sp))
+    l = sb.extra["l_spatial"]
+    es = sb.extra["eps_spatial"]
+    ncs, nos, nvs = sb.extra["n_spatial"]
+    o = ncs + nos
+    ov = np.einsum("Pia,Pjb->iajb", l[:, :o, o:], l[:, :o, o:])
+    E = 0.0
+    for i in range(o):
+        for j in range(o):
+            for a in range(nvs):
+                for b in range(nvs):
+                    d = es[i] + es[j] - es[o + a] - es[o + b]
+                    E += ov[i, a, j, b] * (2 * ov[i, a, j, b] - ov[i, b, j, a]) / d
+    assert abs(e_so - E) < 1e-12 * max(1.0, abs(E)) + 1e-14
+    assert abs(E) > 1e-4
+
+
+# ---------------------------------------------------------------- P5
+def _multiplets(w, tol):
+    groups, cur = [], [w[0]]
+    for x in w[1:]:
+        if x - cur[-1] < tol:
+            cur.append(x)
+        else:
+            groups.append(cur)
+            cur = [x]
+    groups.append(cur)
+    return [len(g) for g in groups]
+
+
+def test_p5_nonrelativistic_limit():
+    sb = make_spin_blocked(1, 2, 4, 12, seed=9, sigma=0.1)
+    L, e, sp = _tensors(sb)
+    a = O.Adc2(sb.L, sb.eps, sb.nc, sb.no, sb.nv)
+    M = a.matrix()
+    assert torch.abs(M.imag).max().item() < 1e-14
+    w = torch.linalg.eigvalsh(M).numpy()
+    dmin = O.m22_diag(e, sp).min().item()
+    low = w[w < dmin - 1e-3]
+    assert len(low) >= 4
+    sizes = _multiplets(low, 1e-9)
+    assert all(sz in (1, 3) for sz in sizes), sizes
+    assert 3 in sizes
+    # CIS limit: spin-orbital CVS-CIS == RHF singlet (x1) and triplet (x3) CIS
+    m1 = O.m11(L, e, sp, order=1)
+    w_so = np.sort(torch.linalg.eigvalsh(m1).numpy())
+    l = sb.extra["l_spatial"]
+    es = sb.extra["eps_spatial"]
+    ncs, nos, nvs = sb.extra["n_spatial"]
+    o = ncs + nos
+    C, U = slice(0, ncs), slice(o, o + nvs)
+    iajb = np.einsum("Pia,Pjb->iajb", l[:, C, U], l[:, C, U])
+    ijab = np.einsum("Pij,Pab->ijab", l[:, C, C], l[:, U, U])
+    de = np.einsum("ij,ab->iajb", np.eye(ncs), np.eye(nvs)) * (es[U][None, :, None, None] - es[C][:, None, None, None])
+    nsx = ncs * nvs
+    A_s = (de + 2 * iajb - ijab.transpose(0, 2, 1, 3)).reshape(nsx, nsx)
+    A_t = (de - ijab.transpose(0, 2, 1, 3)).reshape(nsx, nsx)
+    ref = np.sort(np.concatenate([np.linalg.eigvalsh(A_s), np.repeat(np.linalg.eigvalsh(A_t), 3)]))
+    assert np.abs(ref - w_so).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P6
+def _roots(L, eps, nc, no, nv, k=6):
+    a = O.Adc2(L, eps, nc, no, nv)
+    return torch.linalg.eigvalsh(a.matrix())[:k].numpy()
+
+
+def test_p6_invariances():
+    s = make_system(2, 3, 6, 10, seed=12, sigma=0.08)
+    nc, no, nv = s.nc, s.no, s.nv
+    n = s.n
+    w0 = _roots(s.L, s.eps, nc, no, nv)
+    rng = np.random.default_rng(0)
+    # spinor phase gauge L_pq -> e^{-i f_p} L_pq e^{i f_q}
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    Lg = np.conj(ph)[None, :, None] * s.L * ph[None, None, :]
+    assert np.abs(_roots(Lg, s.eps, nc, no, nv) - w0).max() < 1e-11
+    # real orthogonal mixing of the Cholesky index
+    Q, _ = np.linalg.qr(rng.standard_normal((s.naux, s.naux)))
+    Lq = np.einsum("PQ,Qpq->Ppq", Q, s.L)
+    assert np.abs(_roots(Lq, s.eps, nc, no, nv) - w0).max() < 1e-11
+    # permutation of spinors within each block
+    perm = np.concatenate([rng.permutation(nc), nc + rng.permutation(no),
+                           nc + no + rng.permutation(nv)])
+    Lp = s.L[:, perm][:, :, perm]
+    assert np.abs(_roots(Lp, s.eps[perm], nc, no, nv) - w0).max() < 1e-11
+    # uniform energy shift
+    assert np.abs(_roots(s.L, s.eps + 0.37, nc, no, nv) - w0).max() < 1e-11
+    # a unitary (complex) mixing of P is NOT a symmetry: guards against a
+    # conjugate slipping into (pq|rs) = sum_P L L
+    Zu = np.linalg.qr(rng.standard_normal((s.naux, s.naux)) + 1j * rng.standard_normal((s.naux, s.naux)))[0]
+    Lu = np.einsum("PQ,Qpq->Ppq", Zu, s.L)
+    Lu = 0.5 * (Lu + np.conj(np.transpose(Lu, (0, 2, 1))))
+    assert np.abs(_roots(Lu, s.eps, nc, no, nv) - w0).max() > 1e-6
+
+
+# ---------------------------------------------------------------- P8
+def test_p8_gradient_fd_and_scaling():
+    s = make_system(2, 2, 5, 8, seed=13, sigma=0.1)
+    L, e, sp = _tensors(s)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    k = 3
+    w, X = a.roots_exact(k)
+    X = X.T.contiguous()
+    g = np.array([1.0, -0.5, 0.25])
+    G, de = O.omega_gradient(L, e, sp, X, g)
+    # Hermitian per P
+    assert torch.allclose(G, G.conj().transpose(1, 2), atol=1e-14)
+    rng = np.random.default_rng(1)
+    h = 1e-5
+    for t in range(3):
+        A = rng.standard_normal(L.shape) + 1j * rng.standard_normal(L.shape)
+        D = 0.5 * (A + np.conj(np.transpose(A, (0, 2, 1))))
+        D /= np.linalg.norm(D)
+        Dt = torch.from_numpy(D)
+        fp = float(np.dot(g, _roots(s.L + h * D, s.eps, s.nc, s.no, s.nv, k)))
+        fm = float(np.dot(g, _roots(s.L - h * D, s.eps, s.nc, s.no, s.nv, k)))
+        fd = (fp - fm) / (2 * h)
+        an = float(torch.sum(G.conj() * Dt).real)
+        assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (fd, an)
+    for t in range(3):
+        d = rng.standard_normal(s.n)
+        fp = float(np.dot(g, _roots(s.L, s.eps + h * d, s.nc, s.no, s.nv, k)))
+        fm = float(np.dot(g, _roots(s.L, s.eps - h * d, s.nc, s.no, s.nv, k)))
+        assert abs((fp - fm) / (2 * h) - float(de @ torch.from_numpy(d))) < 1e-7
+    # uniform shift invariance: sum_p d omega / d eps_p = 0
+    assert abs(float(de.sum())) < 1e-10
+    # scaling identity for one root: d/ds omega(sL) = 2 x1'M1x1 + 4 x1'M2x1 + 4 Re x1'M12 x2
+    G1, _ = O.omega_gradient(L, e, sp, X[:1], [1.0])
+    lhs = float(torch.sum(G1.conj() * L).real)
+    t = O.m11_terms(L, e, sp)
+    ns = sp.n_singles
+    x1, x2 = X[0, :ns], X[0, ns:]
+    M1 = t["m1"].reshape(ns, ns)
+    M2 = (t["m2i"] + t["m2ii"] + t["m2iii"]).reshape(ns, ns)
+    M21 = O.m21_dense(L, e, sp)
+    rhs = (2 * (x1.conj() @ M1 @ x1).real + 4 * (x1.conj() @ M2 @ x1).real
+           + 4 * (x1.conj() @ (M21.conj().T @ x2)).real)
+    assert abs(lhs - float(rhs)) < 1e-10 * max(1.0, abs(lhs))
