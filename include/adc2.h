@@ -1,0 +1,153 @@
+/*
+ * adc2.h -- C ABI of the MI355X (gfx950) two-component CVS-ADC(2) library.
+ *
+ * The library computes core-excitation energies of the two-component
+ * core-valence-separated ADC(2) method: the lowest eigenvalues of the
+ * Hermitian intermediate-state secular matrix M (paper, Theory section,
+ * Eq. 11: M X = X Omega, X^H X = 1), with M expanded to second order in the
+ * Moller-Plesset partitioning (Eq. 12) and restricted to the core-valence
+ * separated manifold a+_a a_I, a+_a a+_b a_I a_j with I core, j valence
+ * (CVS section).  Two-electron integrals are never stored with more than two
+ * virtual indices: they are generated on the fly from complex Cholesky
+ * vectors (Implementation section), <pq||rs> = (pr|qs) - (ps|qr) with
+ * (pq|rs) = sum_P L^P_pq L^P_rs.
+ *
+ * Conventions shared by every entry point
+ *   - Spinors are ordered [core nc | valence no | virtual nv], n = nc+no+nv.
+ *   - Complex data are interleaved (re, im) doubles, the layout of
+ *     torch.complex128 (C99 double _Complex).
+ *   - An ADC vector has dim = nc*nv + nc*no*nv*(nv-1)/2 entries: singles
+ *     (I, a) at I*nv + a, then doubles packed lexicographically over
+ *     (I, j, a<b) with the pair (a,b) at a*nv - a*(a+1)/2 + (b-a-1).
+ *     The doubles basis state is a+_a a+_b a_j a_I |Phi0>, orthonormal, so
+ *     plain complex inner products of vectors are the correct metric.
+ *   - "dev" pointers are HIP device pointers; "host" pointers are host memory.
+ *     The caller owns every pointer it passes; the library never frees them.
+ *   - stream is a hipStream_t (may be NULL for the default stream).  Calls
+ *     are stream-ordered; adc2_setup and adc2_davidson synchronise the stream
+ *     before returning because they hand scalars back on the host.
+ *   - A handle is not thread-safe.  Errors never throw across the ABI: every
+ *     call returns an adc2_status and records a message for adc2_last_error.
+ */
+#ifndef ADC2_H
+#define ADC2_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define ADC2_API __attribute__((visibility("default")))
+#else
+#define ADC2_API
+#endif
+
+typedef struct adc2_handle_s* adc2_handle;
+
+typedef enum {
+  ADC2_OK = 0,
+  ADC2_ERR_ARG = 1,            /* bad size, null pointer, unsupported option   */
+  ADC2_ERR_NOT_HERMITIAN = 2,  /* some L^P is not Hermitian beyond 1e-12*max|L| */
+  ADC2_ERR_OOM = 3,            /* device allocation failed                      */
+  ADC2_ERR_HIP = 4,            /* a HIP runtime call failed                     */
+  ADC2_ERR_NOCONV = 5,         /* Davidson hit max_iter; best results written   */
+  ADC2_ERR_NONFINITE = 6       /* NaN/Inf in inputs or in the iteration         */
+} adc2_status;
+
+typedef enum {
+  ADC2_FP64 = 0                /* complex FP64 contractions on the FP64 MFMA     */
+} adc2_precision;
+
+#define ADC2_MAX_ROOTS 32
+
+typedef struct {
+  double tol;          /* converged when every ||M x_k - w_k x_k||_2 <= tol  */
+  int max_iter;        /* Davidson iterations (0 -> 300)                      */
+  int max_subspace;    /* subspace cap before restart (0 -> max(6k, 2k+k))   */
+  int nguess;          /* initial guess vectors (0 -> 2k if k <= 8 else k)    */
+  int verbose;         /* print one line per iteration to stderr              */
+} adc2_dav_opts;
+
+typedef struct {
+  int iters;                        /* Davidson iterations performed          */
+  int n_sigma;                      /* sigma vectors computed                  */
+  int converged;                    /* 1 if every root met tol                 */
+  int subspace;                     /* final subspace size                     */
+  double resnorm[ADC2_MAX_ROOTS];   /* final residual 2-norms                 */
+  double ms_sigma;                  /* HIP-event time inside sigma builds     */
+  double ms_total;                  /* wall time of the adc2_davidson call     */
+  double sigma_flops;               /* algorithmic flops of those sigma builds */
+} adc2_dav_info;
+
+/*
+ * adc2_setup -- build a handle for one system.
+ *   L     dev, complex128 [naux][n][n]; each L[P] must be Hermitian
+ *         (L[P][q][p] = conj(L[P][p][q])); read only during the call.
+ *   eps   dev, float64 [n]: canonical spinor energies (diagonal Fock matrix),
+ *         core < valence < virtual is not required but every virtual minus
+ *         occupied denominator must be nonzero.
+ *   nc, no, nv, naux  > 0 (nv >= 2).
+ *   prec  adc2_precision (only ADC2_FP64 here).
+ * Work done (stream-ordered, then synchronised): slicing L into the
+ * virtual-virtual, virtual-occupied and occupied-occupied blocks; the MP2
+ * amplitudes tau = <ac||kl> / D^{ac}_{kl} over all occupied k,l (denominators
+ * of Eq. 15) and the MP2 energy; the dense CVS singles block through second
+ * order; the diagonal of M used by the preconditioner.
+ * Errors: ADC2_ERR_ARG (sizes, null pointers), ADC2_ERR_NOT_HERMITIAN,
+ * ADC2_ERR_NONFINITE (NaN/Inf in L or eps), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ * On error *out is set to NULL and nothing is leaked.
+ */
+ADC2_API adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
+                       int naux, int prec, void* stream, adc2_handle* out);
+
+/* Vector length nc*nv + nc*no*nv*(nv-1)/2 (0 for a NULL handle). */
+ADC2_API size_t adc2_dim(adc2_handle h);
+
+/*
+ * adc2_sigma -- S = M X for a block of m vectors (Eq. 11 operator).
+ *   X  dev complex128 [m][dim]; S dev complex128 [m][dim] (overwritten;
+ *   must not alias X).  m >= 1.  Stream-ordered, asynchronous.
+ * Errors: ADC2_ERR_ARG, ADC2_ERR_OOM (workspace growth), ADC2_ERR_HIP.
+ */
+ADC2_API adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, void* stream);
+
+/*
+ * adc2_davidson -- lowest nroots eigenpairs of M by block Davidson (FP64).
+ *   nroots   1..ADC2_MAX_ROOTS.
+ *   opt      may be NULL (tol 1e-8, defaults above).
+ *   guess    dev complex128 [g][dim] or NULL (NULL: unit vectors on the
+ *            lowest singles diagonal elements of M); g = opt->nguess or the
+ *            default count.
+ *   omega    host float64 [nroots], ascending.
+ *   X        dev complex128 [nroots][dim] or NULL: normalised eigenvectors.
+ *   info     host, may be NULL.
+ * Returns ADC2_ERR_NOCONV (with the best omega/X/info written) when max_iter
+ * is reached; ADC2_ERR_NONFINITE when the iteration produced NaN/Inf.
+ * Synchronises the stream.
+ */
+ADC2_API adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt,
+                          const void* guess, double* omega, void* X,
+                          adc2_dav_info* info, void* stream);
+
+/* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
+ * column (J,b)) into dev buffer dst.  Stream-ordered. */
+ADC2_API adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream);
+
+/* Copy the real diagonal of M (float64 [dim]) into dev buffer dst. */
+ADC2_API adc2_status adc2_get_diag(adc2_handle h, double* dst, void* stream);
+
+/* MP2 correlation energy -1/4 sum |<ab||ij>|^2 / D^{ab}_{ij} (host scalar). */
+ADC2_API adc2_status adc2_mp2_energy(adc2_handle h, double* e_mp2);
+
+/* Release everything the handle owns.  NULL is accepted. */
+ADC2_API adc2_status adc2_destroy(adc2_handle h);
+
+/* Message of the last error on the calling thread ("" if none). */
+ADC2_API const char* adc2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADC2_H */

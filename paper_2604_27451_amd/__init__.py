@@ -1,0 +1,238 @@
+"""Python binding of the gfx950 CVS-ADC(2) library (libadc2.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/adc2.h.  Torch tensors provide
+device memory and streams.  There is no CPU fallback: if the shared library
+is missing the import of the binding functions fails loudly.
+
+Functions mirror the C ABI names:
+    adc2_setup(L, eps, nc, no, nv, naux, prec=0) -> Handle
+    adc2_dim(h)
+    adc2_sigma(h, X, S=None) -> S
+    adc2_davidson(h, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0,
+                  guess=None, want_vectors=True, verbose=0) -> (omega, X, info)
+    adc2_get_m11(h) -> complex128 tensor
+    adc2_get_diag(h) -> float64 tensor
+    adc2_mp2_energy(h) -> float
+    adc2_destroy(h)
+    adc2_last_error() -> str
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadc2.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "adc2.h")
+
+ADC2_OK = 0
+ADC2_ERR_ARG = 1
+ADC2_ERR_NOT_HERMITIAN = 2
+ADC2_ERR_OOM = 3
+ADC2_ERR_HIP = 4
+ADC2_ERR_NOCONV = 5
+ADC2_ERR_NONFINITE = 6
+ADC2_FP64 = 0
+ADC2_MAX_ROOTS = 32
+
+STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
+                4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
+
+EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_get_m11",
+           "adc2_get_diag", "adc2_mp2_energy", "adc2_destroy", "adc2_last_error"]
+
+
+class DavOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
+
+
+class DavInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("n_sigma", ctypes.c_int),
+                ("converged", ctypes.c_int), ("subspace", ctypes.c_int),
+                ("resnorm", ctypes.c_double * ADC2_MAX_ROOTS),
+                ("ms_sigma", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("sigma_flops", ctypes.c_double)]
+
+    def as_dict(self, nroots):
+        return {"iters": self.iters, "n_sigma": self.n_sigma, "converged": bool(self.converged),
+                "subspace": self.subspace, "resnorm": list(self.resnorm[:nroots]),
+                "ms_sigma": self.ms_sigma, "ms_total": self.ms_total,
+                "sigma_flops": self.sigma_flops}
+
+
+class Adc2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libadc2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2604_27451_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.adc2_setup.argtypes = [vp, vp, i, i, i, i, i, vp, ctypes.POINTER(vp)]
+    lib.adc2_setup.restype = i
+    lib.adc2_dim.argtypes = [vp]
+    lib.adc2_dim.restype = ctypes.c_size_t
+    lib.adc2_sigma.argtypes = [vp, i, vp, vp, vp]
+    lib.adc2_sigma.restype = i
+    lib.adc2_davidson.argtypes = [vp, i, ctypes.POINTER(DavOpts), vp, ctypes.POINTER(d), vp,
+                                  ctypes.POINTER(DavInfo), vp]
+    lib.adc2_davidson.restype = i
+    lib.adc2_get_m11.argtypes = [vp, vp, vp]
+    lib.adc2_get_m11.restype = i
+    lib.adc2_get_diag.argtypes = [vp, vp, vp]
+    lib.adc2_get_diag.restype = i
+    lib.adc2_mp2_energy.argtypes = [vp, ctypes.POINTER(d)]
+    lib.adc2_mp2_energy.restype = i
+    lib.adc2_destroy.argtypes = [vp]
+    lib.adc2_destroy.restype = i
+    lib.adc2_last_error.argtypes = []
+    lib.adc2_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def adc2_last_error() -> str:
+    return load().adc2_last_error().decode()
+
+
+def _check(status, what):
+    if status != ADC2_OK:
+        raise Adc2Error(status, f"{what}: {adc2_last_error()}")
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+class Handle:
+    def __init__(self, ptr, nc, no, nv, naux):
+        self.ptr = ptr
+        self.nc, self.no, self.nv, self.naux = nc, no, nv, naux
+        self.dim = int(load().adc2_dim(ptr))
+        self.ns = nc * nv
+
+    def close(self):
+        if self.ptr:
+            load().adc2_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def adc2_setup(L, eps, nc, no, nv, naux, prec=ADC2_FP64, stream=None) -> Handle:
+    import torch
+    _need(L, torch.complex128, "L")
+    _need(eps, torch.float64, "eps")
+    n = nc + no + nv
+    if tuple(L.shape) != (naux, n, n) or tuple(eps.shape) != (n,):
+        raise ValueError("L must be [naux][n][n] and eps [n]")
+    out = ctypes.c_void_p()
+    st = load().adc2_setup(ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(eps.data_ptr()),
+                           nc, no, nv, naux, prec, _stream_ptr(stream), ctypes.byref(out))
+    _check(st, "adc2_setup")
+    return Handle(out, nc, no, nv, naux)
+
+
+def adc2_dim(h: Handle) -> int:
+    return int(load().adc2_dim(h.ptr))
+
+
+def adc2_sigma(h: Handle, X, S=None, stream=None):
+    import torch
+    _need(X, torch.complex128, "X")
+    if X.dim() == 1:
+        X = X[None]
+    m = X.shape[0]
+    if X.shape[1] != h.dim:
+        raise ValueError("X must be [m][dim]")
+    if S is None:
+        S = torch.empty_like(X)
+    _need(S, torch.complex128, "S")
+    st = load().adc2_sigma(h.ptr, m, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                           _stream_ptr(stream))
+    _check(st, "adc2_sigma")
+    return S
+
+
+def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, guess=None,
+                  want_vectors=True, verbose=0, stream=None, raise_on_noconv=True):
+    import torch
+    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose)
+    info = DavInfo()
+    omega = (ctypes.c_double * nroots)()
+    X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None
+    gp = ctypes.c_void_p(0)
+    if guess is not None:
+        _need(guess, torch.complex128, "guess")
+        gp = ctypes.c_void_p(guess.data_ptr())
+        if opts.nguess == 0:
+            opts.nguess = guess.shape[0]
+    st = load().adc2_davidson(h.ptr, nroots, ctypes.byref(opts), gp, omega,
+                              ctypes.c_void_p(X.data_ptr()) if X is not None else ctypes.c_void_p(0),
+                              ctypes.byref(info), _stream_ptr(stream))
+    res = (list(omega), X, info.as_dict(nroots))
+    if st == ADC2_ERR_NOCONV and not raise_on_noconv:
+        return res
+    _check(st, "adc2_davidson")
+    return res
+
+
+def adc2_get_m11(h: Handle, stream=None):
+    import torch
+    out = torch.empty((h.ns, h.ns), dtype=torch.complex128, device="cuda")
+    _check(load().adc2_get_m11(h.ptr, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "adc2_get_m11")
+    return out
+
+
+def adc2_get_diag(h: Handle, stream=None):
+    import torch
+    out = torch.empty((h.dim,), dtype=torch.float64, device="cuda")
+    _check(load().adc2_get_diag(h.ptr, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "adc2_get_diag")
+    return out
+
+
+def adc2_mp2_energy(h: Handle) -> float:
+    e = ctypes.c_double()
+    _check(load().adc2_mp2_energy(h.ptr, ctypes.byref(e)), "adc2_mp2_energy")
+    return e.value
+
+
+def adc2_destroy(h: Handle):
+    h.close()
+
+
+def header_exports(path: str = HEADER):
+    """Names of the functions include/adc2.h declares."""
+    import re
+    txt = open(path).read()
+    return sorted(set(re.findall(r"ADC2_API\s+[\w\s\*]+?\b(adc2_\w+)\s*\(", txt)))

@@ -1,0 +1,435 @@
+// api.hip -- C ABI entry points of the CVS-ADC(2) library and the host-side
+// driver of the block Davidson solver.  The host only orchestrates: every
+// arithmetic step runs in the kernels of k_setup / k_sigma / k_davidson; the
+// host reads back the residual norms, the Ritz values and the count of new
+// search directions to decide convergence and restarts.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace adc2 {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static adc2_status fail(adc2_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+static void free_handle(adc2_handle h) {
+  if (!h) return;
+  hipFree(h->Lvv);
+  hipFree(h->Lvo);
+  hipFree(h->Loo);
+  hipFree(h->Vt);
+  hipFree(h->eps);
+  hipFree(h->M11);
+  hipFree(h->diag);
+  hipFree(h->X);
+  hipFree(h->Y);
+  hipFree(h->part);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+}
+
+static double sigma_flops_per_vector(const Dims& d) {
+  const double nc = d.nc, no = d.no, nv = d.nv, naux = d.naux;
+  return 8.0 * (2.0 * nc * no * nv * nv * naux + 2.0 * nc * nv * nv * naux + (nc * nv) * (nc * nv));
+}
+
+// ---------------------------------------------------------------------------
+// Small kernel: compact + scale eigenvectors of a block Gram matrix.
+// Keeps columns with lambda > rel * lambda_max, scaled by lambda^-1/2.
+// ---------------------------------------------------------------------------
+__global__ void k_orth_coeffs(const double* __restrict__ lam, const double2* __restrict__ U, int n, int ldu,
+                              double rel, double2* __restrict__ Uo, int ldo, int* __restrict__ count) {
+  __shared__ int keep[64];
+  __shared__ int nk;
+  if (threadIdx.x == 0) {
+    double lmax = 0.0;
+    for (int i = 0; i < n; ++i) lmax = fmax(lmax, lam[i]);
+    int c = 0;
+    for (int i = n - 1; i >= 0; --i)
+      if (lmax > 0.0 && lam[i] > rel * lmax && isfinite(lam[i])) keep[c++] = i;
+    nk = c;
+    *count = c;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * nk; e += blockDim.x) {
+    const int r = e / nk, c = e % nk;
+    const int src = keep[c];
+    const double sc = 1.0 / sqrt(lam[src]);
+    const double2 u = U[(long)r * ldu + src];
+    Uo[(long)r * ldo + c] = make_double2(u.x * sc, u.y * sc);
+  }
+}
+
+__global__ void k_diag_set(double2* __restrict__ G, int ldg, const double* __restrict__ w, int n) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    G[(long)i * ldg + j] = make_double2(i == j ? w[i] : 0.0, 0.0);
+  }
+}
+
+__global__ void k_gather_theta(const double* __restrict__ th, const int* __restrict__ idx, int n,
+                               double* __restrict__ out) {
+  if (threadIdx.x < n) out[threadIdx.x] = th[idx[threadIdx.x]];
+}
+
+}  // namespace adc2
+
+using namespace adc2;
+
+extern "C" {
+
+const char* adc2_last_error(void) { return g_last_error.c_str(); }
+
+size_t adc2_dim(adc2_handle h) { return h ? (size_t)h->d.dim : 0; }
+
+adc2_status adc2_destroy(adc2_handle h) {
+  free_handle(h);
+  return ADC2_OK;
+}
+
+adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv, int naux, int prec,
+                       void* stream, adc2_handle* out) {
+  if (!out) return fail(ADC2_ERR_ARG, "adc2_setup: out is NULL");
+  *out = nullptr;
+  if (!L || !eps) return fail(ADC2_ERR_ARG, "adc2_setup: L or eps is NULL");
+  if (nc <= 0 || no <= 0 || nv < 2 || naux <= 0)
+    return fail(ADC2_ERR_ARG, "adc2_setup: need nc>0, no>0, nv>=2, naux>0");
+  if (prec != ADC2_FP64) return fail(ADC2_ERR_ARG, "adc2_setup: unsupported precision");
+  if (nc > 64) return fail(ADC2_ERR_ARG, "adc2_setup: nc > 64 not supported");
+  hipStream_t st = (hipStream_t)stream;
+  adc2_handle h = new adc2_handle_s();
+  Dims& d = h->d;
+  d.nc = nc;
+  d.no = no;
+  d.nv = nv;
+  d.naux = naux;
+  d.o = nc + no;
+  d.n = d.o + nv;
+  d.ns = (long)nc * nv;
+  d.npair = (long)nv * (nv - 1) / 2;
+  d.nd = (long)nc * no * d.npair;
+  d.dim = d.ns + d.nd;
+  d.nocc_pair = (long)d.o * (d.o - 1) / 2;
+  h->prec = prec;
+#define SETUP_TRY(call)                                                           \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));               \
+      free_handle(h);                                                             \
+      return e_ == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;             \
+    }                                                                             \
+  } while (0)
+  // energies must be finite
+  std::vector<double> he(d.n);
+  SETUP_TRY(hipMemcpyAsync(he.data(), eps, sizeof(double) * d.n, hipMemcpyDeviceToHost, st));
+  SETUP_TRY(hipStreamSynchronize(st));
+  for (double x : he)
+    if (!std::isfinite(x)) {
+      free_handle(h);
+      return fail(ADC2_ERR_NONFINITE, "adc2_setup: non-finite spinor energy");
+    }
+  SETUP_TRY(hipMalloc(&h->Lvv, sizeof(double2) * (size_t)naux * nv * nv));
+  SETUP_TRY(hipMalloc(&h->Lvo, sizeof(double2) * (size_t)d.o * naux * nv));
+  SETUP_TRY(hipMalloc(&h->Loo, sizeof(double2) * (size_t)naux * d.o * d.o));
+  SETUP_TRY(hipMalloc(&h->Vt, sizeof(double2) * (size_t)nc * no * nc * nv));
+  SETUP_TRY(hipMalloc(&h->eps, sizeof(double) * d.n));
+  SETUP_TRY(hipMalloc(&h->M11, sizeof(double2) * (size_t)d.ns * d.ns));
+  SETUP_TRY(hipMalloc(&h->diag, sizeof(double) * (size_t)d.dim));
+  SETUP_TRY(hipEventCreate(&h->ev0));
+  SETUP_TRY(hipEventCreate(&h->ev1));
+  SETUP_TRY(hipMemcpyAsync(h->eps, eps, sizeof(double) * d.n, hipMemcpyDeviceToDevice, st));
+  double herm[2] = {0, 0};
+  adc2_status rc = launch_repack((const double2*)L, eps, h, herm, st);
+  if (rc != ADC2_OK) {
+    free_handle(h);
+    return rc;
+  }
+  if (!std::isfinite(herm[0]) || !std::isfinite(herm[1])) {
+    free_handle(h);
+    return fail(ADC2_ERR_NONFINITE, "adc2_setup: non-finite Cholesky vector element");
+  }
+  if (herm[0] > 1e-12 * herm[1]) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "adc2_setup: L not Hermitian (max |L_pq - conj L_qp| = %.3e, max |L| = %.3e)",
+             herm[0], herm[1]);
+    free_handle(h);
+    return fail(ADC2_ERR_NOT_HERMITIAN, buf);
+  }
+  rc = build_m11(h, st);
+  if (rc != ADC2_OK) {
+    free_handle(h);
+    return rc;
+  }
+  *out = h;
+  return ADC2_OK;
+#undef SETUP_TRY
+}
+
+adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, void* stream) {
+  if (!h || !X || !S || m <= 0) return fail(ADC2_ERR_ARG, "adc2_sigma: bad arguments");
+  if (X == S) return fail(ADC2_ERR_ARG, "adc2_sigma: S must not alias X");
+  return sigma_fp64(h, m, (const double2*)X, (double2*)S, (hipStream_t)stream);
+}
+
+adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream) {
+  if (!h || !dst) return fail(ADC2_ERR_ARG, "adc2_get_m11: bad arguments");
+  ADC2_HIP(hipMemcpyAsync(dst, h->M11, sizeof(double2) * h->d.ns * h->d.ns, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+  return ADC2_OK;
+}
+
+adc2_status adc2_get_diag(adc2_handle h, double* dst, void* stream) {
+  if (!h || !dst) return fail(ADC2_ERR_ARG, "adc2_get_diag: bad arguments");
+  ADC2_HIP(hipMemcpyAsync(dst, h->diag, sizeof(double) * h->d.dim, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return ADC2_OK;
+}
+
+adc2_status adc2_mp2_energy(adc2_handle h, double* e) {
+  if (!h || !e) return fail(ADC2_ERR_ARG, "adc2_mp2_energy: bad arguments");
+  *e = h->e_mp2;
+  return ADC2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Block Davidson
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DavWork {
+  double2 *V = nullptr, *S = nullptr, *Xb = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr;
+  double2 *Vn = nullptr, *Sn = nullptr;
+  double2 *G = nullptr, *Z = nullptr, *Gt = nullptr, *Ut = nullptr, *Cc = nullptr, *scratch = nullptr;
+  double *theta = nullptr, *lam = nullptr, *npart = nullptr, *thact = nullptr;
+  int *idx = nullptr, *count = nullptr;
+  ~DavWork() {
+    hipFree(V); hipFree(S); hipFree(Xb); hipFree(R); hipFree(T); hipFree(T2); hipFree(Vn); hipFree(Sn);
+    hipFree(G); hipFree(Z); hipFree(Gt); hipFree(Ut); hipFree(Cc); hipFree(scratch);
+    hipFree(theta); hipFree(lam); hipFree(npart); hipFree(thact); hipFree(idx); hipFree(count);
+  }
+};
+
+constexpr int LDG = 64;
+
+// Orthonormalise the na vectors in T against V[0..s) (two passes of
+// projection + symmetric orthonormalisation of the block).  Returns the
+// number of surviving vectors (left in T) or -1 on error.
+int orth_block(DavWork& w, const double2* V, int s, int na, long dim, int nblk, hipStream_t st,
+               adc2_status& rc) {
+  (void)nblk;
+  for (int pass = 0; pass < 2 && na > 0; ++pass) {
+    if (s > 0) {
+      if ((rc = dav_gram(V, s, w.T, na, dim, w.Cc, 32, w.scratch, st)) != ADC2_OK) return -1;
+      if ((rc = dav_combine(V, s, w.Cc, 32, na, dim, w.T, -1.0, true, st)) != ADC2_OK) return -1;
+    }
+    if ((rc = dav_gram(w.T, na, w.T, na, dim, w.Gt, LDG, w.scratch, st)) != ADC2_OK) return -1;
+    if ((rc = dav_heevj(w.Gt, na, LDG, w.lam, w.Ut, LDG, st)) != ADC2_OK) return -1;
+    k_orth_coeffs<<<1, 256, 0, st>>>(w.lam, w.Ut, na, LDG, 1e-14, w.Cc, 32, w.count);
+    int cnt = 0;
+    if (hipMemcpyAsync(&cnt, w.count, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(ADC2_ERR_HIP, "orth_block: count readback failed");
+      return -1;
+    }
+    if (cnt > 0) {
+      if ((rc = dav_combine(w.T, na, w.Cc, 32, cnt, dim, w.T2, 1.0, false, st)) != ADC2_OK) return -1;
+      std::swap(w.T, w.T2);
+    }
+    na = cnt;
+  }
+  return na;
+}
+
+}  // namespace
+
+adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, const void* guess,
+                          double* omega, void* Xout, adc2_dav_info* info, void* stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!h || !omega) return fail(ADC2_ERR_ARG, "adc2_davidson: bad arguments");
+  const int k = nroots;
+  if (k <= 0 || k > ADC2_MAX_ROOTS || 3 * k > LDG)
+    return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..21");
+  hipStream_t st = (hipStream_t)stream;
+  const Dims& d = h->d;
+  const long dim = d.dim;
+  if (dim < k) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots exceeds the matrix dimension");
+  double tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
+  int max_iter = (opt && opt->max_iter > 0) ? opt->max_iter : 300;
+  int max_sub = (opt && opt->max_subspace > 0) ? opt->max_subspace : std::max(6 * k, 3 * k);
+  max_sub = std::min<long>(std::min(max_sub, LDG), dim);
+  if (max_sub < std::min<long>(3 * k, dim))
+    return fail(ADC2_ERR_ARG, "adc2_davidson: max_subspace must be >= 3*nroots");
+  int nguess = (opt && opt->nguess > 0) ? opt->nguess : (k <= 8 ? 2 * k : k);
+  nguess = (int)std::min<long>(nguess, max_sub - k);
+  nguess = (int)std::min<long>(nguess, d.ns);
+  nguess = std::max(nguess, k);
+  const int verbose = opt ? opt->verbose : 0;
+  const int keep_max = std::min(std::min(2 * k, 32), max_sub - k);
+  const int nblk = dav_nblk(dim);
+
+  DavWork w;
+#define DAV_TRY(call) ADC2_HIP(call)
+  DAV_TRY(hipMalloc(&w.V, sizeof(double2) * max_sub * dim));
+  DAV_TRY(hipMalloc(&w.S, sizeof(double2) * max_sub * dim));
+  DAV_TRY(hipMalloc(&w.Xb, sizeof(double2) * k * dim));
+  DAV_TRY(hipMalloc(&w.R, sizeof(double2) * k * dim));
+  DAV_TRY(hipMalloc(&w.T, sizeof(double2) * std::max(k, nguess) * dim));
+  DAV_TRY(hipMalloc(&w.T2, sizeof(double2) * std::max(k, nguess) * dim));
+  DAV_TRY(hipMalloc(&w.Vn, sizeof(double2) * keep_max * dim));
+  DAV_TRY(hipMalloc(&w.Sn, sizeof(double2) * keep_max * dim));
+  DAV_TRY(hipMalloc(&w.G, sizeof(double2) * LDG * LDG));
+  DAV_TRY(hipMalloc(&w.Z, sizeof(double2) * LDG * LDG));
+  DAV_TRY(hipMalloc(&w.Gt, sizeof(double2) * LDG * LDG));
+  DAV_TRY(hipMalloc(&w.Ut, sizeof(double2) * LDG * LDG));
+  DAV_TRY(hipMalloc(&w.Cc, sizeof(double2) * LDG * 32));
+  DAV_TRY(hipMalloc(&w.scratch, sizeof(double2) * 256 * (long)nblk * 16 * 4));
+  DAV_TRY(hipMalloc(&w.theta, sizeof(double) * LDG));
+  DAV_TRY(hipMalloc(&w.lam, sizeof(double) * LDG));
+  DAV_TRY(hipMalloc(&w.npart, sizeof(double) * 32 * nblk));
+  DAV_TRY(hipMalloc(&w.thact, sizeof(double) * 32));
+  DAV_TRY(hipMalloc(&w.idx, sizeof(int) * LDG));
+  DAV_TRY(hipMalloc(&w.count, sizeof(int)));
+
+  double ms_sigma = 0.0;
+  int n_sigma = 0;
+  auto run_sigma = [&](const double2* x, double2* s_out, int m) -> adc2_status {
+    DAV_TRY(hipEventRecord(h->ev0, st));
+    adc2_status r = sigma_fp64(h, m, x, s_out, st);
+    if (r != ADC2_OK) return r;
+    DAV_TRY(hipEventRecord(h->ev1, st));
+    DAV_TRY(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    DAV_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    ms_sigma += ms;
+    n_sigma += m;
+    return ADC2_OK;
+  };
+
+  // initial guess into T, then orthonormalise
+  adc2_status rc = ADC2_OK;
+  if (guess) {
+    DAV_TRY(hipMemcpyAsync(w.T, guess, sizeof(double2) * nguess * dim, hipMemcpyDeviceToDevice, st));
+  } else {
+    std::vector<double> hd(d.ns);
+    DAV_TRY(hipMemcpyAsync(hd.data(), h->diag, sizeof(double) * d.ns, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipStreamSynchronize(st));
+    std::vector<int> ord(d.ns);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hd[a] < hd[b]; });
+    ord.resize(nguess);
+    DAV_TRY(hipMemcpyAsync(w.idx, ord.data(), sizeof(int) * nguess, hipMemcpyHostToDevice, st));
+    if ((rc = dav_unit_guess(w.T, nguess, dim, w.idx, st)) != ADC2_OK) return rc;
+  }
+  int g = orth_block(w, w.V, 0, nguess, dim, nblk, st, rc);
+  if (g < 0) return rc;
+  if (g < k) return fail(ADC2_ERR_ARG, "adc2_davidson: guess vectors are linearly dependent");
+  DAV_TRY(hipMemcpyAsync(w.V, w.T, sizeof(double2) * g * dim, hipMemcpyDeviceToDevice, st));
+  if ((rc = run_sigma(w.V, w.S, g)) != ADC2_OK) return rc;
+  if ((rc = dav_gram(w.V, g, w.S, g, dim, w.G, LDG, w.scratch, st)) != ADC2_OK) return rc;
+  int s = g;
+
+  std::vector<double> th(LDG), np(32 * nblk), rn(k);
+  int it = 0;
+  bool conv = false, nonfinite = false, stalled = false;
+  for (it = 1; it <= max_iter; ++it) {
+    if ((rc = dav_heevj(w.G, s, LDG, w.theta, w.Z, LDG, st)) != ADC2_OK) return rc;
+    if ((rc = dav_residual(w.V, w.S, s, w.Z, LDG, w.theta, k, dim, w.Xb, w.R, w.npart, nblk, st)) != ADC2_OK)
+      return rc;
+    DAV_TRY(hipMemcpyAsync(th.data(), w.theta, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipMemcpyAsync(np.data(), w.npart, sizeof(double) * 32 * nblk, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipStreamSynchronize(st));
+    double rmax = 0.0;
+    for (int j = 0; j < k; ++j) {
+      double a = 0.0;
+      for (int b = 0; b < nblk; ++b) a += np[(long)b * 32 + j];
+      rn[j] = std::sqrt(a);
+      if (!std::isfinite(rn[j]) || !std::isfinite(th[j])) nonfinite = true;
+      rmax = std::max(rmax, rn[j]);
+    }
+    if (verbose) {
+      fprintf(stderr, "[adc2 davidson] it %3d  s %2d  w0 %.12f  max|r| %.3e\n", it, s, th[0], rmax);
+    }
+    if (nonfinite) break;
+    std::vector<int> act;
+    for (int j = 0; j < k; ++j)
+      if (rn[j] > tol) act.push_back(j);
+    if (act.empty()) {
+      conv = true;
+      break;
+    }
+    if (it == max_iter) break;
+    const int na = (int)act.size();
+    for (int q = 0; q < na; ++q)
+      DAV_TRY(hipMemcpyAsync(w.T + (long)q * dim, w.R + (long)act[q] * dim, sizeof(double2) * dim,
+                             hipMemcpyDeviceToDevice, st));
+    DAV_TRY(hipMemcpyAsync(w.idx, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+    k_gather_theta<<<1, 64, 0, st>>>(w.theta, w.idx, na, w.thact);
+    if ((rc = dav_precondition(w.T, w.thact, h->diag, na, dim, st)) != ADC2_OK) return rc;
+    int na_use = na;
+    if (s + na > max_sub && keep_max >= k && keep_max < s) {
+      const int keep = keep_max;
+      if ((rc = dav_combine(w.V, s, w.Z, LDG, keep, dim, w.Vn, 1.0, false, st)) != ADC2_OK) return rc;
+      if ((rc = dav_combine(w.S, s, w.Z, LDG, keep, dim, w.Sn, 1.0, false, st)) != ADC2_OK) return rc;
+      DAV_TRY(hipMemcpyAsync(w.V, w.Vn, sizeof(double2) * keep * dim, hipMemcpyDeviceToDevice, st));
+      DAV_TRY(hipMemcpyAsync(w.S, w.Sn, sizeof(double2) * keep * dim, hipMemcpyDeviceToDevice, st));
+      k_diag_set<<<1, 256, 0, st>>>(w.G, LDG, w.theta, keep);
+      s = keep;
+    }
+    // tiny problems: the subspace cannot restart below nroots; take what fits
+    if (s + na_use > max_sub) na_use = max_sub - s;
+    if (na_use <= 0) {
+      stalled = true;
+      break;
+    }
+    const int nt = orth_block(w, w.V, s, na_use, dim, nblk, st, rc);
+    if (nt < 0) return rc;
+    if (nt == 0) {
+      stalled = true;
+      break;
+    }
+    DAV_TRY(hipMemcpyAsync(w.V + (long)s * dim, w.T, sizeof(double2) * nt * dim, hipMemcpyDeviceToDevice, st));
+    if ((rc = run_sigma(w.V + (long)s * dim, w.S + (long)s * dim, nt)) != ADC2_OK) return rc;
+    if ((rc = dav_gram(w.V, s + nt, w.S + (long)s * dim, nt, dim, w.G + s, LDG, w.scratch, st)) != ADC2_OK)
+      return rc;
+    s += nt;
+  }
+  if (it > max_iter) it = max_iter;
+  for (int j = 0; j < k; ++j) omega[j] = th[j];
+  if (Xout) DAV_TRY(hipMemcpyAsync(Xout, w.Xb, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, st));
+  DAV_TRY(hipStreamSynchronize(st));
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->iters = it;
+    info->n_sigma = n_sigma;
+    info->converged = conv ? 1 : 0;
+    info->subspace = s;
+    for (int j = 0; j < k; ++j) info->resnorm[j] = rn[j];
+    info->ms_sigma = ms_sigma;
+    info->sigma_flops = sigma_flops_per_vector(d) * n_sigma;
+    info->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+#undef DAV_TRY
+  if (nonfinite) return fail(ADC2_ERR_NONFINITE, "adc2_davidson: non-finite residual or Ritz value");
+  if (!conv) {
+    return fail(ADC2_ERR_NOCONV, stalled ? "adc2_davidson: subspace stalled before convergence"
+                                         : "adc2_davidson: max_iter reached");
+  }
+  return ADC2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// internal.h -- handle layout and kernel launchers of the CVS-ADC(2) library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+#include "../../include/adc2.h"
+
+namespace adc2 {
+
+void set_error(const std::string& msg);
+
+#define ADC2_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::adc2::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return e_ == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;               \
+    }                                                                               \
+  } while (0)
+
+#define ADC2_CHECK_LAUNCH() ADC2_HIP(hipGetLastError())
+
+// Sizes of one system.
+struct Dims {
+  int nc, no, nv, naux;
+  int o, n;               // o = nc + no, n = o + nv
+  long ns;                // singles nc*nv
+  long npair;             // nv*(nv-1)/2
+  long nd;                // doubles nc*no*npair
+  long dim;               // ns + nd
+  long nocc_pair;         // o*(o-1)/2 pairs k<l of occupied spinors
+};
+
+// Device buffers owned by a handle.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace adc2
+
+struct adc2_handle_s {
+  adc2::Dims d;
+  int prec = 0;
+  // integral blocks
+  double2* Lvv = nullptr;   // [naux][nv][nv]      L^P_{ac}
+  double2* Lvo = nullptr;   // [o][naux][nv]       L^P_{a k}  (k occupied)
+  double2* Loo = nullptr;   // [naux][o][o]        L^P_{k l}
+  double2* Vt = nullptr;    // [nc][no][nc][nv]    <Ka||Ij> at [I][j][K][a]
+  double* eps = nullptr;    // [n]
+  double2* M11 = nullptr;   // [ns][ns]
+  double* diag = nullptr;   // [dim]
+  double e_mp2 = 0.0;
+  // sigma workspace (grown on demand)
+  int ws_m = 0;
+  double2* X = nullptr;     // [m*nc][naux][nv]
+  double2* Y = nullptr;     // [m*nc][naux+nc][nv]
+  double2* part = nullptr;  // split-K partials of the back-contraction
+  int nsplit = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace adc2 {
+
+// ---- setup kernels (k_setup.hip) ----
+adc2_status launch_repack(const double2* L, const double* eps, adc2_handle h, double* herm_out,
+                          hipStream_t st);
+adc2_status build_m11(adc2_handle h, hipStream_t st);
+
+// ---- sigma kernels (k_sigma.hip) ----
+adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipStream_t st);
+
+// ---- generic GEMM helpers (k_sigma.hip) ----
+// C[i][j] = alpha * sum_k A(i,k) B(k,j) (+ beta C), A row-major (k contiguous,
+// lda), B given as B^T row-major (element (k,j) at B[j*ldb + k]), optional conj.
+adc2_status gemm_rr(int M, int N, int K, const double2* A, long lda, bool conjA, const double2* B,
+                    long ldb, bool conjB, double2* C, long ldc, double alpha, bool accumulate,
+                    hipStream_t st);
+
+// ---- Davidson kernels (k_davidson.hip) ----
+adc2_status dav_gram(const double2* V, int s, const double2* W, int m, long dim, double2* G, int ldg,
+                     double2* scratch, hipStream_t st);
+adc2_status dav_combine(const double2* V, int s, const double2* C, int ldc, int m, long dim,
+                        double2* out, double alpha, bool accumulate, hipStream_t st);
+adc2_status dav_residual(const double2* V, const double2* Sg, int s, const double2* Yc, int ldy,
+                         const double* theta, int k, long dim, double2* Xout, double2* R,
+                         double* norms2_partial, int nblk, hipStream_t st);
+adc2_status dav_precondition(double2* T, const double* theta, const double* diag, int k, long dim,
+                             hipStream_t st);
+adc2_status dav_heevj(const double2* G, int n, int ldg, double* w, double2* Z, int ldz,
+                      hipStream_t st);
+adc2_status dav_scale_columns(double2* T, int k, long dim, const double* s, hipStream_t st);
+adc2_status dav_norms(const double2* T, int k, long dim, double* partial, int nblk, hipStream_t st);
+adc2_status dav_unit_guess(double2* V, int g, long dim, const int* idx, hipStream_t st);
+int dav_nblk(long dim);
+
+}  // namespace adc2

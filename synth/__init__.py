@@ -147,6 +147,8 @@ CONFIGS = {
     "c3": dict(nc=6, no=120, nv=600, naux=3000, nroots=10, seed=27451 + 3),
     # several tiles with ragged tails; oracle still finishes in seconds
     "mid": dict(nc=6, no=12, nv=100, naux=300, nroots=6, seed=27451 + 11),
+    # ragged tiles in every dimension; the oracle Davidson converges in seconds
+    "tiles": dict(nc=3, no=6, nv=80, naux=60, nroots=4, seed=27451 + 12),
 }
 
 
