@@ -141,6 +141,25 @@ ADC2_API adc2_status adc2_get_diag(adc2_handle h, double* dst, void* stream);
 /* MP2 correlation energy -1/4 sum |<ab||ij>|^2 / D^{ab}_{ij} (host scalar). */
 ADC2_API adc2_status adc2_mp2_energy(adc2_handle h, double* e_mp2);
 
+/*
+ * Per-kernel timing of the sigma build (for roofline reporting).
+ * adc2_profile(h, 1) resets the counters and brackets every sigma kernel
+ * launch with HIP events on the launch stream (each sigma call then
+ * synchronises its stream once); adc2_profile(h, 0) stops it.
+ * adc2_kernel_stats fills up to max entries and returns how many kernels are
+ * tracked (or -1 for a NULL handle).  flops are the algorithmic flops of the
+ * recorded launches (8 per complex multiply-add).
+ */
+typedef struct {
+  char name[24];
+  long launches;
+  double ms;        /* summed event time of those launches */
+  double flops;     /* summed algorithmic flops */
+} adc2_kstat;
+
+ADC2_API adc2_status adc2_profile(adc2_handle h, int enable);
+ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
+
 /* Release everything the handle owns.  NULL is accepted. */
 ADC2_API adc2_status adc2_destroy(adc2_handle h);
 

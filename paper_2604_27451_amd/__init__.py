@@ -40,7 +40,8 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
 
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_get_m11",
-           "adc2_get_diag", "adc2_mp2_energy", "adc2_destroy", "adc2_last_error"]
+           "adc2_get_diag", "adc2_mp2_energy", "adc2_profile", "adc2_kernel_stats",
+           "adc2_destroy", "adc2_last_error"]
 
 
 class DavOpts(ctypes.Structure):
@@ -61,6 +62,11 @@ class DavInfo(ctypes.Structure):
                 "subspace": self.subspace, "resnorm": list(self.resnorm[:nroots]),
                 "ms_sigma": self.ms_sigma, "ms_total": self.ms_total,
                 "sigma_flops": self.sigma_flops}
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_long),
+                ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class Adc2Error(RuntimeError):
@@ -97,6 +103,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_get_diag.restype = i
     lib.adc2_mp2_energy.argtypes = [vp, ctypes.POINTER(d)]
     lib.adc2_mp2_energy.restype = i
+    lib.adc2_profile.argtypes = [vp, i]
+    lib.adc2_profile.restype = i
+    lib.adc2_kernel_stats.argtypes = [vp, ctypes.POINTER(KStat), i]
+    lib.adc2_kernel_stats.restype = i
     lib.adc2_destroy.argtypes = [vp]
     lib.adc2_destroy.restype = i
     lib.adc2_last_error.argtypes = []
@@ -225,6 +235,19 @@ def adc2_mp2_energy(h: Handle) -> float:
     e = ctypes.c_double()
     _check(load().adc2_mp2_energy(h.ptr, ctypes.byref(e)), "adc2_mp2_energy")
     return e.value
+
+
+def adc2_profile(h: Handle, enable: bool = True):
+    _check(load().adc2_profile(h.ptr, 1 if enable else 0), "adc2_profile")
+
+
+def adc2_kernel_stats(h: Handle):
+    arr = (KStat * 16)()
+    n = load().adc2_kernel_stats(h.ptr, arr, 16)
+    if n < 0:
+        raise Adc2Error(ADC2_ERR_ARG, "adc2_kernel_stats: NULL handle")
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops}
+            for i in range(n)}
 
 
 def adc2_destroy(h: Handle):

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -37,8 +38,12 @@ static void free_handle(adc2_handle h) {
   hipFree(h->X);
   hipFree(h->Y);
   hipFree(h->part);
+  hipFree(h->Zb);
+  hipFree(h->Tp);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (int i = 0; i <= adc2_handle_s::NK; ++i)
+    if (h->kev[i]) hipEventDestroy(h->kev[i]);
   delete h;
 }
 
@@ -125,6 +130,7 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
   d.dim = d.ns + d.nd;
   d.nocc_pair = (long)d.o * (d.o - 1) / 2;
   h->prec = prec;
+  if (const char* v = getenv("ADC2_ZGEMM")) h->gemm3 = (strcmp(v, "3m") == 0) ? 1 : 0;
 #define SETUP_TRY(call)                                                           \
   do {                                                                            \
     hipError_t e_ = (call);                                                       \
@@ -197,6 +203,33 @@ adc2_status adc2_get_diag(adc2_handle h, double* dst, void* stream) {
   if (!h || !dst) return fail(ADC2_ERR_ARG, "adc2_get_diag: bad arguments");
   ADC2_HIP(hipMemcpyAsync(dst, h->diag, sizeof(double) * h->d.dim, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return ADC2_OK;
+}
+
+adc2_status adc2_profile(adc2_handle h, int enable) {
+  if (!h) return fail(ADC2_ERR_ARG, "adc2_profile: NULL handle");
+  for (int i = 0; i <= adc2_handle_s::NK; ++i)
+    if (!h->kev[i]) ADC2_HIP(hipEventCreate(&h->kev[i]));
+  for (int i = 0; i < adc2_handle_s::NK; ++i) {
+    h->k_launches[i] = 0;
+    h->k_ms[i] = 0.0;
+    h->k_flops[i] = 0.0;
+  }
+  h->profiling = enable ? 1 : 0;
+  return ADC2_OK;
+}
+
+int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max) {
+  if (!h) return -1;
+  static const char* names[adc2_handle_s::NK] = {"unpack", "ybuild", "light1", "xbuild",
+                                                 "sigma2", "pack2", "backc", "m11mv"};
+  for (int i = 0; i < adc2_handle_s::NK && i < max && out; ++i) {
+    memset(&out[i], 0, sizeof(out[i]));
+    strncpy(out[i].name, names[i], sizeof(out[i].name) - 1);
+    out[i].launches = h->k_launches[i];
+    out[i].ms = h->k_ms[i];
+    out[i].flops = h->k_flops[i];
+  }
+  return adc2_handle_s::NK;
 }
 
 adc2_status adc2_mp2_energy(adc2_handle h, double* e) {

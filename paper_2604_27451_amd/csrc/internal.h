@@ -55,11 +55,21 @@ struct adc2_handle_s {
   double e_mp2 = 0.0;
   // sigma workspace (grown on demand)
   int ws_m = 0;
-  double2* X = nullptr;     // [m*nc][naux][nv]
-  double2* Y = nullptr;     // [m*nc][naux+nc][nv]
+  double2* X = nullptr;     // [m*nc][naux][nv]      X^P_{Ia}
+  double2* Y = nullptr;     // [m*nc][naux][nv]      Y^P_{Ic}
+  double2* Zb = nullptr;    // [m*nc][no][nv][nv]    unpacked doubles, then sigma2 core product
+  double2* Tp = nullptr;    // light sigma1 partials [m*nc][no/4][nc][nv]
   double2* part = nullptr;  // split-K partials of the back-contraction
   int nsplit = 0;
+  int gemm3 = 0;            // heavy GEMMs: 0 = four-multiplication 128x128 (default), 1 = three-multiplication 128x64
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-kernel profiling of the sigma build
+  static constexpr int NK = 8;   // unpack, ybuild, light1, xbuild, sigma2, pack2, backc, m11mv
+  int profiling = 0;
+  hipEvent_t kev[NK + 1] = {};
+  long k_launches[NK] = {};
+  double k_ms[NK] = {};
+  double k_flops[NK] = {};
 };
 
 namespace adc2 {

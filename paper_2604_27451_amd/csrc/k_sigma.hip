@@ -5,20 +5,22 @@
 //   M21[(Ijab),(Kc)] = d_IK <ab||cj> - d_ac <Kb||Ij> + d_bc <Ka||Ij>
 //   M22 = diag(e_a + e_b - e_I - e_j),  M12 = M21^H.
 // The three-virtual integral <ab||cj> = (ac|bj) - (aj|bc) is never formed:
-//   X^P_{Ia} = sum_c L^P_{ac} r_{Ic}                               (X-build)
-//   s2_{Ijab} = sum_P (X^P_{Ia} L^P_{bj} - L^P_{aj} X^P_{Ib})
-//             + sum_K (<Ka||Ij> r_{Kb} - r_{Ka} <Kb||Ij>) + D r2      (sigma2)
-//   Y^P_{Ic}  = sum_{jd} conj(L^P_{dj}) r_{Ijcd}                       (Y-build)
+//   X^P_{Ia}  = sum_c L^P_{ac} r_{Ic}                                  (X-build)
+//   Z_{Ij}[a][b] = sum_P X^P_{Ia} L^P_{bj}                             (sigma2 GEMM)
+//   s2_{Ijab} = Z_ab - Z_ba + sum_K (<Ka||Ij> r_Kb - r_Ka <Kb||Ij>) + D r2 (pack)
+//   Y^P_{Ic}  = sum_{jd} conj(L^P_{dj}) r_{Ijcd}                          (Y GEMM)
 //   s1_{Ia}   = sum_{Jb} M11 r1 + sum_{Pc} L^P_{ac} Y^P_{Ic}
-//             - sum_{I',jb} conj(<Ib||I'j>) r_{I'jab}                 (sigma1)
-// The sigma2 contraction is an antisymmetric rank-2K product evaluated on
-// the upper tile pairs (a-blk <= b-blk) only, with the light core terms
-// appended as nc extra K entries and D r2 fused into the epilogue.
+//             - sum_{I',jb} conj(<Ib||I'j>) r_{I'jab}                    (sigma1)
+// The two heavy contractions (8 nc no nv^2 naux flops per vector each) are
+// plain complex GEMMs on 128x128 tiles (zgemm.h) with no redundant work; the
+// antisymmetrisation, the denominators and the light core terms run in
+// bandwidth-bound kernels around them.
 #include <algorithm>
 #include <vector>
 
 #include "internal.h"
 #include "tile.h"
+#include "zgemm.h"
 
 namespace adc2 {
 
@@ -104,152 +106,302 @@ __global__ __launch_bounds__(256) void k_xbuild(const double2* __restrict__ x, l
 }
 
 // ---------------------------------------------------------------------------
-// sigma2 (antisymmetric rank-2K product + light core terms + D r2)
+// Large-tile sources.  Rows of a K-major operand are grouped: row i = (g, a)
+// with a < inner, element (k, i) at base[g*gstride + a + k*ld].
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void upper_pair(int t, int nb, int& ab, int& bb) {
-  int r = 0;
-  while (t >= nb - r) {
-    t -= nb - r;
-    ++r;
+template <int NS>
+struct SrcGroupedK {
+  static constexpr int MAP = KMAJOR;
+  const double2* base;
+  long gstride;
+  long ld;
+  int inner, nrows, nk;
+  long off[NS];
+  unsigned okmask;
+  int kk;
+  __device__ __forceinline__ void begin(int tid, int i0) {
+    kk = tid >> 4;
+    okmask = 0;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const int i = i0 + (tid & 15) + 16 * e;
+      const int g = i / inner;
+      off[e] = (long)g * gstride + (i - g * inner);
+      if (i < nrows) okmask |= 1u << e;
+    }
   }
-  ab = r;
-  bb = r + t;
+  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
+    const int k = kc * BK + kk;
+    const long ko = (long)k * ld;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) r.v[e] = ((okmask >> e) & 1u) && k < nk ? base[off[e] + ko] : czero();
+  }
+};
+
+// Y-build A: element (k = (j, d), i = P) = conj(L^P_{d j}) = conj(Lvo[nc+j][P][d]);
+// k runs over j-blocks of cpe chunks (d padded to a multiple of BK).
+template <int NS>
+struct SrcLconjRows {
+  static constexpr int MAP = RMAJOR;
+  const double2* base;   // Lvo + nc*naux*nv
+  long jstride;          // naux*nv
+  int nv, cpe, nrows;
+  long off[NS];
+  unsigned okmask;
+  int kk;
+  __device__ __forceinline__ void begin(int tid, int i0) {
+    kk = tid & 15;
+    okmask = 0;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const int P = i0 + (tid >> 4) + 16 * e;
+      off[e] = (long)P * nv;
+      if (P < nrows) okmask |= 1u << e;
+    }
+  }
+  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
+    const int j = kc / cpe;
+    const int d = (kc - j * cpe) * BK + kk;
+    const long jo = (long)j * jstride + d;
+    const bool dok = d < nv;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      if (((okmask >> e) & 1u) && dok) {
+        const double2 v = base[off[e] + jo];
+        r.v[e] = make_double2(v.x, -v.y);
+      } else {
+        r.v[e] = czero();
+      }
+    }
+  }
+};
+
+// Y-build B: element (k = (j, d), col = (mI, c)) = R_{mI j}[c][d] from the
+// unpacked antisymmetric doubles Rf[mI][j][c][d].
+template <int NS>
+struct SrcRfull {
+  static constexpr int MAP = RMAJOR;
+  const double2* R;
+  int nv, no, cpe, ncols;
+  long off[NS];
+  unsigned okmask;
+  int kk;
+  __device__ __forceinline__ void begin(int tid, int i0) {
+    kk = tid & 15;
+    okmask = 0;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const int col = i0 + (tid >> 4) + 16 * e;
+      const int g = col / nv, c = col - g * nv;
+      off[e] = ((long)g * no * nv + c) * nv;
+      if (col < ncols) okmask |= 1u << e;
+    }
+  }
+  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
+    const int j = kc / cpe;
+    const int d = (kc - j * cpe) * BK + kk;
+    const long jo = (long)j * nv * nv + d;
+    const bool dok = d < nv;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) r.v[e] = (((okmask >> e) & 1u) && dok) ? R[off[e] + jo] : czero();
+  }
+};
+
+// sigma2 core:  Z[mI][j][a][b] = sum_P X[mI][P][a] Lvo[nc+j][P][b]
+// G3: three-multiplication 128x64 tiles; otherwise four-multiplication 128x128.
+template <bool G3>
+__global__ __launch_bounds__(256) void k_zsig2(const double2* __restrict__ X, const double2* __restrict__ Lvo,
+                                                int rows, int nc, int no, int nv, int naux,
+                                                double2* __restrict__ Z) {
+  constexpr int TNC = G3 ? BT3N : BT;
+  constexpr int NSB = G3 ? 4 : 8;
+  const int ncols = no * nv;
+  const int nbm = (rows + BT - 1) / BT, nbn = (ncols + TNC - 1) / TNC;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * TNC;
+  const long lds = (long)naux * nv;
+  SrcGroupedK<8> A{X, lds, nv, nv, rows, naux};
+  SrcGroupedK<NSB> B{Lvo + (long)nc * lds, lds, nv, nv, ncols, naux};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  auto store = [&](int r, int c, double2 v) {
+    const int i = i0 + r, jc = j0 + c;
+    if (i < rows && jc < ncols) {
+      const int mI = i / nv, a = i - mI * nv;
+      const int j = jc / nv, b = jc - j * nv;
+      Z[(((long)mI * no + j) * nv + a) * nv + b] = v;
+    }
+  };
+  const int nkc = (naux + BK - 1) / BK;
+  if constexpr (G3) {
+    __shared__ BigSmem3 s;
+    BigAcc3 acc;
+    acc.zero();
+    big_mainloop3(s, A, B, 0, nkc, acc);
+    big_for_each3(acc, store);
+  } else {
+    __shared__ BigSmem s;
+    BigAcc acc;
+    acc.zero();
+    big_mainloop(s, A, B, 0, nkc, acc);
+    big_for_each(acc, store);
+  }
+}
+
+// Y-build:  Y[mI][P][c] = sum_{j,d} conj(L^P_{dj}) R_{mIj}[c][d]
+template <bool G3>
+__global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ Lvo, const double2* __restrict__ Rf,
+                                                int rows, int nc, int no, int nv, int naux,
+                                                double2* __restrict__ Y) {
+  constexpr int TNC = G3 ? BT3N : BT;
+  constexpr int NSB = G3 ? 4 : 8;
+  const int ncols = rows * nv;
+  const int nbm = (naux + BT - 1) / BT, nbn = (ncols + TNC - 1) / TNC;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * TNC;
+  const int cpe = (nv + BK - 1) / BK;
+  const long lds = (long)naux * nv;
+  SrcLconjRows<8> A{Lvo + (long)nc * lds, lds, nv, cpe, naux};
+  SrcRfull<NSB> B{Rf, nv, no, cpe, ncols};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  auto store = [&](int r, int c, double2 v) {
+    const int P = i0 + r, col = j0 + c;
+    if (P < naux && col < ncols) {
+      const int mI = col / nv, cc = col - mI * nv;
+      Y[((long)mI * naux + P) * nv + cc] = v;
+    }
+  };
+  if constexpr (G3) {
+    __shared__ BigSmem3 s;
+    BigAcc3 acc;
+    acc.zero();
+    big_mainloop3(s, A, B, 0, no * cpe, acc);
+    big_for_each3(acc, store);
+  } else {
+    __shared__ BigSmem s;
+    BigAcc acc;
+    acc.zero();
+    big_mainloop(s, A, B, 0, no * cpe, acc);
+    big_for_each(acc, store);
+  }
 }
 
 __device__ __forceinline__ long pair_offset(int a, int b, int nv) {
   return (long)a * nv - (long)a * (a + 1) / 2 + (b - a - 1);
 }
 
-__global__ __launch_bounds__(256) void k_sigma2(const double2* __restrict__ xin, double2* __restrict__ sout,
-                                                 long dim, const double2* __restrict__ X,
-                                                 const double2* __restrict__ Lvo, const double2* __restrict__ Vt,
-                                                 const double* __restrict__ eps, int m, int nc, int no, int nv,
-                                                 int naux) {
-  __shared__ TileSmem s;
-  __shared__ double ea[TM], eb[TN];
-  const int nb = (nv + TM - 1) / TM;
-  const int ntp = nb * (nb + 1) / 2;
-  const long nblocks = (long)m * nc * no * ntp;
-  const long lid = xcd_remap(blockIdx.x, nblocks);
-  const int t = (int)(lid % ntp);
-  const int j = (int)((lid / ntp) % no);
-  const int mI = (int)(lid / ((long)ntp * no));
-  const int mv = mI / nc, I = mI - mv * nc;
-  int abk, bbk;
-  upper_pair(t, nb, abk, bbk);
-  const int a0 = abk * TM, b0 = bbk * TN;
-  const int o = nc + no;
-  const long lds = (long)naux * nv;
-  const double2* Xm = X + (long)mI * lds;
-  const double2* Lj = Lvo + (long)(nc + j) * lds;
-  const double2* Vij = Vt + ((long)(I * no + j) * nc) * nv;
-  const double2* r1 = xin + (long)mv * dim;
-  const int tid = threadIdx.x;
-  if (tid < TM) ea[tid] = (a0 + tid < nv) ? eps[o + a0 + tid] : 0.0;
-  else if (tid < TM + TN) eb[tid - TM] = (b0 + tid - TM < nv) ? eps[o + b0 + tid - TM] : 0.0;
+// Rf[m][I][j][c][d] = r2 of vector m, antisymmetric (c<d packed, c>d negated, 0 on c=d)
+__global__ void k_unpack(const double2* __restrict__ xin, long dim, int m, int nc, int no, int nv,
+                         double2* __restrict__ Rf) {
+  const long nv2 = (long)nv * nv;
+  const long total = (long)m * nc * no * nv2;
+  const long ns = (long)nc * nv;
+  const long npair = (long)nv * (nv - 1) / 2;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long g = e / nv2;
+    const int cd = (int)(e - g * nv2);
+    const int c = cd / nv, d = cd - c * nv;
+    const int mv = (int)(g / ((long)nc * no));
+    const long blk = g - (long)mv * nc * no;
+    const double2* r2 = xin + (long)mv * dim + ns + blk * npair;
+    double2 v = czero();
+    if (c < d) v = r2[pair_offset(c, d, nv)];
+    else if (c > d) v = cneg(r2[pair_offset(d, c, nv)]);
+    Rf[e] = v;
+  }
+}
 
-  Acc acc;
-  acc.zero();
-  const int nkc = cdiv(naux + nc, TK);
-  {
-    SrcK2 A{Xm + a0, nv, naux, Vij + a0, nv, nc, nv - a0, 1.0};
-    SrcK2 B{Lj + b0, nv, naux, r1 + b0, nv, nc, nv - b0, 1.0};
-    mainloop(s, A, B, 0, nkc, acc);
+// light sigma1 term, partial over a group of 4 valence j:
+//   Tp[mI][jg][K][c] = sum_{j in group} sum_d conj(<Kd||Ij>) R_{mIj}[c][d]
+//                    = -sum_j sum_d conj(Vt[I][j][K][d]) Rf[mI][j][d][c]
+constexpr int LJG = 4;
+__global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rf, const double2* __restrict__ Vt,
+                                                 int rows, int nc, int no, int nv, double2* __restrict__ Tp) {
+  const int ncb = (nv + 255) / 256;
+  const int njg = (no + LJG - 1) / LJG;
+  const int cb = blockIdx.x % ncb;
+  const int jg = (blockIdx.x / ncb) % njg;
+  const int mI = blockIdx.x / (ncb * njg);
+  const int I = mI % nc;
+  const int c = cb * 256 + threadIdx.x;
+  for (int K0 = 0; K0 < nc; K0 += 8) {
+    double2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = czero();
+    for (int j = jg * LJG; j < min(no, (jg + 1) * LJG); ++j) {
+      const double2* R = Rf + ((long)mI * no + j) * nv * nv;
+      const double2* V = Vt + ((long)I * no + j) * nc * nv;
+      for (int d = 0; d < nv; ++d) {
+        const double2 r = (c < nv) ? R[(long)d * nv + c] : czero();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (K0 + q < nc) acc[q] = csub(acc[q], cmul(cconj(V[(long)(K0 + q) * nv + d]), r));
+      }
+    }
+    if (c < nv)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (K0 + q < nc) Tp[(((long)mI * njg + jg) * nc + K0 + q) * nv + c] = acc[q];
   }
-  {
-    SrcK2 A{Lj + a0, nv, naux, r1 + a0, nv, nc, nv - a0, 1.0};
-    SrcK2 B{Xm + b0, nv, naux, Vij + b0, nv, nc, nv - b0, -1.0};
-    mainloop(s, A, B, 0, nkc, acc);
+}
+
+// sigma2 = Z_ab - Z_ba + D r2 + sum_K (<Ka||Ij> r1_Kb - r1_Ka <Kb||Ij>), a < b, packed.
+// One workgroup per (g = (m,I,j), 32x32 tile pair ab <= bb); the mirror tile
+// is staged in LDS so that both reads of Z are coalesced.
+constexpr int PT = 32;
+__global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, const double2* __restrict__ xin,
+                                                double2* __restrict__ sout, long dim, const double2* __restrict__ Vt,
+                                                const double* __restrict__ eps, int m, int nc, int no, int nv) {
+  __shared__ double2 zt[PT][PT + 1];
+  __shared__ double ea[PT], eb[PT];
+  const int nb = (nv + PT - 1) / PT;
+  const int ntp = nb * (nb + 1) / 2;
+  const long g = blockIdx.x / ntp;
+  int t = blockIdx.x % ntp, abk = 0;
+  while (t >= nb - abk) {
+    t -= nb - abk;
+    ++abk;
   }
+  const int bbk = abk + t;
+  const int a0 = abk * PT, b0 = bbk * PT;
+  const int mv = (int)(g / ((long)nc * no));
+  const int I = (int)((g / no) % nc), j = (int)(g % no);
+  const int o = nc + no;
+  const double2* Zg = Z + g * (long)nv * nv;
+  const int tid = threadIdx.x;
+  // mirror tile Z[b][a] -> zt[b - b0][a - a0]
+  for (int e = tid; e < PT * PT; e += 256) {
+    const int rb = e / PT, ca = e % PT;
+    const int b = b0 + rb, a = a0 + ca;
+    zt[rb][ca] = (b < nv && a < nv) ? Zg[(long)b * nv + a] : czero();
+  }
+  if (tid < PT) ea[tid] = (a0 + tid < nv) ? eps[o + a0 + tid] : 0.0;
+  else if (tid < 2 * PT) eb[tid - PT] = (b0 + tid - PT < nv) ? eps[o + b0 + tid - PT] : 0.0;
+  __syncthreads();
   const long ns = (long)nc * nv;
   const long npair = (long)nv * (nv - 1) / 2;
   const long off = (long)mv * dim + ns + ((long)I * no + j) * npair;
-  const double2* r2 = xin + off;
-  double2* s2 = sout + off;
+  const double2* r1 = xin + (long)mv * dim;
+  const double2* V = Vt + ((long)I * no + j) * nc * nv;
   const double eIj = eps[I] + eps[nc + j];
-  for_each_acc(acc, [&](int r, int c, double2 v) {
-    const int a = a0 + r, b = b0 + c;
+  for (int e = tid; e < PT * PT; e += 256) {
+    const int ra = e / PT, cb = e % PT;
+    const int a = a0 + ra, b = b0 + cb;
     if (a < b && b < nv) {
+      double2 v = csub(Zg[(long)a * nv + b], zt[cb][ra]);
+      for (int K = 0; K < nc; ++K)
+        v = cadd(v, csub(cmul(V[(long)K * nv + a], r1[(long)K * nv + b]), cmul(r1[(long)K * nv + a], V[(long)K * nv + b])));
       const long q = pair_offset(a, b, nv);
-      const double D = ea[r] + eb[c] - eIj;
-      const double2 x2 = r2[q];
-      s2[q] = make_double2(v.x + D * x2.x, v.y + D * x2.y);
+      const double D = ea[ra] + eb[cb] - eIj;
+      const double2 x2 = xin[off + q];
+      sout[off + q] = make_double2(v.x + D * x2.x, v.y + D * x2.y);
     }
-  });
-}
-
-// ---------------------------------------------------------------------------
-// Y-build:  Y[mI][P][c] = sum_{j,d} conj(L^P_{dj}) R_{Ij}[c][d]   (P < naux)
-//           Y[mI][naux+K][c] = sum_{j,d} conj(<Kd||Ij>) R_{Ij}[c][d]
-// with R_{Ij}[c][d] the antisymmetric doubles block of vector m.
-// K index = (j, d) with d padded to a multiple of TK per j.
-// ---------------------------------------------------------------------------
-struct SrcLconj {    // element (k=(j,d), i=P) ; rows P >= naux read <Kd||Ij>
-  static constexpr int MAP = RMAJOR;
-  const double2* Lvo;   // + nc*naux*nv already (valence rows)
-  const double2* VI;    // Vt + I*no*nc*nv
-  int naux, nv, nc, cpe, p0;
-  long lds;
-  __device__ __forceinline__ double2 get(int k, int i) const {
-    const int chunk = k / TK;
-    const int j = chunk / cpe;
-    const int d = (chunk - j * cpe) * TK + (k % TK);
-    const int P = p0 + i;
-    if (d >= nv) return czero();
-    double2 v;
-    if (P < naux) v = Lvo[(long)j * lds + (long)P * nv + d];
-    else if (P < naux + nc) v = VI[((long)j * nc + (P - naux)) * nv + d];
-    else return czero();
-    return make_double2(v.x, -v.y);
   }
-};
-
-struct SrcR2 {       // element (k=(j,d), i=c) = R_{Ij}[c][d] from packed a<b storage
-  static constexpr int MAP = KMAJOR;
-  const double2* r2;    // doubles of (m, I, j=0)
-  long npair;
-  int nv, cpe, c0;
-  __device__ __forceinline__ double2 get(int k, int i) const {
-    const int chunk = k / TK;
-    const int j = chunk / cpe;
-    const int d = (chunk - j * cpe) * TK + (k % TK);
-    const int c = c0 + i;
-    if (d >= nv || c >= nv || c == d) return czero();
-    const double2* blk = r2 + (long)j * npair;
-    if (c < d) return blk[pair_offset(c, d, nv)];
-    const double2 v = blk[pair_offset(d, c, nv)];
-    return make_double2(-v.x, -v.y);
-  }
-};
-
-__global__ __launch_bounds__(256) void k_ybuild(const double2* __restrict__ xin, long dim,
-                                                 const double2* __restrict__ Lvo, const double2* __restrict__ Vt,
-                                                 int m, int nc, int no, int nv, int naux,
-                                                 double2* __restrict__ Y) {
-  __shared__ TileSmem s;
-  const int nrow = naux + nc;
-  const int nbp = cdiv(nrow, TM), nbc = cdiv(nv, TN);
-  const long nblocks = (long)m * nc * nbp * nbc;
-  const long lid = xcd_remap(blockIdx.x, nblocks);
-  const int cb = (int)(lid % nbc);
-  const int pb = (int)((lid / nbc) % nbp);
-  const int mI = (int)(lid / ((long)nbc * nbp));
-  const int mv = mI / nc, I = mI - mv * nc;
-  const int p0 = pb * TM, c0 = cb * TN;
-  const int cpe = cdiv(nv, TK);
-  const long lds = (long)naux * nv;
-  const long ns = (long)nc * nv;
-  const long npair = (long)nv * (nv - 1) / 2;
-  SrcLconj A{Lvo + (long)nc * lds, Vt + (long)I * no * nc * nv, naux, nv, nc, cpe, p0, lds};
-  SrcR2 B{xin + (long)mv * dim + ns + (long)I * no * npair, npair, nv, cpe, c0};
-  Acc acc;
-  acc.zero();
-  mainloop(s, A, B, 0, no * cpe, acc);
-  double2* Ym = Y + (long)mI * nrow * nv;
-  for_each_acc(acc, [&](int r, int c, double2 v) {
-    const int P = p0 + r, cc = c0 + c;
-    if (P < nrow && cc < nv) Ym[(long)P * nv + cc] = v;
-  });
 }
 
 // ---------------------------------------------------------------------------
@@ -284,7 +436,7 @@ struct SrcLvvT {     // element (k=(P,c), i=a) = Lvv[P][a][c]
 };
 
 __global__ __launch_bounds__(256) void k_backc(const double2* __restrict__ Y, const double2* __restrict__ Lvv,
-                                                int nrows, int nv, int naux, int nc, int nsplit,
+                                                int nrows, int nv, int naux, int nsplit,
                                                 double2* __restrict__ part) {
   __shared__ TileSmem s;
   const int nbi = cdiv(nrows, TM), nba = cdiv(nv, TN);
@@ -297,7 +449,7 @@ __global__ __launch_bounds__(256) void k_backc(const double2* __restrict__ Y, co
   const int nchunks = naux * cpe;
   const int per = cdiv(nchunks, nsplit);
   const int kc0 = split * per, kc1 = min(nchunks, kc0 + per);
-  SrcYrows A{Y, naux + nc, nv, cpe, nrows, i0};
+  SrcYrows A{Y, naux, nv, cpe, nrows, i0};
   SrcLvvT B{Lvv, nv, cpe, a0};
   Acc acc;
   acc.zero();
@@ -309,18 +461,20 @@ __global__ __launch_bounds__(256) void k_backc(const double2* __restrict__ Y, co
   });
 }
 
-// s1[m][K][a] += sum_split part[split][mK][a] - sum_I Y[m*nc+I][naux+K][a]
-__global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, const double2* __restrict__ Y,
-                                int m, int nc, int nv, int naux, long dim, double2* __restrict__ sout) {
+// s1[m][K][a] += sum_split part[split][mK][a] + sum_{I,jg} Tp[mI][jg][K][a]
+__global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, const double2* __restrict__ Tp,
+                                int m, int nc, int no, int nv, long dim, double2* __restrict__ sout) {
   const long total = (long)m * nc * nv;
-  const int nrow = naux + nc;
+  const int njg = (no + LJG - 1) / LJG;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int a = (int)(e % nv);
     const int mK = (int)(e / nv);
     const int mv = mK / nc, K = mK - mv * nc;
     double2 acc = make_double2(0, 0);
     for (int sp = 0; sp < nsplit; ++sp) acc = cadd(acc, part[((long)sp * m * nc + mK) * nv + a]);
-    for (int I = 0; I < nc; ++I) acc = csub(acc, Y[((long)(mv * nc + I) * nrow + naux + K) * nv + a]);
+    for (int I = 0; I < nc; ++I)
+      for (int jg = 0; jg < njg; ++jg)
+        acc = csub(acc, Tp[((((long)(mv * nc + I)) * njg + jg) * nc + K) * nv + a]);
     double2* p = sout + (long)mv * dim + (long)K * nv + a;
     *p = cadd(*p, acc);
   }
@@ -333,11 +487,16 @@ static adc2_status ensure_ws(adc2_handle h, int m) {
   hipFree(h->X);
   hipFree(h->Y);
   hipFree(h->part);
-  h->X = h->Y = h->part = nullptr;
+  hipFree(h->Zb);
+  hipFree(h->Tp);
+  h->X = h->Y = h->part = h->Zb = h->Tp = nullptr;
   h->ws_m = 0;
   const long rows = (long)m * d.nc;
   ADC2_HIP(hipMalloc(&h->X, sizeof(double2) * rows * d.naux * d.nv));
-  ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * (d.naux + d.nc) * d.nv));
+  ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * d.naux * d.nv));
+  ADC2_HIP(hipMalloc(&h->Zb, sizeof(double2) * rows * d.no * (long)d.nv * d.nv));
+  const int njg = (d.no + LJG - 1) / LJG;
+  ADC2_HIP(hipMalloc(&h->Tp, sizeof(double2) * rows * njg * d.nc * d.nv));
   const int nbi = cdiv(rows, TM), nba = cdiv(d.nv, TN);
   int nsplit = std::max(1, std::min(256, 2048 / std::max(1, nbi * nba)));
   nsplit = std::min(nsplit, d.naux);
@@ -347,43 +506,101 @@ static adc2_status ensure_ws(adc2_handle h, int m) {
   return ADC2_OK;
 }
 
+static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
+  long g = (n + per - 1) / per;
+  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
+}
+
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, hipStream_t st) {
   adc2_status rc = ensure_ws(h, m);
   if (rc != ADC2_OK) return rc;
   const Dims& d = h->d;
   const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux;
   const int rows = m * nc;
-  // X-build
+  const bool prof = h->profiling != 0;
+  auto mark = [&](int i) -> adc2_status {
+    if (prof) ADC2_HIP(hipEventRecord(h->kev[i], st));
+    return ADC2_OK;
+  };
+  // kernel order (profiling slots): unpack, ygemm, light1, xbuild, zsig2, pack2, backc, m11mv+finish
+  if ((rc = mark(0)) != ADC2_OK) return rc;
+  k_unpack<<<grid_for((long)rows * no * nv * nv), 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
+  ADC2_CHECK_LAUNCH();
+  if ((rc = mark(1)) != ADC2_OK) return rc;
+  if (h->gemm3) {
+    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT3N);
+    k_ygemm<true><<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, h->Zb, rows, nc, no, nv, naux, h->Y);
+    ADC2_CHECK_LAUNCH();
+  } else {
+    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
+    k_ygemm<false><<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, h->Zb, rows, nc, no, nv, naux, h->Y);
+    ADC2_CHECK_LAUNCH();
+  }
+  if ((rc = mark(2)) != ADC2_OK) return rc;
+  {
+    const int njg = (no + LJG - 1) / LJG;
+    k_light1<<<(unsigned)(rows * njg * ((nv + 255) / 256)), 256, 0, st>>>(h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
+    ADC2_CHECK_LAUNCH();
+  }
+  if ((rc = mark(3)) != ADC2_OK) return rc;
   {
     const long nblk = (long)cdiv(rows, TM) * cdiv((long)naux * nv, TN);
     k_xbuild<<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, h->X);
     ADC2_CHECK_LAUNCH();
   }
-  // sigma2
-  {
-    const int nb = cdiv(nv, TM);
-    const long nblk = (long)m * nc * no * (nb * (nb + 1) / 2);
-    k_sigma2<<<(unsigned)nblk, 256, 0, st>>>(xin, sout, d.dim, h->X, h->Lvo, h->Vt, h->eps, m, nc, no, nv, naux);
+  if ((rc = mark(4)) != ADC2_OK) return rc;
+  if (h->gemm3) {
+    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT3N);
+    k_zsig2<true><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * nv, nc, no, nv, naux, h->Zb);
+    ADC2_CHECK_LAUNCH();
+  } else {
+    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
+    k_zsig2<false><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * nv, nc, no, nv, naux, h->Zb);
     ADC2_CHECK_LAUNCH();
   }
-  // Y-build
+  if ((rc = mark(5)) != ADC2_OK) return rc;
   {
-    const long nblk = (long)m * nc * cdiv(naux + nc, TM) * cdiv(nv, TN);
-    k_ybuild<<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, h->Lvo, h->Vt, m, nc, no, nv, naux, h->Y);
+    const int nb = cdiv(nv, PT);
+    const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
+    k_pack2<<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv);
     ADC2_CHECK_LAUNCH();
   }
-  // sigma1 = M11 r1 (writes the singles of S), then back-contraction
+  if ((rc = mark(6)) != ADC2_OK) return rc;
+  {
+    const long nblk = (long)cdiv(rows, TM) * cdiv(nv, TN) * h->nsplit;
+    k_backc<<<(unsigned)nblk, 256, 0, st>>>(h->Y, h->Lvv, rows, nv, naux, h->nsplit, h->part);
+    ADC2_CHECK_LAUNCH();
+  }
+  if ((rc = mark(7)) != ADC2_OK) return rc;
   {
     adc2_status r2 = gemm_rr(m, (int)d.ns, (int)d.ns, xin, d.dim, false, h->M11, d.ns, false, sout, d.dim, 1.0,
                              false, st);
     if (r2 != ADC2_OK) return r2;
-    const long nblk = (long)cdiv(rows, TM) * cdiv(nv, TN) * h->nsplit;
-    k_backc<<<(unsigned)nblk, 256, 0, st>>>(h->Y, h->Lvv, rows, nv, naux, nc, h->nsplit, h->part);
+    k_sigma1_finish<<<grid_for((long)rows * nv, 256, 4096), 256, 0, st>>>(h->part, h->nsplit, h->Tp, m, nc, no,
+                                                                            nv, d.dim, sout);
     ADC2_CHECK_LAUNCH();
-    const long tot = (long)rows * nv;
-    const int g = (int)std::min<long>(4096, (tot + 255) / 256);
-    k_sigma1_finish<<<g, 256, 0, st>>>(h->part, h->nsplit, h->Y, m, nc, nv, naux, d.dim, sout);
-    ADC2_CHECK_LAUNCH();
+  }
+  if ((rc = mark(8)) != ADC2_OK) return rc;
+  if (prof) {
+    ADC2_HIP(hipEventSynchronize(h->kev[8]));
+    const double nc_ = nc, no_ = no, nv_ = nv, na_ = naux, m_ = m;
+    const double heavy = 8.0 * m_ * nc_ * no_ * nv_ * nv_ * na_;
+    const double fl[adc2_handle_s::NK] = {
+        0.0,                                        // unpack (data movement)
+        heavy,                                      // Y-build GEMM
+        8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // light sigma1 core term
+        8.0 * m_ * nc_ * nv_ * nv_ * na_,           // X-build
+        heavy,                                      // sigma2 GEMM
+        8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // pack + light sigma2 core term
+        8.0 * m_ * nc_ * nv_ * nv_ * na_,           // back-contraction
+        8.0 * m_ * (nc_ * nv_) * (nc_ * nv_)};      // M11 r1 + finish
+    for (int i = 0; i < adc2_handle_s::NK; ++i) {
+      float ms = 0.f;
+      ADC2_HIP(hipEventElapsedTime(&ms, h->kev[i], h->kev[i + 1]));
+      h->k_ms[i] += ms;
+      h->k_launches[i] += 1;
+      h->k_flops[i] += fl[i];
+    }
   }
   return ADC2_OK;
 }

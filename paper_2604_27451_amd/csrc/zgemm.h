@@ -1,0 +1,303 @@
+// zgemm.h -- large-tile complex FP64 GEMM engine for gfx950.
+//
+// C[i][j] = sum_k A(k, i) B(k, j) over a 128 x 128 complex output tile per
+// workgroup (256 threads = 4 waves, each wave a 64 x 64 quadrant made of
+// 4 x 4 blocks of v_mfma_f64_16x16x4_f64, real and imaginary accumulators
+// kept in the accumulation registers).  Compared with a 64 x 64 tile this
+// halves the operand bytes per MFMA, so the sigma contractions stay
+// matrix-bound with one wave per SIMD.  Operands stream through LDS in
+// chunks of 16 complex k-values; the next chunk's global loads are issued
+// into registers before the current chunk's MFMAs.
+//
+// A source provides
+//   static constexpr int MAP;                      // KMAJOR or RMAJOR (tile.h)
+//   void begin(int tid, int i0);                   // once per tile: row bases
+//   void load(int kchunk, Regs8& r) const;         // 8 elements of a [16][128] chunk
+// and decides element (k, i) of chunk kchunk for the 8 slots of thread tid
+// with the same maps as tile.h, extended to 8 slots (i = base + 16*e).
+#pragma once
+#include "tile.h"
+
+namespace adc2 {
+
+constexpr int BT = 128;          // tile edge (rows and columns)
+constexpr int BK = 16;           // complex k per chunk
+constexpr int BLDP = BT + 1;     // padded LDS row (doubles): odd stride, no bank conflicts
+
+struct BigSmem {
+  double a_re[BK][BLDP];
+  double a_im[BK][BLDP];
+  double b_re[BK][BLDP];
+  double b_im[BK][BLDP];
+};
+
+template <int N>
+struct RegsN {
+  double2 v[N];
+};
+using Regs8 = RegsN<8>;
+using Regs4 = RegsN<4>;
+
+template <int MAP>
+__device__ __forceinline__ void big_coords(int tid, int e, int& kk, int& ii) {
+  if (MAP == KMAJOR) {
+    kk = tid >> 4;
+    ii = (tid & 15) + 16 * e;
+  } else {
+    kk = tid & 15;
+    ii = (tid >> 4) + 16 * e;
+  }
+}
+
+template <int MAP>
+__device__ __forceinline__ void big_stash(double (*re)[BLDP], double (*im)[BLDP], const Regs8& r, int tid) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int kk, ii;
+    big_coords<MAP>(tid, e, kk, ii);
+    re[kk][ii] = r.v[e].x;
+    im[kk][ii] = r.v[e].y;
+  }
+}
+
+struct BigAcc {
+  d4 re[4][4];
+  d4 im[4][4];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        re[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        im[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+  }
+};
+
+__device__ __forceinline__ void big_mma(const BigSmem& s, BigAcc& acc, int wr, int wc, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < BK; kg += 4) {
+    double ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ar[t] = s.a_re[kg + lk][wr + 16 * t + li];
+      ai[t] = s.a_im[kg + lk][wr + 16 * t + li];
+      br[t] = s.b_re[kg + lk][wc + 16 * t + li];
+      bi[t] = s.b_im[kg + lk][wc + 16 * t + li];
+    }
+    double nai[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) nai[t] = -ai[t];
+    // four passes of 16 independent MFMAs each, so consecutive MFMAs never
+    // feed the same accumulator
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc.im[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], bi[b], acc.re[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc.im[a][b], 0, 0, 0);
+  }
+}
+
+template <class SA, class SB>
+__device__ __forceinline__ void big_mainloop(BigSmem& s, const SA& A, const SB& B, int kc0, int kc1, BigAcc& acc) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  if (kc0 >= kc1) return;
+  Regs8 ra, rb;
+  A.load(kc0, ra);
+  B.load(kc0, rb);
+  for (int c = kc0; c < kc1; ++c) {
+    __syncthreads();
+    big_stash<SA::MAP>(s.a_re, s.a_im, ra, tid);
+    big_stash<SB::MAP>(s.b_re, s.b_im, rb, tid);
+    __syncthreads();
+    if (c + 1 < kc1) {
+      A.load(c + 1, ra);
+      B.load(c + 1, rb);
+    }
+    big_mma(s, acc, wr, wc, lane);
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void big_for_each(const BigAcc& acc, F&& f) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr + 16 * a + (lane >> 4) + 4 * r;
+        const int col = wc + 16 * b + (lane & 15);
+        f(row, col, make_double2(acc.re[a][b][r], acc.im[a][b][r]));
+      }
+}
+
+// Tile order: groups of GROUP_M row-tiles sweep all column tiles, so the
+// row panels of A stay in L2 while B streams; consecutive tiles land on the
+// same XCD through xcd_remap.
+__device__ __forceinline__ void big_tile_coords(long lid, int nbm, int nbn, int& bm, int& bn) {
+  const int GROUP_M = 8;
+  const long per_group = (long)GROUP_M * nbn;
+  const int g = (int)(lid / per_group);
+  const int first = g * GROUP_M;
+  const int gsize = min(GROUP_M, nbm - first);
+  const int r = (int)(lid % per_group);
+  bm = first + r % gsize;
+  bn = r / gsize;
+}
+
+// ---------------------------------------------------------------------------
+// Three-multiplication variant (Gauss): for each 16x16 block
+//   T1 += Ar Br,  T2 += Ai Bi,  T3 += (Ar + Ai)(Br + Bi)
+//   Re = T1 - T2,  Im = T3 - T1 - T2
+// 3 real MFMAs per complex block product instead of 4.  Three accumulator
+// sets need 192 accumulation registers for a 64 x 32 wave tile, so the
+// workgroup tile is 128 x 64 (4 waves as 2 x 2).
+// ---------------------------------------------------------------------------
+constexpr int BT3N = 64;
+constexpr int B3LDP = BT3N + 1;
+
+struct BigSmem3 {
+  double a_re[BK][BLDP];
+  double a_im[BK][BLDP];
+  double b_re[BK][B3LDP];
+  double b_im[BK][B3LDP];
+};
+
+template <int MAP>
+__device__ __forceinline__ void coords4(int tid, int e, int& kk, int& ii) {
+  if (MAP == KMAJOR) {
+    kk = tid >> 4;
+    ii = (tid & 15) + 16 * e;
+  } else {
+    kk = tid & 15;
+    ii = (tid >> 4) + 16 * e;
+  }
+}
+
+template <int MAP>
+__device__ __forceinline__ void stash4(double (*re)[B3LDP], double (*im)[B3LDP], const Regs4& r, int tid) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    int kk, ii;
+    coords4<MAP>(tid, e, kk, ii);
+    re[kk][ii] = r.v[e].x;
+    im[kk][ii] = r.v[e].y;
+  }
+}
+
+struct BigAcc3 {
+  d4 t1[4][2];
+  d4 t2[4][2];
+  d4 t3[4][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        t1[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        t2[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        t3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+  }
+};
+
+__device__ __forceinline__ void big_mma3(const BigSmem3& s, BigAcc3& acc, int wr, int wc, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < BK; kg += 4) {
+    double ar[4], ai[4], as[4], br[2], bi[2], bs[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ar[t] = s.a_re[kg + lk][wr + 16 * t + li];
+      ai[t] = s.a_im[kg + lk][wr + 16 * t + li];
+      as[t] = ar[t] + ai[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      br[t] = s.b_re[kg + lk][wc + 16 * t + li];
+      bi[t] = s.b_im[kg + lk][wc + 16 * t + li];
+      bs[t] = br[t] + bi[t];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.t1[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], acc.t2[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bs[b], acc.t3[a][b], 0, 0, 0);
+  }
+}
+
+template <class SA, class SB>
+__device__ __forceinline__ void big_mainloop3(BigSmem3& s, const SA& A, const SB& B, int kc0, int kc1,
+                                              BigAcc3& acc) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 32;
+  if (kc0 >= kc1) return;
+  Regs8 ra;
+  Regs4 rb;
+  A.load(kc0, ra);
+  B.load(kc0, rb);
+  for (int c = kc0; c < kc1; ++c) {
+    __syncthreads();
+    big_stash<SA::MAP>(s.a_re, s.a_im, ra, tid);
+    stash4<SB::MAP>(s.b_re, s.b_im, rb, tid);
+    __syncthreads();
+    if (c + 1 < kc1) {
+      A.load(c + 1, ra);
+      B.load(c + 1, rb);
+    }
+    big_mma3(s, acc, wr, wc, lane);
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void big_for_each3(const BigAcc3& acc, F&& f) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 32;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr + 16 * a + (lane >> 4) + 4 * r;
+        const int col = wc + 16 * b + (lane & 15);
+        const double t1 = acc.t1[a][b][r], t2 = acc.t2[a][b][r], t3 = acc.t3[a][b][r];
+        f(row, col, make_double2(t1 - t2, t3 - t1 - t2));
+      }
+}
+
+}  // namespace adc2
