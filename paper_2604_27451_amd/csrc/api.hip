@@ -32,6 +32,7 @@ static void free_handle(adc2_handle h) {
   hipFree(h->Lvo);
   hipFree(h->Loo);
   hipFree(h->Vt);
+  hipFree(h->LvT);
   hipFree(h->eps);
   hipFree(h->M11);
   hipFree(h->diag);
@@ -177,6 +178,8 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
     return fail(ADC2_ERR_NOT_HERMITIAN, buf);
   }
   rc = build_m11(h, st);
+  if (rc == ADC2_OK) rc = build_lvt(h, st);
+  if (rc == ADC2_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(ADC2_ERR_HIP, "adc2_setup: sync failed");
   if (rc != ADC2_OK) {
     free_handle(h);
     return rc;

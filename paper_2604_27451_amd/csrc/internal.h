@@ -49,6 +49,7 @@ struct adc2_handle_s {
   double2* Lvo = nullptr;   // [o][naux][nv]       L^P_{a k}  (k occupied)
   double2* Loo = nullptr;   // [naux][o][o]        L^P_{k l}
   double2* Vt = nullptr;    // [nc][no][nc][nv]    <Ka||Ij> at [I][j][K][a]
+  double2* LvT = nullptr;   // [no*nv][naux]       conj(L^P_{dj}) at [(j,d)][P] (valence j)
   double* eps = nullptr;    // [n]
   double2* M11 = nullptr;   // [ns][ns]
   double* diag = nullptr;   // [dim]
@@ -57,10 +58,11 @@ struct adc2_handle_s {
   int ws_m = 0;
   double2* X = nullptr;     // [m*nc][naux][nv]      X^P_{Ia}
   double2* Y = nullptr;     // [m*nc][naux][nv]      Y^P_{Ic}
-  double2* Zb = nullptr;    // [m*nc][no][nv][nv]    unpacked doubles, then sigma2 core product
+  double2* Zb = nullptr;    // unpacked doubles [(j,d)][(mI,c)], then the sigma2 core product [mI][j][a][b]
   double2* Tp = nullptr;    // light sigma1 partials [m*nc][no/4][nc][nv]
   double2* part = nullptr;  // split-K partials of the back-contraction
   int nsplit = 0;
+  int ysplit = 1;           // K-splits of the Y-build GEMM
   int gemm3 = 0;            // heavy GEMMs: 0 = four-multiplication 128x128 (default), 1 = three-multiplication 128x64
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // per-kernel profiling of the sigma build
@@ -81,6 +83,7 @@ adc2_status build_m11(adc2_handle h, hipStream_t st);
 
 // ---- sigma kernels (k_sigma.hip) ----
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipStream_t st);
+adc2_status build_lvt(adc2_handle h, hipStream_t st);
 
 // ---- generic GEMM helpers (k_sigma.hip) ----
 // C[i][j] = alpha * sum_k A(i,k) B(k,j) (+ beta C), A row-major (k contiguous,

@@ -16,6 +16,7 @@
 // antisymmetrisation, the denominators and the light core terms run in
 // bandwidth-bound kernels around them.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.h"
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void k_zsig2(const double2* __restrict__ X, co
     big_mainloop3(s, A, B, 0, nkc, acc);
     big_for_each3(acc, store);
   } else {
-    __shared__ BigSmem s;
+    __shared__ BigSmem s[2];
     BigAcc acc;
     acc.zero();
     big_mainloop(s, A, B, 0, nkc, acc);
@@ -250,9 +251,11 @@ __global__ __launch_bounds__(256) void k_zsig2(const double2* __restrict__ X, co
   }
 }
 
-// Y-build:  Y[mI][P][c] = sum_{j,d} conj(L^P_{dj}) R_{mIj}[c][d]
+// Y-build:  Y[mI][P][c] = sum_{(j,d)} LvT[(j,d)][P] Rt[(j,d)][(mI,c)]
+//                      = sum_{j,d} conj(L^P_{dj}) R_{mIj}[c][d]
+// Both operands are k-major rows (contiguous in P and in (mI,c)).
 template <bool G3>
-__global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ Lvo, const double2* __restrict__ Rf,
+__global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ LvT, const double2* __restrict__ Rt,
                                                 int rows, int nc, int no, int nv, int naux,
                                                 double2* __restrict__ Y) {
   constexpr int TNC = G3 ? BT3N : BT;
@@ -263,31 +266,44 @@ __global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ Lvo, 
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * TNC;
-  const int cpe = (nv + BK - 1) / BK;
-  const long lds = (long)naux * nv;
-  SrcLconjRows<8> A{Lvo + (long)nc * lds, lds, nv, cpe, naux};
-  SrcRfull<NSB> B{Rf, nv, no, cpe, ncols};
+  const int K = no * nv;
+  SrcGroupedK<8> A{LvT, 0, naux, naux, naux, K};
+  SrcGroupedK<NSB> B{Rt, 0, ncols, ncols, ncols, K};
   A.begin(threadIdx.x, i0);
   B.begin(threadIdx.x, j0);
+  // split over K: blockIdx.y of gridDim.y writes its own partial of Y
+  const int nchunks = (K + BK - 1) / BK;
+  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
+  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
   auto store = [&](int r, int c, double2 v) {
     const int P = i0 + r, col = j0 + c;
     if (P < naux && col < ncols) {
       const int mI = col / nv, cc = col - mI * nv;
-      Y[((long)mI * naux + P) * nv + cc] = v;
+      Ys[((long)mI * naux + P) * nv + cc] = v;
     }
   };
   if constexpr (G3) {
     __shared__ BigSmem3 s;
     BigAcc3 acc;
     acc.zero();
-    big_mainloop3(s, A, B, 0, no * cpe, acc);
+    big_mainloop3(s, A, B, kc0, kc1, acc);
     big_for_each3(acc, store);
   } else {
-    __shared__ BigSmem s;
+    __shared__ BigSmem s[2];
     BigAcc acc;
     acc.zero();
-    big_mainloop(s, A, B, 0, no * cpe, acc);
+    big_mainloop(s, A, B, kc0, kc1, acc);
     big_for_each(acc, store);
+  }
+}
+
+// Y = sum of the split partials (in place into split 0)
+__global__ void k_ysum(double2* __restrict__ Y, long len, int nsplit) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < len; e += (long)gridDim.x * blockDim.x) {
+    double2 a = Y[e];
+    for (int s = 1; s < nsplit; ++s) a = cadd(a, Y[(long)s * len + e]);
+    Y[e] = a;
   }
 }
 
@@ -295,24 +311,83 @@ __device__ __forceinline__ long pair_offset(int a, int b, int nv) {
   return (long)a * nv - (long)a * (a + 1) / 2 + (b - a - 1);
 }
 
-// Rf[m][I][j][c][d] = r2 of vector m, antisymmetric (c<d packed, c>d negated, 0 on c=d)
-__global__ void k_unpack(const double2* __restrict__ xin, long dim, int m, int nc, int no, int nv,
-                         double2* __restrict__ Rf) {
-  const long nv2 = (long)nv * nv;
-  const long total = (long)m * nc * no * nv2;
+// Unpack the doubles of all m vectors into the k-major Y-build operand
+//   Rt[(j, d)][(mI, c)] = R_{mI j}[c][d]   (c<d packed, c>d negated, 0 on c=d)
+// with row (j,d) = j*nv + d of length m*nc*nv.  One workgroup per
+// (mI, j, 32x32 tile pair cb <= db): the packed upper tile is read along d
+// (contiguous) and written both straight and, through LDS, transposed; every
+// global access is coalesced.
+constexpr int UT = 32;
+__global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin, long dim, int m, int nc, int no,
+                                                 int nv, double2* __restrict__ Rt) {
+  __shared__ double2 t[UT][UT + 1];
+  const int nb = (nv + UT - 1) / UT;
+  const int ntp = nb * (nb + 1) / 2;
+  const long g = blockIdx.x / ntp;           // g = mI*no + j
+  int tt = blockIdx.x % ntp, cbk = 0;
+  while (tt >= nb - cbk) {
+    tt -= nb - cbk;
+    ++cbk;
+  }
+  const int dbk = cbk + tt;
+  const int c0 = cbk * UT, d0 = dbk * UT;
   const long ns = (long)nc * nv;
   const long npair = (long)nv * (nv - 1) / 2;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const long g = e / nv2;
-    const int cd = (int)(e - g * nv2);
-    const int c = cd / nv, d = cd - c * nv;
-    const int mv = (int)(g / ((long)nc * no));
-    const long blk = g - (long)mv * nc * no;
-    const double2* r2 = xin + (long)mv * dim + ns + blk * npair;
+  const int mI = (int)(g / no), j = (int)(g % no);
+  const int mv = mI / nc, I = mI - mv * nc;
+  const double2* r2 = xin + (long)mv * dim + ns + ((long)I * no + j) * npair;
+  const long ld = (long)m * nc * nv;
+  double2* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c] = R_{mIj}[c][d]
+  const int tid = threadIdx.x;
+  for (int e = tid; e < UT * UT; e += 256) {
+    const int rc = e / UT, cd = e % UT;
+    const int c = c0 + rc, d = d0 + cd;
     double2 v = czero();
-    if (c < d) v = r2[pair_offset(c, d, nv)];
-    else if (c > d) v = cneg(r2[pair_offset(d, c, nv)]);
-    Rf[e] = v;
+    if (c < nv && d < nv && c < d) v = r2[pair_offset(c, d, nv)];
+    t[rc][cd] = v;    // t[c][d] = R[c][d] on the upper tile
+  }
+  __syncthreads();
+  // rows d of the d-tile, columns c of the c-tile: R[c][d] = t[c][d] (c<d)
+  for (int e = tid; e < UT * UT; e += 256) {
+    const int rd = e / UT, cc = e % UT;
+    const int d = d0 + rd, c = c0 + cc;
+    if (c < nv && d < nv) {
+      double2 v;
+      if (cbk == dbk) v = (c < d) ? t[cc][rd] : (c > d ? cneg(t[rd][cc]) : czero());
+      else v = t[cc][rd];
+      R[(long)d * ld + c] = v;
+    }
+  }
+  if (cbk != dbk) {
+    // rows c of the c-tile, columns d of the d-tile: R[d][c] = -R[c][d]
+    for (int e = tid; e < UT * UT; e += 256) {
+      const int rc = e / UT, cd = e % UT;
+      const int c = c0 + rc, d = d0 + cd;
+      if (c < nv && d < nv) R[(long)c * ld + d] = cneg(t[rc][cd]);
+    }
+  }
+}
+
+// One-time conjugate transpose of the valence Cholesky block for the Y-build:
+//   LvT[(j, d)][P] = conj(L^P_{d j}) = conj(Lvo[nc+j][P][d])
+__global__ __launch_bounds__(256) void k_lvo_transpose(const double2* __restrict__ Lvo, int nc, int no, int nv,
+                                                        int naux, double2* __restrict__ LvT) {
+  __shared__ double2 t[UT][UT + 1];
+  const int nbd = (nv + UT - 1) / UT, nbp = (naux + UT - 1) / UT;
+  const int j = blockIdx.x / (nbd * nbp);
+  const int rem = blockIdx.x % (nbd * nbp);
+  const int p0 = (rem / nbd) * UT, d0 = (rem % nbd) * UT;
+  const double2* src = Lvo + (long)(nc + j) * naux * nv;
+  for (int e = threadIdx.x; e < UT * UT; e += 256) {
+    const int rp = e / UT, cd = e % UT;
+    const int P = p0 + rp, d = d0 + cd;
+    t[rp][cd] = (P < naux && d < nv) ? src[(long)P * nv + d] : czero();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < UT * UT; e += 256) {
+    const int rd = e / UT, cp = e % UT;
+    const int d = d0 + rd, P = p0 + cp;
+    if (P < naux && d < nv) LvT[((long)j * nv + d) * naux + P] = cconj(t[cp][rd]);
   }
 }
 
@@ -320,8 +395,11 @@ __global__ void k_unpack(const double2* __restrict__ xin, long dim, int m, int n
 //   Tp[mI][jg][K][c] = sum_{j in group} sum_d conj(<Kd||Ij>) R_{mIj}[c][d]
 //                    = -sum_j sum_d conj(Vt[I][j][K][d]) Rf[mI][j][d][c]
 constexpr int LJG = 4;
-__global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rf, const double2* __restrict__ Vt,
+//   Tp[mI][jg][K][c] = sum_{j in group} sum_d conj(<Kd||Ij>) R_{mIj}[c][d]
+//                    = sum_j sum_d conj(Vt[I][j][K][d]) Rt[(j,d)][(mI,c)]
+__global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rt, const double2* __restrict__ Vt,
                                                  int rows, int nc, int no, int nv, double2* __restrict__ Tp) {
+  __shared__ double2 vs[8][256];
   const int ncb = (nv + 255) / 256;
   const int njg = (no + LJG - 1) / LJG;
   const int cb = blockIdx.x % ncb;
@@ -329,21 +407,42 @@ __global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rf, 
   const int mI = blockIdx.x / (ncb * njg);
   const int I = mI % nc;
   const int c = cb * 256 + threadIdx.x;
+  const bool cok = c < nv;
+  const long ld = (long)rows * nv;
   for (int K0 = 0; K0 < nc; K0 += 8) {
     double2 acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = czero();
     for (int j = jg * LJG; j < min(no, (jg + 1) * LJG); ++j) {
-      const double2* R = Rf + ((long)mI * no + j) * nv * nv;
+      const double2* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c]
       const double2* V = Vt + ((long)I * no + j) * nc * nv;
-      for (int d = 0; d < nv; ++d) {
-        const double2 r = (c < nv) ? R[(long)d * nv + c] : czero();
+      for (int dd0 = 0; dd0 < nv; dd0 += 256) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 8 * 256; e += 256) {
+          const int q = e / 256, dd = e % 256;
+          const int K = K0 + q, d = dd0 + dd;
+          vs[q][dd] = (K < nc && d < nv) ? cconj(V[(long)K * nv + d]) : czero();
+        }
+        __syncthreads();
+        const int dend = min(256, nv - dd0);
+        int dd = 0;
+        for (; dd + 4 <= dend; dd += 4) {
+          double2 r[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (K0 + q < nc) acc[q] = csub(acc[q], cmul(cconj(V[(long)(K0 + q) * nv + d]), r));
+          for (int u = 0; u < 4; ++u) r[u] = cok ? R[(long)(dd0 + dd + u) * ld + c] : czero();
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd + u], r[u]));
+        }
+        for (; dd < dend; ++dd) {
+          const double2 r = cok ? R[(long)(dd0 + dd) * ld + c] : czero();
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd], r));
+        }
       }
     }
-    if (c < nv)
+    if (cok)
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (K0 + q < nc) Tp[(((long)mI * njg + jg) * nc + K0 + q) * nv + c] = acc[q];
@@ -354,10 +453,12 @@ __global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rf, 
 // One workgroup per (g = (m,I,j), 32x32 tile pair ab <= bb); the mirror tile
 // is staged in LDS so that both reads of Z are coalesced.
 constexpr int PT = 32;
+constexpr int PK = 16;   // core spinors staged in LDS by the pack kernel
 __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, const double2* __restrict__ xin,
                                                 double2* __restrict__ sout, long dim, const double2* __restrict__ Vt,
                                                 const double* __restrict__ eps, int m, int nc, int no, int nv) {
   __shared__ double2 zt[PT][PT + 1];
+  __shared__ double2 va[PK][PT], vb[PK][PT], ra[PK][PT], rb[PK][PT];
   __shared__ double ea[PT], eb[PT];
   const int nb = (nv + PT - 1) / PT;
   const int ntp = nb * (nb + 1) / 2;
@@ -373,12 +474,25 @@ __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, co
   const int I = (int)((g / no) % nc), j = (int)(g % no);
   const int o = nc + no;
   const double2* Zg = Z + g * (long)nv * nv;
+  const double2* r1 = xin + (long)mv * dim;
+  const double2* V = Vt + ((long)I * no + j) * nc * nv;
   const int tid = threadIdx.x;
+  const bool staged = nc <= PK;
   // mirror tile Z[b][a] -> zt[b - b0][a - a0]
   for (int e = tid; e < PT * PT; e += 256) {
-    const int rb = e / PT, ca = e % PT;
-    const int b = b0 + rb, a = a0 + ca;
-    zt[rb][ca] = (b < nv && a < nv) ? Zg[(long)b * nv + a] : czero();
+    const int rb_ = e / PT, ca = e % PT;
+    const int b = b0 + rb_, a = a0 + ca;
+    zt[rb_][ca] = (b < nv && a < nv) ? Zg[(long)b * nv + a] : czero();
+  }
+  if (staged) {
+    for (int e = tid; e < nc * PT; e += 256) {
+      const int K = e / PT, x = e % PT;
+      const int a = a0 + x, b = b0 + x;
+      va[K][x] = a < nv ? V[(long)K * nv + a] : czero();
+      ra[K][x] = a < nv ? r1[(long)K * nv + a] : czero();
+      vb[K][x] = b < nv ? V[(long)K * nv + b] : czero();
+      rb[K][x] = b < nv ? r1[(long)K * nv + b] : czero();
+    }
   }
   if (tid < PT) ea[tid] = (a0 + tid < nv) ? eps[o + a0 + tid] : 0.0;
   else if (tid < 2 * PT) eb[tid - PT] = (b0 + tid - PT < nv) ? eps[o + b0 + tid - PT] : 0.0;
@@ -386,18 +500,22 @@ __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, co
   const long ns = (long)nc * nv;
   const long npair = (long)nv * (nv - 1) / 2;
   const long off = (long)mv * dim + ns + ((long)I * no + j) * npair;
-  const double2* r1 = xin + (long)mv * dim;
-  const double2* V = Vt + ((long)I * no + j) * nc * nv;
   const double eIj = eps[I] + eps[nc + j];
   for (int e = tid; e < PT * PT; e += 256) {
-    const int ra = e / PT, cb = e % PT;
-    const int a = a0 + ra, b = b0 + cb;
+    const int ra_ = e / PT, cb = e % PT;
+    const int a = a0 + ra_, b = b0 + cb;
     if (a < b && b < nv) {
-      double2 v = csub(Zg[(long)a * nv + b], zt[cb][ra]);
-      for (int K = 0; K < nc; ++K)
-        v = cadd(v, csub(cmul(V[(long)K * nv + a], r1[(long)K * nv + b]), cmul(r1[(long)K * nv + a], V[(long)K * nv + b])));
+      double2 v = csub(Zg[(long)a * nv + b], zt[cb][ra_]);
+      if (staged) {
+        for (int K = 0; K < nc; ++K)
+          v = cadd(v, csub(cmul(va[K][ra_], rb[K][cb]), cmul(ra[K][ra_], vb[K][cb])));
+      } else {
+        for (int K = 0; K < nc; ++K)
+          v = cadd(v, csub(cmul(V[(long)K * nv + a], r1[(long)K * nv + b]),
+                           cmul(r1[(long)K * nv + a], V[(long)K * nv + b])));
+      }
       const long q = pair_offset(a, b, nv);
-      const double D = ea[ra] + eb[cb] - eIj;
+      const double D = ea[ra_] + eb[cb] - eIj;
       const double2 x2 = xin[off + q];
       sout[off + q] = make_double2(v.x + D * x2.x, v.y + D * x2.y);
     }
@@ -481,6 +599,16 @@ __global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, co
 }
 
 // ---------------------------------------------------------------------------
+adc2_status build_lvt(adc2_handle h, hipStream_t st) {
+  const Dims& d = h->d;
+  if (h->LvT) return ADC2_OK;
+  ADC2_HIP(hipMalloc(&h->LvT, sizeof(double2) * (long)d.no * d.nv * d.naux));
+  const long nblk = (long)d.no * cdiv(d.nv, UT) * cdiv(d.naux, UT);
+  k_lvo_transpose<<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, d.nc, d.no, d.nv, d.naux, h->LvT);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
 static adc2_status ensure_ws(adc2_handle h, int m) {
   if (h->ws_m >= m) return ADC2_OK;
   const Dims& d = h->d;
@@ -493,7 +621,14 @@ static adc2_status ensure_ws(adc2_handle h, int m) {
   h->ws_m = 0;
   const long rows = (long)m * d.nc;
   ADC2_HIP(hipMalloc(&h->X, sizeof(double2) * rows * d.naux * d.nv));
-  ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * d.naux * d.nv));
+  {
+    // split the Y-build over K so that the long-K tiles fill the GPU
+    const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, BT);
+    int ys = (int)std::max<long>(1, std::min<long>(8, (16L * 256 + ytiles - 1) / ytiles));
+    if (const char* v = getenv("ADC2_YSPLIT")) ys = std::max(1, std::min(16, atoi(v)));
+    h->ysplit = ys;
+  }
+  ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * d.naux * d.nv * h->ysplit));
   ADC2_HIP(hipMalloc(&h->Zb, sizeof(double2) * rows * d.no * (long)d.nv * d.nv));
   const int njg = (d.no + LJG - 1) / LJG;
   ADC2_HIP(hipMalloc(&h->Tp, sizeof(double2) * rows * njg * d.nc * d.nv));
@@ -524,17 +659,28 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   };
   // kernel order (profiling slots): unpack, ygemm, light1, xbuild, zsig2, pack2, backc, m11mv+finish
   if ((rc = mark(0)) != ADC2_OK) return rc;
-  k_unpack<<<grid_for((long)rows * no * nv * nv), 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
+  {
+    const int nb = cdiv(nv, UT);
+    const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
+    k_unpack<<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
+    ADC2_CHECK_LAUNCH();
+  }
   ADC2_CHECK_LAUNCH();
   if ((rc = mark(1)) != ADC2_OK) return rc;
-  if (h->gemm3) {
-    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT3N);
-    k_ygemm<true><<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, h->Zb, rows, nc, no, nv, naux, h->Y);
+  {
+    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, h->gemm3 ? BT3N : BT);
+    const int ys = h->ysplit;
+    dim3 grid((unsigned)nblk, ys);
+    if (h->gemm3)
+      k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, nc, no, nv, naux, h->Y);
+    else
+      k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, nc, no, nv, naux, h->Y);
     ADC2_CHECK_LAUNCH();
-  } else {
-    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
-    k_ygemm<false><<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, h->Zb, rows, nc, no, nv, naux, h->Y);
-    ADC2_CHECK_LAUNCH();
+    if (ys > 1) {
+      const long len = (long)rows * naux * nv;
+      k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, ys);
+      ADC2_CHECK_LAUNCH();
+    }
   }
   if ((rc = mark(2)) != ADC2_OK) return rc;
   {

@@ -114,8 +114,14 @@ __device__ __forceinline__ void big_mma(const BigSmem& s, BigAcc& acc, int wr, i
   }
 }
 
+// Double-buffered main loop: stage (c & 1) holds chunk c.  In iteration c
+// the registers holding chunk c+1 are written into the other stage (whose
+// previous contents were consumed in iteration c-1, fenced by the barrier
+// that closed it), the global loads of chunk c+2 are issued, and the MFMAs
+// of chunk c run; one barrier per chunk.
 template <class SA, class SB>
-__device__ __forceinline__ void big_mainloop(BigSmem& s, const SA& A, const SB& B, int kc0, int kc1, BigAcc& acc) {
+__device__ __forceinline__ void big_mainloop(BigSmem (&s)[2], const SA& A, const SB& B, int kc0, int kc1,
+                                             BigAcc& acc) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
@@ -123,16 +129,25 @@ __device__ __forceinline__ void big_mainloop(BigSmem& s, const SA& A, const SB& 
   Regs8 ra, rb;
   A.load(kc0, ra);
   B.load(kc0, rb);
+  big_stash<SA::MAP>(s[0].a_re, s[0].a_im, ra, tid);
+  big_stash<SB::MAP>(s[0].b_re, s[0].b_im, rb, tid);
+  if (kc0 + 1 < kc1) {
+    A.load(kc0 + 1, ra);
+    B.load(kc0 + 1, rb);
+  }
+  __syncthreads();
   for (int c = kc0; c < kc1; ++c) {
-    __syncthreads();
-    big_stash<SA::MAP>(s.a_re, s.a_im, ra, tid);
-    big_stash<SB::MAP>(s.b_re, s.b_im, rb, tid);
-    __syncthreads();
+    const int cur = (c - kc0) & 1;
     if (c + 1 < kc1) {
-      A.load(c + 1, ra);
-      B.load(c + 1, rb);
+      big_stash<SA::MAP>(s[cur ^ 1].a_re, s[cur ^ 1].a_im, ra, tid);
+      big_stash<SB::MAP>(s[cur ^ 1].b_re, s[cur ^ 1].b_im, rb, tid);
+      if (c + 2 < kc1) {
+        A.load(c + 2, ra);
+        B.load(c + 2, rb);
+      }
     }
-    big_mma(s, acc, wr, wc, lane);
+    big_mma(s[cur], acc, wr, wc, lane);
+    __syncthreads();
   }
 }
 
