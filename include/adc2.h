@@ -57,7 +57,12 @@ typedef enum {
 } adc2_status;
 
 typedef enum {
-  ADC2_FP64 = 0                /* complex FP64 contractions on the FP64 MFMA     */
+  ADC2_FP64 = 0,               /* complex FP64 contractions on the FP64 MFMA     */
+  ADC2_C64 = 1                 /* precision form: the two heavy sigma
+                                  contractions on complex64 operands with the
+                                  FP32 MFMA and FP32 accumulation; setup,
+                                  denominators, packing, Davidson and subspace
+                                  eigensolver stay FP64                          */
 } adc2_precision;
 
 #define ADC2_MAX_ROOTS 32
@@ -89,7 +94,7 @@ typedef struct {
  *         core < valence < virtual is not required but every virtual minus
  *         occupied denominator must be nonzero.
  *   nc, no, nv, naux  > 0 (nv >= 2).
- *   prec  adc2_precision (only ADC2_FP64 here).
+ *   prec  adc2_precision: arithmetic of the sigma build (setup is always FP64).
  * Work done (stream-ordered, then synchronised): slicing L into the
  * virtual-virtual, virtual-occupied and occupied-occupied blocks; the MP2
  * amplitudes tau = <ac||kl> / D^{ac}_{kl} over all occupied k,l (denominators
@@ -130,6 +135,26 @@ ADC2_API adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, vo
 ADC2_API adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt,
                           const void* guess, double* omega, void* X,
                           adc2_dav_info* info, void* stream);
+
+/*
+ * adc2_set_precision -- switch the arithmetic of subsequent sigma builds
+ * (adc2_sigma, adc2_davidson) on an existing handle.  ADC2_C64 builds its
+ * complex64 operand copies on first use (stream-ordered).  ADC2_ERR_ARG for an
+ * unknown precision.
+ */
+ADC2_API adc2_status adc2_set_precision(adc2_handle h, int prec);
+
+/*
+ * adc2_rayleigh -- FP64 Rayleigh quotients and residual norms of k vectors:
+ *   omega[i] = x_i^H M x_i / x_i^H x_i,  resnorm[i] = ||M x_i - omega_i x_i|| / ||x_i||
+ * computed with an FP64 sigma build whatever the handle's precision (the
+ * final polish of the precision form, and an a-posteriori certificate: for
+ * Hermitian M an eigenvalue lies within resnorm of omega).
+ *   X dev complex128 [k][dim]; omega, resnorm host float64 [k] (resnorm may be
+ *   NULL).  Synchronises the stream.
+ */
+ADC2_API adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, double* resnorm,
+                                   void* stream);
 
 /* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
  * column (J,b)) into dev buffer dst.  Stream-ordered. */

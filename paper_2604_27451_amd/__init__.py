@@ -34,14 +34,15 @@ ADC2_ERR_HIP = 4
 ADC2_ERR_NOCONV = 5
 ADC2_ERR_NONFINITE = 6
 ADC2_FP64 = 0
+ADC2_C64 = 1
 ADC2_MAX_ROOTS = 32
 
 STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
 
-EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_get_m11",
-           "adc2_get_diag", "adc2_mp2_energy", "adc2_profile", "adc2_kernel_stats",
-           "adc2_destroy", "adc2_last_error"]
+EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
+           "adc2_rayleigh", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
+           "adc2_kernel_stats", "adc2_destroy", "adc2_last_error"]
 
 
 class DavOpts(ctypes.Structure):
@@ -97,6 +98,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson.argtypes = [vp, i, ctypes.POINTER(DavOpts), vp, ctypes.POINTER(d), vp,
                                   ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson.restype = i
+    lib.adc2_set_precision.argtypes = [vp, i]
+    lib.adc2_set_precision.restype = i
+    lib.adc2_rayleigh.argtypes = [vp, i, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp]
+    lib.adc2_rayleigh.restype = i
     lib.adc2_get_m11.argtypes = [vp, vp, vp]
     lib.adc2_get_m11.restype = i
     lib.adc2_get_diag.argtypes = [vp, vp, vp]
@@ -215,6 +220,22 @@ def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, ngues
         return res
     _check(st, "adc2_davidson")
     return res
+
+
+def adc2_set_precision(h: Handle, prec: int):
+    _check(load().adc2_set_precision(h.ptr, prec), "adc2_set_precision")
+
+
+def adc2_rayleigh(h: Handle, X, stream=None):
+    """FP64 Rayleigh quotients and residual norms of the rows of X."""
+    import torch
+    _need(X, torch.complex128, "X")
+    k = X.shape[0]
+    om = (ctypes.c_double * k)()
+    rn = (ctypes.c_double * k)()
+    _check(load().adc2_rayleigh(h.ptr, k, ctypes.c_void_p(X.data_ptr()), om, rn, _stream_ptr(stream)),
+           "adc2_rayleigh")
+    return list(om), list(rn)
 
 
 def adc2_get_m11(h: Handle, stream=None):

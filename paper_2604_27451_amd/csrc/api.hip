@@ -33,6 +33,8 @@ static void free_handle(adc2_handle h) {
   hipFree(h->Loo);
   hipFree(h->Vt);
   hipFree(h->LvT);
+  hipFree(h->Lv32);
+  hipFree(h->LvT32);
   hipFree(h->eps);
   hipFree(h->M11);
   hipFree(h->diag);
@@ -87,6 +89,14 @@ __global__ void k_diag_set(double2* __restrict__ G, int ldg, const double* __res
   }
 }
 
+__global__ void k_sub_scaled(double2* __restrict__ S, const double2* __restrict__ X, const double* __restrict__ w,
+                             int k, long dim) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < dim * k; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / dim);
+    S[e] = make_double2(S[e].x - w[j] * X[e].x, S[e].y - w[j] * X[e].y);
+  }
+}
+
 __global__ void k_gather_theta(const double* __restrict__ th, const int* __restrict__ idx, int n,
                                double* __restrict__ out) {
   if (threadIdx.x < n) out[threadIdx.x] = th[idx[threadIdx.x]];
@@ -114,7 +124,7 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
   if (!L || !eps) return fail(ADC2_ERR_ARG, "adc2_setup: L or eps is NULL");
   if (nc <= 0 || no <= 0 || nv < 2 || naux <= 0)
     return fail(ADC2_ERR_ARG, "adc2_setup: need nc>0, no>0, nv>=2, naux>0");
-  if (prec != ADC2_FP64) return fail(ADC2_ERR_ARG, "adc2_setup: unsupported precision");
+  if (prec != ADC2_FP64 && prec != ADC2_C64) return fail(ADC2_ERR_ARG, "adc2_setup: unsupported precision");
   if (nc > 64) return fail(ADC2_ERR_ARG, "adc2_setup: nc > 64 not supported");
   hipStream_t st = (hipStream_t)stream;
   adc2_handle h = new adc2_handle_s();
@@ -193,6 +203,74 @@ adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, void* strea
   if (!h || !X || !S || m <= 0) return fail(ADC2_ERR_ARG, "adc2_sigma: bad arguments");
   if (X == S) return fail(ADC2_ERR_ARG, "adc2_sigma: S must not alias X");
   return sigma_fp64(h, m, (const double2*)X, (double2*)S, (hipStream_t)stream);
+}
+
+adc2_status adc2_set_precision(adc2_handle h, int prec) {
+  if (!h) return fail(ADC2_ERR_ARG, "adc2_set_precision: NULL handle");
+  if (prec != ADC2_FP64 && prec != ADC2_C64) return fail(ADC2_ERR_ARG, "adc2_set_precision: unknown precision");
+  h->prec = prec;
+  return ADC2_OK;
+}
+
+adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, double* resnorm, void* stream) {
+  if (!h || !X || !omega || k <= 0 || k > 32) return fail(ADC2_ERR_ARG, "adc2_rayleigh: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const long dim = h->d.dim;
+  const int nblk = dav_nblk(dim);
+  double2 *S = nullptr, *G = nullptr, *scr = nullptr;
+  double *w = nullptr, *np = nullptr;
+  adc2_status rc = ADC2_OK;
+  const int saved = h->prec;
+  std::vector<double2> hg(32 * 32), hn(32 * 32);
+  std::vector<double> hp(32 * (size_t)nblk);
+  auto done = [&](adc2_status r) {
+    h->prec = saved;
+    hipFree(S); hipFree(G); hipFree(scr); hipFree(w); hipFree(np);
+    return r;
+  };
+#define RQ_TRY(call)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return done(e_ == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP);     \
+    }                                                                           \
+  } while (0)
+  RQ_TRY(hipMalloc(&S, sizeof(double2) * k * dim));
+  RQ_TRY(hipMalloc(&G, sizeof(double2) * 2 * 32 * 32));
+  RQ_TRY(hipMalloc(&scr, sizeof(double2) * 256 * (long)nblk * 16 * 4));
+  RQ_TRY(hipMalloc(&w, sizeof(double) * 32));
+  RQ_TRY(hipMalloc(&np, sizeof(double) * 32 * nblk));
+  h->prec = ADC2_FP64;
+  if ((rc = sigma_fp64(h, k, (const double2*)X, S, st)) != ADC2_OK) return done(rc);
+  if ((rc = dav_gram((const double2*)X, k, S, k, dim, G, 32, scr, st)) != ADC2_OK) return done(rc);
+  if ((rc = dav_gram((const double2*)X, k, (const double2*)X, k, dim, G + 32 * 32, 32, scr, st)) != ADC2_OK)
+    return done(rc);
+  RQ_TRY(hipMemcpyAsync(hg.data(), G, sizeof(double2) * 32 * 32, hipMemcpyDeviceToHost, st));
+  RQ_TRY(hipMemcpyAsync(hn.data(), G + 32 * 32, sizeof(double2) * 32 * 32, hipMemcpyDeviceToHost, st));
+  RQ_TRY(hipStreamSynchronize(st));
+  std::vector<double> wn(k), nn(k);
+  for (int i = 0; i < k; ++i) {
+    nn[i] = hn[i * 32 + i].x;
+    wn[i] = hg[i * 32 + i].x / nn[i];
+    omega[i] = wn[i];
+  }
+  if (resnorm) {
+    RQ_TRY(hipMemcpyAsync(w, wn.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    k_sub_scaled<<<(unsigned)std::min<long>(8192, (dim * k + 255) / 256), 256, 0, st>>>(S, (const double2*)X, w, k,
+                                                                                       dim);
+    RQ_TRY(hipGetLastError());
+    if ((rc = dav_norms(S, k, dim, np, nblk, st)) != ADC2_OK) return done(rc);
+    RQ_TRY(hipMemcpyAsync(hp.data(), np, sizeof(double) * 32 * nblk, hipMemcpyDeviceToHost, st));
+    RQ_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < k; ++i) {
+      double a = 0.0;
+      for (int b = 0; b < nblk; ++b) a += hp[(size_t)b * 32 + i];
+      resnorm[i] = std::sqrt(a / nn[i]);
+    }
+  }
+#undef RQ_TRY
+  return done(ADC2_OK);
 }
 
 adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream) {

@@ -50,6 +50,8 @@ struct adc2_handle_s {
   double2* Loo = nullptr;   // [naux][o][o]        L^P_{k l}
   double2* Vt = nullptr;    // [nc][no][nc][nv]    <Ka||Ij> at [I][j][K][a]
   double2* LvT = nullptr;   // [no*nv][naux]       conj(L^P_{dj}) at [(j,d)][P] (valence j)
+  float2* Lv32 = nullptr;   // precision form: complex64 copy of the valence rows of Lvo
+  float2* LvT32 = nullptr;  // precision form: complex64 copy of LvT
   double* eps = nullptr;    // [n]
   double2* M11 = nullptr;   // [ns][ns]
   double* diag = nullptr;   // [dim]
@@ -84,6 +86,7 @@ adc2_status build_m11(adc2_handle h, hipStream_t st);
 // ---- sigma kernels (k_sigma.hip) ----
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipStream_t st);
 adc2_status build_lvt(adc2_handle h, hipStream_t st);
+adc2_status build_c64(adc2_handle h, hipStream_t st);
 
 // ---- generic GEMM helpers (k_sigma.hip) ----
 // C[i][j] = alpha * sum_k A(i,k) B(k,j) (+ beta C), A row-major (k contiguous,

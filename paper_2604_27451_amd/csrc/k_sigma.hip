@@ -22,10 +22,18 @@
 #include "internal.h"
 #include "tile.h"
 #include "zgemm.h"
+#include "zgemm32.h"
 
 namespace adc2 {
 
 __host__ __device__ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// storage conversions of the precision form (complex64 operands, FP64 arithmetic around them)
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+template <class T> __device__ __forceinline__ T from_d2(double2 v);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
 // ---------------------------------------------------------------------------
 // generic  C[i][j] = alpha * sum_k A[i][k] B^T[j][k]  (both k-contiguous)
@@ -84,9 +92,10 @@ struct SrcR1Rows {   // element (k=c, i=mI) = r1 of vector m, core I
   }
 };
 
+template <class TO>
 __global__ __launch_bounds__(256) void k_xbuild(const double2* __restrict__ x, long dim, int nc, int nv, int naux,
                                                  int nrows, const double2* __restrict__ Lvv,
-                                                 double2* __restrict__ X) {
+                                                 TO* __restrict__ X) {
   __shared__ TileSmem s;
   const long ncol = (long)naux * nv;
   const int nbj = cdiv(ncol, TN);
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void k_xbuild(const double2* __restrict__ x, l
   for_each_acc(acc, [&](int r, int c, double2 v) {
     const int mi = i0 + r;
     const long j = j0 + c;
-    if (mi < nrows && j < ncol) X[(long)mi * ncol + j] = v;
+    if (mi < nrows && j < ncol) X[(long)mi * ncol + j] = from_d2<TO>(v);
   });
 }
 
@@ -298,6 +307,70 @@ __global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ LvT, 
   }
 }
 
+// Precision form: the two heavy contractions on complex64 operands with the
+// FP32 MFMA and FP32 accumulation.
+__global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
+                                                    int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+  const int ncols = no * nv;
+  const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const long lds = (long)naux * nv;
+  SrcGroupedKF A{X32, lds, nv, nv, rows, naux};
+  SrcGroupedKF B{Lv32, lds, nv, nv, ncols, naux};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  __shared__ BigSmemF s[2];
+  BigAccF acc;
+  acc.zero();
+  big_mainloopF(s, A, B, 0, (naux + BK - 1) / BK, acc);
+  big_for_eachF(acc, [&](int r, int c, float2 v) {
+    const int i = i0 + r, jc = j0 + c;
+    if (i < rows && jc < ncols) {
+      const int mI = i / nv, a = i - mI * nv;
+      const int j = jc / nv, b = jc - j * nv;
+      Z[(((long)mI * no + j) * nv + a) * nv + b] = v;
+    }
+  });
+}
+
+__global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+                                                    int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+  const int ncols = rows * nv;
+  const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const int K = no * nv;
+  SrcGroupedKF A{LvT32, 0, naux, naux, naux, K};
+  SrcGroupedKF B{Rt32, 0, ncols, ncols, ncols, K};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  const int nchunks = (K + BK - 1) / BK;
+  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
+  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
+  __shared__ BigSmemF s[2];
+  BigAccF acc;
+  acc.zero();
+  big_mainloopF(s, A, B, kc0, kc1, acc);
+  big_for_eachF(acc, [&](int r, int c, float2 v) {
+    const int P = i0 + r, col = j0 + c;
+    if (P < naux && col < ncols) {
+      const int mI = col / nv, cc = col - mI * nv;
+      Ys[((long)mI * naux + P) * nv + cc] = make_double2((double)v.x, (double)v.y);
+    }
+  });
+}
+
+__global__ void k_to_c64(const double2* __restrict__ src, long n, float2* __restrict__ dst) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    dst[e] = make_float2((float)src[e].x, (float)src[e].y);
+}
+
 // Y = sum of the split partials (in place into split 0)
 __global__ void k_ysum(double2* __restrict__ Y, long len, int nsplit) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < len; e += (long)gridDim.x * blockDim.x) {
@@ -318,8 +391,9 @@ __device__ __forceinline__ long pair_offset(int a, int b, int nv) {
 // (contiguous) and written both straight and, through LDS, transposed; every
 // global access is coalesced.
 constexpr int UT = 32;
+template <class TO>
 __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin, long dim, int m, int nc, int no,
-                                                 int nv, double2* __restrict__ Rt) {
+                                                 int nv, TO* __restrict__ Rt) {
   __shared__ double2 t[UT][UT + 1];
   const int nb = (nv + UT - 1) / UT;
   const int ntp = nb * (nb + 1) / 2;
@@ -337,7 +411,7 @@ __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin,
   const int mv = mI / nc, I = mI - mv * nc;
   const double2* r2 = xin + (long)mv * dim + ns + ((long)I * no + j) * npair;
   const long ld = (long)m * nc * nv;
-  double2* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c] = R_{mIj}[c][d]
+  TO* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c] = R_{mIj}[c][d]
   const int tid = threadIdx.x;
   for (int e = tid; e < UT * UT; e += 256) {
     const int rc = e / UT, cd = e % UT;
@@ -355,7 +429,7 @@ __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin,
       double2 v;
       if (cbk == dbk) v = (c < d) ? t[cc][rd] : (c > d ? cneg(t[rd][cc]) : czero());
       else v = t[cc][rd];
-      R[(long)d * ld + c] = v;
+      R[(long)d * ld + c] = from_d2<TO>(v);
     }
   }
   if (cbk != dbk) {
@@ -363,7 +437,7 @@ __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin,
     for (int e = tid; e < UT * UT; e += 256) {
       const int rc = e / UT, cd = e % UT;
       const int c = c0 + rc, d = d0 + cd;
-      if (c < nv && d < nv) R[(long)c * ld + d] = cneg(t[rc][cd]);
+      if (c < nv && d < nv) R[(long)c * ld + d] = from_d2<TO>(cneg(t[rc][cd]));
     }
   }
 }
@@ -397,7 +471,8 @@ __global__ __launch_bounds__(256) void k_lvo_transpose(const double2* __restrict
 constexpr int LJG = 4;
 //   Tp[mI][jg][K][c] = sum_{j in group} sum_d conj(<Kd||Ij>) R_{mIj}[c][d]
 //                    = sum_j sum_d conj(Vt[I][j][K][d]) Rt[(j,d)][(mI,c)]
-__global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rt, const double2* __restrict__ Vt,
+template <class TI>
+__global__ __launch_bounds__(256) void k_light1(const TI* __restrict__ Rt, const double2* __restrict__ Vt,
                                                  int rows, int nc, int no, int nv, double2* __restrict__ Tp) {
   __shared__ double2 vs[8][256];
   const int ncb = (nv + 255) / 256;
@@ -414,7 +489,7 @@ __global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rt, 
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = czero();
     for (int j = jg * LJG; j < min(no, (jg + 1) * LJG); ++j) {
-      const double2* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c]
+      const TI* R = Rt + (long)j * nv * ld + (long)mI * nv;   // R[d*ld + c]
       const double2* V = Vt + ((long)I * no + j) * nc * nv;
       for (int dd0 = 0; dd0 < nv; dd0 += 256) {
         __syncthreads();
@@ -429,14 +504,14 @@ __global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rt, 
         for (; dd + 4 <= dend; dd += 4) {
           double2 r[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) r[u] = cok ? R[(long)(dd0 + dd + u) * ld + c] : czero();
+          for (int u = 0; u < 4; ++u) r[u] = cok ? to_d2(R[(long)(dd0 + dd + u) * ld + c]) : czero();
 #pragma unroll
           for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd + u], r[u]));
         }
         for (; dd < dend; ++dd) {
-          const double2 r = cok ? R[(long)(dd0 + dd) * ld + c] : czero();
+          const double2 r = cok ? to_d2(R[(long)(dd0 + dd) * ld + c]) : czero();
 #pragma unroll
           for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd], r));
         }
@@ -454,7 +529,8 @@ __global__ __launch_bounds__(256) void k_light1(const double2* __restrict__ Rt, 
 // is staged in LDS so that both reads of Z are coalesced.
 constexpr int PT = 32;
 constexpr int PK = 16;   // core spinors staged in LDS by the pack kernel
-__global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, const double2* __restrict__ xin,
+template <class TZ>
+__global__ __launch_bounds__(256) void k_pack2(const TZ* __restrict__ Z, const double2* __restrict__ xin,
                                                 double2* __restrict__ sout, long dim, const double2* __restrict__ Vt,
                                                 const double* __restrict__ eps, int m, int nc, int no, int nv) {
   __shared__ double2 zt[PT][PT + 1];
@@ -473,7 +549,7 @@ __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, co
   const int mv = (int)(g / ((long)nc * no));
   const int I = (int)((g / no) % nc), j = (int)(g % no);
   const int o = nc + no;
-  const double2* Zg = Z + g * (long)nv * nv;
+  const TZ* Zg = Z + g * (long)nv * nv;
   const double2* r1 = xin + (long)mv * dim;
   const double2* V = Vt + ((long)I * no + j) * nc * nv;
   const int tid = threadIdx.x;
@@ -482,7 +558,7 @@ __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, co
   for (int e = tid; e < PT * PT; e += 256) {
     const int rb_ = e / PT, ca = e % PT;
     const int b = b0 + rb_, a = a0 + ca;
-    zt[rb_][ca] = (b < nv && a < nv) ? Zg[(long)b * nv + a] : czero();
+    zt[rb_][ca] = (b < nv && a < nv) ? to_d2(Zg[(long)b * nv + a]) : czero();
   }
   if (staged) {
     for (int e = tid; e < nc * PT; e += 256) {
@@ -505,7 +581,7 @@ __global__ __launch_bounds__(256) void k_pack2(const double2* __restrict__ Z, co
     const int ra_ = e / PT, cb = e % PT;
     const int a = a0 + ra_, b = b0 + cb;
     if (a < b && b < nv) {
-      double2 v = csub(Zg[(long)a * nv + b], zt[cb][ra_]);
+      double2 v = csub(to_d2(Zg[(long)a * nv + b]), zt[cb][ra_]);
       if (staged) {
         for (int K = 0; K < nc; ++K)
           v = cadd(v, csub(cmul(va[K][ra_], rb[K][cb]), cmul(ra[K][ra_], vb[K][cb])));
@@ -599,12 +675,30 @@ __global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, co
 }
 
 // ---------------------------------------------------------------------------
+static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
+  long g = (n + per - 1) / per;
+  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
+}
+
 adc2_status build_lvt(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
   if (h->LvT) return ADC2_OK;
   ADC2_HIP(hipMalloc(&h->LvT, sizeof(double2) * (long)d.no * d.nv * d.naux));
   const long nblk = (long)d.no * cdiv(d.nv, UT) * cdiv(d.naux, UT);
   k_lvo_transpose<<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, d.nc, d.no, d.nv, d.naux, h->LvT);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
+adc2_status build_c64(adc2_handle h, hipStream_t st) {
+  const Dims& d = h->d;
+  if (h->Lv32 && h->LvT32) return ADC2_OK;
+  const long nlv = (long)d.no * d.naux * d.nv;
+  ADC2_HIP(hipMalloc(&h->Lv32, sizeof(float2) * nlv));
+  ADC2_HIP(hipMalloc(&h->LvT32, sizeof(float2) * nlv));
+  k_to_c64<<<grid_for(nlv), 256, 0, st>>>(h->Lvo + (long)d.nc * d.naux * d.nv, nlv, h->Lv32);
+  ADC2_CHECK_LAUNCH();
+  k_to_c64<<<grid_for(nlv), 256, 0, st>>>(h->LvT, nlv, h->LvT32);
   ADC2_CHECK_LAUNCH();
   return ADC2_OK;
 }
@@ -641,10 +735,6 @@ static adc2_status ensure_ws(adc2_handle h, int m) {
   return ADC2_OK;
 }
 
-static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
-  long g = (n + per - 1) / per;
-  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
-}
 
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, hipStream_t st) {
   adc2_status rc = ensure_ws(h, m);
@@ -653,6 +743,8 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux;
   const int rows = m * nc;
   const bool prof = h->profiling != 0;
+  const bool c64 = h->prec == ADC2_C64;
+  if (c64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
   auto mark = [&](int i) -> adc2_status {
     if (prof) ADC2_HIP(hipEventRecord(h->kev[i], st));
     return ADC2_OK;
@@ -662,12 +754,26 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   {
     const int nb = cdiv(nv, UT);
     const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
-    k_unpack<<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
+    if (c64)
+      k_unpack<float2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, (float2*)h->Zb);
+    else
+      k_unpack<double2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
     ADC2_CHECK_LAUNCH();
   }
   ADC2_CHECK_LAUNCH();
   if ((rc = mark(1)) != ADC2_OK) return rc;
-  {
+  if (c64) {
+    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
+    const int ys = h->ysplit;
+    dim3 grid((unsigned)nblk, ys);
+    k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
+    ADC2_CHECK_LAUNCH();
+    if (ys > 1) {
+      const long len = (long)rows * naux * nv;
+      k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, ys);
+      ADC2_CHECK_LAUNCH();
+    }
+  } else {
     const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, h->gemm3 ? BT3N : BT);
     const int ys = h->ysplit;
     dim3 grid((unsigned)nblk, ys);
@@ -685,17 +791,29 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   if ((rc = mark(2)) != ADC2_OK) return rc;
   {
     const int njg = (no + LJG - 1) / LJG;
-    k_light1<<<(unsigned)(rows * njg * ((nv + 255) / 256)), 256, 0, st>>>(h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
+    const unsigned g = (unsigned)(rows * njg * ((nv + 255) / 256));
+    if (c64)
+      k_light1<float2><<<g, 256, 0, st>>>((const float2*)h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
+    else
+      k_light1<double2><<<g, 256, 0, st>>>(h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(3)) != ADC2_OK) return rc;
   {
     const long nblk = (long)cdiv(rows, TM) * cdiv((long)naux * nv, TN);
-    k_xbuild<<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, h->X);
+    if (c64)
+      k_xbuild<float2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, (float2*)h->X);
+    else
+      k_xbuild<double2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, h->X);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(4)) != ADC2_OK) return rc;
-  if (h->gemm3) {
+  if (c64) {
+    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
+    k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
+                                                  (float2*)h->Zb);
+    ADC2_CHECK_LAUNCH();
+  } else if (h->gemm3) {
     const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT3N);
     k_zsig2<true><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * nv, nc, no, nv, naux, h->Zb);
     ADC2_CHECK_LAUNCH();
@@ -708,7 +826,11 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   {
     const int nb = cdiv(nv, PT);
     const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
-    k_pack2<<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv);
+    if (c64)
+      k_pack2<float2><<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc,
+                                                      no, nv);
+    else
+      k_pack2<double2><<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(6)) != ADC2_OK) return rc;
