@@ -156,6 +156,34 @@ ADC2_API adc2_status adc2_set_precision(adc2_handle h, int prec);
 ADC2_API adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, double* resnorm,
                                    void* stream);
 
+/*
+ * adc2_omega_backward -- adjoint of the eigenvalues (spec differentiation
+ * form; Hellmann-Feynman theorem applied to the Hermitian eigenproblem of
+ * Eq. 11 with M through second order, Eq. 12).  For vectors x_k and weights
+ * g_k it returns the gradient of
+ *     f(L, eps) = sum_k g_k x_k^H M(L, eps) x_k / (x_k^H x_k)
+ * with the x_k held fixed, which is the vector-Jacobian product
+ * sum_k g_k d omega_k when the x_k are eigenvectors (e.g. the X of
+ * adc2_davidson).  All arithmetic is FP64 on the GPU whatever the handle's
+ * precision.
+ *   nroots   number of vectors, 1..ADC2_MAX_ROOTS
+ *   X        dev complex128 [nroots][dim], each with non-zero norm
+ *   g_omega  host float64 [nroots], the upstream gradient d(loss)/d omega_k
+ *   dL       dev complex128 [naux][n][n], overwritten with G^P_pq: the
+ *            Hermitian projection of df/dRe L + i df/dIm L, so that
+ *            df = Re sum conj(G) dL for every Hermitian perturbation dL
+ *            (torch's complex-gradient convention restricted to Hermitian L)
+ *   deps     dev float64 [n], overwritten with df/d eps_p
+ * The Cholesky blocks and energies are those the handle was set up with.
+ * Device workspace of the order of o^2 nv^2 + 2 nroots nc no nv^2 complex
+ * values is allocated for the call and freed before it returns (about 30 GB
+ * at nc=6, no=60, nv=300, 10 roots).  Synchronises the stream.  Errors:
+ * ADC2_ERR_ARG (NULL pointers, nroots out of range, non-finite g_omega, a
+ * zero vector), ADC2_ERR_OOM, ADC2_ERR_HIP; dL and deps are then undefined.
+ */
+ADC2_API adc2_status adc2_omega_backward(adc2_handle h, int nroots, const void* X, const double* g_omega,
+                                         void* dL, double* deps, void* stream);
+
 /* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
  * column (J,b)) into dev buffer dst.  Stream-ordered. */
 ADC2_API adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream);

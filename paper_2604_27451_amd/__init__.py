@@ -11,11 +11,17 @@ Functions mirror the C ABI names:
     adc2_sigma(h, X, S=None) -> S
     adc2_davidson(h, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0,
                   guess=None, want_vectors=True, verbose=0) -> (omega, X, info)
+    adc2_set_precision(h, prec)
+    adc2_rayleigh(h, X) -> (omega, resnorm)
+    adc2_omega_backward(h, X, g_omega, dL=None, deps=None) -> (dL, deps)
     adc2_get_m11(h) -> complex128 tensor
     adc2_get_diag(h) -> float64 tensor
     adc2_mp2_energy(h) -> float
     adc2_destroy(h)
     adc2_last_error() -> str
+and the autograd wrapper
+    adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, ...) -> omega (float64 tensor)
+whose backward is adc2_omega_backward.
 """
 from __future__ import annotations
 
@@ -41,7 +47,7 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
 
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
-           "adc2_rayleigh", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
+           "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error"]
 
 
@@ -102,6 +108,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_set_precision.restype = i
     lib.adc2_rayleigh.argtypes = [vp, i, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp]
     lib.adc2_rayleigh.restype = i
+    lib.adc2_omega_backward.argtypes = [vp, i, vp, ctypes.POINTER(d), vp, vp, vp]
+    lib.adc2_omega_backward.restype = i
     lib.adc2_get_m11.argtypes = [vp, vp, vp]
     lib.adc2_get_m11.restype = i
     lib.adc2_get_diag.argtypes = [vp, vp, vp]
@@ -236,6 +244,71 @@ def adc2_rayleigh(h: Handle, X, stream=None):
     _check(load().adc2_rayleigh(h.ptr, k, ctypes.c_void_p(X.data_ptr()), om, rn, _stream_ptr(stream)),
            "adc2_rayleigh")
     return list(om), list(rn)
+
+
+def adc2_omega_backward(h: Handle, X, g_omega, dL=None, deps=None, stream=None):
+    """Gradient of sum_k g_k x_k^H M x_k / x_k^H x_k with respect to L
+    (Hermitian-projected, complex128 [naux][n][n]) and eps (float64 [n])."""
+    import torch
+    _need(X, torch.complex128, "X")
+    if X.dim() == 1:
+        X = X[None]
+    k = X.shape[0]
+    if X.shape[1] != h.dim:
+        raise ValueError("X must be [nroots][dim]")
+    g = [float(v) for v in (g_omega.tolist() if isinstance(g_omega, torch.Tensor) else g_omega)]
+    if len(g) != k:
+        raise ValueError("g_omega must have one entry per vector")
+    n = h.nc + h.no + h.nv
+    if dL is None:
+        dL = torch.empty((h.naux, n, n), dtype=torch.complex128, device=X.device)
+    if deps is None:
+        deps = torch.empty((n,), dtype=torch.float64, device=X.device)
+    _need(dL, torch.complex128, "dL")
+    _need(deps, torch.float64, "deps")
+    if tuple(dL.shape) != (h.naux, n, n) or tuple(deps.shape) != (n,):
+        raise ValueError("dL must be [naux][n][n] and deps [n]")
+    ga = (ctypes.c_double * k)(*g)
+    _check(load().adc2_omega_backward(h.ptr, k, ctypes.c_void_p(X.data_ptr()), ga,
+                                      ctypes.c_void_p(dL.data_ptr()), ctypes.c_void_p(deps.data_ptr()),
+                                      _stream_ptr(stream)), "adc2_omega_backward")
+    return dL, deps
+
+
+_omega_fn = None
+
+
+def _omega_function():
+    global _omega_fn
+    if _omega_fn is not None:
+        return _omega_fn
+    import torch
+
+    class Adc2Omega(torch.autograd.Function):
+        """omega = lowest eigenvalues of M(L, eps); backward by adc2_omega_backward."""
+
+        @staticmethod
+        def forward(ctx, L, eps, nc, no, nv, nroots, tol, max_iter):
+            naux = L.shape[0]
+            h = adc2_setup(L.detach().contiguous(), eps.detach().contiguous(), nc, no, nv, naux)
+            w, X, _ = adc2_davidson(h, nroots, tol=tol, max_iter=max_iter)
+            ctx.h, ctx.X = h, X
+            return torch.tensor(w, dtype=torch.float64, device=L.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            dL, de = adc2_omega_backward(ctx.h, ctx.X, g.detach().cpu())
+            ctx.h.close()
+            ctx.h = ctx.X = None
+            return dL, de, None, None, None, None, None, None
+
+    _omega_fn = Adc2Omega
+    return _omega_fn
+
+
+def adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, max_iter=0):
+    """Lowest nroots eigenvalues as a differentiable function of (L, eps)."""
+    return _omega_function().apply(L, eps, nc, no, nv, nroots, tol, max_iter)
 
 
 def adc2_get_m11(h: Handle, stream=None):

@@ -32,7 +32,7 @@ static void free_handle(adc2_handle h) {
   hipFree(h->Lvo);
   hipFree(h->Loo);
   hipFree(h->Vt);
-  hipFree(h->LvT);
+  hipFree(h->LoT);
   hipFree(h->Lv32);
   hipFree(h->LvT32);
   hipFree(h->eps);
@@ -271,6 +271,16 @@ adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, do
   }
 #undef RQ_TRY
   return done(ADC2_OK);
+}
+
+adc2_status adc2_omega_backward(adc2_handle h, int nroots, const void* X, const double* g_omega, void* dL,
+                                double* deps, void* stream) {
+  if (!h || !X || !g_omega || !dL || !deps) return fail(ADC2_ERR_ARG, "adc2_omega_backward: NULL argument");
+  if (nroots <= 0 || nroots > ADC2_MAX_ROOTS)
+    return fail(ADC2_ERR_ARG, "adc2_omega_backward: nroots must be in 1..ADC2_MAX_ROOTS");
+  for (int k = 0; k < nroots; ++k)
+    if (!std::isfinite(g_omega[k])) return fail(ADC2_ERR_ARG, "adc2_omega_backward: non-finite g_omega");
+  return omega_backward(h, nroots, (const double2*)X, g_omega, (double2*)dL, deps, (hipStream_t)stream);
 }
 
 adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream) {

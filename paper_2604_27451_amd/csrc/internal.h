@@ -49,7 +49,8 @@ struct adc2_handle_s {
   double2* Lvo = nullptr;   // [o][naux][nv]       L^P_{a k}  (k occupied)
   double2* Loo = nullptr;   // [naux][o][o]        L^P_{k l}
   double2* Vt = nullptr;    // [nc][no][nc][nv]    <Ka||Ij> at [I][j][K][a]
-  double2* LvT = nullptr;   // [no*nv][naux]       conj(L^P_{dj}) at [(j,d)][P] (valence j)
+  double2* LoT = nullptr;   // [o*nv][naux]        conj(L^P_{dl}) at [(l,d)][P] (every occupied l)
+  double2* LvT = nullptr;   // LoT + nc*nv*naux:   its valence rows (not a separate allocation)
   float2* Lv32 = nullptr;   // precision form: complex64 copy of the valence rows of Lvo
   float2* LvT32 = nullptr;  // precision form: complex64 copy of LvT
   double* eps = nullptr;    // [n]
@@ -87,6 +88,17 @@ adc2_status build_m11(adc2_handle h, hipStream_t st);
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipStream_t st);
 adc2_status build_lvt(adc2_handle h, hipStream_t st);
 adc2_status build_c64(adc2_handle h, hipStream_t st);
+adc2_status ensure_ws(adc2_handle h, int m);
+adc2_status unpack_weighted(adc2_handle h, int m, const double2* xin, const double* wts, hipStream_t st);
+adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
+
+// ---- setup pieces reused by the adjoint (k_setup.hip) ----
+// W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.
+adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st);
+
+// ---- adjoint (k_adjoint.hip) ----
+adc2_status omega_backward(adc2_handle h, int m, const double2* X, const double* g, double2* dL, double* deps,
+                           hipStream_t st);
 
 // ---- generic GEMM helpers (k_sigma.hip) ----
 // C[i][j] = alpha * sum_k A(i,k) B(k,j) (+ beta C), A row-major (k contiguous,

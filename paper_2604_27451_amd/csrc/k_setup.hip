@@ -456,6 +456,36 @@ static inline int grid_for(long n, int per = 256, int cap = 8192) {
   return (int)std::max<long>(1, std::min<long>(g, cap));
 }
 
+// W for every occupied pair (k<l), in the same pair order as build_m11.
+adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st) {
+  const Dims& d = h->d;
+  const int o = d.o, nv = d.nv;
+  std::vector<int2> pairs;
+  for (int k = 0; k < o; ++k)
+    for (int l = k + 1; l < o; ++l) pairs.push_back(make_int2(k, l));
+  const int npairs = (int)pairs.size();
+  if (npairs == 0) return ADC2_OK;
+  const int nb = (nv + TM - 1) / TM;
+  const long nwblk = (long)npairs * (nb * (nb + 1) / 2);
+  int2* dpairs = nullptr;
+  double* epart = nullptr;
+  hipError_t e = hipMalloc(&dpairs, sizeof(int2) * npairs);
+  if (e == hipSuccess) e = hipMalloc(&epart, sizeof(double) * nwblk);
+  if (e == hipSuccess) e = hipMemcpyAsync(dpairs, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    k_wbuild<<<(unsigned)nwblk, 256, 0, st>>>(h->Lvo, h->eps, dpairs, npairs, d.naux, nv, o, W, epart);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(dpairs);
+  hipFree(epart);
+  if (e != hipSuccess) {
+    set_error(std::string("wbuild: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+  }
+  return ADC2_OK;
+}
+
 adc2_status build_m11(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
   const int nc = d.nc, o = d.o, nv = d.nv, naux = d.naux;

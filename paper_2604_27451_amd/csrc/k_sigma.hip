@@ -115,39 +115,6 @@ __global__ __launch_bounds__(256) void k_xbuild(const double2* __restrict__ x, l
   });
 }
 
-// ---------------------------------------------------------------------------
-// Large-tile sources.  Rows of a K-major operand are grouped: row i = (g, a)
-// with a < inner, element (k, i) at base[g*gstride + a + k*ld].
-// ---------------------------------------------------------------------------
-template <int NS>
-struct SrcGroupedK {
-  static constexpr int MAP = KMAJOR;
-  const double2* base;
-  long gstride;
-  long ld;
-  int inner, nrows, nk;
-  long off[NS];
-  unsigned okmask;
-  int kk;
-  __device__ __forceinline__ void begin(int tid, int i0) {
-    kk = tid >> 4;
-    okmask = 0;
-#pragma unroll
-    for (int e = 0; e < NS; ++e) {
-      const int i = i0 + (tid & 15) + 16 * e;
-      const int g = i / inner;
-      off[e] = (long)g * gstride + (i - g * inner);
-      if (i < nrows) okmask |= 1u << e;
-    }
-  }
-  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
-    const int k = kc * BK + kk;
-    const long ko = (long)k * ld;
-#pragma unroll
-    for (int e = 0; e < NS; ++e) r.v[e] = ((okmask >> e) & 1u) && k < nk ? base[off[e] + ko] : czero();
-  }
-};
-
 // Y-build A: element (k = (j, d), i = P) = conj(L^P_{d j}) = conj(Lvo[nc+j][P][d]);
 // k runs over j-blocks of cpe chunks (d padded to a multiple of BK).
 template <int NS>
@@ -391,9 +358,9 @@ __device__ __forceinline__ long pair_offset(int a, int b, int nv) {
 // (contiguous) and written both straight and, through LDS, transposed; every
 // global access is coalesced.
 constexpr int UT = 32;
-template <class TO>
+template <class TO, bool WTS>
 __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin, long dim, int m, int nc, int no,
-                                                 int nv, TO* __restrict__ Rt) {
+                                                 int nv, TO* __restrict__ Rt, const double* __restrict__ wts) {
   __shared__ double2 t[UT][UT + 1];
   const int nb = (nv + UT - 1) / UT;
   const int ntp = nb * (nb + 1) / 2;
@@ -418,6 +385,7 @@ __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin,
     const int c = c0 + rc, d = d0 + cd;
     double2 v = czero();
     if (c < nv && d < nv && c < d) v = r2[pair_offset(c, d, nv)];
+    if (WTS) v = cscale(v, wts[mv]);
     t[rc][cd] = v;    // t[c][d] = R[c][d] on the upper tile
   }
   __syncthreads();
@@ -442,16 +410,17 @@ __global__ __launch_bounds__(256) void k_unpack(const double2* __restrict__ xin,
   }
 }
 
-// One-time conjugate transpose of the valence Cholesky block for the Y-build:
-//   LvT[(j, d)][P] = conj(L^P_{d j}) = conj(Lvo[nc+j][P][d])
-__global__ __launch_bounds__(256) void k_lvo_transpose(const double2* __restrict__ Lvo, int nc, int no, int nv,
-                                                        int naux, double2* __restrict__ LvT) {
+// One-time conjugate transpose of the occupied Cholesky block:
+//   LoT[(l, d)][P] = conj(L^P_{d l}) = conj(Lvo[l][P][d])   for every occupied l.
+// Its valence rows are the Y-build operand; the adjoint also uses the core rows.
+__global__ __launch_bounds__(256) void k_lvo_transpose(const double2* __restrict__ Lvo, int nv, int naux,
+                                                        double2* __restrict__ LoT) {
   __shared__ double2 t[UT][UT + 1];
   const int nbd = (nv + UT - 1) / UT, nbp = (naux + UT - 1) / UT;
-  const int j = blockIdx.x / (nbd * nbp);
+  const int l = blockIdx.x / (nbd * nbp);
   const int rem = blockIdx.x % (nbd * nbp);
   const int p0 = (rem / nbd) * UT, d0 = (rem % nbd) * UT;
-  const double2* src = Lvo + (long)(nc + j) * naux * nv;
+  const double2* src = Lvo + (long)l * naux * nv;
   for (int e = threadIdx.x; e < UT * UT; e += 256) {
     const int rp = e / UT, cd = e % UT;
     const int P = p0 + rp, d = d0 + cd;
@@ -461,7 +430,7 @@ __global__ __launch_bounds__(256) void k_lvo_transpose(const double2* __restrict
   for (int e = threadIdx.x; e < UT * UT; e += 256) {
     const int rd = e / UT, cp = e % UT;
     const int d = d0 + rd, P = p0 + cp;
-    if (P < naux && d < nv) LvT[((long)j * nv + d) * naux + P] = cconj(t[cp][rd]);
+    if (P < naux && d < nv) LoT[((long)l * nv + d) * naux + P] = cconj(t[cp][rd]);
   }
 }
 
@@ -682,10 +651,11 @@ static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
 
 adc2_status build_lvt(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
-  if (h->LvT) return ADC2_OK;
-  ADC2_HIP(hipMalloc(&h->LvT, sizeof(double2) * (long)d.no * d.nv * d.naux));
-  const long nblk = (long)d.no * cdiv(d.nv, UT) * cdiv(d.naux, UT);
-  k_lvo_transpose<<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, d.nc, d.no, d.nv, d.naux, h->LvT);
+  if (h->LoT) return ADC2_OK;
+  ADC2_HIP(hipMalloc(&h->LoT, sizeof(double2) * (long)d.o * d.nv * d.naux));
+  h->LvT = h->LoT + (long)d.nc * d.nv * d.naux;
+  const long nblk = (long)d.o * cdiv(d.nv, UT) * cdiv(d.naux, UT);
+  k_lvo_transpose<<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, d.nv, d.naux, h->LoT);
   ADC2_CHECK_LAUNCH();
   return ADC2_OK;
 }
@@ -703,7 +673,7 @@ adc2_status build_c64(adc2_handle h, hipStream_t st) {
   return ADC2_OK;
 }
 
-static adc2_status ensure_ws(adc2_handle h, int m) {
+adc2_status ensure_ws(adc2_handle h, int m) {
   if (h->ws_m >= m) return ADC2_OK;
   const Dims& d = h->d;
   hipFree(h->X);
@@ -736,6 +706,32 @@ static adc2_status ensure_ws(adc2_handle h, int m) {
 }
 
 
+// Weighted unpack Rt[(j,d)][(mI,c)] = w_m R_{mIj}[c][d] into h->Zb, and the
+// FP64 Y-build on it into h->Y (split partials summed); used by the adjoint.
+adc2_status unpack_weighted(adc2_handle h, int m, const double2* xin, const double* wts, hipStream_t st) {
+  const Dims& d = h->d;
+  const int nb = cdiv(d.nv, UT);
+  const long nblk = (long)m * d.nc * d.no * (nb * (nb + 1) / 2);
+  k_unpack<double2, true><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, d.nc, d.no, d.nv, h->Zb, wts);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
+adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st) {
+  const Dims& d = h->d;
+  const int rows = m * d.nc;
+  const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
+  dim3 grid((unsigned)nblk, h->ysplit);
+  k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
+  ADC2_CHECK_LAUNCH();
+  if (h->ysplit > 1) {
+    const long len = (long)rows * d.naux * d.nv;
+    k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, h->ysplit);
+    ADC2_CHECK_LAUNCH();
+  }
+  return ADC2_OK;
+}
+
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, hipStream_t st) {
   adc2_status rc = ensure_ws(h, m);
   if (rc != ADC2_OK) return rc;
@@ -755,9 +751,9 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     const int nb = cdiv(nv, UT);
     const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
     if (c64)
-      k_unpack<float2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, (float2*)h->Zb);
+      k_unpack<float2, false><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, (float2*)h->Zb, nullptr);
     else
-      k_unpack<double2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb);
+      k_unpack<double2, false><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb, nullptr);
     ADC2_CHECK_LAUNCH();
   }
   ADC2_CHECK_LAUNCH();

@@ -190,6 +190,39 @@ __device__ __forceinline__ void big_tile_coords(long lid, int nbm, int nbn, int&
 // sets need 192 accumulation registers for a 64 x 32 wave tile, so the
 // workgroup tile is 128 x 64 (4 waves as 2 x 2).
 // ---------------------------------------------------------------------------
+// Large-tile sources.  Rows of a K-major operand are grouped: row i = (g, a)
+// with a < inner, element (k, i) at base[g*gstride + a + k*ld].
+// ---------------------------------------------------------------------------
+template <int NS>
+struct SrcGroupedK {
+  static constexpr int MAP = KMAJOR;
+  const double2* base;
+  long gstride;
+  long ld;
+  int inner, nrows, nk;
+  long off[NS];
+  unsigned okmask;
+  int kk;
+  __device__ __forceinline__ void begin(int tid, int i0) {
+    kk = tid >> 4;
+    okmask = 0;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const int i = i0 + (tid & 15) + 16 * e;
+      const int g = i / inner;
+      off[e] = (long)g * gstride + (i - g * inner);
+      if (i < nrows) okmask |= 1u << e;
+    }
+  }
+  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
+    const int k = kc * BK + kk;
+    const long ko = (long)k * ld;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) r.v[e] = ((okmask >> e) & 1u) && k < nk ? base[off[e] + ko] : czero();
+  }
+};
+
+// ---------------------------------------------------------------------------
 constexpr int BT3N = 64;
 constexpr int B3LDP = BT3N + 1;
 

@@ -58,6 +58,11 @@ def test_argument_errors_without_gpu(lib):
     assert lib.adc2_get_diag(None, None, None) == A.ADC2_ERR_ARG
     e = ctypes.c_double()
     assert lib.adc2_mp2_energy(None, ctypes.byref(e)) == A.ADC2_ERR_ARG
+    assert lib.adc2_set_precision(None, 0) == A.ADC2_ERR_ARG
+    assert lib.adc2_rayleigh(None, 1, None, om, None, None) == A.ADC2_ERR_ARG
+    g = (ctypes.c_double * 1)(1.0)
+    assert lib.adc2_omega_backward(None, 1, None, g, None, None, None) == A.ADC2_ERR_ARG
+    assert "NULL" in A.adc2_last_error()
 
 
 def test_binding_has_no_cpu_fallback(tmp_path):
