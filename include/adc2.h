@@ -73,7 +73,19 @@ typedef struct {
   int max_subspace;    /* subspace cap before restart (0 -> max(6k, 2k+k))   */
   int nguess;          /* initial guess vectors (0 -> 2k if k <= 8 else k)    */
   int verbose;         /* print one line per iteration to stderr              */
+  int solver;          /* ADC2_SOLVER_FULL (0) or ADC2_SOLVER_FOLDED (1)      */
 } adc2_dav_opts;
+
+/* Eigensolvers of adc2_davidson.
+ * ADC2_SOLVER_FULL: block Davidson in the full singles+doubles space.
+ * ADC2_SOLVER_FOLDED: the doubles block M22 = diag(D) is eliminated exactly,
+ *   [M11 + M12 (omega - D)^-1 M21] x1 = omega x1, x2 = (omega - D)^-1 M21 x1,
+ *   and the search space holds singles only; valid for roots below the
+ *   lowest doubles energy (min D minus 0.2 times half the width of the D
+ *   range); otherwise it returns ADC2_ERR_NOCONV with a message naming the
+ *   root.  The returned vectors are the full (x1, x2), unit norm. */
+#define ADC2_SOLVER_FULL 0
+#define ADC2_SOLVER_FOLDED 1
 
 typedef struct {
   int iters;                        /* Davidson iterations performed          */

@@ -42,6 +42,8 @@ ADC2_ERR_NONFINITE = 6
 ADC2_FP64 = 0
 ADC2_C64 = 1
 ADC2_MAX_ROOTS = 32
+ADC2_SOLVER_FULL = 0
+ADC2_SOLVER_FOLDED = 1
 
 STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
@@ -54,7 +56,7 @@ EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_pr
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class DavInfo(ctypes.Structure):
@@ -208,9 +210,9 @@ def adc2_sigma(h: Handle, X, S=None, stream=None):
 
 
 def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, guess=None,
-                  want_vectors=True, verbose=0, stream=None, raise_on_noconv=True):
+                  want_vectors=True, verbose=0, stream=None, raise_on_noconv=True, solver=ADC2_SOLVER_FULL):
     import torch
-    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose)
+    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver)
     info = DavInfo()
     omega = (ctypes.c_double * nroots)()
     X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None

@@ -384,6 +384,11 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
                           double* omega, void* Xout, adc2_dav_info* info, void* stream) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!h || !omega) return fail(ADC2_ERR_ARG, "adc2_davidson: bad arguments");
+  if (opt && opt->solver == ADC2_SOLVER_FOLDED) {
+    if (nroots <= 0 || nroots > ADC2_MAX_ROOTS) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..32");
+    return fold_davidson(h, nroots, opt, guess, omega, Xout, info, (hipStream_t)stream);
+  }
+  if (opt && opt->solver != ADC2_SOLVER_FULL) return fail(ADC2_ERR_ARG, "adc2_davidson: unknown solver");
   const int k = nroots;
   if (k <= 0 || k > ADC2_MAX_ROOTS || 3 * k > LDG)
     return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..21");

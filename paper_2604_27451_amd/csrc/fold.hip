@@ -1,0 +1,759 @@
+// fold.hip -- folded (doubles-free) Davidson solver for the lowest roots of
+// the CVS-ADC(2) secular matrix (paper Eq. 11-12, CVS section).
+//
+// The doubles block is diagonal at second order, M22 = diag(D), so for an
+// eigenvalue omega below min D the doubles are eliminated exactly:
+//   x2 = (omega - D)^-1 M21 x1,
+//   [M11 + M12 (omega - D)^-1 M21] x1 = omega x1.
+// The search space is kept in singles only, V = {v_i}, with U_i = M21 v_i
+// stored on the GPU.  The projected problem
+//   G(omega) = V^H M11 V + U^H (omega - D)^-1 U
+// is expanded in Chebyshev polynomials of D on [min D, max D]:
+//   (omega - D)^-1 = (1/h) sum_m b_m(x) T_m((D - c)/h),  x = (omega - c)/h,
+// so that K_m = U^H T_m U is computed once per basis vector on the GPU and
+// G(omega) for any omega < min D costs only host arithmetic.  Each root j
+// solves lambda_j(G(omega)) = omega by safeguarded Newton steps
+// (d lambda_j / d omega = -|x2|^2).  The residual of the Ritz pair
+// (x1, x2) is r1 = M11 x1 + M12 x2 - omega x1 (the doubles residual vanishes
+// by construction), so each iteration applies M21 to the new directions and
+// M12 to the Ritz doubles: one sigma build's worth of GEMMs per root, as in
+// the full-space solver, with the doubles never entering the search space.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "hostla.h"
+#include "internal.h"
+#include "tile.h"
+
+namespace adc2 {
+
+using hostla::cplx;
+
+namespace {
+
+constexpr int FMM = 64;     // Chebyshev moments stored
+constexpr int FGB = 16;     // Gram tile edge
+constexpr int FCH = 64;     // doubles per LDS chunk
+constexpr int FMB = 16;     // moments per workgroup
+constexpr int FSMAX = 64;   // largest search space
+
+__host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
+
+// part[((tile * nmb + mb) * nchb + chb)][mm][tid] =
+//   sum over this block's chunks of conj(U_i[d]) T_{16 mb + mm}(Dt_d) U_j[d]
+// for i = i0 + tid/16 < s, j = j0 + tid%16 < q (j counted from column jc0).
+__global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
+                                                    int q, const double* __restrict__ D, double c, double ih,
+                                                    int nchb, double2* __restrict__ part) {
+  __shared__ double2 ui[FGB][FCH + 1];
+  __shared__ double2 uj[FGB][FCH + 1];
+  __shared__ double tm[FMB][FCH];
+  const int nbj = (q + FGB - 1) / FGB;
+  const int tile = blockIdx.y;
+  const int mb = blockIdx.z;
+  const int i0 = (tile / nbj) * FGB, j0 = jc0 + (tile % nbj) * FGB;
+  const int tid = threadIdx.x;
+  const int ii = tid / FGB, jj = tid % FGB;
+  double2 acc[FMB];
+#pragma unroll
+  for (int k = 0; k < FMB; ++k) acc[k] = make_double2(0.0, 0.0);
+  const long nch = (nd + FCH - 1) / FCH;
+  for (long ch = blockIdx.x; ch < nch; ch += nchb) {
+    const long e0 = ch * FCH;
+    __syncthreads();
+    for (int q2 = 0; q2 < (2 * FGB * FCH) / 256; ++q2) {
+      const int idx = q2 * 256 + tid;
+      const int row = idx / FCH, e = idx % FCH;
+      const long ge = e0 + e;
+      if (row < FGB) {
+        const int i = i0 + row;
+        ui[row][e] = (i < s && ge < nd) ? U[(long)i * ldu + ge] : make_double2(0.0, 0.0);
+      } else {
+        const int j = j0 + row - FGB;
+        uj[row - FGB][e] = (j < jc0 + q && ge < nd) ? U[(long)j * ldu + ge] : make_double2(0.0, 0.0);
+      }
+    }
+    if (tid < FCH) {
+      const long ge = e0 + tid;
+      const double t = ge < nd ? (D[ge] - c) * ih : 0.0;
+      double t0 = 1.0, t1 = t;
+      const int m0 = mb * FMB;
+      for (int m = 0; m < m0 + FMB; ++m) {
+        double tv;
+        if (m == 0) tv = 1.0;
+        else if (m == 1) tv = t;
+        else {
+          tv = 2.0 * t * t1 - t0;
+          t0 = t1;
+          t1 = tv;
+        }
+        if (m >= m0) tm[m - m0][tid] = ge < nd ? tv : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = 0; e < FCH; ++e) {
+      const double2 p = cdotc(ui[ii][e], uj[jj][e]);
+#pragma unroll
+      for (int k = 0; k < FMB; ++k) {
+        const double tv = tm[k][e];
+        acc[k].x += tv * p.x;
+        acc[k].y += tv * p.y;
+      }
+    }
+  }
+  double2* out = part + (((long)tile * gridDim.z + mb) * nchb + blockIdx.x) * (FMB * 256);
+#pragma unroll
+  for (int k = 0; k < FMB; ++k) out[k * 256 + tid] = acc[k];
+}
+
+// K[m][i][jq] = sum_chb part   for m < MM, i < s, jq < q
+__global__ void k_cheb_reduce(const double2* __restrict__ part, int s, int q, int nmb, int nchb, int MM,
+                              double2* __restrict__ K) {
+  const int nbj = (q + FGB - 1) / FGB;
+  const long total = (long)MM * s * q;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int m = (int)(e / ((long)s * q));
+    const int i = (int)((e / q) % s), jq = (int)(e % q);
+    const int tile = (i / FGB) * nbj + jq / FGB;
+    const int t = (i % FGB) * FGB + (jq % FGB);
+    const int mb = m / FMB, k = m % FMB;
+    double2 a = make_double2(0.0, 0.0);
+    for (int b = 0; b < nchb; ++b) a = cadd(a, part[(((long)tile * nmb + mb) * nchb + b) * (FMB * 256) + k * 256 + t]);
+    K[e] = a;
+  }
+}
+
+// out_j[d] = f_j(d) sum_{i<s} U_i[d] Y[i][j],  f_j(d) = 1 / (om_j - D_d), j < q <= 32, s <= 64
+__global__ __launch_bounds__(256) void k_fold_x2(const double2* __restrict__ U, long ldu, long nd, int s,
+                                                  const double2* __restrict__ Y, int q,
+                                                  const double* __restrict__ om, const double* __restrict__ D,
+                                                  double2* __restrict__ out, long ldo) {
+  __shared__ double2 ys[FSMAX * 32];
+  __shared__ double oms[32];
+  for (int t = threadIdx.x; t < s * q; t += blockDim.x) ys[(t / q) * 32 + t % q] = Y[t];
+  if (threadIdx.x < q) oms[threadIdx.x] = om[threadIdx.x];
+  __syncthreads();
+  for (long d = blockIdx.x * (long)blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+    const double Dd = D[d];
+    for (int jb = 0; jb < q; jb += 8) {
+      double2 acc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
+      for (int i = 0; i < s; ++i) {
+        const double2 u = U[(long)i * ldu + d];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (jb + k < q) acc[k] = cadd(acc[k], cmul(u, ys[i * 32 + jb + k]));
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (jb + k < q) out[(long)(jb + k) * ldo + d] = cscale(acc[k], 1.0 / (oms[jb + k] - Dd));
+    }
+  }
+}
+
+// In place U_j <- sum_{i<s} U_i C[i][j] for j < q <= s <= 64; one workgroup
+// per 64 doubles, the block of U staged in LDS before any row is rewritten.
+__global__ __launch_bounds__(256) void k_fold_rotate(double2* __restrict__ U, long ldu, long nd, int s,
+                                                      const double2* __restrict__ C, int q) {
+  __shared__ double2 cs[FSMAX * FSMAX];
+  __shared__ double2 us[FSMAX][65];
+  for (int t = threadIdx.x; t < s * q; t += blockDim.x) cs[(t / q) * FSMAX + t % q] = C[t];
+  const long d0 = (long)blockIdx.x * 64;
+  for (int t = threadIdx.x; t < s * 64; t += blockDim.x) {
+    const int i = t / 64, e = t % 64;
+    us[i][e] = (d0 + e < nd) ? U[(long)i * ldu + d0 + e] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int e = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  if (d0 + e < nd) {
+    for (int j = jg; j < q; j += 4) {
+      double2 a = make_double2(0.0, 0.0);
+      for (int i = 0; i < s; ++i) a = cadd(a, cmul(us[i][e], cs[i * FSMAX + j]));
+      U[(long)j * ldu + d0 + e] = a;
+    }
+  }
+}
+
+// min / max of D (per-block partials)
+__global__ void k_minmax(const double* __restrict__ D, long n, double* __restrict__ out) {
+  __shared__ double lo[256], hi[256];
+  double a = 1e300, b = -1e300;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    a = fmin(a, D[e]);
+    b = fmax(b, D[e]);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + st]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = lo[0];
+    out[2 * blockIdx.x + 1] = hi[0];
+  }
+}
+
+struct FoldRoot {
+  double omega = 0.0;
+  double n2 = 0.0;               // |x2|^2 for the unit-norm y
+  std::vector<cplx> y;           // eigenvector of G(omega) for this root
+  std::vector<cplx> Z;           // all eigenvectors of G(omega) (columns)
+  int status = 0;                // 0 ok, 1 root not below the doubles threshold, 2 expansion too long,
+                                 // 3 more moments needed (need)
+  int need = 0;
+};
+
+}  // namespace
+
+adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
+                          void* Xout, adc2_dav_info* info, hipStream_t st) {
+  const Dims& dd = h->d;
+  const long ns = dd.ns, nd = dd.nd, dim = dd.dim;
+  const double tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
+  const int max_iter = (opt && opt->max_iter > 0) ? opt->max_iter : 300;
+  const int verbose = opt ? opt->verbose : 0;
+  int smax = (opt && opt->max_subspace > 0) ? opt->max_subspace : FSMAX;
+  smax = std::min(smax, FSMAX);
+  smax = std::max(smax, 2 * k);            // room for k Ritz vectors plus k new directions
+  smax = (int)std::min<long>(smax, ns);
+  if (k > smax) {
+    set_error("adc2_davidson (folded): nroots exceeds the singles dimension or the search-space limit");
+    return ADC2_ERR_ARG;
+  }
+  const int keep_max = std::max(k, std::min(2 * k, smax - k));   // vectors kept at a restart
+  int nguess = (opt && opt->nguess > 0) ? opt->nguess : (k <= 8 ? 2 * k : k);
+  nguess = (int)std::min<long>(std::min(nguess, smax), ns);
+  const int qmax = std::max(nguess, k);
+
+  // ---- device buffers ----
+  std::vector<void*> owned;
+  auto release = [&]() {
+    for (void* p : owned) hipFree(p);
+    owned.clear();
+  };
+  auto dalloc = [&](void** p, size_t bytes) -> adc2_status {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+      set_error(std::string("adc2_davidson (folded): hipMalloc: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+    }
+    owned.push_back(*p);
+    return ADC2_OK;
+  };
+#define FD_TRY(expr)            \
+  do {                          \
+    adc2_status r_ = (expr);    \
+    if (r_ != ADC2_OK) {        \
+      hipStreamSynchronize(st); \
+      release();                \
+      return r_;                \
+    }                           \
+  } while (0)
+#define FD_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      set_error(std::string("adc2_davidson (folded): ") + #call + ": " + hipGetErrorString(e_)); \
+      hipStreamSynchronize(st);                                                           \
+      release();                                                                          \
+      return e_ == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;                     \
+    }                                                                                     \
+  } while (0)
+
+  double2 *Sb, *Tin, *X2, *Sx, *Kd, *part, *Yd, *Cd;
+  double *omd, *mm;
+  const int nchb = (int)std::max<long>(1, std::min<long>(128, nd / 8192));
+  const int nmb = FMM / FMB;
+  const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;
+  FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
+  FD_TRY(dalloc((void**)&Tin, sizeof(double2) * qmax * dim));
+  FD_TRY(dalloc((void**)&X2, sizeof(double2) * k * dim));
+  FD_TRY(dalloc((void**)&Sx, sizeof(double2) * k * dim));
+  FD_TRY(dalloc((void**)&Kd, sizeof(double2) * FMM * smax * FGB));
+  FD_TRY(dalloc((void**)&part, sizeof(double2) * part_len));
+  FD_TRY(dalloc((void**)&Yd, sizeof(double2) * FSMAX * FSMAX));
+  FD_TRY(dalloc((void**)&Cd, sizeof(double2) * FSMAX * FSMAX));
+  FD_TRY(dalloc((void**)&omd, sizeof(double) * 32));
+  FD_TRY(dalloc((void**)&mm, sizeof(double) * 2 * 256));
+  const double* Ddev = h->diag + ns;       // doubles diagonal D
+  const double2* Uro = nullptr;            // doubles part of Sb rows
+  double2* Urw = Sb + ns;
+  Uro = Urw;
+
+  // ---- Chebyshev interval ----
+  k_minmax<<<256, 256, 0, st>>>(Ddev, nd, mm);
+  FD_HIP(hipGetLastError());
+  std::vector<double> hm(512), d11(ns);
+  FD_HIP(hipMemcpyAsync(hm.data(), mm, sizeof(double) * 512, hipMemcpyDeviceToHost, st));
+  FD_HIP(hipMemcpyAsync(d11.data(), h->diag, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  FD_HIP(hipStreamSynchronize(st));
+  double Dmin = 1e300, Dmax = -1e300;
+  for (int b = 0; b < 256; ++b) {
+    Dmin = std::min(Dmin, hm[2 * b]);
+    Dmax = std::max(Dmax, hm[2 * b + 1]);
+  }
+  const double cc = 0.5 * (Dmin + Dmax);
+  const double hh = std::max(0.5 * (Dmax - Dmin), 1e-6 * std::max(1.0, std::fabs(cc)));
+  const double ih = 1.0 / hh;
+
+  // ---- host state ----
+  std::vector<cplx> Vs((size_t)smax * ns), S1((size_t)smax * ns), H11((size_t)smax * smax);
+  std::vector<cplx> K((size_t)FMM * smax * smax);
+  int s = 0;
+  long n21 = 0, n12 = 0;
+  double ms_sigma = 0.0;
+  hipEvent_t e0, e1;
+  FD_HIP(hipEventCreate(&e0));
+  FD_HIP(hipEventCreate(&e1));
+  auto sig_time = [&](int m, const double2* xin, double2* sout, int parts) -> adc2_status {
+    ADC2_HIP(hipEventRecord(e0, st));
+    adc2_status r = sigma_parts(h, m, xin, sout, parts, st);
+    if (r != ADC2_OK) return r;
+    ADC2_HIP(hipEventRecord(e1, st));
+    ADC2_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ADC2_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms_sigma += ms;
+    return ADC2_OK;
+  };
+  auto cleanup_events = [&]() {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  };
+
+  // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 16 * mblocks
+  int mcomp = 2;                 // moment blocks held for every basis vector
+  std::vector<cplx> Kh((size_t)FMM * smax * FGB);
+  auto cheb_cols = [&](int srows, int j0, int q, int mblocks) -> adc2_status {
+    for (int c0 = j0; c0 < j0 + q; c0 += FGB) {
+      const int qc = std::min(FGB, j0 + q - c0);
+      const int ntile = ((srows + FGB - 1) / FGB) * ((qc + FGB - 1) / FGB);
+      dim3 g(nchb, ntile, mblocks);
+      k_cheb_part<<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, Ddev, cc, ih, nchb, part);
+      ADC2_CHECK_LAUNCH();
+      const int mm_ = mblocks * FMB;
+      const long tot = (long)mm_ * srows * qc;
+      k_cheb_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, mblocks,
+                                                                                      nchb, mm_, Kd);
+      ADC2_CHECK_LAUNCH();
+      ADC2_HIP(hipMemcpyAsync(Kh.data(), Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
+      ADC2_HIP(hipStreamSynchronize(st));
+      for (int m = 0; m < mm_; ++m)
+        for (int i = 0; i < srows; ++i)
+          for (int j = 0; j < qc; ++j) {
+            const cplx v = Kh[((size_t)m * srows + i) * qc + j];
+            K[((size_t)m * smax + i) * smax + c0 + j] = v;
+            K[((size_t)m * smax + c0 + j) * smax + i] = std::conj(v);
+          }
+    }
+    return ADC2_OK;
+  };
+
+  // append q orthonormal singles vectors T (host, q x ns): sigma of (v, 0), moments
+  auto add_vectors = [&](const std::vector<cplx>& T, int q) -> adc2_status {
+    ADC2_HIP(hipMemcpy2DAsync(Tin, sizeof(double2) * dim, T.data(), sizeof(double2) * ns, sizeof(double2) * ns, q,
+                              hipMemcpyHostToDevice, st));
+    adc2_status r = sig_time(q, Tin, Sb + (long)s * dim, SIGMA_SINGLES_IN);
+    if (r != ADC2_OK) return r;
+    n21 += q;
+    ADC2_HIP(hipMemcpy2DAsync(S1.data() + (size_t)s * ns, sizeof(double2) * ns, Sb + (long)s * dim,
+                              sizeof(double2) * dim, sizeof(double2) * ns, q, hipMemcpyDeviceToHost, st));
+    for (int j = 0; j < q; ++j)
+      std::copy(T.begin() + (size_t)j * ns, T.begin() + (size_t)(j + 1) * ns, Vs.begin() + (size_t)(s + j) * ns);
+    const int snew = s + q;
+    r = cheb_cols(snew, s, q, mcomp);
+    if (r != ADC2_OK) return r;
+    for (int i = 0; i < snew; ++i)
+      for (int j = s; j < snew; ++j) {
+        cplx a = 0.0;
+        const cplx* vi = &Vs[(size_t)i * ns];
+        const cplx* sj = &S1[(size_t)j * ns];
+        for (long e = 0; e < ns; ++e) a += std::conj(vi[e]) * sj[e];
+        H11[(size_t)i * smax + j] = a;
+        H11[(size_t)j * smax + i] = std::conj(a);
+      }
+    for (int j = s; j < snew; ++j) H11[(size_t)j * smax + j] = H11[(size_t)j * smax + j].real();
+    s = snew;
+    return ADC2_OK;
+  };
+
+  // orthonormalise rows of T against Vs[0..s) and among themselves; returns the kept count
+  auto orthonormalise = [&](std::vector<cplx>& T, int q) -> int {
+    int kept = 0;
+    for (int r = 0; r < q; ++r) {
+      cplx* t = &T[(size_t)r * ns];
+      double n0 = 0.0;
+      for (long e = 0; e < ns; ++e) n0 += std::norm(t[e]);
+      n0 = std::sqrt(n0);
+      if (!(n0 > 0.0) || !std::isfinite(n0)) continue;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < s; ++i) {
+          const cplx* v = &Vs[(size_t)i * ns];
+          cplx a = 0.0;
+          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * t[e];
+          for (long e = 0; e < ns; ++e) t[e] -= a * v[e];
+        }
+        for (int i = 0; i < kept; ++i) {
+          const cplx* v = &T[(size_t)i * ns];
+          cplx a = 0.0;
+          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * t[e];
+          for (long e = 0; e < ns; ++e) t[e] -= a * v[e];
+        }
+      }
+      double n1 = 0.0;
+      for (long e = 0; e < ns; ++e) n1 += std::norm(t[e]);
+      n1 = std::sqrt(n1);
+      if (n1 <= 1e-10 * n0) continue;
+      for (long e = 0; e < ns; ++e) t[e] /= n1;
+      if (kept != r) std::copy(t, t + ns, &T[(size_t)kept * ns]);
+      ++kept;
+    }
+    return kept;
+  };
+
+  // ---- initial space ----
+  {
+    std::vector<cplx> T((size_t)nguess * ns, cplx(0.0, 0.0));
+    if (guess) {
+      FD_HIP(hipMemcpy2DAsync(T.data(), sizeof(double2) * ns, guess, sizeof(double2) * dim, sizeof(double2) * ns,
+                              nguess, hipMemcpyDeviceToHost, st));
+      FD_HIP(hipStreamSynchronize(st));
+    } else {
+      std::vector<int> idx(ns);
+      for (long i = 0; i < ns; ++i) idx[i] = (int)i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d11[a] < d11[b]; });
+      for (int g = 0; g < nguess; ++g) T[(size_t)g * ns + idx[g]] = 1.0;
+    }
+    const int q = orthonormalise(T, nguess);
+    if (q < k) {
+      cleanup_events();
+      release();
+      set_error("adc2_davidson (folded): the initial space has fewer vectors than roots");
+      return ADC2_ERR_ARG;
+    }
+    adc2_status r = add_vectors(T, q);
+    if (r != ADC2_OK) {
+      cleanup_events();
+      hipStreamSynchronize(st);
+      release();
+      return r;
+    }
+  }
+
+  std::vector<FoldRoot> roots(k);
+  std::vector<double> res(k, 1e300);
+  bool have_omega = false, converged = false;
+  int it = 0;
+  std::vector<cplx> x1((size_t)k * ns), r1((size_t)k * ns), mx2((size_t)k * ns);
+  std::vector<double> nrm(k);
+  const auto t_start = std::chrono::steady_clock::now();
+  adc2_status final_rc = ADC2_OK;
+
+  for (it = 1; it <= max_iter; ++it) {
+    // ---- projected nonlinear problem, one thread per root ----
+    double lam_min;
+    {
+      std::vector<double> w(s);
+      std::vector<cplx> Z((size_t)s * s), Hs((size_t)s * s);
+      for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) Hs[(size_t)i * s + j] = H11[(size_t)i * smax + j];
+      hostla::herm_eig(s, Hs.data(), w.data(), Z.data());
+      lam_min = w[0];
+    }
+    double T0 = 0.0;
+    for (int i = 0; i < s; ++i) T0 += K[(size_t)i * smax + i].real();
+    const double zb = 0.5 * (-(lam_min - Dmin) + std::sqrt((lam_min - Dmin) * (lam_min - Dmin) + 4.0 * std::max(T0, 0.0))) + 1.0;
+    const double lo0 = Dmin - zb;
+    const double hi0 = cc - 1.2 * hh;      // |x| >= 1.2: at most 64 Chebyshev terms
+    auto solve_root = [&](int j) {
+      FoldRoot& R = roots[j];
+      double wv = have_omega ? R.omega : lo0;
+      if (!(wv > lo0 && wv < hi0)) wv = have_omega ? std::min(std::max(wv, lo0), hi0 - 1e-9 * std::fabs(hi0)) : lo0;
+      double lo = lo0, hi = hi0;
+      std::vector<double> b(FMM), e(FMM), w(s);
+      std::vector<cplx> G((size_t)s * s), Z((size_t)s * s);
+      R.status = 0;
+      for (int nit = 0; nit < 80; ++nit) {
+        const int M = hostla::cheb_resolvent((wv - cc) * ih, FMM, b.data(), e.data());
+        if (M < 0) {
+          R.status = 2;
+          return;
+        }
+        if (M > FMB * mcomp) {
+          R.status = 3;
+          R.need = M;
+          return;
+        }
+        for (int i = 0; i < s; ++i)
+          for (int l = 0; l < s; ++l) {
+            cplx a = H11[(size_t)i * smax + l];
+            for (int m = 0; m < M; ++m) a += (b[m] * ih) * K[((size_t)m * smax + i) * smax + l];
+            G[(size_t)i * s + l] = a;
+          }
+        for (int i = 0; i < s; ++i) {
+          G[(size_t)i * s + i] = G[(size_t)i * s + i].real();
+          for (int l = i + 1; l < s; ++l) {
+            const cplx a = 0.5 * (G[(size_t)i * s + l] + std::conj(G[(size_t)l * s + i]));
+            G[(size_t)i * s + l] = a;
+            G[(size_t)l * s + i] = std::conj(a);
+          }
+        }
+        hostla::herm_eig(s, G.data(), w.data(), Z.data());
+        // |x2|^2 = y^H E y,  E = (1/h^2) sum e_m K_m
+        double n2 = 0.0;
+        {
+          std::vector<cplx> y(s);
+          for (int i = 0; i < s; ++i) y[i] = Z[(size_t)i * s + j];
+          cplx acc = 0.0;
+          for (int i = 0; i < s; ++i) {
+            cplx row = 0.0;
+            for (int l = 0; l < s; ++l) {
+              cplx kk = 0.0;
+              for (int m = 0; m < M; ++m) kk += e[m] * K[((size_t)m * smax + i) * smax + l];
+              row += kk * y[l];
+            }
+            acc += std::conj(y[i]) * row;
+          }
+          n2 = acc.real() * ih * ih;
+        }
+        const double f = w[j] - wv;
+        if (f > 0.0) lo = std::max(lo, wv);
+        else hi = std::min(hi, wv);
+        double wn = wv + f / (1.0 + std::max(n2, 0.0));
+        if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
+        const bool done = std::fabs(wn - wv) <= 1e-14 * std::max(1.0, std::fabs(wv)) || (hi - lo) <= 1e-15 * std::max(1.0, std::fabs(wv));
+        R.omega = wv;
+        R.n2 = n2;
+        R.y.assign(s, 0.0);
+        for (int i = 0; i < s; ++i) R.y[i] = Z[(size_t)i * s + j];
+        R.Z = Z;
+        if (done) break;
+        wv = wn;
+      }
+      if (!(R.omega < hi0 - 1e-12 * std::fabs(hi0))) R.status = 1;
+    };
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      {
+        std::vector<std::thread> th;
+        for (int j = 1; j < k; ++j) th.emplace_back(solve_root, j);
+        solve_root(0);
+        for (auto& t : th) t.join();
+      }
+      int need = 0;
+      for (int j = 0; j < k; ++j)
+        if (roots[j].status == 3) need = std::max(need, roots[j].need);
+      if (need == 0) break;
+      // more Chebyshev moments: recompute them for the whole space
+      mcomp = std::min(nmb, (need + FMB - 1) / FMB);
+      FD_TRY(cheb_cols(s, 0, s, mcomp));
+    }
+    for (int j = 0; j < k; ++j) {
+      if (roots[j].status != 0) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "adc2_davidson (folded): root %d is not below the doubles threshold min D = %.6f (use the "
+                 "full-space solver)",
+                 j, Dmin);
+        set_error(buf);
+        final_rc = ADC2_ERR_NOCONV;
+        break;
+      }
+    }
+    if (final_rc != ADC2_OK) break;
+    have_omega = true;
+
+    // ---- Ritz vectors and residuals ----
+    std::vector<cplx> Yc((size_t)s * k);
+    std::vector<double> om(k);
+    for (int j = 0; j < k; ++j) {
+      om[j] = roots[j].omega;
+      for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i];
+      nrm[j] = std::sqrt(1.0 + std::max(roots[j].n2, 0.0));
+    }
+    FD_HIP(hipMemcpyAsync(Yd, Yc.data(), sizeof(double2) * s * k, hipMemcpyHostToDevice, st));
+    FD_HIP(hipMemcpyAsync(omd, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
+                                                                                X2 + ns, dim);
+    FD_HIP(hipGetLastError());
+    FD_TRY(sig_time(k, X2, Sx, SIGMA_DOUBLES_IN));
+    n12 += k;
+    FD_HIP(hipMemcpy2DAsync(mx2.data(), sizeof(double2) * ns, Sx, sizeof(double2) * dim, sizeof(double2) * ns, k,
+                            hipMemcpyDeviceToHost, st));
+    FD_HIP(hipStreamSynchronize(st));
+    double rmax = 0.0;
+    for (int j = 0; j < k; ++j) {
+      cplx* xj = &x1[(size_t)j * ns];
+      cplx* rj = &r1[(size_t)j * ns];
+      for (long e = 0; e < ns; ++e) {
+        xj[e] = 0.0;
+        rj[e] = mx2[(size_t)j * ns + e];
+      }
+      for (int i = 0; i < s; ++i) {
+        const cplx y = roots[j].y[i];
+        const cplx* v = &Vs[(size_t)i * ns];
+        const cplx* sv = &S1[(size_t)i * ns];
+        for (long e = 0; e < ns; ++e) {
+          xj[e] += y * v[e];
+          rj[e] += y * sv[e];
+        }
+      }
+      double rr = 0.0;
+      for (long e = 0; e < ns; ++e) {
+        rj[e] -= om[j] * xj[e];
+        rr += std::norm(rj[e]);
+      }
+      res[j] = std::sqrt(rr) / nrm[j];
+      rmax = std::max(rmax, res[j]);
+    }
+    if (verbose) {
+      fprintf(stderr, "[adc2 folded] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", it, s, rmax, om[0]);
+    }
+    if (rmax <= tol) {
+      converged = true;
+      break;
+    }
+    if (it == max_iter) break;
+
+    // ---- new directions: diagonal preconditioner on the singles ----
+    std::vector<cplx> T((size_t)k * ns);
+    int q = 0;
+    for (int j = 0; j < k; ++j) {
+      if (res[j] <= tol) continue;
+      cplx* t = &T[(size_t)q * ns];
+      for (long e = 0; e < ns; ++e) {
+        double den = om[j] - d11[e];
+        if (std::fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        t[e] = r1[(size_t)j * ns + e] / den;
+      }
+      ++q;
+    }
+    // ---- restart: keep the Ritz singles of every root and the next ones of the highest root ----
+    if (s + q > smax) {
+      const int nk = std::min(keep_max, s);
+      std::vector<cplx> C((size_t)s * nk, 0.0);
+      for (int j = 0; j < k && j < nk; ++j)
+        for (int i = 0; i < s; ++i) C[(size_t)i * nk + j] = roots[j].y[i];
+      for (int c = k; c < nk; ++c)
+        for (int i = 0; i < s; ++i) C[(size_t)i * nk + c] = roots[k - 1].Z[(size_t)i * s + c];
+      // orthonormalise the columns of C (modified Gram-Schmidt, two passes)
+      int kc = 0;
+      for (int c = 0; c < nk; ++c) {
+        for (int pass = 0; pass < 2; ++pass)
+          for (int p = 0; p < kc; ++p) {
+            cplx a = 0.0;
+            for (int i = 0; i < s; ++i) a += std::conj(C[(size_t)i * nk + p]) * C[(size_t)i * nk + c];
+            for (int i = 0; i < s; ++i) C[(size_t)i * nk + c] -= a * C[(size_t)i * nk + p];
+          }
+        double nn = 0.0;
+        for (int i = 0; i < s; ++i) nn += std::norm(C[(size_t)i * nk + c]);
+        nn = std::sqrt(nn);
+        if (nn < 1e-8) continue;
+        for (int i = 0; i < s; ++i) C[(size_t)i * nk + kc] = C[(size_t)i * nk + c] / nn;
+        ++kc;
+      }
+      std::vector<cplx> Cc((size_t)s * kc);
+      for (int i = 0; i < s; ++i)
+        for (int c = 0; c < kc; ++c) Cc[(size_t)i * kc + c] = C[(size_t)i * nk + c];
+      FD_HIP(hipMemcpyAsync(Cd, Cc.data(), sizeof(double2) * s * kc, hipMemcpyHostToDevice, st));
+      k_fold_rotate<<<(unsigned)((nd + 63) / 64), 256, 0, st>>>(Urw, dim, nd, s, Cd, kc);
+      FD_HIP(hipGetLastError());
+      // host side: V, S1, H11, K
+      auto rot_rows = [&](std::vector<cplx>& A) {
+        std::vector<cplx> out((size_t)kc * ns, 0.0);
+        for (int c = 0; c < kc; ++c)
+          for (int i = 0; i < s; ++i) {
+            const cplx w = Cc[(size_t)i * kc + c];
+            if (w == cplx(0.0, 0.0)) continue;
+            for (long e = 0; e < ns; ++e) out[(size_t)c * ns + e] += w * A[(size_t)i * ns + e];
+          }
+        std::copy(out.begin(), out.end(), A.begin());
+      };
+      rot_rows(Vs);
+      rot_rows(S1);
+      auto rot_mat = [&](cplx* A) {   // A (s x s, ld smax) <- C^H A C
+        std::vector<cplx> T1((size_t)s * kc, 0.0), T2((size_t)kc * kc, 0.0);
+        for (int i = 0; i < s; ++i)
+          for (int c = 0; c < kc; ++c) {
+            cplx a = 0.0;
+            for (int l = 0; l < s; ++l) a += A[(size_t)i * smax + l] * Cc[(size_t)l * kc + c];
+            T1[(size_t)i * kc + c] = a;
+          }
+        for (int r = 0; r < kc; ++r)
+          for (int c = 0; c < kc; ++c) {
+            cplx a = 0.0;
+            for (int i = 0; i < s; ++i) a += std::conj(Cc[(size_t)i * kc + r]) * T1[(size_t)i * kc + c];
+            T2[(size_t)r * kc + c] = a;
+          }
+        for (int r = 0; r < kc; ++r)
+          for (int c = 0; c < kc; ++c) A[(size_t)r * smax + c] = T2[(size_t)r * kc + c];
+      };
+      rot_mat(H11.data());
+      for (int m = 0; m < FMB * mcomp; ++m) rot_mat(&K[(size_t)m * smax * smax]);
+      for (int j = 0; j < k; ++j) roots[j].y.clear();
+      s = kc;
+    }
+    const int qk = orthonormalise(T, q);
+    if (qk == 0) {
+      set_error("adc2_davidson (folded): no new search directions (stagnation)");
+      final_rc = ADC2_ERR_NOCONV;
+      break;
+    }
+    FD_TRY(add_vectors(T, qk));
+  }
+
+  // ---- outputs ----
+  if (final_rc == ADC2_OK || final_rc == ADC2_ERR_NOCONV) {
+    for (int j = 0; j < k; ++j) omega[j] = roots[j].omega;
+    if (Xout && have_omega && !roots[0].y.empty() && (int)roots[0].y.size() == s) {
+      double2* X = (double2*)Xout;
+      std::vector<cplx> Yc((size_t)s * k), xs((size_t)k * ns);
+      std::vector<double> om(k);
+      for (int j = 0; j < k; ++j) {
+        om[j] = roots[j].omega;
+        for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i] / nrm[j];
+        for (long e = 0; e < ns; ++e) xs[(size_t)j * ns + e] = x1[(size_t)j * ns + e] / nrm[j];
+      }
+      FD_HIP(hipMemcpyAsync(Yd, Yc.data(), sizeof(double2) * s * k, hipMemcpyHostToDevice, st));
+      FD_HIP(hipMemcpyAsync(omd, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+      k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
+                                                                                  X + ns, dim);
+      FD_HIP(hipGetLastError());
+      FD_HIP(hipMemcpy2DAsync(X, sizeof(double2) * dim, xs.data(), sizeof(double2) * ns, sizeof(double2) * ns, k,
+                              hipMemcpyHostToDevice, st));
+      FD_HIP(hipStreamSynchronize(st));
+    }
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->iters = std::min(it, max_iter);
+    info->n_sigma = (int)((n21 + n12 + 1) / 2);
+    info->converged = converged ? 1 : 0;
+    info->subspace = s;
+    for (int j = 0; j < k && j < ADC2_MAX_ROOTS; ++j) info->resnorm[j] = res[j];
+    info->ms_sigma = ms_sigma;
+    info->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    const double nc_ = dd.nc, no_ = dd.no, nv_ = dd.nv, na_ = dd.naux;
+    const double heavy = 8.0 * nc_ * no_ * nv_ * nv_ * na_, light = 8.0 * nc_ * nv_ * nv_ * na_;
+    info->sigma_flops = (double)n21 * (heavy + light + 8.0 * (nc_ * nv_) * (nc_ * nv_)) + (double)n12 * (heavy + light);
+  }
+  cleanup_events();
+  FD_HIP(hipStreamSynchronize(st));
+  release();
+#undef FD_TRY
+#undef FD_HIP
+  if (final_rc != ADC2_OK) return final_rc;
+  return converged ? ADC2_OK : ADC2_ERR_NOCONV;
+}
+
+}  // namespace adc2

@@ -86,6 +86,9 @@ adc2_status build_m11(adc2_handle h, hipStream_t st);
 
 // ---- sigma kernels (k_sigma.hip) ----
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipStream_t st);
+constexpr int SIGMA_SINGLES_IN = 1;   // (r1, 0) -> (M11 r1, M21 r1)
+constexpr int SIGMA_DOUBLES_IN = 2;   // (0, r2) -> singles M12 r2 only
+adc2_status sigma_parts(adc2_handle h, int m, const double2* X, double2* S, int parts, hipStream_t st);
 adc2_status build_lvt(adc2_handle h, hipStream_t st);
 adc2_status build_c64(adc2_handle h, hipStream_t st);
 adc2_status ensure_ws(adc2_handle h, int m);
@@ -95,6 +98,10 @@ adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
 // ---- setup pieces reused by the adjoint (k_setup.hip) ----
 // W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.
 adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st);
+
+// ---- folded solver (fold.hip) ----
+adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
+                          void* Xout, adc2_dav_info* info, hipStream_t st);
 
 // ---- adjoint (k_adjoint.hip) ----
 adc2_status omega_backward(adc2_handle h, int m, const double2* X, const double* g, double2* dL, double* deps,

@@ -501,7 +501,8 @@ constexpr int PK = 16;   // core spinors staged in LDS by the pack kernel
 template <class TZ>
 __global__ __launch_bounds__(256) void k_pack2(const TZ* __restrict__ Z, const double2* __restrict__ xin,
                                                 double2* __restrict__ sout, long dim, const double2* __restrict__ Vt,
-                                                const double* __restrict__ eps, int m, int nc, int no, int nv) {
+                                                const double* __restrict__ eps, int m, int nc, int no, int nv,
+                                                int with_d) {
   __shared__ double2 zt[PT][PT + 1];
   __shared__ double2 va[PK][PT], vb[PK][PT], ra[PK][PT], rb[PK][PT];
   __shared__ double ea[PT], eb[PT];
@@ -561,8 +562,11 @@ __global__ __launch_bounds__(256) void k_pack2(const TZ* __restrict__ Z, const d
       }
       const long q = pair_offset(a, b, nv);
       const double D = ea[ra_] + eb[cb] - eIj;
-      const double2 x2 = xin[off + q];
-      sout[off + q] = make_double2(v.x + D * x2.x, v.y + D * x2.y);
+      if (with_d) {
+        const double2 x2 = xin[off + q];
+        v = make_double2(v.x + D * x2.x, v.y + D * x2.y);
+      }
+      sout[off + q] = v;
     }
   }
 }
@@ -733,6 +737,21 @@ adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st) {
 }
 
 adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, hipStream_t st) {
+  return sigma_parts(h, m, xin, sout, SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN, st);
+}
+
+// zero the singles block of m vectors
+__global__ void k_zero_singles(double2* __restrict__ s, long dim, long ns, int m) {
+  const long total = ns * m;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+    s[(e / ns) * dim + e % ns] = make_double2(0.0, 0.0);
+}
+
+// parts = SIGMA_SINGLES_IN: sigma of (r1, 0):  s1 = M11 r1, s2 = M21 r1 (doubles of xin not read)
+// parts = SIGMA_DOUBLES_IN: singles of the sigma of (0, r2): s1 = M12 r2 (singles of xin not read,
+//                           doubles of sout not written)
+// both: the full sigma.
+adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout, int parts, hipStream_t st) {
   adc2_status rc = ensure_ws(h, m);
   if (rc != ADC2_OK) return rc;
   const Dims& d = h->d;
@@ -745,9 +764,10 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     if (prof) ADC2_HIP(hipEventRecord(h->kev[i], st));
     return ADC2_OK;
   };
+  const bool sgl = (parts & SIGMA_SINGLES_IN) != 0, dbl = (parts & SIGMA_DOUBLES_IN) != 0;
   // kernel order (profiling slots): unpack, ygemm, light1, xbuild, zsig2, pack2, backc, m11mv+finish
   if ((rc = mark(0)) != ADC2_OK) return rc;
-  {
+  if (dbl) {
     const int nb = cdiv(nv, UT);
     const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
     if (c64)
@@ -758,7 +778,8 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
   }
   ADC2_CHECK_LAUNCH();
   if ((rc = mark(1)) != ADC2_OK) return rc;
-  if (c64) {
+  if (!dbl) {
+  } else if (c64) {
     const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
     const int ys = h->ysplit;
     dim3 grid((unsigned)nblk, ys);
@@ -785,7 +806,7 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     }
   }
   if ((rc = mark(2)) != ADC2_OK) return rc;
-  {
+  if (dbl) {
     const int njg = (no + LJG - 1) / LJG;
     const unsigned g = (unsigned)(rows * njg * ((nv + 255) / 256));
     if (c64)
@@ -795,7 +816,7 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(3)) != ADC2_OK) return rc;
-  {
+  if (sgl) {
     const long nblk = (long)cdiv(rows, TM) * cdiv((long)naux * nv, TN);
     if (c64)
       k_xbuild<float2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, (float2*)h->X);
@@ -804,7 +825,8 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(4)) != ADC2_OK) return rc;
-  if (c64) {
+  if (!sgl) {
+  } else if (c64) {
     const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
     k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
                                                   (float2*)h->Zb);
@@ -819,27 +841,34 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(5)) != ADC2_OK) return rc;
-  {
+  if (sgl) {
+    const int with_d = dbl ? 1 : 0;
     const int nb = cdiv(nv, PT);
     const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
     if (c64)
       k_pack2<float2><<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc,
-                                                      no, nv);
+                                                      no, nv, with_d);
     else
-      k_pack2<double2><<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv);
+      k_pack2<double2><<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv,
+                                                       with_d);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(6)) != ADC2_OK) return rc;
-  {
+  if (dbl) {
     const long nblk = (long)cdiv(rows, TM) * cdiv(nv, TN) * h->nsplit;
     k_backc<<<(unsigned)nblk, 256, 0, st>>>(h->Y, h->Lvv, rows, nv, naux, h->nsplit, h->part);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(7)) != ADC2_OK) return rc;
-  {
+  if (sgl) {
     adc2_status r2 = gemm_rr(m, (int)d.ns, (int)d.ns, xin, d.dim, false, h->M11, d.ns, false, sout, d.dim, 1.0,
                              false, st);
     if (r2 != ADC2_OK) return r2;
+  } else {
+    k_zero_singles<<<grid_for(d.ns * m), 256, 0, st>>>(sout, d.dim, d.ns, m);
+    ADC2_CHECK_LAUNCH();
+  }
+  if (dbl) {
     k_sigma1_finish<<<grid_for((long)rows * nv, 256, 4096), 256, 0, st>>>(h->part, h->nsplit, h->Tp, m, nc, no,
                                                                             nv, d.dim, sout);
     ADC2_CHECK_LAUNCH();
@@ -849,15 +878,16 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* xin, double2* sout, 
     ADC2_HIP(hipEventSynchronize(h->kev[8]));
     const double nc_ = nc, no_ = no, nv_ = nv, na_ = naux, m_ = m;
     const double heavy = 8.0 * m_ * nc_ * no_ * nv_ * nv_ * na_;
+    const double fs = sgl ? 1.0 : 0.0, fd = dbl ? 1.0 : 0.0;
     const double fl[adc2_handle_s::NK] = {
-        0.0,                                        // unpack (data movement)
-        heavy,                                      // Y-build GEMM
-        8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // light sigma1 core term
-        8.0 * m_ * nc_ * nv_ * nv_ * na_,           // X-build
-        heavy,                                      // sigma2 GEMM
-        8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // pack + light sigma2 core term
-        8.0 * m_ * nc_ * nv_ * nv_ * na_,           // back-contraction
-        8.0 * m_ * (nc_ * nv_) * (nc_ * nv_)};      // M11 r1 + finish
+        0.0,                                             // unpack (data movement)
+        fd * heavy,                                      // Y-build GEMM
+        fd * 8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // light sigma1 core term
+        fs * 8.0 * m_ * nc_ * nv_ * nv_ * na_,           // X-build
+        fs * heavy,                                      // sigma2 GEMM
+        fs * 8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // pack + light sigma2 core term
+        fd * 8.0 * m_ * nc_ * nv_ * nv_ * na_,           // back-contraction
+        fs * 8.0 * m_ * (nc_ * nv_) * (nc_ * nv_)};      // M11 r1 + finish
     for (int i = 0; i < adc2_handle_s::NK; ++i) {
       float ms = 0.f;
       ADC2_HIP(hipEventElapsedTime(&ms, h->kev[i], h->kev[i + 1]));

@@ -6,7 +6,9 @@ sign, a misplaced conjugate, a transposed operand):
   P1  brute-force intermediate-state construction (paper Eq. 4-12) in a tiny
       Fock space -> E_MP2, singles block through 2nd order, first-order
       coupling, zeroth-order doubles block.
-  P2  exact diagonalisation of the explicit matrix vs the oracle Davidson.
+  P2  exact diagonalisation of the explicit matrix vs the oracle Davidson
+      and vs the elimination of the diagonal doubles block (roots below
+      the doubles threshold).
   P3  Hermiticity, sigma linearity, matrix-free sigma == explicit matrix.
   P4  MP2 closed form vs the textbook closed-shell RMP2 formula.
   P5  nonrelativistic limit: real M, singlet/triplet multiplets, CIS limit
@@ -87,6 +89,32 @@ def test_p2_davidson_vs_exact():
     R = X @ M.T - w_dv[:, None] * X
     assert torch.linalg.vector_norm(R, dim=1).max().item() < 1e-8
     assert torch.allclose(X.conj() @ X.T, torch.eye(4, dtype=O.C128), atol=1e-10)
+
+
+def test_p2_folded_roots_vs_exact():
+    # strong coupling pushes the lowest roots below min D
+    s = make_system(2, 3, 7, 24, seed=303, sigma=0.25)
+    L, e, sp = _tensors(s)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    w_ex, V = a.roots_exact(4)
+    assert float(w_ex[3]) < float(O.m22_diag(e, sp).min())
+    w, x1 = O.roots_folded(L, e, sp, 4)
+    assert np.abs(w - w_ex.numpy()).max() < 1e-10
+    # the singles parts are those of the exact eigenvectors up to normalisation and phase
+    ns = sp.n_singles
+    for j in range(4):
+        v = V[:ns, j].numpy()
+        v = v / np.linalg.norm(v)
+        assert abs(abs(np.vdot(v, x1[j])) - 1.0) < 1e-8
+    # here the third root lies just above min D (a doubles state shifted by weak
+    # coupling) and the elimination refuses it
+    s2 = make_system(1, 2, 3, 5, seed=7)
+    L2, e2, sp2 = _tensors(s2)
+    w2, _ = O.roots_folded(L2, e2, sp2, 2)
+    a2 = O.Adc2(s2.L, s2.eps, s2.nc, s2.no, s2.nv)
+    assert np.abs(w2 - a2.roots_exact(2)[0].numpy()).max() < 1e-10
+    with pytest.raises(ValueError):
+        O.roots_folded(L2, e2, sp2, 3)
 
 
 # ---------------------------------------------------------------- P3
