@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
-"""Benchmark: time-to-N-roots and sigma-build complex TFLOP/s of the FP64
-CVS-ADC(2) path on one MI355X.
+"""Benchmark: sigma-build complex TFLOP/s and time-to-N-roots of the CVS-ADC(2)
+hot path on one MI355X, FP64 and mixed precision side by side.
 
 One step = the whole hot path on one synthetic system already resident in
-HBM: adc2_setup (Cholesky-block slicing, MP2 amplitudes, singles block) and
-adc2_davidson to the lowest 10 roots at residual tolerance 1e-8 (every sigma
-build inside it).  Workload: nc=6, no=60, nv=300, naux=1500, complex128
-(the 3d-transition-metal-compound-sized configuration).
+HBM (nc=6, no=60, nv=300, naux=1500, complex128: the 3d-transition-metal-
+compound-sized configuration, 10 roots):
+  1. adc2_setup: Cholesky-block slicing, MP2 amplitudes, singles block (FP64)
+  2. FP64 roots: adc2_davidson, folded solver, residual tolerance 1e-8
+  3. adjoint: adc2_omega_backward for the 10 roots (unit weights)
+  4. mixed roots: complex64 heavy contractions on the FP32 MFMA, folded
+     solver to the complex64 residual floor (tolerance 1e-5), then the FP64
+     Rayleigh quotients of those vectors (adc2_rayleigh)
+Every sigma build inside 2 and 4 is timed per kernel with HIP events on the
+stream it is launched on.
 
-Printed JSON line (rank 0):
-  value        sigma-build complex TFLOP/s over the timed steps
-               (algorithmic flops, 8 per complex multiply-add, / HIP-event
-               time of the sigma builds)
-  ms_per_step  wall time of one step = time to the 10 roots
-  roofline     the dominant sigma kernel: algorithmic flops per launch /
-               mean launch time from HIP events bracketing that kernel on its
-               stream during the timed steps, against the FP64 MFMA peak
-  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+Printed JSON line:
+  value          FP64 sigma-build complex TFLOP/s over the timed steps
+                 (algorithmic flops, 8 per complex multiply-add, / HIP-event
+                 time of the sigma builds)
+  ms_per_step    wall time of one step (1-4)
+  time_to_roots  FP64: setup + solve; mixed: setup + solve + FP64 polish
+  mixed          the same for the precision form, with |omega_mixed -
+                 omega_FP64| in eV per root (raw and after the FP64 polish)
+  roofline       the dominant FP64 sigma kernel: algorithmic flops per launch
+                 / mean launch time, against the FP64 matrix peak
+  cpu_baseline   the CPU oracle timed on a bounded sample of the same workload
 """
 from __future__ import annotations
 
@@ -32,10 +40,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sigma-build complex TFLOP/s and time-to-N-roots, mixed vs FP64, 1 MI355X"
 PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X dense FP64 matrix
-PEAK_HBM = 8000.0          # GB/s
+PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
+HARTREE_EV = 27.211386245988
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 KERNEL_SOURCES = ["paper_2604_27451_amd/csrc/k_sigma.hip", "paper_2604_27451_amd/csrc/tile.h",
-                  "paper_2604_27451_amd/csrc/zgemm.h"]
+                  "paper_2604_27451_amd/csrc/zgemm.h", "paper_2604_27451_amd/csrc/zgemm32.h"]
 
 
 def kernel_hash() -> str:
@@ -78,20 +87,52 @@ def cpu_baseline(sysm, nj: int = 4):
             "seconds": dt}
 
 
+def load_traffic(prec):
+    """Calibrated HBM bytes per launch of the sigma kernels (m = 10 vectors)
+    from the committed hardware-counter profile, if it was taken on the
+    current kernel sources; {} otherwise."""
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return {}
+    if tr.get("kernel_hash") != kernel_hash():
+        return {}
+    return tr.get("bytes_per_launch", {}).get(prec, {})
+
+
+def roofline_of(stats, peak, traffic):
+    dom = max(stats, key=lambda k: stats[k]["ms"])
+    d = stats[dom]
+    # the counter profile is per launch of m = 10 vectors; in the folded solver every Y-build
+    # launch has m = nroots = 10, the sigma2 launches have as many vectors as new directions
+    tb = traffic.get(dom) if dom == "ybuild" else None
+    per_flops = d["flops"] / max(1, d["launches"])
+    per_ms = d["ms"] / max(1, d["launches"])
+    achieved = per_flops / (per_ms * 1e-3) / 1e12 if per_ms > 0 else 0.0
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": tb,
+            "kernel": dom, "launches": d["launches"], "ms_per_launch": round(per_ms, 3),
+            "flops_per_launch": per_flops}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--nroots", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol-mixed", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=400)
+    ap.add_argument("--solver", choices=["folded", "full"], default="folded")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--sigma-probe", action="store_true",
-                    help="short run for hardware counters: 3 sigma builds (m=10) and a 2 GiB "
-                         "read+write calibration kernel; prints no JSON")
+                    help="short run for hardware counters: 3 FP64 and 3 complex64 sigma builds (m=10) "
+                         "and a 2 GiB read+write calibration kernel; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -109,6 +150,7 @@ def main():
     A.load()
     cfg = CONFIGS[args.config]
     nroots = args.nroots or cfg["nroots"]
+    solver = A.ADC2_SOLVER_FOLDED if args.solver == "folded" else A.ADC2_SOLVER_FULL
     t = time.time()
     sysm = config_system(args.config)
     print(f"[bench] generated {args.config} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
@@ -122,8 +164,10 @@ def main():
         h = A.adc2_setup(L, eps, nc, no, nv, naux)
         x = torch.from_numpy(random_vectors(1, 10, h.dim)).cuda()
         S = torch.empty_like(x)
-        for _ in range(3):
-            A.adc2_sigma(h, x, S)
+        for prec in (A.ADC2_FP64, A.ADC2_C64):
+            A.adc2_set_precision(h, prec)
+            for _ in range(3):
+                A.adc2_sigma(h, x, S)
         torch.cuda.synchronize()
         src = torch.ones(2 ** 31 // 8, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
@@ -132,26 +176,53 @@ def main():
         print(f"[bench] sigma probe done ({float(dst[5]):.1f})", file=sys.stderr, flush=True)
         return
 
+    def solve(h, tol):
+        A.adc2_profile(h, True)
+        w, X, info = A.adc2_davidson(h, nroots, tol=tol, max_iter=args.max_iter, solver=solver,
+                                     verbose=1 if args.verbose else 0, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        return w, X, info, A.adc2_kernel_stats(h)
+
     def step(i, timed):
+        r = {}
         t0 = time.perf_counter()
         h = A.adc2_setup(L, eps, nc, no, nv, naux)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        A.adc2_profile(h, True)
-        w, X, info = A.adc2_davidson(h, nroots, tol=args.tol, max_iter=args.max_iter,
-                                     want_vectors=True, verbose=1 if args.verbose else 0,
-                                     raise_on_noconv=False)
-        torch.cuda.synchronize()
+        w64, X64, info64, ks64 = solve(h, args.tol)
         t2 = time.perf_counter()
-        ks = A.adc2_kernel_stats(h)
-        emp2 = A.adc2_mp2_energy(h)
+        r.update(setup_s=t1 - t0, fp64_solve_s=t2 - t1, w64=w64, info64=info64, ks64=ks64,
+                 emp2=A.adc2_mp2_energy(h))
+        if not args.no_adjoint:
+            dL, de = A.adc2_omega_backward(h, X64, [1.0] * nroots)
+            torch.cuda.synchronize()
+            r["adjoint_s"] = time.perf_counter() - t2
+            r["adjoint_norm"] = float(torch.linalg.vector_norm(dL))
+            del dL, de
+        del X64
+        if not args.no_mixed:
+            t3 = time.perf_counter()
+            A.adc2_set_precision(h, A.ADC2_C64)
+            w32, X32, info32, ks32 = solve(h, args.tol_mixed)
+            t4 = time.perf_counter()
+            A.adc2_set_precision(h, A.ADC2_FP64)
+            wp, rn = A.adc2_rayleigh(h, X32)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            r.update(mixed_solve_s=t4 - t3, polish_s=t5 - t4, w32=w32, wp=wp, rn_polish=rn, info32=info32,
+                     ks32=ks32)
+            del X32
         h.close()
-        del X
-        print(f"[bench] step {i} ({'timed' if timed else 'warmup'}): setup {t1 - t0:.3f}s "
-              f"davidson {t2 - t1:.2f}s iters {info['iters']} sigma-vectors {info['n_sigma']} "
-              f"converged {info['converged']} max|r| {max(info['resnorm']):.2e}", file=sys.stderr, flush=True)
-        return {"setup_s": t1 - t0, "dav_s": t2 - t1, "wall_s": t2 - t0, "omega": w, "info": info,
-                "kstats": ks, "emp2": emp2}
+        r["wall_s"] = time.perf_counter() - t0
+        msg = (f"[bench] step {i} ({'timed' if timed else 'warmup'}): setup {r['setup_s']:.3f}s "
+               f"fp64 {r['fp64_solve_s']:.2f}s ({info64['iters']} it, max|r| {max(info64['resnorm']):.1e})")
+        if "adjoint_s" in r:
+            msg += f" adjoint {r['adjoint_s']:.2f}s"
+        if "w32" in r:
+            msg += (f" mixed {r['mixed_solve_s']:.2f}s ({r['info32']['iters']} it) polish {r['polish_s']:.2f}s "
+                    f"max|dw| raw {np.abs(np.array(r['w32']) - np.array(w64)).max() * HARTREE_EV:.2e} eV")
+        print(msg, file=sys.stderr, flush=True)
+        return r
 
     for i in range(args.warmup):
         step(i, False)
@@ -161,39 +232,27 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
 
-    sig_flops = sum(r["info"]["sigma_flops"] for r in res)
-    sig_ms = sum(r["info"]["ms_sigma"] for r in res)
-    value = sig_flops / (sig_ms * 1e-3) / 1e12 if sig_ms > 0 else 0.0
-    ms_per_step = t_total / args.steps * 1e3
-    # dominant kernel of the sigma build
-    agg = {}
-    for r in res:
-        for k, v in r["kstats"].items():
-            a = agg.setdefault(k, {"launches": 0, "ms": 0.0, "flops": 0.0})
-            for f in a:
-                a[f] += v[f]
-    dom = max(agg, key=lambda k: agg[k]["ms"])
-    d = agg[dom]
-    per_launch_flops = d["flops"] / max(1, d["launches"])
-    per_launch_ms = d["ms"] / max(1, d["launches"])
-    achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("kernel_hash") == kernel_hash() and tr.get("kernel") == dom:
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": traffic,
-                "kernel": dom, "launches": d["launches"], "ms_per_launch": round(per_launch_ms, 3),
-                "flops_per_launch": per_launch_flops}
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(sysm)
+    def agg_stats(key):
+        agg = {}
+        for r in res:
+            for k, v in r[key].items():
+                if v["launches"] == 0:
+                    continue
+                a = agg.setdefault(k, {"launches": 0, "ms": 0.0, "flops": 0.0})
+                for f in a:
+                    a[f] += v[f]
+        return agg
+
+    def tflops(infos):
+        fl = sum(i["sigma_flops"] for i in infos)
+        ms = sum(i["ms_sigma"] for i in infos)
+        return fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+
+    agg64 = agg_stats("ks64")
+    value = tflops([r["info64"] for r in res])
+    roofline = roofline_of(agg64, PEAK_FP64_MFMA, load_traffic("fp64"))
     last = res[-1]
+    w64 = np.array(last["w64"])
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -201,31 +260,61 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
+        "ms_per_step": round(t_total / args.steps * 1e3, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"CVS-ADC(2) FP64 {args.config}: nc={nc} no={no} nv={nv} naux={naux} "
-                               f"complex128, {nroots} roots, Davidson tol {args.tol:g}",
-                   "nc": nc, "no": no, "nv": nv, "naux": naux, "nroots": nroots, "dim": nc * nv + nc * no * nv * (nv - 1) // 2,
-                   "precision": "fp64"},
-        "time_to_roots_s": round(np.mean([r["wall_s"] for r in res]), 3),
-        "setup_s": round(np.mean([r["setup_s"] for r in res]), 4),
-        "davidson_iters": last["info"]["iters"],
-        "sigma_vectors": last["info"]["n_sigma"],
-        "converged": last["info"]["converged"],
-        "max_resnorm": max(last["info"]["resnorm"]),
-        "omega_ha": last["omega"],
+        "config": {"workload": f"CVS-ADC(2) {args.config}: nc={nc} no={no} nv={nv} naux={naux} complex128, "
+                               f"{nroots} roots, {args.solver} solver, FP64 tol {args.tol:g}",
+                   "nc": nc, "no": no, "nv": nv, "naux": naux, "nroots": nroots,
+                   "dim": nc * nv + nc * no * nv * (nv - 1) // 2, "solver": args.solver},
+        "time_to_roots_s": round(float(np.mean([r["setup_s"] + r["fp64_solve_s"] for r in res])), 3),
+        "setup_s": round(float(np.mean([r["setup_s"] for r in res])), 4),
+        "iterations": last["info64"]["iters"],
+        "sigma_vectors": last["info64"]["n_sigma"],
+        "converged": last["info64"]["converged"],
+        "max_resnorm": max(last["info64"]["resnorm"]),
+        "omega_ha": last["w64"],
         "e_mp2_ha": last["emp2"],
-        "sigma_ms_share": round(sig_ms / (t_total * 1e3), 4),
+        "sigma_ms_share": round(sum(r["info64"]["ms_sigma"] for r in res) /
+                                (1e3 * sum(r["fp64_solve_s"] for r in res)), 4),
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2),
                         "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
-                    for k, v in agg.items()},
+                    for k, v in agg64.items()},
         "roofline": roofline,
-        "cpu_baseline": cpu,
     }
+    if "adjoint_s" in last:
+        out["adjoint_s"] = round(float(np.mean([r["adjoint_s"] for r in res])), 3)
+    if "w32" in last:
+        agg32 = agg_stats("ks32")
+        w32 = np.array(last["w32"])
+        wp = np.array(last["wp"])
+        out["mixed"] = {
+            "dtype": "c64 operands, FP32 MFMA accumulation; FP64 setup, denominators and subspace",
+            "sigma_tflops": round(tflops([r["info32"] for r in res]), 4),
+            "time_to_roots_s": round(float(np.mean([r["setup_s"] + r["mixed_solve_s"] + r["polish_s"]
+                                                    for r in res])), 3),
+            "solve_s": round(float(np.mean([r["mixed_solve_s"] for r in res])), 3),
+            "polish_s": round(float(np.mean([r["polish_s"] for r in res])), 3),
+            "iterations": last["info32"]["iters"],
+            "converged": last["info32"]["converged"],
+            "tol": args.tol_mixed,
+            "max_resnorm": max(last["info32"]["resnorm"]),
+            "ev_err_raw": [float(x) for x in (w32 - w64) * HARTREE_EV],
+            "ev_err_polished": [float(x) for x in (wp - w64) * HARTREE_EV],
+            "polished_resnorm": [float(x) for x in last["rn_polish"]],
+            "roofline": roofline_of(agg32, PEAK_FP32_MFMA, load_traffic("c64")),
+            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2),
+                            "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
+                        for k, v in agg32.items()},
+        }
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(sysm)
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

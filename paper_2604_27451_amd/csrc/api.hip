@@ -462,6 +462,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     ord.resize(nguess);
     DAV_TRY(hipMemcpyAsync(w.idx, ord.data(), sizeof(int) * nguess, hipMemcpyHostToDevice, st));
     if ((rc = dav_unit_guess(w.T, nguess, dim, w.idx, st)) != ADC2_OK) return rc;
+    DAV_TRY(hipStreamSynchronize(st));   // ord (pageable, block-local) consumed before it is freed
   }
   int g = orth_block(w, w.V, 0, nguess, dim, nblk, st, rc);
   if (g < 0) return rc;
@@ -506,6 +507,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
       DAV_TRY(hipMemcpyAsync(w.T + (long)q * dim, w.R + (long)act[q] * dim, sizeof(double2) * dim,
                              hipMemcpyDeviceToDevice, st));
     DAV_TRY(hipMemcpyAsync(w.idx, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+    DAV_TRY(hipStreamSynchronize(st));   // act (pageable, loop-local) consumed before it is freed
     k_gather_theta<<<1, 64, 0, st>>>(w.theta, w.idx, na, w.thact);
     if ((rc = dav_precondition(w.T, w.thact, h->diag, na, dim, st)) != ADC2_OK) return rc;
     int na_use = na;

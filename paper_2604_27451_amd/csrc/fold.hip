@@ -180,6 +180,16 @@ __global__ __launch_bounds__(256) void k_fold_rotate(double2* __restrict__ U, lo
   }
 }
 
+// dst[r * ldd + e] = src[r * lds + e] for r < q, e < n  (row gather / scatter)
+__global__ void k_rows_copy(const double2* __restrict__ src, long lds, double2* __restrict__ dst, long ldd, int q,
+                            long n) {
+  const long total = (long)q * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long r = e / n, c = e - r * n;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
 // min / max of D (per-block partials)
 __global__ void k_minmax(const double* __restrict__ D, long n, double* __restrict__ out) {
   __shared__ double lo[256], hi[256];
@@ -238,9 +248,14 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   // ---- device buffers ----
   std::vector<void*> owned;
+  std::vector<void*>* pinned_list = nullptr;
   auto release = [&]() {
     for (void* p : owned) hipFree(p);
     owned.clear();
+    if (pinned_list) {
+      for (void* p : *pinned_list) hipHostFree(p);
+      pinned_list->clear();
+    }
   };
   auto dalloc = [&](void** p, size_t bytes) -> adc2_status {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
@@ -286,6 +301,64 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   FD_TRY(dalloc((void**)&Cd, sizeof(double2) * FSMAX * FSMAX));
   FD_TRY(dalloc((void**)&omd, sizeof(double) * 32));
   FD_TRY(dalloc((void**)&mm, sizeof(double) * 2 * 256));
+  // Host <-> device traffic goes through pinned staging and contiguous device
+  // rows only; strided rows are gathered / scattered by k_rows_copy.
+  double2* Rowc;
+  FD_TRY(dalloc((void**)&Rowc, sizeof(double2) * qmax * ns));
+  std::vector<void*> pinned;
+  auto release_pinned = [&]() {
+    for (void* p : pinned) hipHostFree(p);
+    pinned.clear();
+  };
+  auto palloc = [&](void** p, size_t bytes) -> adc2_status {
+    hipError_t e = hipHostMalloc(p, std::max<size_t>(bytes, 16), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_error(std::string("adc2_davidson (folded): hipHostMalloc: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+    }
+    pinned.push_back(*p);
+    return ADC2_OK;
+  };
+  pinned_list = &pinned;
+  cplx *hRow, *hK, *hY;
+  double* hD;
+  {
+    adc2_status r = palloc((void**)&hRow, sizeof(cplx) * qmax * ns);
+    if (r == ADC2_OK) r = palloc((void**)&hK, sizeof(cplx) * FMM * smax * FGB);
+    if (r == ADC2_OK) r = palloc((void**)&hY, sizeof(cplx) * FSMAX * FSMAX);
+    if (r == ADC2_OK) r = palloc((void**)&hD, sizeof(double) * std::max<long>(512 + 32, ns));
+    if (r != ADC2_OK) {
+      release_pinned();
+      release();
+      return r;
+    }
+  }
+  const unsigned rgrid = (unsigned)std::min<long>(4096, ((long)qmax * ns + 255) / 256);
+  // host rows (q x ns) -> device rows with stride dim
+  auto h2d_rows = [&](const cplx* host, int q, double2* dst) -> adc2_status {
+    memcpy(hRow, host, sizeof(cplx) * q * ns);
+    ADC2_HIP(hipMemcpyAsync(Rowc, hRow, sizeof(double2) * q * ns, hipMemcpyHostToDevice, st));
+    k_rows_copy<<<rgrid, 256, 0, st>>>(Rowc, ns, dst, dim, q, ns);
+    ADC2_CHECK_LAUNCH();
+    ADC2_HIP(hipStreamSynchronize(st));
+    return ADC2_OK;
+  };
+  // device rows with stride dim (singles block) -> host rows (q x ns)
+  auto d2h_rows = [&](const double2* src, int q, cplx* host) -> adc2_status {
+    k_rows_copy<<<rgrid, 256, 0, st>>>(src, dim, Rowc, ns, q, ns);
+    ADC2_CHECK_LAUNCH();
+    ADC2_HIP(hipMemcpyAsync(hRow, Rowc, sizeof(double2) * q * ns, hipMemcpyDeviceToHost, st));
+    ADC2_HIP(hipStreamSynchronize(st));
+    memcpy(host, hRow, sizeof(cplx) * q * ns);
+    return ADC2_OK;
+  };
+  // small host array -> device, through pinned staging
+  auto h2d_small = [&](void* dst, const void* src, size_t bytes) -> adc2_status {
+    memcpy(hY, src, bytes);
+    ADC2_HIP(hipMemcpyAsync(dst, hY, bytes, hipMemcpyHostToDevice, st));
+    ADC2_HIP(hipStreamSynchronize(st));
+    return ADC2_OK;
+  };
   const double* Ddev = h->diag + ns;       // doubles diagonal D
   const double2* Uro = nullptr;            // doubles part of Sb rows
   double2* Urw = Sb + ns;
@@ -295,9 +368,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   k_minmax<<<256, 256, 0, st>>>(Ddev, nd, mm);
   FD_HIP(hipGetLastError());
   std::vector<double> hm(512), d11(ns);
-  FD_HIP(hipMemcpyAsync(hm.data(), mm, sizeof(double) * 512, hipMemcpyDeviceToHost, st));
-  FD_HIP(hipMemcpyAsync(d11.data(), h->diag, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  FD_HIP(hipMemcpyAsync(hD, mm, sizeof(double) * 512, hipMemcpyDeviceToHost, st));
   FD_HIP(hipStreamSynchronize(st));
+  memcpy(hm.data(), hD, sizeof(double) * 512);
+  FD_HIP(hipMemcpyAsync(hD, h->diag, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  FD_HIP(hipStreamSynchronize(st));
+  memcpy(d11.data(), hD, sizeof(double) * ns);
   double Dmin = 1e300, Dmax = -1e300;
   for (int b = 0; b < 256; ++b) {
     Dmin = std::min(Dmin, hm[2 * b]);
@@ -334,7 +410,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 16 * mblocks
   int mcomp = 2;                 // moment blocks held for every basis vector
-  std::vector<cplx> Kh((size_t)FMM * smax * FGB);
+  cplx* Kh = hK;
   auto cheb_cols = [&](int srows, int j0, int q, int mblocks) -> adc2_status {
     for (int c0 = j0; c0 < j0 + q; c0 += FGB) {
       const int qc = std::min(FGB, j0 + q - c0);
@@ -347,7 +423,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       k_cheb_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, mblocks,
                                                                                       nchb, mm_, Kd);
       ADC2_CHECK_LAUNCH();
-      ADC2_HIP(hipMemcpyAsync(Kh.data(), Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
+      ADC2_HIP(hipMemcpyAsync(Kh, Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
       ADC2_HIP(hipStreamSynchronize(st));
       for (int m = 0; m < mm_; ++m)
         for (int i = 0; i < srows; ++i)
@@ -362,13 +438,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   // append q orthonormal singles vectors T (host, q x ns): sigma of (v, 0), moments
   auto add_vectors = [&](const std::vector<cplx>& T, int q) -> adc2_status {
-    ADC2_HIP(hipMemcpy2DAsync(Tin, sizeof(double2) * dim, T.data(), sizeof(double2) * ns, sizeof(double2) * ns, q,
-                              hipMemcpyHostToDevice, st));
-    adc2_status r = sig_time(q, Tin, Sb + (long)s * dim, SIGMA_SINGLES_IN);
+    adc2_status r = h2d_rows(T.data(), q, Tin);
+    if (r != ADC2_OK) return r;
+    r = sig_time(q, Tin, Sb + (long)s * dim, SIGMA_SINGLES_IN);
     if (r != ADC2_OK) return r;
     n21 += q;
-    ADC2_HIP(hipMemcpy2DAsync(S1.data() + (size_t)s * ns, sizeof(double2) * ns, Sb + (long)s * dim,
-                              sizeof(double2) * dim, sizeof(double2) * ns, q, hipMemcpyDeviceToHost, st));
+    r = d2h_rows(Sb + (long)s * dim, q, S1.data() + (size_t)s * ns);
+    if (r != ADC2_OK) return r;
     for (int j = 0; j < q; ++j)
       std::copy(T.begin() + (size_t)j * ns, T.begin() + (size_t)(j + 1) * ns, Vs.begin() + (size_t)(s + j) * ns);
     const int snew = s + q;
@@ -426,9 +502,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   {
     std::vector<cplx> T((size_t)nguess * ns, cplx(0.0, 0.0));
     if (guess) {
-      FD_HIP(hipMemcpy2DAsync(T.data(), sizeof(double2) * ns, guess, sizeof(double2) * dim, sizeof(double2) * ns,
-                              nguess, hipMemcpyDeviceToHost, st));
-      FD_HIP(hipStreamSynchronize(st));
+      FD_TRY(d2h_rows((const double2*)guess, nguess, T.data()));
     } else {
       std::vector<int> idx(ns);
       for (long i = 0; i < ns; ++i) idx[i] = (int)i;
@@ -581,16 +655,14 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i];
       nrm[j] = std::sqrt(1.0 + std::max(roots[j].n2, 0.0));
     }
-    FD_HIP(hipMemcpyAsync(Yd, Yc.data(), sizeof(double2) * s * k, hipMemcpyHostToDevice, st));
-    FD_HIP(hipMemcpyAsync(omd, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    FD_TRY(h2d_small(Yd, Yc.data(), sizeof(double2) * s * k));
+    FD_TRY(h2d_small(omd, om.data(), sizeof(double) * k));
     k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
                                                                                 X2 + ns, dim);
     FD_HIP(hipGetLastError());
     FD_TRY(sig_time(k, X2, Sx, SIGMA_DOUBLES_IN));
     n12 += k;
-    FD_HIP(hipMemcpy2DAsync(mx2.data(), sizeof(double2) * ns, Sx, sizeof(double2) * dim, sizeof(double2) * ns, k,
-                            hipMemcpyDeviceToHost, st));
-    FD_HIP(hipStreamSynchronize(st));
+    FD_TRY(d2h_rows(Sx, k, mx2.data()));
     double rmax = 0.0;
     for (int j = 0; j < k; ++j) {
       cplx* xj = &x1[(size_t)j * ns];
@@ -665,9 +737,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       std::vector<cplx> Cc((size_t)s * kc);
       for (int i = 0; i < s; ++i)
         for (int c = 0; c < kc; ++c) Cc[(size_t)i * kc + c] = C[(size_t)i * nk + c];
-      FD_HIP(hipMemcpyAsync(Cd, Cc.data(), sizeof(double2) * s * kc, hipMemcpyHostToDevice, st));
+      FD_TRY(h2d_small(Cd, Cc.data(), sizeof(double2) * s * kc));
       k_fold_rotate<<<(unsigned)((nd + 63) / 64), 256, 0, st>>>(Urw, dim, nd, s, Cd, kc);
       FD_HIP(hipGetLastError());
+      // Cc is pageable host memory local to this block: the copy must have
+      // consumed it before the block ends
+      FD_HIP(hipStreamSynchronize(st));
       // host side: V, S1, H11, K
       auto rot_rows = [&](std::vector<cplx>& A) {
         std::vector<cplx> out((size_t)kc * ns, 0.0);
@@ -724,14 +799,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i] / nrm[j];
         for (long e = 0; e < ns; ++e) xs[(size_t)j * ns + e] = x1[(size_t)j * ns + e] / nrm[j];
       }
-      FD_HIP(hipMemcpyAsync(Yd, Yc.data(), sizeof(double2) * s * k, hipMemcpyHostToDevice, st));
-      FD_HIP(hipMemcpyAsync(omd, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+      FD_TRY(h2d_small(Yd, Yc.data(), sizeof(double2) * s * k));
+      FD_TRY(h2d_small(omd, om.data(), sizeof(double) * k));
       k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
                                                                                   X + ns, dim);
       FD_HIP(hipGetLastError());
-      FD_HIP(hipMemcpy2DAsync(X, sizeof(double2) * dim, xs.data(), sizeof(double2) * ns, sizeof(double2) * ns, k,
-                              hipMemcpyHostToDevice, st));
-      FD_HIP(hipStreamSynchronize(st));
+      FD_TRY(h2d_rows(xs.data(), k, X));
     }
   }
   if (info) {

@@ -888,7 +888,9 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
         fs * 8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // pack + light sigma2 core term
         fd * 8.0 * m_ * nc_ * nv_ * nv_ * na_,           // back-contraction
         fs * 8.0 * m_ * (nc_ * nv_) * (nc_ * nv_)};      // M11 r1 + finish
+    const bool ran[adc2_handle_s::NK] = {dbl, dbl, dbl, sgl, sgl, sgl, dbl, true};
     for (int i = 0; i < adc2_handle_s::NK; ++i) {
+      if (!ran[i]) continue;
       float ms = 0.f;
       ADC2_HIP(hipEventElapsedTime(&ms, h->kev[i], h->kev[i + 1]));
       h->k_ms[i] += ms;
