@@ -13,7 +13,13 @@
 // so that K_m = U^H T_m U is computed once per basis vector on the GPU and
 // G(omega) for any omega < min D costs only host arithmetic.  Each root j
 // solves lambda_j(G(omega)) = omega by safeguarded Newton steps
-// (d lambda_j / d omega = -|x2|^2).  The residual of the Ritz pair
+// (d lambda_j / d omega = -|x2|^2); the Newton update
+// (lambda + omega |x2|^2) / (1 + |x2|^2) is the Rayleigh quotient of the Ritz
+// vector built at omega and is the value returned.  New directions are the
+// singles residuals divided by an approximate diagonal of the folded
+// operator, omega - d11_e - nu_e / (omega - Dbar_e), with nu_e the squared
+// norm of column e of M21 and Dbar_e its weighted mean doubles energy.
+// The residual of the Ritz pair
 // (x1, x2) is r1 = M11 x1 + M12 x2 - omega x1 (the doubles residual vanishes
 // by construction), so each iteration applies M21 to the new directions and
 // M12 to the Ritz doubles: one sigma build's worth of GEMMs per root, as in
@@ -38,47 +44,50 @@ namespace {
 
 constexpr int FMM = 64;     // Chebyshev moments stored
 constexpr int FGB = 16;     // Gram tile edge
-constexpr int FCH = 64;     // doubles per LDS chunk
-constexpr int FMB = 16;     // moments per workgroup
+constexpr int FCH = 32;     // doubles per LDS chunk
+constexpr int FMB = 8;      // moments per workgroup
+constexpr int FTI = 32;     // largest row tile of the moment kernel
 constexpr int FSMAX = 64;   // largest search space
 
 __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
 
-// part[((tile * nmb + mb) * nchb + chb)][mm][tid] =
-//   sum over this block's chunks of conj(U_i[d]) T_{16 mb + mm}(Dt_d) U_j[d]
-// for i = i0 + tid/16 < s, j = j0 + tid%16 < q (j counted from column jc0).
+// Chebyshev moments of the new columns.  A workgroup owns ti rows (i) x qc
+// columns (j, qc <= 16, ti = min(64, 256 / qc)) and one block of FMB moments:
+//   part[((tile * nmb + mb) * nchb + chb)][mm][t] =
+//     sum over this block's chunks of conj(U_i[d]) T_{FMB mb + mm}(Dt_d) U_j[d],
+// t = (i - i0) * qc + (j - jc0), i < s, j < jc0 + qc.
 __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
-                                                    int q, const double* __restrict__ D, double c, double ih,
-                                                    int nchb, double2* __restrict__ part) {
-  __shared__ double2 ui[FGB][FCH + 1];
+                                                    int qc, int ti, const double* __restrict__ D, double c,
+                                                    double ih, int nchb, double2* __restrict__ part) {
+  __shared__ double2 ui[FTI][FCH + 1];
   __shared__ double2 uj[FGB][FCH + 1];
   __shared__ double tm[FMB][FCH];
-  const int nbj = (q + FGB - 1) / FGB;
   const int tile = blockIdx.y;
   const int mb = blockIdx.z;
-  const int i0 = (tile / nbj) * FGB, j0 = jc0 + (tile % nbj) * FGB;
+  const int i0 = tile * ti;
   const int tid = threadIdx.x;
-  const int ii = tid / FGB, jj = tid % FGB;
+  const int ii = tid / qc, jj = tid - ii * qc;
+  const bool act = ii < ti;
   double2 acc[FMB];
 #pragma unroll
   for (int k = 0; k < FMB; ++k) acc[k] = make_double2(0.0, 0.0);
   const long nch = (nd + FCH - 1) / FCH;
+  const int nrow = ti + qc;
   for (long ch = blockIdx.x; ch < nch; ch += nchb) {
     const long e0 = ch * FCH;
     __syncthreads();
-    for (int q2 = 0; q2 < (2 * FGB * FCH) / 256; ++q2) {
-      const int idx = q2 * 256 + tid;
-      const int row = idx / FCH, e = idx % FCH;
+    for (int idx = tid; idx < nrow * FCH; idx += 256) {
+      const int row = idx / FCH, e = idx - row * FCH;
       const long ge = e0 + e;
-      if (row < FGB) {
+      if (row < ti) {
         const int i = i0 + row;
         ui[row][e] = (i < s && ge < nd) ? U[(long)i * ldu + ge] : make_double2(0.0, 0.0);
       } else {
-        const int j = j0 + row - FGB;
-        uj[row - FGB][e] = (j < jc0 + q && ge < nd) ? U[(long)j * ldu + ge] : make_double2(0.0, 0.0);
+        const int j = jc0 + row - ti;
+        uj[row - ti][e] = (ge < nd) ? U[(long)j * ldu + ge] : make_double2(0.0, 0.0);
       }
     }
-    if (tid < FCH) {
+    if (tid < FCH) {   // T_m of this chunk's doubles energies
       const long ge = e0 + tid;
       const double t = ge < nd ? (D[ge] - c) * ih : 0.0;
       double t0 = 1.0, t1 = t;
@@ -96,13 +105,15 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
       }
     }
     __syncthreads();
-    for (int e = 0; e < FCH; ++e) {
-      const double2 p = cdotc(ui[ii][e], uj[jj][e]);
+    if (act) {
+      for (int e = 0; e < FCH; ++e) {
+        const double2 p = cdotc(ui[ii][e], uj[jj][e]);
 #pragma unroll
-      for (int k = 0; k < FMB; ++k) {
-        const double tv = tm[k][e];
-        acc[k].x += tv * p.x;
-        acc[k].y += tv * p.y;
+        for (int k = 0; k < FMB; ++k) {
+          const double tv = tm[k][e];
+          acc[k].x += tv * p.x;
+          acc[k].y += tv * p.y;
+        }
       }
     }
   }
@@ -111,16 +122,15 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
   for (int k = 0; k < FMB; ++k) out[k * 256 + tid] = acc[k];
 }
 
-// K[m][i][jq] = sum_chb part   for m < MM, i < s, jq < q
-__global__ void k_cheb_reduce(const double2* __restrict__ part, int s, int q, int nmb, int nchb, int MM,
+// K[m][i][jq] = sum_chb part   for m < MM, i < s, jq < qc
+__global__ void k_cheb_reduce(const double2* __restrict__ part, int s, int qc, int ti, int nmb, int nchb, int MM,
                               double2* __restrict__ K) {
-  const int nbj = (q + FGB - 1) / FGB;
-  const long total = (long)MM * s * q;
+  const long total = (long)MM * s * qc;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int m = (int)(e / ((long)s * q));
-    const int i = (int)((e / q) % s), jq = (int)(e % q);
-    const int tile = (i / FGB) * nbj + jq / FGB;
-    const int t = (i % FGB) * FGB + (jq % FGB);
+    const int m = (int)(e / ((long)s * qc));
+    const int i = (int)((e / qc) % s), jq = (int)(e % qc);
+    const int tile = i / ti;
+    const int t = (i - tile * ti) * qc + jq;
     const int mb = m / FMB, k = m % FMB;
     double2 a = make_double2(0.0, 0.0);
     for (int b = 0; b < nchb; ++b) a = cadd(a, part[(((long)tile * nmb + mb) * nchb + b) * (FMB * 256) + k * 256 + t]);
@@ -214,8 +224,64 @@ __global__ void k_minmax(const double* __restrict__ D, long n, double* __restric
   }
 }
 
+// Main coupling term of the preconditioner for one valence j:
+//   nu[c] += sum_{a<b} |V_abc|^2,  mu[c] += sum_{a<b} |V_abc|^2 (e_a + e_b - e_j),
+//   V_abc = <ab||cj> = C[(a,c)][b] - C[(b,c)][a],  C[(x,c)][y] = (xc|yj).
+// One workgroup per c; 32x32 tile pairs (a-block <= b-block) through LDS so
+// that both C reads are coalesced.
+__global__ __launch_bounds__(256) void k_schur_red(const double2* __restrict__ C, int nv,
+                                                    const double* __restrict__ ev, double ej,
+                                                    double* __restrict__ nu, double* __restrict__ mu) {
+  __shared__ double2 t1[32][33];
+  __shared__ double2 t2[32][33];
+  __shared__ double red[2][256];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nb = (nv + 31) / 32;
+  double s0 = 0.0, s1 = 0.0;
+  for (int ab = 0; ab < nb; ++ab) {
+    for (int bb = ab; bb < nb; ++bb) {
+      const int a0 = ab * 32, b0 = bb * 32;
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e / 32, q = e % 32;
+        const int a = a0 + r, b = b0 + q;
+        t1[r][q] = (a < nv && b < nv) ? C[((long)a * nv + c) * nv + b] : make_double2(0.0, 0.0);
+        const int b2 = b0 + r, a2 = a0 + q;
+        t2[r][q] = (a2 < nv && b2 < nv) ? C[((long)b2 * nv + c) * nv + a2] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e / 32, q = e % 32;
+        const int a = a0 + r, b = b0 + q;
+        if (a < nv && b < nv && a < b) {
+          const double2 v = csub(t1[r][q], t2[q][r]);
+          const double w2 = v.x * v.x + v.y * v.y;
+          s0 += w2;
+          s1 += w2 * (ev[a] + ev[b] - ej);
+        }
+      }
+    }
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      red[0][tid] += red[0][tid + st];
+      red[1][tid] += red[1][tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    nu[c] += red[0][0];
+    mu[c] += red[1][0];
+  }
+}
+
 struct FoldRoot {
-  double omega = 0.0;
+  double omega = 0.0;            // evaluation point: x2 = (omega - D)^-1 U y
+  double rq = 0.0;               // Rayleigh quotient of that (x1, x2): (lambda + omega |x2|^2) / (1 + |x2|^2)
   double n2 = 0.0;               // |x2|^2 for the unit-norm y
   std::vector<cplx> y;           // eigenvector of G(omega) for this root
   std::vector<cplx> Z;           // all eigenvectors of G(omega) (columns)
@@ -225,6 +291,81 @@ struct FoldRoot {
 };
 
 }  // namespace
+
+// Diagonal of the folded operator without the omega dependence of each
+// doubles energy: per singles e = (K,c), nu_e = sum_d |M21_{d,e}|^2 and the
+// weighted mean Dbar_e = sum_d |M21_{d,e}|^2 D_d / nu_e, so that
+//   diag[M11 + M12 (omega - D)^-1 M21]_e ~ d11_e + nu_e / (omega - Dbar_e).
+// The dominant three-virtual column  <ab||cj> (same for every K) comes from one
+// 128x128 FP64 GEMM per valence j, C[(a,c)][b] = sum_P L^P_ac L^P_bj; the
+// light columns -d_ac <Kb||Ij> + d_bc <Ka||Ij> from the stored <Ka||Ij>
+// (their interference with the main term is left out: this is a preconditioner).
+static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
+  if (!h->pre_nu.empty()) return ADC2_OK;
+  const Dims& d = h->d;
+  const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux, o = d.o;
+  const long nv2 = (long)nv * nv;
+  double2* C = nullptr;
+  double* nm = nullptr;
+  std::vector<double> eps(d.n);
+  std::vector<double2> Vt((size_t)nc * no * nc * nv);
+  std::vector<double> hnm(2 * nv);
+  hipError_t e = hipMalloc(&C, sizeof(double2) * nv2 * nv);
+  if (e == hipSuccess) e = hipMalloc(&nm, sizeof(double) * 2 * nv);
+  if (e == hipSuccess) e = hipMemsetAsync(nm, 0, sizeof(double) * 2 * nv, st);
+  if (e == hipSuccess) e = hipMemcpy(eps.data(), h->eps, sizeof(double) * d.n, hipMemcpyDeviceToHost);
+  adc2_status rc = ADC2_OK;
+  for (int j = 0; j < no && e == hipSuccess && rc == ADC2_OK; ++j) {
+    // C[(a,c)][b] = sum_P Lvv[P][a][c] Lvo[nc+j][P][b]
+    rc = bgemm_kmajor(h->Lvv, 0, nv2, (int)nv2, h->Lvo + (long)(nc + j) * naux * nv, 0, nv, nv, (int)nv2, nv, naux,
+                      1, C, st);
+    if (rc != ADC2_OK) break;
+    k_schur_red<<<nv, 256, 0, st>>>(C, nv, h->eps + o, eps[nc + j], nm, nm + nv);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && rc == ADC2_OK) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && rc == ADC2_OK) e = hipMemcpy(hnm.data(), nm, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rc == ADC2_OK)
+    e = hipMemcpy(Vt.data(), h->Vt, sizeof(double2) * Vt.size(), hipMemcpyDeviceToHost);
+  hipFree(C);
+  hipFree(nm);
+  if (rc != ADC2_OK) return rc;
+  if (e != hipSuccess) {
+    set_error(std::string("adc2_davidson (folded): preconditioner: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+  }
+  const double* ev = eps.data() + o;
+  std::vector<double> nu((size_t)nc * nv), db((size_t)nc * nv);
+  for (int K = 0; K < nc; ++K) {
+    // light columns: sum over I, j and x != c of |<Kx||Ij>|^2, weighted by D = e_c + e_x - e_I - e_j
+    std::vector<double> lnu(nv, 0.0), lmu(nv, 0.0);
+    for (int I = 0; I < nc; ++I)
+      for (int j = 0; j < no; ++j) {
+        const double2* V = &Vt[(((size_t)I * no + j) * nc + K) * nv];
+        double T0 = 0.0, T1 = 0.0;
+        for (int x = 0; x < nv; ++x) {
+          const double w2 = V[x].x * V[x].x + V[x].y * V[x].y;
+          T0 += w2;
+          T1 += w2 * ev[x];
+        }
+        const double eIj = eps[I] + eps[nc + j];
+        for (int c = 0; c < nv; ++c) {
+          const double wc = V[c].x * V[c].x + V[c].y * V[c].y;
+          lnu[c] += T0 - wc;
+          lmu[c] += (ev[c] - eIj) * (T0 - wc) + (T1 - wc * ev[c]);
+        }
+      }
+    for (int c = 0; c < nv; ++c) {
+      const double n0 = hnm[c], m0 = hnm[nv + c] - eps[K] * hnm[c];
+      const double nn = n0 + lnu[c], mm = m0 + lmu[c];
+      nu[(size_t)K * nv + c] = nn;
+      db[(size_t)K * nv + c] = nn > 0.0 ? mm / nn : 0.0;
+    }
+  }
+  h->pre_nu.swap(nu);
+  h->pre_dbar.swap(db);
+  return ADC2_OK;
+}
 
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
                           void* Xout, adc2_dav_info* info, hipStream_t st) {
@@ -290,7 +431,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   double *omd, *mm;
   const int nchb = (int)std::max<long>(1, std::min<long>(128, nd / 8192));
   const int nmb = FMM / FMB;
-  const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;
+  const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;   // row tiles have >= 16 rows
   FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
   FD_TRY(dalloc((void**)&Tin, sizeof(double2) * qmax * dim));
   FD_TRY(dalloc((void**)&X2, sizeof(double2) * k * dim));
@@ -364,6 +505,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   double2* Urw = Sb + ns;
   Uro = Urw;
 
+  FD_TRY(build_fold_precond(h, st));
+  const std::vector<double>& pnu = h->pre_nu;
+  const std::vector<double>& pdb = h->pre_dbar;
+
   // ---- Chebyshev interval ----
   k_minmax<<<256, 256, 0, st>>>(Ddev, nd, mm);
   FD_HIP(hipGetLastError());
@@ -409,19 +554,22 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   };
 
   // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 16 * mblocks
-  int mcomp = 2;                 // moment blocks held for every basis vector
+  int mcomp = 3;                 // moment blocks held for every basis vector
   cplx* Kh = hK;
+  double tm_cheb = 0.0;
   auto cheb_cols = [&](int srows, int j0, int q, int mblocks) -> adc2_status {
+    const auto tc0 = std::chrono::steady_clock::now();
     for (int c0 = j0; c0 < j0 + q; c0 += FGB) {
       const int qc = std::min(FGB, j0 + q - c0);
-      const int ntile = ((srows + FGB - 1) / FGB) * ((qc + FGB - 1) / FGB);
+      const int ti = std::min(FTI, 256 / qc);
+      const int ntile = (srows + ti - 1) / ti;
       dim3 g(nchb, ntile, mblocks);
-      k_cheb_part<<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, Ddev, cc, ih, nchb, part);
+      k_cheb_part<<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, part);
       ADC2_CHECK_LAUNCH();
       const int mm_ = mblocks * FMB;
       const long tot = (long)mm_ * srows * qc;
-      k_cheb_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, mblocks,
-                                                                                      nchb, mm_, Kd);
+      k_cheb_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, ti,
+                                                                                      mblocks, nchb, mm_, Kd);
       ADC2_CHECK_LAUNCH();
       ADC2_HIP(hipMemcpyAsync(Kh, Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
       ADC2_HIP(hipStreamSynchronize(st));
@@ -433,6 +581,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
             K[((size_t)m * smax + c0 + j) * smax + i] = std::conj(v);
           }
     }
+    tm_cheb += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
     return ADC2_OK;
   };
 
@@ -533,9 +682,15 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   std::vector<double> nrm(k);
   const auto t_start = std::chrono::steady_clock::now();
   adc2_status final_rc = ADC2_OK;
+  double tm_proj = 0.0, tm_res = 0.0, tm_new = 0.0;   // host-side phases (ms)
+  auto now = []() { return std::chrono::steady_clock::now(); };
+  auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
 
   for (it = 1; it <= max_iter; ++it) {
     // ---- projected nonlinear problem, one thread per root ----
+    const auto tp0 = now();
     double lam_min;
     {
       std::vector<double> w(s);
@@ -556,7 +711,15 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       if (!(wv > lo0 && wv < hi0)) wv = have_omega ? std::min(std::max(wv, lo0), hi0 - 1e-9 * std::fabs(hi0)) : lo0;
       double lo = lo0, hi = hi0;
       std::vector<double> b(FMM), e(FMM), w(s);
-      std::vector<cplx> G((size_t)s * s), Z((size_t)s * s);
+      std::vector<cplx> G((size_t)s * s), Z((size_t)s * s), Zp;
+      // warm start from this root's last eigenvector basis, padded with the identity for the new vectors
+      const int zs = R.Z.empty() ? 0 : (int)std::lround(std::sqrt((double)R.Z.size()));
+      if (zs > 0 && zs <= s) {
+        Zp.assign((size_t)s * s, cplx(0.0, 0.0));
+        for (int i = 0; i < zs; ++i)
+          for (int l = 0; l < zs; ++l) Zp[(size_t)i * s + l] = R.Z[(size_t)i * zs + l];
+        for (int i = zs; i < s; ++i) Zp[(size_t)i * s + i] = 1.0;
+      }
       R.status = 0;
       for (int nit = 0; nit < 80; ++nit) {
         const int M = hostla::cheb_resolvent((wv - cc) * ih, FMM, b.data(), e.data());
@@ -583,7 +746,9 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
             G[(size_t)l * s + i] = std::conj(a);
           }
         }
-        hostla::herm_eig(s, G.data(), w.data(), Z.data());
+        if (Zp.empty()) hostla::herm_eig(s, G.data(), w.data(), Z.data());
+        else hostla::herm_eig_warm(s, G.data(), Zp.data(), w.data(), Z.data());
+        Zp = Z;
         // |x2|^2 = y^H E y,  E = (1/h^2) sum e_m K_m
         double n2 = 0.0;
         {
@@ -606,8 +771,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         else hi = std::min(hi, wv);
         double wn = wv + f / (1.0 + std::max(n2, 0.0));
         if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
-        const bool done = std::fabs(wn - wv) <= 1e-14 * std::max(1.0, std::fabs(wv)) || (hi - lo) <= 1e-15 * std::max(1.0, std::fabs(wv));
+        // (wv, y) is an exact eigenpair of G(wv); its distance to the root is ~|wn - wv|, which only has
+        // to stay well below the residual tolerance of the outer iteration
+        const double wtol = std::min(1e-10, 1e-3 * tol) * std::max(1.0, std::fabs(wv));
+        const bool done = std::fabs(wn - wv) <= wtol || (hi - lo) <= 1e-15 * std::max(1.0, std::fabs(wv));
         R.omega = wv;
+        R.rq = (w[j] + wv * std::max(n2, 0.0)) / (1.0 + std::max(n2, 0.0));
         R.n2 = n2;
         R.y.assign(s, 0.0);
         for (int i = 0; i < s; ++i) R.y[i] = Z[(size_t)i * s + j];
@@ -646,6 +815,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     }
     if (final_rc != ADC2_OK) break;
     have_omega = true;
+    tm_proj += ms_since(tp0);
+    const auto tr0 = now();
 
     // ---- Ritz vectors and residuals ----
     std::vector<cplx> Yc((size_t)s * k);
@@ -688,6 +859,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       res[j] = std::sqrt(rr) / nrm[j];
       rmax = std::max(rmax, res[j]);
     }
+    tm_res += ms_since(tr0);
     if (verbose) {
       fprintf(stderr, "[adc2 folded] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", it, s, rmax, om[0]);
     }
@@ -698,13 +870,17 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     if (it == max_iter) break;
 
     // ---- new directions: diagonal preconditioner on the singles ----
+    const auto tn0 = now();
     std::vector<cplx> T((size_t)k * ns);
     int q = 0;
     for (int j = 0; j < k; ++j) {
       if (res[j] <= tol) continue;
       cplx* t = &T[(size_t)q * ns];
       for (long e = 0; e < ns; ++e) {
+        // approximate diagonal of the folded operator minus omega
         double den = om[j] - d11[e];
+        const double gap = om[j] - pdb[e];
+        if (pnu[e] > 0.0 && std::fabs(gap) > 1e-12) den -= pnu[e] / gap;
         if (std::fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
         t[e] = r1[(size_t)j * ns + e] / den;
       }
@@ -775,7 +951,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       };
       rot_mat(H11.data());
       for (int m = 0; m < FMB * mcomp; ++m) rot_mat(&K[(size_t)m * smax * smax]);
-      for (int j = 0; j < k; ++j) roots[j].y.clear();
+      for (int j = 0; j < k; ++j) {
+        roots[j].y.clear();
+        roots[j].Z.clear();   // the basis changed: next solve starts cold
+      }
       s = kc;
     }
     const int qk = orthonormalise(T, q);
@@ -784,12 +963,18 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       final_rc = ADC2_ERR_NOCONV;
       break;
     }
+    tm_new += ms_since(tn0);
     FD_TRY(add_vectors(T, qk));
   }
+  if (verbose)
+    fprintf(stderr,
+            "[adc2 folded] host ms: projected problem %.0f, residuals (incl. M12 sigma) %.0f, new directions + "
+            "restarts %.0f; moments %.0f; sigma %.0f; total %.0f\n",
+            tm_proj, tm_res, tm_new, tm_cheb, ms_sigma, ms_since(t_start));
 
   // ---- outputs ----
   if (final_rc == ADC2_OK || final_rc == ADC2_ERR_NOCONV) {
-    for (int j = 0; j < k; ++j) omega[j] = roots[j].omega;
+    for (int j = 0; j < k; ++j) omega[j] = roots[j].rq;
     if (Xout && have_omega && !roots[0].y.empty() && (int)roots[0].y.size() == s) {
       double2* X = (double2*)Xout;
       std::vector<cplx> Yc((size_t)s * k), xs((size_t)k * ns);

@@ -78,6 +78,46 @@ inline void herm_eig(int n, const cplx* A, double* w, cplx* Z) {
   }
 }
 
+// Same, warm-started from an orthonormal basis Zp (columns, row-major n x n)
+// close to the eigenvectors: A is rotated into that basis, where it is nearly
+// diagonal, so the Jacobi sweeps converge in one or two passes.
+inline void herm_eig_warm(int n, const cplx* A, const cplx* Zp, double* w, cplx* Z) {
+  std::vector<cplx> T((size_t)n * n, cplx(0.0, 0.0)), B((size_t)n * n, cplx(0.0, 0.0)), Y((size_t)n * n);
+  for (int i = 0; i < n; ++i)          // T = A Zp
+    for (int l = 0; l < n; ++l) {
+      const cplx a = A[(size_t)i * n + l];
+      if (a == cplx(0.0, 0.0)) continue;
+      const cplx* zr = &Zp[(size_t)l * n];
+      cplx* tr = &T[(size_t)i * n];
+      for (int c = 0; c < n; ++c) tr[c] += a * zr[c];
+    }
+  for (int i = 0; i < n; ++i)          // B = Zp^H T
+    for (int r = 0; r < n; ++r) {
+      const cplx z = std::conj(Zp[(size_t)i * n + r]);
+      const cplx* tr = &T[(size_t)i * n];
+      cplx* br = &B[(size_t)r * n];
+      for (int c = 0; c < n; ++c) br[c] += z * tr[c];
+    }
+  for (int r = 0; r < n; ++r) {
+    B[(size_t)r * n + r] = B[(size_t)r * n + r].real();
+    for (int c = r + 1; c < n; ++c) {
+      const cplx a = 0.5 * (B[(size_t)r * n + c] + std::conj(B[(size_t)c * n + r]));
+      B[(size_t)r * n + c] = a;
+      B[(size_t)c * n + r] = std::conj(a);
+    }
+  }
+  herm_eig(n, B.data(), w, Y.data());
+  for (int i = 0; i < n; ++i) {        // Z = Zp Y
+    cplx* zr = &Z[(size_t)i * n];
+    for (int c = 0; c < n; ++c) zr[c] = 0.0;
+    for (int l = 0; l < n; ++l) {
+      const cplx zp = Zp[(size_t)i * n + l];
+      const cplx* yr = &Y[(size_t)l * n];
+      for (int c = 0; c < n; ++c) zr[c] += zp * yr[c];
+    }
+  }
+}
+
 // Chebyshev expansions of the resolvent for real |x| > 1 and t in [-1, 1]:
 //   1/(x - t)   = sum_m b[m] T_m(t),   1/(x - t)^2 = sum_m e[m] T_m(t).
 // With u = |x|, s = sqrt(u^2 - 1), r = u - s < 1 and sg = sign(x), the

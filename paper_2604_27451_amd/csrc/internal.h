@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <string>
+#include <vector>
 
 #include "../../include/adc2.h"
 
@@ -67,6 +68,9 @@ struct adc2_handle_s {
   int nsplit = 0;
   int ysplit = 1;           // K-splits of the Y-build GEMM
   int gemm3 = 0;            // heavy GEMMs: 0 = four-multiplication 128x128 (default), 1 = three-multiplication 128x64
+  // folded-solver preconditioner (host, built on first use): per singles (K,c) the coupling
+  // column norm sum_d |M21_{d,(Kc)}|^2 and its |M21|^2-weighted mean doubles energy
+  std::vector<double> pre_nu, pre_dbar;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // per-kernel profiling of the sigma build
   static constexpr int NK = 8;   // unpack, ybuild, light1, xbuild, sigma2, pack2, backc, m11mv
@@ -98,6 +102,12 @@ adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
 // ---- setup pieces reused by the adjoint (k_setup.hip) ----
 // W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.
 adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st);
+
+// ---- large-tile FP64 GEMM of two K-major grouped operands (k_adjoint.hip) ----
+// C[s][i][j] = sum_{k in split s} A(k, i) B(k, j), A(k, i) = A[g*a_gstride + x + k*a_ld] with
+// i = g*a_inner + x (likewise B); gridDim.y = nsplit K-splits, C holds nsplit partials.
+adc2_status bgemm_kmajor(const double2* A, long a_gstride, long a_ld, int a_inner, const double2* B, long b_gstride,
+                         long b_ld, int b_inner, int M, int N, int K, int nsplit, double2* C, hipStream_t st);
 
 // ---- folded solver (fold.hip) ----
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,

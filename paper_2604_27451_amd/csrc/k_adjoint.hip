@@ -164,6 +164,19 @@ __global__ __launch_bounds__(256) void k_bgemm(SrcGroupedK<8> A, SrcGroupedK<8> 
   });
 }
 
+// Host launcher of k_bgemm for other translation units: both operands
+// K-major grouped rows (SrcGroupedK), output C[split][M][N].
+adc2_status bgemm_kmajor(const double2* A, long a_gstride, long a_ld, int a_inner, const double2* B, long b_gstride,
+                         long b_ld, int b_inner, int M, int N, int K, int nsplit, double2* C, hipStream_t st) {
+  if (M <= 0 || N <= 0) return ADC2_OK;
+  SrcGroupedK<8> sa{A, a_gstride, a_ld, a_inner, M, K};
+  SrcGroupedK<8> sb{B, b_gstride, b_ld, b_inner, N, K};
+  const long tiles = (long)cdv(M, BT) * cdv(N, BT);
+  k_bgemm<<<dim3((unsigned)tiles, nsplit), 256, 0, st>>>(sa, sb, M, N, K, C);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
 __global__ void k_scatter_add(const double2* __restrict__ C, int nsplit, int M, int N, int inner, long gs, long ld,
                               double alpha, double2* __restrict__ dst) {
   const long len = (long)M * N;
