@@ -25,9 +25,11 @@
 // M12 to the Ritz doubles: one sigma build's worth of GEMMs per root, as in
 // the full-space solver, with the doubles never entering the search space.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -52,25 +54,28 @@ constexpr int FSMAX = 64;   // largest search space
 __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
 
 // Chebyshev moments of the new columns.  A workgroup owns ti rows (i) x qc
-// columns (j, qc <= 16, ti = min(64, 256 / qc)) and one block of FMB moments:
+// columns (j, qc <= 16, ti = min(32, 256 / qc)) and NB consecutive blocks of
+// FMB moments, so that each chunk of U is read once per row tile:
 //   part[((tile * nmb + mb) * nchb + chb)][mm][t] =
 //     sum over this block's chunks of conj(U_i[d]) T_{FMB mb + mm}(Dt_d) U_j[d],
-// t = (i - i0) * qc + (j - jc0), i < s, j < jc0 + qc.
+// t = (i - i0) * qc + (j - jc0), i < s, j < jc0 + qc, mb = NB * blockIdx.z + (0..NB-1).
+template <int NB>
 __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
                                                     int qc, int ti, const double* __restrict__ D, double c,
-                                                    double ih, int nchb, double2* __restrict__ part) {
+                                                    double ih, int nchb, int nmb, double2* __restrict__ part) {
+  constexpr int NM = NB * FMB;
   __shared__ double2 ui[FTI][FCH + 1];
   __shared__ double2 uj[FGB][FCH + 1];
-  __shared__ double tm[FMB][FCH];
+  __shared__ double tm[NM][FCH];
   const int tile = blockIdx.y;
-  const int mb = blockIdx.z;
+  const int mb0 = blockIdx.z * NB;
   const int i0 = tile * ti;
   const int tid = threadIdx.x;
   const int ii = tid / qc, jj = tid - ii * qc;
   const bool act = ii < ti;
-  double2 acc[FMB];
+  double2 acc[NM];
 #pragma unroll
-  for (int k = 0; k < FMB; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int k = 0; k < NM; ++k) acc[k] = make_double2(0.0, 0.0);
   const long nch = (nd + FCH - 1) / FCH;
   const int nrow = ti + qc;
   for (long ch = blockIdx.x; ch < nch; ch += nchb) {
@@ -91,8 +96,8 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
       const long ge = e0 + tid;
       const double t = ge < nd ? (D[ge] - c) * ih : 0.0;
       double t0 = 1.0, t1 = t;
-      const int m0 = mb * FMB;
-      for (int m = 0; m < m0 + FMB; ++m) {
+      const int m0 = mb0 * FMB;
+      for (int m = 0; m < m0 + NM; ++m) {
         double tv;
         if (m == 0) tv = 1.0;
         else if (m == 1) tv = t;
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
       for (int e = 0; e < FCH; ++e) {
         const double2 p = cdotc(ui[ii][e], uj[jj][e]);
 #pragma unroll
-        for (int k = 0; k < FMB; ++k) {
+        for (int k = 0; k < NM; ++k) {
           const double tv = tm[k][e];
           acc[k].x += tv * p.x;
           acc[k].y += tv * p.y;
@@ -117,9 +122,14 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
       }
     }
   }
-  double2* out = part + (((long)tile * gridDim.z + mb) * nchb + blockIdx.x) * (FMB * 256);
 #pragma unroll
-  for (int k = 0; k < FMB; ++k) out[k * 256 + tid] = acc[k];
+  for (int b = 0; b < NB; ++b) {
+    const int mb = mb0 + b;
+    if (mb >= nmb) break;
+    double2* out = part + (((long)tile * nmb + mb) * nchb + blockIdx.x) * (FMB * 256);
+#pragma unroll
+    for (int k = 0; k < FMB; ++k) out[k * 256 + tid] = acc[b * FMB + k];
+  }
 }
 
 // K[m][i][jq] = sum_chb part   for m < MM, i < s, jq < qc
@@ -279,6 +289,24 @@ __global__ __launch_bounds__(256) void k_schur_red(const double2* __restrict__ C
   }
 }
 
+// f(0..n-1) on up to 16 host threads
+template <class F>
+static void par_for(int n, F&& f) {
+  const int nt = std::min(n, (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      int i;
+      while ((i = next++) < n) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
 struct FoldRoot {
   double omega = 0.0;            // evaluation point: x2 = (omega - D)^-1 U y
   double rq = 0.0;               // Rayleigh quotient of that (x1, x2): (lambda + omega |x2|^2) / (1 + |x2|^2)
@@ -429,7 +457,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   double2 *Sb, *Tin, *X2, *Sx, *Kd, *part, *Yd, *Cd;
   double *omd, *mm;
-  const int nchb = (int)std::max<long>(1, std::min<long>(128, nd / 8192));
+  int nchb = (int)std::max<long>(1, std::min<long>(512, nd / 4096));
+  int cheb_nb = 2;          // 8-moment blocks per workgroup of the moment kernel (measured best at c2)
+  if (const char* v = getenv("ADC2_CHEB_NB")) cheb_nb = std::max(1, std::min(4, atoi(v)));
+  if (const char* v = getenv("ADC2_CHEB_NCHB")) nchb = (int)std::max<long>(1, std::min<long>(1024, atol(v)));
   const int nmb = FMM / FMB;
   const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;   // row tiles have >= 16 rows
   FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
@@ -563,8 +594,15 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       const int qc = std::min(FGB, j0 + q - c0);
       const int ti = std::min(FTI, 256 / qc);
       const int ntile = (srows + ti - 1) / ti;
-      dim3 g(nchb, ntile, mblocks);
-      k_cheb_part<<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, part);
+      // up to four 8-moment blocks per workgroup (one read of U), more in further z-slices
+      const int nbw = std::min(cheb_nb, mblocks);
+      dim3 g(nchb, ntile, (mblocks + nbw - 1) / nbw);
+      switch (nbw) {
+        case 1: k_cheb_part<1><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
+        case 2: k_cheb_part<2><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
+        case 3: k_cheb_part<3><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
+        default: k_cheb_part<4><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
+      }
       ADC2_CHECK_LAUNCH();
       const int mm_ = mblocks * FMB;
       const long tot = (long)mm_ * srows * qc;
@@ -599,15 +637,17 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     const int snew = s + q;
     r = cheb_cols(snew, s, q, mcomp);
     if (r != ADC2_OK) return r;
-    for (int i = 0; i < snew; ++i)
+    par_for(snew, [&](int i) {
       for (int j = s; j < snew; ++j) {
         cplx a = 0.0;
         const cplx* vi = &Vs[(size_t)i * ns];
         const cplx* sj = &S1[(size_t)j * ns];
         for (long e = 0; e < ns; ++e) a += std::conj(vi[e]) * sj[e];
         H11[(size_t)i * smax + j] = a;
-        H11[(size_t)j * smax + i] = std::conj(a);
       }
+    });
+    for (int i = 0; i < snew; ++i)
+      for (int j = s; j < snew; ++j) H11[(size_t)j * smax + i] = std::conj(H11[(size_t)i * smax + j]);
     for (int j = s; j < snew; ++j) H11[(size_t)j * smax + j] = H11[(size_t)j * smax + j].real();
     s = snew;
     return ADC2_OK;
@@ -615,31 +655,43 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   // orthonormalise rows of T against Vs[0..s) and among themselves; returns the kept count
   auto orthonormalise = [&](std::vector<cplx>& T, int q) -> int {
+    std::vector<double> n0(q);
+    // against the space (two classical Gram-Schmidt passes, rows in parallel)
+    par_for(q, [&](int r) {
+      cplx* t = &T[(size_t)r * ns];
+      double a0 = 0.0;
+      for (long e = 0; e < ns; ++e) a0 += std::norm(t[e]);
+      n0[r] = std::sqrt(a0);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<cplx> a(s);
+        for (int i = 0; i < s; ++i) {
+          const cplx* v = &Vs[(size_t)i * ns];
+          cplx acc = 0.0;
+          for (long e = 0; e < ns; ++e) acc += std::conj(v[e]) * t[e];
+          a[i] = acc;
+        }
+        for (int i = 0; i < s; ++i) {
+          const cplx* v = &Vs[(size_t)i * ns];
+          for (long e = 0; e < ns; ++e) t[e] -= a[i] * v[e];
+        }
+      }
+    });
+    // among themselves (modified Gram-Schmidt, two passes)
     int kept = 0;
     for (int r = 0; r < q; ++r) {
       cplx* t = &T[(size_t)r * ns];
-      double n0 = 0.0;
-      for (long e = 0; e < ns; ++e) n0 += std::norm(t[e]);
-      n0 = std::sqrt(n0);
-      if (!(n0 > 0.0) || !std::isfinite(n0)) continue;
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i < s; ++i) {
-          const cplx* v = &Vs[(size_t)i * ns];
-          cplx a = 0.0;
-          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * t[e];
-          for (long e = 0; e < ns; ++e) t[e] -= a * v[e];
-        }
+      if (!(n0[r] > 0.0) || !std::isfinite(n0[r])) continue;
+      for (int pass = 0; pass < 2; ++pass)
         for (int i = 0; i < kept; ++i) {
           const cplx* v = &T[(size_t)i * ns];
           cplx a = 0.0;
           for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * t[e];
           for (long e = 0; e < ns; ++e) t[e] -= a * v[e];
         }
-      }
       double n1 = 0.0;
       for (long e = 0; e < ns; ++e) n1 += std::norm(t[e]);
       n1 = std::sqrt(n1);
-      if (n1 <= 1e-10 * n0) continue;
+      if (n1 <= 1e-10 * n0[r]) continue;
       for (long e = 0; e < ns; ++e) t[e] /= n1;
       if (kept != r) std::copy(t, t + ns, &T[(size_t)kept * ns]);
       ++kept;
@@ -835,7 +887,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     n12 += k;
     FD_TRY(d2h_rows(Sx, k, mx2.data()));
     double rmax = 0.0;
-    for (int j = 0; j < k; ++j) {
+    par_for(k, [&](int j) {
       cplx* xj = &x1[(size_t)j * ns];
       cplx* rj = &r1[(size_t)j * ns];
       for (long e = 0; e < ns; ++e) {
@@ -857,8 +909,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         rr += std::norm(rj[e]);
       }
       res[j] = std::sqrt(rr) / nrm[j];
-      rmax = std::max(rmax, res[j]);
-    }
+    });
+    for (int j = 0; j < k; ++j) rmax = std::max(rmax, res[j]);
     tm_res += ms_since(tr0);
     if (verbose) {
       fprintf(stderr, "[adc2 folded] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", it, s, rmax, om[0]);
