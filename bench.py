@@ -8,9 +8,11 @@ compound-sized configuration, 10 roots):
   1. adc2_setup: Cholesky-block slicing, MP2 amplitudes, singles block (FP64)
   2. FP64 roots: adc2_davidson, folded solver, residual tolerance 1e-8
   3. adjoint: adc2_omega_backward for the 10 roots (unit weights)
-  4. mixed roots: complex64 heavy contractions on the FP32 MFMA, folded
-     solver to the complex64 residual floor (tolerance 1e-5), then the FP64
-     Rayleigh quotients of those vectors (adc2_rayleigh)
+  4. mixed roots: split-BF16 heavy contractions on the BF16 MFMA (each
+     complex64 operand as hi + lo bf16, three products), folded solver to
+     residual 1e-3, then the FP64 Rayleigh quotients of those vectors
+     (adc2_rayleigh); the same with complex64 operands on the FP32 MFMA to
+     residual 1e-5 is reported as mixed_c64
 Every sigma build inside 2 and 4 is timed per kernel with HIP events on the
 stream it is launched on.
 
@@ -41,10 +43,13 @@ sys.path.insert(0, ROOT)
 METRIC = "sigma-build complex TFLOP/s and time-to-N-roots, mixed vs FP64, 1 MI355X"
 PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
+# split-BF16: 2.5 PFLOP/s dense BF16, 3 real products per split real product -> 8/24 of it in
+# algorithmic complex flops (8 per complex multiply-add)
+PEAK_BF16X3 = 2500.0 * 8.0 / 24.0
 HARTREE_EV = 27.211386245988
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 KERNEL_SOURCES = ["paper_2604_27451_amd/csrc/k_sigma.hip", "paper_2604_27451_amd/csrc/tile.h",
-                  "paper_2604_27451_amd/csrc/zgemm.h", "paper_2604_27451_amd/csrc/zgemm32.h"]
+                  "paper_2604_27451_amd/csrc/zgemm.h", "paper_2604_27451_amd/csrc/zgemm32.h", "paper_2604_27451_amd/csrc/zgemmb.h"]
 
 
 def kernel_hash() -> str:
@@ -123,7 +128,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--nroots", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--tol-mixed", type=float, default=1e-5)
+    ap.add_argument("--tol-mixed", type=float, default=1e-3)
+    ap.add_argument("--tol-c64", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--solver", choices=["folded", "full"], default="folded")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,8 +137,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--sigma-probe", action="store_true",
-                    help="short run for hardware counters: 3 FP64 and 3 complex64 sigma builds (m=10) "
-                         "and a 2 GiB read+write calibration kernel; prints no JSON")
+                    help="short run for hardware counters: 3 FP64, 3 complex64 and 3 split-BF16 sigma "
+                         "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -164,7 +170,7 @@ def main():
         h = A.adc2_setup(L, eps, nc, no, nv, naux)
         x = torch.from_numpy(random_vectors(1, 10, h.dim)).cuda()
         S = torch.empty_like(x)
-        for prec in (A.ADC2_FP64, A.ADC2_C64):
+        for prec in (A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3):
             A.adc2_set_precision(h, prec)
             for _ in range(3):
                 A.adc2_sigma(h, x, S)
@@ -201,26 +207,28 @@ def main():
             del dL, de
         del X64
         if not args.no_mixed:
-            t3 = time.perf_counter()
-            A.adc2_set_precision(h, A.ADC2_C64)
-            w32, X32, info32, ks32 = solve(h, args.tol_mixed)
-            t4 = time.perf_counter()
-            A.adc2_set_precision(h, A.ADC2_FP64)
-            wp, rn = A.adc2_rayleigh(h, X32)
-            torch.cuda.synchronize()
-            t5 = time.perf_counter()
-            r.update(mixed_solve_s=t4 - t3, polish_s=t5 - t4, w32=w32, wp=wp, rn_polish=rn, info32=info32,
-                     ks32=ks32)
-            del X32
+            for tag, prec, tol in (("b3", A.ADC2_BF16X3, args.tol_mixed), ("c64", A.ADC2_C64, args.tol_c64)):
+                t3 = time.perf_counter()
+                A.adc2_set_precision(h, prec)
+                wm, Xm, infom, ksm = solve(h, tol)
+                t4 = time.perf_counter()
+                A.adc2_set_precision(h, A.ADC2_FP64)
+                wp, rn = A.adc2_rayleigh(h, Xm)
+                torch.cuda.synchronize()
+                t5 = time.perf_counter()
+                r[tag] = dict(solve_s=t4 - t3, polish_s=t5 - t4, w=wm, wp=wp, rn_polish=rn, info=infom, ks=ksm)
+                del Xm
         h.close()
         r["wall_s"] = time.perf_counter() - t0
         msg = (f"[bench] step {i} ({'timed' if timed else 'warmup'}): setup {r['setup_s']:.3f}s "
                f"fp64 {r['fp64_solve_s']:.2f}s ({info64['iters']} it, max|r| {max(info64['resnorm']):.1e})")
         if "adjoint_s" in r:
             msg += f" adjoint {r['adjoint_s']:.2f}s"
-        if "w32" in r:
-            msg += (f" mixed {r['mixed_solve_s']:.2f}s ({r['info32']['iters']} it) polish {r['polish_s']:.2f}s "
-                    f"max|dw| raw {np.abs(np.array(r['w32']) - np.array(w64)).max() * HARTREE_EV:.2e} eV")
+        for tag in ("b3", "c64"):
+            if tag in r:
+                m = r[tag]
+                msg += (f" {tag} {m['solve_s']:.2f}s ({m['info']['iters']} it) polish {m['polish_s']:.2f}s "
+                        f"max|dw| {np.abs(np.array(m['w']) - np.array(w64)).max() * HARTREE_EV:.1e} eV")
         print(msg, file=sys.stderr, flush=True)
         return r
 
@@ -287,29 +295,46 @@ def main():
     }
     if "adjoint_s" in last:
         out["adjoint_s"] = round(float(np.mean([r["adjoint_s"] for r in res])), 3)
-    if "w32" in last:
-        agg32 = agg_stats("ks32")
-        w32 = np.array(last["w32"])
-        wp = np.array(last["wp"])
-        out["mixed"] = {
-            "dtype": "c64 operands, FP32 MFMA accumulation; FP64 setup, denominators and subspace",
-            "sigma_tflops": round(tflops([r["info32"] for r in res]), 4),
-            "time_to_roots_s": round(float(np.mean([r["setup_s"] + r["mixed_solve_s"] + r["polish_s"]
+    def mixed_block(tag, dtype, peak):
+        agg = {}
+        for r in res:
+            for k, v in r[tag]["ks"].items():
+                if v["launches"] == 0:
+                    continue
+                a = agg.setdefault(k, {"launches": 0, "ms": 0.0, "flops": 0.0})
+                for f in a:
+                    a[f] += v[f]
+        m = last[tag]
+        wm, wp = np.array(m["w"]), np.array(m["wp"])
+        return {
+            "dtype": dtype,
+            "sigma_tflops": round(tflops([r[tag]["info"] for r in res]), 4),
+            "time_to_roots_s": round(float(np.mean([r["setup_s"] + r[tag]["solve_s"] + r[tag]["polish_s"]
                                                     for r in res])), 3),
-            "solve_s": round(float(np.mean([r["mixed_solve_s"] for r in res])), 3),
-            "polish_s": round(float(np.mean([r["polish_s"] for r in res])), 3),
-            "iterations": last["info32"]["iters"],
-            "converged": last["info32"]["converged"],
-            "tol": args.tol_mixed,
-            "max_resnorm": max(last["info32"]["resnorm"]),
-            "ev_err_raw": [float(x) for x in (w32 - w64) * HARTREE_EV],
+            "solve_s": round(float(np.mean([r[tag]["solve_s"] for r in res])), 3),
+            "polish_s": round(float(np.mean([r[tag]["polish_s"] for r in res])), 3),
+            "iterations": m["info"]["iters"],
+            "converged": m["info"]["converged"],
+            "max_resnorm": max(m["info"]["resnorm"]),
+            "ev_err_raw": [float(x) for x in (wm - w64) * HARTREE_EV],
             "ev_err_polished": [float(x) for x in (wp - w64) * HARTREE_EV],
-            "polished_resnorm": [float(x) for x in last["rn_polish"]],
-            "roofline": roofline_of(agg32, PEAK_FP32_MFMA, load_traffic("c64")),
+            "polished_resnorm": [float(x) for x in m["rn_polish"]],
+            "roofline": roofline_of(agg, peak, load_traffic(tag)),
             "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2),
                             "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
-                        for k, v in agg32.items()},
+                        for k, v in agg.items()},
         }
+
+    if "b3" in last:
+        out["mixed"] = mixed_block("b3", "split-BF16 operands (hi + lo), BF16 MFMA, FP32 accumulation; "
+                                         "FP64 setup, denominators and subspace; tolerance "
+                                         f"{args.tol_mixed:g}", PEAK_BF16X3)
+        out["mixed"]["tol"] = args.tol_mixed
+    if "c64" in last:
+        out["mixed_c64"] = mixed_block("c64", "complex64 operands, FP32 MFMA accumulation; FP64 setup, "
+                                              f"denominators and subspace; tolerance {args.tol_c64:g}",
+                                       PEAK_FP32_MFMA)
+        out["mixed_c64"]["tol"] = args.tol_c64
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)

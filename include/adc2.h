@@ -63,6 +63,12 @@ typedef enum {
                                   FP32 MFMA and FP32 accumulation; setup,
                                   denominators, packing, Davidson and subspace
                                   eigensolver stay FP64                          */
+  ,
+  ADC2_BF16X3 = 2              /* precision form, split-BF16 variant: the same
+                                  two contractions on the BF16 MFMA with each
+                                  complex64 operand split into hi = bf16(x),
+                                  lo = bf16(x - hi); hi*hi + hi*lo + lo*hi
+                                  accumulated in FP32 (relative error ~1e-5)     */
 } adc2_precision;
 
 #define ADC2_MAX_ROOTS 32

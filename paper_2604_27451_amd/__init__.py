@@ -41,6 +41,7 @@ ADC2_ERR_NOCONV = 5
 ADC2_ERR_NONFINITE = 6
 ADC2_FP64 = 0
 ADC2_C64 = 1
+ADC2_BF16X3 = 2
 ADC2_MAX_ROOTS = 32
 ADC2_SOLVER_FULL = 0
 ADC2_SOLVER_FOLDED = 1

@@ -124,7 +124,8 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
   if (!L || !eps) return fail(ADC2_ERR_ARG, "adc2_setup: L or eps is NULL");
   if (nc <= 0 || no <= 0 || nv < 2 || naux <= 0)
     return fail(ADC2_ERR_ARG, "adc2_setup: need nc>0, no>0, nv>=2, naux>0");
-  if (prec != ADC2_FP64 && prec != ADC2_C64) return fail(ADC2_ERR_ARG, "adc2_setup: unsupported precision");
+  if (prec != ADC2_FP64 && prec != ADC2_C64 && prec != ADC2_BF16X3)
+    return fail(ADC2_ERR_ARG, "adc2_setup: unsupported precision");
   if (nc > 64) return fail(ADC2_ERR_ARG, "adc2_setup: nc > 64 not supported");
   hipStream_t st = (hipStream_t)stream;
   adc2_handle h = new adc2_handle_s();
@@ -207,7 +208,8 @@ adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, void* strea
 
 adc2_status adc2_set_precision(adc2_handle h, int prec) {
   if (!h) return fail(ADC2_ERR_ARG, "adc2_set_precision: NULL handle");
-  if (prec != ADC2_FP64 && prec != ADC2_C64) return fail(ADC2_ERR_ARG, "adc2_set_precision: unknown precision");
+  if (prec != ADC2_FP64 && prec != ADC2_C64 && prec != ADC2_BF16X3)
+    return fail(ADC2_ERR_ARG, "adc2_set_precision: unknown precision");
   h->prec = prec;
   return ADC2_OK;
 }

@@ -23,6 +23,7 @@
 #include "tile.h"
 #include "zgemm.h"
 #include "zgemm32.h"
+#include "zgemmb.h"
 
 namespace adc2 {
 
@@ -324,6 +325,67 @@ __global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ Lv
   BigAccF acc;
   acc.zero();
   big_mainloopF(s, A, B, kc0, kc1, acc);
+  big_for_eachF(acc, [&](int r, int c, float2 v) {
+    const int P = i0 + r, col = j0 + c;
+    if (P < naux && col < ncols) {
+      const int mI = col / nv, cc = col - mI * nv;
+      Ys[((long)mI * naux + P) * nv + cc] = make_double2((double)v.x, (double)v.y);
+    }
+  });
+}
+
+// Precision form, split-BF16 variant: the same two contractions on the BF16
+// matrix cores with hi/lo operand splitting (zgemmb.h), FP32 accumulation.
+__global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
+                                                   int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+  const int ncols = no * nv;
+  const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const long lds = (long)naux * nv;
+  SrcBF A{X32, lds, nv, nv, rows, naux};
+  SrcBF B{Lv32, lds, nv, nv, ncols, naux};
+  A.begin(threadIdx.x & 255, i0);
+  B.begin(threadIdx.x & 255, j0);
+  __shared__ BigSmemB s[2];
+  BigAccF acc;
+  acc.zero();
+  big_mainloopB(s, A, B, 0, (naux + BKB - 1) / BKB, acc);
+  if (wave_id() >= 4) return;
+  big_for_eachF(acc, [&](int r, int c, float2 v) {
+    const int i = i0 + r, jc = j0 + c;
+    if (i < rows && jc < ncols) {
+      const int mI = i / nv, a = i - mI * nv;
+      const int j = jc / nv, b = jc - j * nv;
+      Z[(((long)mI * no + j) * nv + a) * nv + b] = v;
+    }
+  });
+}
+
+__global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+                                                   int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+  const int ncols = rows * nv;
+  const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const int K = no * nv;
+  SrcBF A{LvT32, 0, naux, naux, naux, K};
+  SrcBF B{Rt32, 0, ncols, ncols, ncols, K};
+  A.begin(threadIdx.x & 255, i0);
+  B.begin(threadIdx.x & 255, j0);
+  const int nchunks = (K + BKB - 1) / BKB;
+  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
+  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
+  __shared__ BigSmemB s[2];
+  BigAccF acc;
+  acc.zero();
+  big_mainloopB(s, A, B, kc0, kc1, acc);
+  if (wave_id() >= 4) return;
   big_for_eachF(acc, [&](int r, int c, float2 v) {
     const int P = i0 + r, col = j0 + c;
     if (P < naux && col < ncols) {
@@ -758,8 +820,20 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
   const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux;
   const int rows = m * nc;
   const bool prof = h->profiling != 0;
-  const bool c64 = h->prec == ADC2_C64;
+  const bool b3 = h->prec == ADC2_BF16X3;
+  const bool c64 = h->prec == ADC2_C64 || b3;   // complex64 operand copies
   if (c64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
+  if (b3) {
+    // the split-BF16 GEMMs address a tile's rows by 32-bit byte offsets from a
+    // workgroup base (grouped rows span at most (126 + nv) / nv groups) plus
+    // up to 15 k strides (the longest k stride: rows * nv), all in 32 bits
+    const double span_x = ((double)((126 + nv) / nv) * naux * nv + 17.0 * nv) * sizeof(float2);
+    const double span_r = 17.0 * rows * nv * sizeof(float2);
+    if (span_x >= 4294967296.0 || span_r >= 4294967296.0) {
+      set_error("split-BF16 sigma: operand row span exceeds 4 GiB; use fewer vectors per call");
+      return ADC2_ERR_ARG;
+    }
+  }
   auto mark = [&](int i) -> adc2_status {
     if (prof) ADC2_HIP(hipEventRecord(h->kev[i], st));
     return ADC2_OK;
@@ -783,7 +857,10 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
     const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
     const int ys = h->ysplit;
     dim3 grid((unsigned)nblk, ys);
-    k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
+    if (b3)
+      k_ygemm_b3<<<grid, 512, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
+    else
+      k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
     ADC2_CHECK_LAUNCH();
     if (ys > 1) {
       const long len = (long)rows * naux * nv;
@@ -828,8 +905,12 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
   if (!sgl) {
   } else if (c64) {
     const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
-    k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
-                                                  (float2*)h->Zb);
+    if (b3)
+      k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
+                                                   (float2*)h->Zb);
+    else
+      k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
+                                                    (float2*)h->Zb);
     ADC2_CHECK_LAUNCH();
   } else if (h->gemm3) {
     const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT3N);

@@ -1,12 +1,15 @@
-"""GPU precision form: complex64 operands on the FP32 MFMA for the two heavy
-sigma contractions, FP64 everywhere else.
+"""GPU precision form: the two heavy sigma contractions on complex64 operands
+with the FP32 MFMA, or on split-BF16 operands (hi + lo, three products) with
+the BF16 MFMA; FP64 everywhere else.
 
 Tolerances: the sigma of the precision form is compared with the FP64 oracle
 at 2e-5 of max|sigma| (FP32 unit roundoff 6e-8 times the sqrt of a
 1500-term accumulation, with margin); it must also differ from the FP64 path
 (so the FP32 kernels really ran).  Roots of the precision form must be within
 1e-3 eV of the FP64 roots before the FP64 Rayleigh polish and within 1e-6 Ha
-after it.
+after it.  The split-BF16 sigma must be within 1e-5 of the oracle (it keeps
+~16 bits per operand) and its folded roots, converged to residual 1e-3,
+within 1e-4 eV of FP64 before and after the polish.
 """
 import numpy as np
 import pytest
@@ -73,3 +76,40 @@ def test_rayleigh_certifies_fp64_roots():
     wr, rn = A.adc2_rayleigh(h, X)
     assert np.abs(np.array(wr) - np.array(w)).max() < 1e-10
     assert max(rn) < 1e-8
+
+
+# ---------------------------------------------------------------- split-BF16
+def test_b3_sigma_mid(mid):
+    """Split-BF16: each complex64 operand as hi + lo bf16 parts, three
+    products per real product on the BF16 MFMA, FP32 accumulation."""
+    s, o, h = mid
+    x = random_vectors(202, 3, o.dim)
+    ref = o.sigma(torch.from_numpy(x)).numpy()
+    A.adc2_set_precision(h, A.ADC2_BF16X3)
+    got = A.adc2_sigma(h, dev(x)).cpu().numpy()
+    A.adc2_set_precision(h, A.ADC2_C64)
+    got32 = A.adc2_sigma(h, dev(x)).cpu().numpy()
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    err32 = np.abs(got32 - ref).max() / scale
+    print(f"split-bf16 sigma rel err {err:.3e}, c64 {err32:.3e}")
+    assert err < 1e-5                 # measured 1.4e-6: hi+lo keeps ~16 bits, lo*lo dropped
+    assert err > 3 * err32            # the BF16 kernels ran
+
+
+def test_b3_roots_c1():
+    s = config_system("c1")
+    L, e = dev(s.L), dev(s.eps)
+    h = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    w64, _, info64 = A.adc2_davidson(h, 4, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED, want_vectors=False)
+    A.adc2_set_precision(h, A.ADC2_BF16X3)
+    wb, Xb, infob = A.adc2_davidson(h, 4, tol=1e-3, solver=A.ADC2_SOLVER_FOLDED, raise_on_noconv=False)
+    A.adc2_set_precision(h, A.ADC2_FP64)
+    wp, rn = A.adc2_rayleigh(h, Xb)
+    d_raw = np.abs(np.array(wb) - np.array(w64)) * EV
+    d_pol = np.abs(np.array(wp) - np.array(w64)) * EV
+    print("split-bf16 roots eV err", d_raw.tolist(), "polished eV err", d_pol.tolist(), "iters", infob["iters"],
+          "max res", max(infob["resnorm"]), "fp64 residuals", rn)
+    assert info64["converged"]
+    assert d_raw.max() < 1e-4          # eV; measured 6e-6 (eigenvalue error ~ residual^2)
+    assert d_pol.max() < 1e-4
