@@ -202,6 +202,61 @@ ADC2_API adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* 
 ADC2_API adc2_status adc2_omega_backward(adc2_handle h, int nroots, const void* X, const double* g_omega,
                                          void* dL, double* deps, void* stream);
 
+/*
+ * Batching form: several independent systems (molecules) of uneven size
+ * solved together.  Each system keeps its own handle; what is shared is the
+ * launch sequence.  In a batched sigma every phase of the sigma build runs for
+ * all systems before the next phase, and the two heavy contractions (the
+ * sigma2 product and the Y-build of the Cholesky-vector-driven sigma) of all
+ * systems in the complex64 or split-BF16 form are ONE launch each, whose
+ * workgroups walk a ragged list of (system, K-split, output tile) work items.
+ */
+typedef struct {
+  const void* L;        /* dev complex128 [naux][n][n], Hermitian per P (as adc2_setup) */
+  const double* eps;    /* dev float64 [n] */
+  int nc, no, nv, naux;
+} adc2_mol;
+
+/*
+ * adc2_setup_batch -- adc2_setup for nmol systems (1..64) with one precision.
+ *   mols   host [nmol]; out host [nmol] receives the handles (each released
+ *          with adc2_destroy).  On error every handle already built is
+ *          destroyed, out[] is set to NULL and the failing system's index is
+ *          named in adc2_last_error.  Synchronises the stream.
+ */
+ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, void* stream,
+                                      adc2_handle* out);
+
+/*
+ * adc2_sigma_batch -- S_i = M_i X_i for nmol systems in one batched launch
+ * sequence (stream-ordered, asynchronous).
+ *   hs host [nmol] distinct handles; m host [nmol] (>= 1); X, S host arrays
+ *   [nmol] of dev pointers, complex128 [m_i][dim_i] as adc2_sigma.
+ * Results equal nmol separate adc2_sigma calls: the same kernels compute the
+ * same tiles in the same order.  Errors: ADC2_ERR_ARG (NULL, m < 1, a handle
+ * repeated), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ */
+ADC2_API adc2_status adc2_sigma_batch(int nmol, const adc2_handle* hs, const int* m, const void* const* X,
+                                      void* const* S, void* stream);
+
+/*
+ * adc2_davidson_batch -- adc2_davidson for nmol systems solved concurrently.
+ * Each system runs its own solver (opt->solver, same options for all) on its
+ * own host thread and HIP stream; whenever the solvers need sigma builds
+ * they meet at a rendezvous and the pending requests of all systems still
+ * iterating run as one batched sigma (adc2_sigma_batch).  A system that
+ * converges (or fails) leaves the rendezvous and the others continue.  Each
+ * system's iterates, and so its roots, equal those of a separate
+ * adc2_davidson call.
+ *   omega  host float64 [nmol][nroots];  X host [nmol] of dev pointers
+ *   (complex128 [nroots][dim_i]) or NULL;  info host [nmol] or NULL.
+ * Returns the first non-OK status in system order (every system's results
+ * are still written; adc2_last_error names the system).  Synchronises the
+ * stream; guesses are the default ones.
+ */
+ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nroots, const adc2_dav_opts* opt,
+                                         double* omega, void* const* X, adc2_dav_info* info, void* stream);
+
 /* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
  * column (J,b)) into dev buffer dst.  Stream-ordered. */
 ADC2_API adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream);

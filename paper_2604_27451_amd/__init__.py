@@ -51,13 +51,20 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
-           "adc2_kernel_stats", "adc2_destroy", "adc2_last_error"]
+           "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
+           "adc2_davidson_batch"]
 
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("solver", ctypes.c_int)]
+
+
+class Mol(ctypes.Structure):
+    """adc2_mol: one system of a batch."""
+    _fields_ = [("L", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("nc", ctypes.c_int), ("no", ctypes.c_int),
+                ("nv", ctypes.c_int), ("naux", ctypes.c_int)]
 
 
 class DavInfo(ctypes.Structure):
@@ -123,6 +130,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_profile.restype = i
     lib.adc2_kernel_stats.argtypes = [vp, ctypes.POINTER(KStat), i]
     lib.adc2_kernel_stats.restype = i
+    lib.adc2_setup_batch.argtypes = [i, ctypes.POINTER(Mol), i, vp, ctypes.POINTER(vp)]
+    lib.adc2_setup_batch.restype = i
+    lib.adc2_sigma_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), vp]
+    lib.adc2_sigma_batch.restype = i
+    lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), ctypes.POINTER(d),
+                                        ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
+    lib.adc2_davidson_batch.restype = i
     lib.adc2_destroy.argtypes = [vp]
     lib.adc2_destroy.restype = i
     lib.adc2_last_error.argtypes = []
@@ -231,6 +246,64 @@ def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, ngues
         return res
     _check(st, "adc2_davidson")
     return res
+
+
+def adc2_setup_batch(systems, prec=ADC2_FP64, stream=None):
+    """Handles for a batch of systems; systems is a list of (L, eps, nc, no, nv, naux)."""
+    import torch
+    n = len(systems)
+    mols = (Mol * n)()
+    for q, (L, eps, nc, no, nv, naux) in enumerate(systems):
+        _need(L, torch.complex128, f"L[{q}]")
+        _need(eps, torch.float64, f"eps[{q}]")
+        nn = nc + no + nv
+        if tuple(L.shape) != (naux, nn, nn) or tuple(eps.shape) != (nn,):
+            raise ValueError(f"system {q}: L must be [naux][n][n] and eps [n]")
+        mols[q] = Mol(L.data_ptr(), eps.data_ptr(), nc, no, nv, naux)
+    out = (ctypes.c_void_p * n)()
+    _check(load().adc2_setup_batch(n, mols, prec, _stream_ptr(stream), out), "adc2_setup_batch")
+    return [Handle(ctypes.c_void_p(out[q]), *systems[q][2:6]) for q in range(n)]
+
+
+def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):
+    """S_i = M_i X_i for every system of a batch in one batched launch sequence."""
+    import torch
+    n = len(hs)
+    Xs = [X[None] if X.dim() == 1 else X for X in Xs]
+    if Ss is None:
+        Ss = [torch.empty_like(X) for X in Xs]
+    hp = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in hs])
+    ms = (ctypes.c_int * n)()
+    xp = (ctypes.c_void_p * n)()
+    sp = (ctypes.c_void_p * n)()
+    for q in range(n):
+        _need(Xs[q], torch.complex128, f"X[{q}]")
+        _need(Ss[q], torch.complex128, f"S[{q}]")
+        if Xs[q].shape[1] != hs[q].dim or Ss[q].shape != Xs[q].shape:
+            raise ValueError(f"system {q}: X and S must be [m][dim]")
+        ms[q] = Xs[q].shape[0]
+        xp[q] = Xs[q].data_ptr()
+        sp[q] = Ss[q].data_ptr()
+    _check(load().adc2_sigma_batch(n, hp, ms, xp, sp, _stream_ptr(stream)), "adc2_sigma_batch")
+    return Ss
+
+
+def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, want_vectors=True,
+                        verbose=0, stream=None, solver=ADC2_SOLVER_FOLDED):
+    """Lowest nroots eigenpairs of every system of a batch, solved concurrently.
+    Returns (omega [nmol][nroots] as lists, list of X or None, list of info dicts)."""
+    import torch
+    n = len(hs)
+    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver)
+    infos = (DavInfo * n)()
+    omega = (ctypes.c_double * (n * nroots))()
+    Xs = [torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") for h in hs] if want_vectors else None
+    hp = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in hs])
+    xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs]) if want_vectors else None
+    st = load().adc2_davidson_batch(n, hp, nroots, ctypes.byref(opts), omega, xp, infos, _stream_ptr(stream))
+    _check(st, "adc2_davidson_batch")
+    om = [list(omega[q * nroots:(q + 1) * nroots]) for q in range(n)]
+    return om, Xs, [infos[q].as_dict(nroots) for q in range(n)]
 
 
 def adc2_set_precision(h: Handle, prec: int):

@@ -439,7 +439,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   int n_sigma = 0;
   auto run_sigma = [&](const double2* x, double2* s_out, int m) -> adc2_status {
     DAV_TRY(hipEventRecord(h->ev0, st));
-    adc2_status r = sigma_fp64(h, m, x, s_out, st);
+    adc2_status r = sigma_call(h, m, x, s_out, SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN, st);
     if (r != ADC2_OK) return r;
     DAV_TRY(hipEventRecord(h->ev1, st));
     DAV_TRY(hipEventSynchronize(h->ev1));

@@ -1,0 +1,186 @@
+// batch.hip -- batching form: several systems of uneven size set up, applied
+// and solved together.
+//
+// Batched sigma: sigma_multi runs every phase of the sigma build for all
+// requests before the next phase; the two heavy contractions of the complex64
+// and split-BF16 forms are one grouped launch each over the ragged
+// (system, K-split, tile) item list (k_sigma.hip).
+//
+// Batched Davidson: one host thread and one HIP stream per system run the
+// ordinary solver.  Their sigma requests meet at a rendezvous: a request
+// waits until every system still iterating has one pending (or has left),
+// then the last arrival runs all pending requests as one sigma_multi on the
+// batch stream and releases the others.  Every system therefore sees exactly
+// the sigma results (and so the iterates) of a solve on its own.
+#include <condition_variable>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace adc2 {
+namespace {
+
+adc2_status bfail(adc2_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+struct Rendezvous {
+  std::mutex mu;
+  std::condition_variable cv;
+  int active = 0;               // systems still iterating
+  std::vector<SigReq> pend;     // requests of the current round
+  long round = 0;               // completed rounds
+  adc2_status status = ADC2_OK; // result of the last round
+  std::string msg;
+  hipStream_t st = nullptr;
+
+  // Run the pending round (mu held on entry and on return).
+  void fire(std::unique_lock<std::mutex>& lk) {
+    std::vector<SigReq> reqs;
+    reqs.swap(pend);
+    lk.unlock();
+    adc2_status r = sigma_multi((int)reqs.size(), reqs.data(), st);
+    std::string m;
+    if (r != ADC2_OK) {
+      m = adc2_last_error();
+    } else {
+      const hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        r = ADC2_ERR_HIP;
+        m = std::string("batched sigma: ") + hipGetErrorString(e);
+      }
+    }
+    lk.lock();
+    status = r;
+    msg = m;
+    ++round;
+    cv.notify_all();
+  }
+
+  adc2_status submit(const SigReq& q, hipStream_t own) {
+    // the request's input was produced on the system's own stream
+    const hipError_t e = hipStreamSynchronize(own);
+    if (e != hipSuccess) return bfail(ADC2_ERR_HIP, std::string("batched sigma: ") + hipGetErrorString(e));
+    std::unique_lock<std::mutex> lk(mu);
+    pend.push_back(q);
+    const long my = round;
+    if ((int)pend.size() == active)
+      fire(lk);
+    else
+      cv.wait(lk, [&] { return round != my; });
+    if (status != ADC2_OK) set_error(msg);
+    return status;
+  }
+
+  void leave() {
+    std::unique_lock<std::mutex> lk(mu);
+    --active;
+    if (active > 0 && (int)pend.size() == active) fire(lk);
+  }
+};
+
+}  // namespace
+}  // namespace adc2
+
+using namespace adc2;
+
+extern "C" {
+
+ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, void* stream, adc2_handle* out) {
+  if (!out) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: out is NULL");
+  if (nmol < 1 || nmol > 64) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: nmol must be 1..64");
+  for (int i = 0; i < nmol; ++i) out[i] = nullptr;
+  if (!mols) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: mols is NULL");
+  for (int i = 0; i < nmol; ++i) {
+    const adc2_mol& mo = mols[i];
+    adc2_status r = adc2_setup(mo.L, mo.eps, mo.nc, mo.no, mo.nv, mo.naux, prec, stream, &out[i]);
+    if (r != ADC2_OK) {
+      const std::string m = std::string("adc2_setup_batch: system ") + std::to_string(i) + ": " + adc2_last_error();
+      for (int j = 0; j < i; ++j) {
+        adc2_destroy(out[j]);
+        out[j] = nullptr;
+      }
+      return bfail(r, m);
+    }
+  }
+  return ADC2_OK;
+}
+
+ADC2_API adc2_status adc2_sigma_batch(int nmol, const adc2_handle* hs, const int* m, const void* const* X,
+                                      void* const* S, void* stream) {
+  if (nmol < 1 || !hs || !m || !X || !S) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: bad arguments");
+  std::vector<SigReq> rq(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    if (!hs[i] || !X[i] || !S[i] || m[i] < 1)
+      return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: system " + std::to_string(i) + ": NULL pointer or m < 1");
+    if (X[i] == S[i]) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: S must not alias X");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: a handle appears twice");
+    rq[i] = SigReq{hs[i], m[i], (const double2*)X[i], (double2*)S[i], SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN};
+  }
+  return sigma_multi(nmol, rq.data(), (hipStream_t)stream);
+}
+
+ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nroots, const adc2_dav_opts* opt,
+                                         double* omega, void* const* X, adc2_dav_info* info, void* stream) {
+  if (nmol < 1 || nmol > 64 || !hs || !omega) return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: bad arguments");
+  for (int i = 0; i < nmol; ++i) {
+    if (!hs[i]) return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: NULL handle");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: a handle appears twice");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  {
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bfail(ADC2_ERR_HIP, std::string("adc2_davidson_batch: ") + hipGetErrorString(e));
+  }
+  std::vector<hipStream_t> own(nmol, nullptr);
+  for (int i = 0; i < nmol; ++i) {
+    const hipError_t e = hipStreamCreateWithFlags(&own[i], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipStreamDestroy(own[j]);
+      return bfail(ADC2_ERR_HIP, std::string("adc2_davidson_batch: hipStreamCreate: ") + hipGetErrorString(e));
+    }
+  }
+  Rendezvous rv;
+  rv.active = nmol;
+  rv.st = st;
+  std::vector<adc2_status> rc(nmol, ADC2_OK);
+  std::vector<std::string> msg(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    adc2_handle h = hs[i];
+    hs[i]->sigma_hook = [&rv, h, i, &own](int m, const double2* xin, double2* sout, int parts, hipStream_t) {
+      return rv.submit(SigReq{h, m, xin, sout, parts}, own[i]);
+    };
+  }
+  std::vector<std::thread> th;
+  th.reserve(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    try {
+      th.emplace_back([&, i]() {
+        rc[i] = adc2_davidson(hs[i], nroots, opt, nullptr, omega + (size_t)i * (size_t)std::max(nroots, 0),
+                              X ? X[i] : nullptr, info ? &info[i] : nullptr, own[i]);
+        if (rc[i] != ADC2_OK) msg[i] = adc2_last_error();
+        rv.leave();
+      });
+    } catch (...) {   // no thread for this system: it never joins the rendezvous
+      rc[i] = ADC2_ERR_ARG;
+      msg[i] = "could not start a host thread";
+      rv.leave();
+    }
+  }
+  for (auto& t : th) t.join();
+  for (int i = 0; i < nmol; ++i) {
+    hs[i]->sigma_hook = nullptr;
+    hipStreamDestroy(own[i]);
+  }
+  for (int i = 0; i < nmol; ++i)
+    if (rc[i] != ADC2_OK) return bfail(rc[i], "adc2_davidson_batch: system " + std::to_string(i) + ": " + msg[i]);
+  return ADC2_OK;
+}
+
+}  // extern "C"

@@ -44,12 +44,13 @@ using hostla::cplx;
 
 namespace {
 
-constexpr int FMM = 64;     // Chebyshev moments stored
+constexpr int FMM = 128;    // Chebyshev moments stored (computed on demand, 8 at a time)
 constexpr int FGB = 16;     // Gram tile edge
 constexpr int FCH = 32;     // doubles per LDS chunk
 constexpr int FMB = 8;      // moments per workgroup
 constexpr int FTI = 32;     // largest row tile of the moment kernel
 constexpr int FSMAX = 64;   // largest search space
+constexpr int FCLAMP = 25;  // iterations a projected root may stay at the expansion limit
 
 __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -316,6 +317,7 @@ struct FoldRoot {
   int status = 0;                // 0 ok, 1 root not below the doubles threshold, 2 expansion too long,
                                  // 3 more moments needed (need)
   int need = 0;
+  int clamped = 0;               // consecutive iterations with status 1 (held at the expansion limit)
 };
 
 }  // namespace
@@ -570,7 +572,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   FD_HIP(hipEventCreate(&e1));
   auto sig_time = [&](int m, const double2* xin, double2* sout, int parts) -> adc2_status {
     ADC2_HIP(hipEventRecord(e0, st));
-    adc2_status r = sigma_parts(h, m, xin, sout, parts, st);
+    adc2_status r = sigma_call(h, m, xin, sout, parts, st);
     if (r != ADC2_OK) return r;
     ADC2_HIP(hipEventRecord(e1, st));
     ADC2_HIP(hipEventSynchronize(e1));
@@ -727,6 +729,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   }
 
   std::vector<FoldRoot> roots(k);
+  std::vector<char> prov(k, 0);   // root held at the expansion limit this iteration
   std::vector<double> res(k, 1e300);
   bool have_omega = false, converged = false;
   int it = 0;
@@ -756,7 +759,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     for (int i = 0; i < s; ++i) T0 += K[(size_t)i * smax + i].real();
     const double zb = 0.5 * (-(lam_min - Dmin) + std::sqrt((lam_min - Dmin) * (lam_min - Dmin) + 4.0 * std::max(T0, 0.0))) + 1.0;
     const double lo0 = Dmin - zb;
-    const double hi0 = cc - 1.2 * hh;      // |x| >= 1.2: at most 64 Chebyshev terms
+    // |x| >= 1.05: r = |x| - sqrt(x^2 - 1) < 0.73 and r^126 < 1e-17, so at most
+    // 126 Chebyshev terms; roots closer to min D than 0.05 of the half-width
+    // of the doubles spectrum are out of reach of this solver
+    const double hi0 = cc - 1.05 * hh;
     auto solve_root = [&](int j) {
       FoldRoot& R = roots[j];
       double wv = have_omega ? R.omega : lo0;
@@ -853,6 +859,22 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       mcomp = std::min(nmb, (need + FMB - 1) / FMB);
       FD_TRY(cheb_cols(s, 0, s, mcomp));
     }
+    // A projected root that is not below the limit of the resolvent expansion
+    // (status 1) is held there, as an unconverged Ritz pair of G at that
+    // point, while the search space grows: with a poor early space the
+    // projected root lies above the true one (interlacing).  It fails only if
+    // it stays there for FCLAMP iterations in a row.
+    for (int j = 0; j < k; ++j) {
+      if (roots[j].status == 1 && ++roots[j].clamped <= FCLAMP) {
+        roots[j].status = 0;
+        prov[j] = 1;
+        continue;
+      }
+      if (roots[j].status == 0) {
+        roots[j].clamped = 0;
+        prov[j] = 0;
+      }
+    }
     for (int j = 0; j < k; ++j) {
       if (roots[j].status != 0) {
         char buf[200];
@@ -915,7 +937,9 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     if (verbose) {
       fprintf(stderr, "[adc2 folded] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", it, s, rmax, om[0]);
     }
-    if (rmax <= tol) {
+    bool any_prov = false;
+    for (int j = 0; j < k; ++j) any_prov = any_prov || prov[j];
+    if (rmax <= tol && !any_prov) {
       converged = true;
       break;
     }
@@ -926,7 +950,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     std::vector<cplx> T((size_t)k * ns);
     int q = 0;
     for (int j = 0; j < k; ++j) {
-      if (res[j] <= tol) continue;
+      if (res[j] <= tol && !prov[j]) continue;
       cplx* t = &T[(size_t)q * ns];
       for (long e = 0; e < ns; ++e) {
         // approximate diagonal of the folded operator minus omega

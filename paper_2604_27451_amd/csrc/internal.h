@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/adc2.h"
@@ -72,6 +73,9 @@ struct adc2_handle_s {
   // column norm sum_d |M21_{d,(Kc)}|^2 and its |M21|^2-weighted mean doubles energy
   std::vector<double> pre_nu, pre_dbar;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // set while the handle solves inside adc2_davidson_batch: the solvers' sigma
+  // requests go to the batch's rendezvous instead of running alone
+  std::function<adc2_status(int m, const double2* xin, double2* sout, int parts, hipStream_t st)> sigma_hook;
   // per-kernel profiling of the sigma build
   static constexpr int NK = 8;   // unpack, ybuild, light1, xbuild, sigma2, pack2, backc, m11mv
   int profiling = 0;
@@ -93,6 +97,17 @@ adc2_status sigma_fp64(adc2_handle h, int m, const double2* X, double2* S, hipSt
 constexpr int SIGMA_SINGLES_IN = 1;   // (r1, 0) -> (M11 r1, M21 r1)
 constexpr int SIGMA_DOUBLES_IN = 2;   // (0, r2) -> singles M12 r2 only
 adc2_status sigma_parts(adc2_handle h, int m, const double2* X, double2* S, int parts, hipStream_t st);
+// One sigma request: m vectors of system h, parts as above.
+struct SigReq {
+  adc2_handle h;
+  int m;
+  const double2* xin;
+  double2* sout;
+  int parts;
+};
+adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st);
+// A solver's sigma: through h->sigma_hook when set, else sigma_parts.
+adc2_status sigma_call(adc2_handle h, int m, const double2* X, double2* S, int parts, hipStream_t st);
 adc2_status build_lvt(adc2_handle h, hipStream_t st);
 adc2_status build_c64(adc2_handle h, hipStream_t st);
 adc2_status ensure_ws(adc2_handle h, int m);

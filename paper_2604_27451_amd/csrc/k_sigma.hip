@@ -276,12 +276,16 @@ __global__ __launch_bounds__(256) void k_ygemm(const double2* __restrict__ LvT, 
 }
 
 // Precision form: the two heavy contractions on complex64 operands with the
-// FP32 MFMA and FP32 accumulation.
-__global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
-                                                    int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+// FP32 MFMA and FP32 accumulation.  Each kernel body is an "item" (one output
+// tile and one K-split) so that the plain launches below and the grouped
+// launches of several systems (GemmJobs) share it.
+//   sigma2: Z[mI][j][a][b] = sum_P X^P_{(mI)a} L^P_{bj}      (rows = m*nc*nv)
+//   Y-build: Y[s][mI][P][c] = sum_{(j,d) in split s} conj(L^P_dj) Rt[(j,d)][(mI,c)]
+__device__ __forceinline__ void zsig2_c64_item(BigSmemF (&s)[2], const float2* __restrict__ X32,
+                                               const float2* __restrict__ Lv32, int rows, int no, int nv, int naux,
+                                               float2* __restrict__ Z, long lid) {
   const int ncols = no * nv;
   const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
-  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
@@ -290,7 +294,6 @@ __global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X3
   SrcGroupedKF B{Lv32, lds, nv, nv, ncols, naux};
   A.begin(threadIdx.x, i0);
   B.begin(threadIdx.x, j0);
-  __shared__ BigSmemF s[2];
   BigAccF acc;
   acc.zero();
   big_mainloopF(s, A, B, 0, (naux + BK - 1) / BK, acc);
@@ -304,11 +307,11 @@ __global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X3
   });
 }
 
-__global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
-                                                    int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+__device__ __forceinline__ void ygemm_c64_item(BigSmemF (&s)[2], const float2* __restrict__ LvT32,
+                                               const float2* __restrict__ Rt32, int rows, int no, int nv, int naux,
+                                               double2* __restrict__ Y, long lid, int split, int nsplit) {
   const int ncols = rows * nv;
   const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
-  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
@@ -318,10 +321,9 @@ __global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ Lv
   A.begin(threadIdx.x, i0);
   B.begin(threadIdx.x, j0);
   const int nchunks = (K + BK - 1) / BK;
-  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
-  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
-  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
-  __shared__ BigSmemF s[2];
+  const int per = (nchunks + nsplit - 1) / nsplit;
+  const int kc0 = split * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)split * ((long)rows * naux * nv);
   BigAccF acc;
   acc.zero();
   big_mainloopF(s, A, B, kc0, kc1, acc);
@@ -335,12 +337,13 @@ __global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ Lv
 }
 
 // Precision form, split-BF16 variant: the same two contractions on the BF16
-// matrix cores with hi/lo operand splitting (zgemmb.h), FP32 accumulation.
-__global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
-                                                   int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+// matrix cores with hi/lo operand splitting (zgemmb.h), FP32 accumulation,
+// 512-thread workgroups (consumer waves 0-3 write the tile).
+__device__ __forceinline__ void zsig2_b3_item(BigSmemB (&s)[2], const float2* __restrict__ X32,
+                                              const float2* __restrict__ Lv32, int rows, int no, int nv, int naux,
+                                              float2* __restrict__ Z, long lid) {
   const int ncols = no * nv;
   const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
-  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
@@ -349,7 +352,6 @@ __global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32
   SrcBF B{Lv32, lds, nv, nv, ncols, naux};
   A.begin(threadIdx.x & 255, i0);
   B.begin(threadIdx.x & 255, j0);
-  __shared__ BigSmemB s[2];
   BigAccF acc;
   acc.zero();
   big_mainloopB(s, A, B, 0, (naux + BKB - 1) / BKB, acc);
@@ -364,11 +366,11 @@ __global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32
   });
 }
 
-__global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
-                                                   int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+__device__ __forceinline__ void ygemm_b3_item(BigSmemB (&s)[2], const float2* __restrict__ LvT32,
+                                              const float2* __restrict__ Rt32, int rows, int no, int nv, int naux,
+                                              double2* __restrict__ Y, long lid, int split, int nsplit) {
   const int ncols = rows * nv;
   const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
-  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
@@ -378,10 +380,9 @@ __global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT
   A.begin(threadIdx.x & 255, i0);
   B.begin(threadIdx.x & 255, j0);
   const int nchunks = (K + BKB - 1) / BKB;
-  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
-  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
-  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
-  __shared__ BigSmemB s[2];
+  const int per = (nchunks + nsplit - 1) / nsplit;
+  const int kc0 = split * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)split * ((long)rows * naux * nv);
   BigAccF acc;
   acc.zero();
   big_mainloopB(s, A, B, kc0, kc1, acc);
@@ -393,6 +394,95 @@ __global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT
       Ys[((long)mI * naux + P) * nv + cc] = make_double2((double)v.x, (double)v.y);
     }
   });
+}
+
+__global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
+                                                    int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+  __shared__ BigSmemF s[2];
+  const long nt = (long)((rows + BT - 1) / BT) * ((no * nv + BT - 1) / BT);
+  zsig2_c64_item(s, X32, Lv32, rows, no, nv, naux, Z, xcd_remap(blockIdx.x, nt));
+}
+
+__global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+                                                    int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+  __shared__ BigSmemF s[2];
+  const long nt = (long)((naux + BT - 1) / BT) * ((rows * nv + BT - 1) / BT);
+  ygemm_c64_item(s, LvT32, Rt32, rows, no, nv, naux, Y, xcd_remap(blockIdx.x, nt), blockIdx.y, gridDim.y);
+}
+
+__global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
+                                                   int rows, int no, int nv, int naux, float2* __restrict__ Z) {
+  __shared__ BigSmemB s[2];
+  const long nt = (long)((rows + BT - 1) / BT) * ((no * nv + BT - 1) / BT);
+  zsig2_b3_item(s, X32, Lv32, rows, no, nv, naux, Z, xcd_remap(blockIdx.x, nt));
+}
+
+__global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+                                                   int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+  __shared__ BigSmemB s[2];
+  const long nt = (long)((naux + BT - 1) / BT) * ((rows * nv + BT - 1) / BT);
+  ygemm_b3_item(s, LvT32, Rt32, rows, no, nv, naux, Y, xcd_remap(blockIdx.x, nt), blockIdx.y, gridDim.y);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches of the heavy GEMMs over several systems (batching form).
+// One job per system; its work items are (K-split, tile) pairs numbered from
+// w0.  The launch walks the concatenated item list [0, total): workgroup b
+// takes items b, b + gridDim.x, ...  Logical items are spread with xcd_remap
+// so that consecutive items of one system (which share operand panels) run on
+// one XCD; the ragged sizes of the systems only change the item table.
+constexpr int GMAX = 16;   // systems per grouped launch
+struct GemmJob {
+  const float2* A;   // LvT32 (Y-build) or X32 (sigma2)
+  const float2* B;   // Rt32 (Y-build) or Lv32 (sigma2)
+  void* C;           // Y (double2, nsplit partials) or Z (float2)
+  int rows, no, nv, naux, nsplit;
+  long ntile;        // output tiles of one K-split
+  long w0;           // first item
+};
+struct GemmJobs {
+  int n;
+  long total;
+  GemmJob j[GMAX];
+};
+
+__device__ __forceinline__ int job_of(const GemmJobs& J, long item) {
+  int q = 0;
+  for (int t = 1; t < J.n; ++t)
+    if (item >= J.j[t].w0) q = t;
+  return q;
+}
+
+template <bool YBUILD>
+__global__ __launch_bounds__(256) void k_gemm_c64_grouped(const GemmJobs J) {
+  __shared__ BigSmemF s[2];
+  for (long w = blockIdx.x; w < J.total; w += gridDim.x) {
+    const long item = xcd_remap(w, J.total);
+    const GemmJob& g = J.j[job_of(J, item)];
+    const long loc = item - g.w0;
+    const int split = (int)(loc / g.ntile);
+    const long lid = loc - (long)split * g.ntile;
+    if (YBUILD)
+      ygemm_c64_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid, split, g.nsplit);
+    else
+      zsig2_c64_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
+  }
+}
+
+template <bool YBUILD>
+__global__ __launch_bounds__(512) void k_gemm_b3_grouped(const GemmJobs J) {
+  __shared__ BigSmemB s[2];
+  for (long w = blockIdx.x; w < J.total; w += gridDim.x) {
+    const long item = xcd_remap(w, J.total);
+    const GemmJob& g = J.j[job_of(J, item)];
+    const long loc = item - g.w0;
+    const int split = (int)(loc / g.ntile);
+    const long lid = loc - (long)split * g.ntile;
+    if (YBUILD)
+      ygemm_b3_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid, split, g.nsplit);
+    else
+      zsig2_b3_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
+  }
 }
 
 __global__ void k_to_c64(const double2* __restrict__ src, long n, float2* __restrict__ dst) {
@@ -814,152 +904,276 @@ __global__ void k_zero_singles(double2* __restrict__ s, long dim, long ns, int m
 //                           doubles of sout not written)
 // both: the full sigma.
 adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout, int parts, hipStream_t st) {
-  adc2_status rc = ensure_ws(h, m);
-  if (rc != ADC2_OK) return rc;
-  const Dims& d = h->d;
-  const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux;
-  const int rows = m * nc;
-  const bool prof = h->profiling != 0;
-  const bool b3 = h->prec == ADC2_BF16X3;
-  const bool c64 = h->prec == ADC2_C64 || b3;   // complex64 operand copies
-  if (c64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
-  if (b3) {
-    // the split-BF16 GEMMs address a tile's rows by 32-bit byte offsets from a
-    // workgroup base (grouped rows span at most (126 + nv) / nv groups) plus
-    // up to 15 k strides (the longest k stride: rows * nv), all in 32 bits
-    const double span_x = ((double)((126 + nv) / nv) * naux * nv + 17.0 * nv) * sizeof(float2);
-    const double span_r = 17.0 * rows * nv * sizeof(float2);
-    if (span_x >= 4294967296.0 || span_r >= 4294967296.0) {
-      set_error("split-BF16 sigma: operand row span exceeds 4 GiB; use fewer vectors per call");
-      return ADC2_ERR_ARG;
+  const SigReq r{h, m, xin, sout, parts};
+  return sigma_multi(1, &r, st);
+}
+
+adc2_status sigma_call(adc2_handle h, int m, const double2* xin, double2* sout, int parts, hipStream_t st) {
+  if (h->sigma_hook) return h->sigma_hook(m, xin, sout, parts, st);
+  return sigma_parts(h, m, xin, sout, parts, st);
+}
+
+// Launch the grouped heavy GEMM (Y-build if ybuild, else sigma2) of the
+// requests selected by use[] whose handles share the precision form prec
+// (complex64 or split-BF16), GMAX systems per launch.
+static adc2_status grouped_gemm(int nreq, const SigReq* rq, const std::vector<char>& use, int prec, bool ybuild,
+                                hipStream_t st) {
+  GemmJobs J;
+  J.n = 0;
+  J.total = 0;
+  auto flush = [&]() -> adc2_status {
+    if (J.n == 0) return ADC2_OK;
+    const unsigned grid = (unsigned)std::min<long>(J.total, 1L << 20);
+    if (prec == ADC2_BF16X3) {
+      if (ybuild) k_gemm_b3_grouped<true><<<grid, 512, 0, st>>>(J);
+      else k_gemm_b3_grouped<false><<<grid, 512, 0, st>>>(J);
+    } else {
+      if (ybuild) k_gemm_c64_grouped<true><<<grid, 256, 0, st>>>(J);
+      else k_gemm_c64_grouped<false><<<grid, 256, 0, st>>>(J);
     }
-  }
-  auto mark = [&](int i) -> adc2_status {
-    if (prof) ADC2_HIP(hipEventRecord(h->kev[i], st));
+    ADC2_CHECK_LAUNCH();
+    J.n = 0;
+    J.total = 0;
     return ADC2_OK;
   };
-  const bool sgl = (parts & SIGMA_SINGLES_IN) != 0, dbl = (parts & SIGMA_DOUBLES_IN) != 0;
+  for (int q = 0; q < nreq; ++q) {
+    if (!use[q] || rq[q].h->prec != prec) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
+    GemmJob& g = J.j[J.n];
+    g.rows = ybuild ? rows : rows * d.nv;
+    g.no = d.no;
+    g.nv = d.nv;
+    g.naux = d.naux;
+    if (ybuild) {
+      g.A = h->LvT32;
+      g.B = (const float2*)h->Zb;
+      g.C = h->Y;
+      g.nsplit = h->ysplit;
+      g.ntile = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
+    } else {
+      g.A = (const float2*)h->X;
+      g.B = h->Lv32;
+      g.C = h->Zb;
+      g.nsplit = 1;
+      g.ntile = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
+    }
+    g.w0 = J.total;
+    J.total += g.ntile * g.nsplit;
+    if (++J.n == GMAX) {
+      adc2_status r = flush();
+      if (r != ADC2_OK) return r;
+    }
+  }
+  return flush();
+}
+
+// Several sigma requests (possibly of different systems) on one stream.  Each
+// phase runs for every request before the next phase; with more than one
+// request the two heavy GEMMs of the requests in the complex64 and split-BF16
+// forms are one grouped launch per form.  Per-kernel profiling (adc2_profile)
+// is recorded for single requests only.
+adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
+  adc2_status rc;
+  for (int q = 0; q < nreq; ++q) {
+    adc2_handle h = rq[q].h;
+    if ((rc = ensure_ws(h, rq[q].m)) != ADC2_OK) return rc;
+    const Dims& d = h->d;
+    const int nv = d.nv, naux = d.naux, rows = rq[q].m * d.nc;
+    const bool b3 = h->prec == ADC2_BF16X3;
+    const bool c64 = h->prec == ADC2_C64 || b3;   // complex64 operand copies
+    if (c64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
+    if (b3) {
+      // the split-BF16 GEMMs address a tile's rows by 32-bit byte offsets from a
+      // workgroup base (grouped rows span at most (126 + nv) / nv groups) plus
+      // up to 15 k strides (the longest k stride: rows * nv), all in 32 bits
+      const double span_x = ((double)((126 + nv) / nv) * naux * nv + 17.0 * nv) * sizeof(float2);
+      const double span_r = 17.0 * rows * nv * sizeof(float2);
+      if (span_x >= 4294967296.0 || span_r >= 4294967296.0) {
+        set_error("split-BF16 sigma: operand row span exceeds 4 GiB; use fewer vectors per call");
+        return ADC2_ERR_ARG;
+      }
+    }
+  }
+  adc2_handle h0 = rq[0].h;
+  const bool prof = nreq == 1 && h0->profiling != 0;
+  auto mark = [&](int i) -> adc2_status {
+    if (prof) ADC2_HIP(hipEventRecord(h0->kev[i], st));
+    return ADC2_OK;
+  };
+  std::vector<char> sgl(nreq), dbl(nreq);
+  for (int q = 0; q < nreq; ++q) {
+    sgl[q] = (rq[q].parts & SIGMA_SINGLES_IN) != 0;
+    dbl[q] = (rq[q].parts & SIGMA_DOUBLES_IN) != 0;
+  }
+  // precision forms that have a grouped GEMM and more than one request
+  auto grouped = [&](const std::vector<char>& use, int prec) {
+    if (nreq < 2) return false;
+    int n = 0;
+    for (int q = 0; q < nreq; ++q) n += use[q] && rq[q].h->prec == prec;
+    return n > 0;
+  };
+  auto is_grouped = [&](int q) { return nreq > 1 && rq[q].h->prec != ADC2_FP64; };
+
   // kernel order (profiling slots): unpack, ygemm, light1, xbuild, zsig2, pack2, backc, m11mv+finish
   if ((rc = mark(0)) != ADC2_OK) return rc;
-  if (dbl) {
-    const int nb = cdiv(nv, UT);
-    const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
+  for (int q = 0; q < nreq; ++q) {
+    if (!dbl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const bool c64 = h->prec != ADC2_FP64;
+    const int nb = cdiv(d.nv, UT);
+    const long nblk = (long)rq[q].m * d.nc * d.no * (nb * (nb + 1) / 2);
     if (c64)
-      k_unpack<float2, false><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, (float2*)h->Zb, nullptr);
+      k_unpack<float2, false><<<(unsigned)nblk, 256, 0, st>>>(rq[q].xin, d.dim, rq[q].m, d.nc, d.no, d.nv,
+                                                               (float2*)h->Zb, nullptr);
     else
-      k_unpack<double2, false><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, m, nc, no, nv, h->Zb, nullptr);
+      k_unpack<double2, false><<<(unsigned)nblk, 256, 0, st>>>(rq[q].xin, d.dim, rq[q].m, d.nc, d.no, d.nv, h->Zb,
+                                                                nullptr);
     ADC2_CHECK_LAUNCH();
   }
-  ADC2_CHECK_LAUNCH();
   if ((rc = mark(1)) != ADC2_OK) return rc;
-  if (!dbl) {
-  } else if (c64) {
-    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, BT);
+  for (int prec : {ADC2_C64, ADC2_BF16X3})
+    if (grouped(dbl, prec) && (rc = grouped_gemm(nreq, rq, dbl, prec, true, st)) != ADC2_OK) return rc;
+  for (int q = 0; q < nreq; ++q) {
+    if (!dbl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
     const int ys = h->ysplit;
-    dim3 grid((unsigned)nblk, ys);
-    if (b3)
-      k_ygemm_b3<<<grid, 512, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
-    else
-      k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, no, nv, naux, h->Y);
-    ADC2_CHECK_LAUNCH();
-    if (ys > 1) {
-      const long len = (long)rows * naux * nv;
-      k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, ys);
+    if (!is_grouped(q)) {
+      if (h->prec != ADC2_FP64) {
+        const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
+        dim3 grid((unsigned)nblk, ys);
+        if (h->prec == ADC2_BF16X3)
+          k_ygemm_b3<<<grid, 512, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
+        else
+          k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
+      } else {
+        const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, h->gemm3 ? BT3N : BT);
+        dim3 grid((unsigned)nblk, ys);
+        if (h->gemm3)
+          k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
+        else
+          k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
+      }
       ADC2_CHECK_LAUNCH();
     }
-  } else {
-    const long nblk = (long)cdiv(naux, BT) * cdiv((long)rows * nv, h->gemm3 ? BT3N : BT);
-    const int ys = h->ysplit;
-    dim3 grid((unsigned)nblk, ys);
-    if (h->gemm3)
-      k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, nc, no, nv, naux, h->Y);
-    else
-      k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, nc, no, nv, naux, h->Y);
-    ADC2_CHECK_LAUNCH();
     if (ys > 1) {
-      const long len = (long)rows * naux * nv;
+      const long len = (long)rows * d.naux * d.nv;
       k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, ys);
       ADC2_CHECK_LAUNCH();
     }
   }
   if ((rc = mark(2)) != ADC2_OK) return rc;
-  if (dbl) {
-    const int njg = (no + LJG - 1) / LJG;
-    const unsigned g = (unsigned)(rows * njg * ((nv + 255) / 256));
-    if (c64)
-      k_light1<float2><<<g, 256, 0, st>>>((const float2*)h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
+  for (int q = 0; q < nreq; ++q) {
+    if (!dbl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
+    const int njg = (d.no + LJG - 1) / LJG;
+    const unsigned g = (unsigned)(rows * njg * ((d.nv + 255) / 256));
+    if (h->prec != ADC2_FP64)
+      k_light1<float2><<<g, 256, 0, st>>>((const float2*)h->Zb, h->Vt, rows, d.nc, d.no, d.nv, h->Tp);
     else
-      k_light1<double2><<<g, 256, 0, st>>>(h->Zb, h->Vt, rows, nc, no, nv, h->Tp);
+      k_light1<double2><<<g, 256, 0, st>>>(h->Zb, h->Vt, rows, d.nc, d.no, d.nv, h->Tp);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(3)) != ADC2_OK) return rc;
-  if (sgl) {
-    const long nblk = (long)cdiv(rows, TM) * cdiv((long)naux * nv, TN);
-    if (c64)
-      k_xbuild<float2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, (float2*)h->X);
+  for (int q = 0; q < nreq; ++q) {
+    if (!sgl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
+    const long nblk = (long)cdiv(rows, TM) * cdiv((long)d.naux * d.nv, TN);
+    if (h->prec != ADC2_FP64)
+      k_xbuild<float2><<<(unsigned)nblk, 256, 0, st>>>(rq[q].xin, d.dim, d.nc, d.nv, d.naux, rows, h->Lvv,
+                                                       (float2*)h->X);
     else
-      k_xbuild<double2><<<(unsigned)nblk, 256, 0, st>>>(xin, d.dim, nc, nv, naux, rows, h->Lvv, h->X);
+      k_xbuild<double2><<<(unsigned)nblk, 256, 0, st>>>(rq[q].xin, d.dim, d.nc, d.nv, d.naux, rows, h->Lvv, h->X);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(4)) != ADC2_OK) return rc;
-  if (!sgl) {
-  } else if (c64) {
-    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
-    if (b3)
-      k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
-                                                   (float2*)h->Zb);
-    else
-      k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * nv, no, nv, naux,
-                                                    (float2*)h->Zb);
-    ADC2_CHECK_LAUNCH();
-  } else if (h->gemm3) {
-    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT3N);
-    k_zsig2<true><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * nv, nc, no, nv, naux, h->Zb);
-    ADC2_CHECK_LAUNCH();
-  } else {
-    const long nblk = (long)cdiv((long)rows * nv, BT) * cdiv((long)no * nv, BT);
-    k_zsig2<false><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * nv, nc, no, nv, naux, h->Zb);
+  for (int prec : {ADC2_C64, ADC2_BF16X3})
+    if (grouped(sgl, prec) && (rc = grouped_gemm(nreq, rq, sgl, prec, false, st)) != ADC2_OK) return rc;
+  for (int q = 0; q < nreq; ++q) {
+    if (!sgl[q] || is_grouped(q)) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
+    if (h->prec != ADC2_FP64) {
+      const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
+      if (h->prec == ADC2_BF16X3)
+        k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>((const float2*)h->X, h->Lv32, rows * d.nv, d.no, d.nv, d.naux,
+                                                     (float2*)h->Zb);
+      else
+        k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * d.nv, d.no, d.nv, d.naux,
+                                                      (float2*)h->Zb);
+    } else if (h->gemm3) {
+      const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT3N);
+      k_zsig2<true><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * d.nv, d.nc, d.no, d.nv, d.naux, h->Zb);
+    } else {
+      const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
+      k_zsig2<false><<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * d.nv, d.nc, d.no, d.nv, d.naux, h->Zb);
+    }
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(5)) != ADC2_OK) return rc;
-  if (sgl) {
-    const int with_d = dbl ? 1 : 0;
-    const int nb = cdiv(nv, PT);
-    const long nblk = (long)rows * no * (nb * (nb + 1) / 2);
-    if (c64)
-      k_pack2<float2><<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc,
-                                                      no, nv, with_d);
+  for (int q = 0; q < nreq; ++q) {
+    if (!sgl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int m = rq[q].m;
+    const int with_d = dbl[q] ? 1 : 0;
+    const int nb = cdiv(d.nv, PT);
+    const long nblk = (long)m * d.nc * d.no * (nb * (nb + 1) / 2);
+    if (h->prec != ADC2_FP64)
+      k_pack2<float2><<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->Zb, rq[q].xin, rq[q].sout, d.dim, h->Vt,
+                                                      h->eps, m, d.nc, d.no, d.nv, with_d);
     else
-      k_pack2<double2><<<(unsigned)nblk, 256, 0, st>>>(h->Zb, xin, sout, d.dim, h->Vt, h->eps, m, nc, no, nv,
-                                                       with_d);
+      k_pack2<double2><<<(unsigned)nblk, 256, 0, st>>>(h->Zb, rq[q].xin, rq[q].sout, d.dim, h->Vt, h->eps, m, d.nc,
+                                                       d.no, d.nv, with_d);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(6)) != ADC2_OK) return rc;
-  if (dbl) {
-    const long nblk = (long)cdiv(rows, TM) * cdiv(nv, TN) * h->nsplit;
-    k_backc<<<(unsigned)nblk, 256, 0, st>>>(h->Y, h->Lvv, rows, nv, naux, h->nsplit, h->part);
+  for (int q = 0; q < nreq; ++q) {
+    if (!dbl[q]) continue;
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int rows = rq[q].m * d.nc;
+    const long nblk = (long)cdiv(rows, TM) * cdiv(d.nv, TN) * h->nsplit;
+    k_backc<<<(unsigned)nblk, 256, 0, st>>>(h->Y, h->Lvv, rows, d.nv, d.naux, h->nsplit, h->part);
     ADC2_CHECK_LAUNCH();
   }
   if ((rc = mark(7)) != ADC2_OK) return rc;
-  if (sgl) {
-    adc2_status r2 = gemm_rr(m, (int)d.ns, (int)d.ns, xin, d.dim, false, h->M11, d.ns, false, sout, d.dim, 1.0,
-                             false, st);
-    if (r2 != ADC2_OK) return r2;
-  } else {
-    k_zero_singles<<<grid_for(d.ns * m), 256, 0, st>>>(sout, d.dim, d.ns, m);
-    ADC2_CHECK_LAUNCH();
-  }
-  if (dbl) {
-    k_sigma1_finish<<<grid_for((long)rows * nv, 256, 4096), 256, 0, st>>>(h->part, h->nsplit, h->Tp, m, nc, no,
-                                                                            nv, d.dim, sout);
-    ADC2_CHECK_LAUNCH();
+  for (int q = 0; q < nreq; ++q) {
+    adc2_handle h = rq[q].h;
+    const Dims& d = h->d;
+    const int m = rq[q].m;
+    if (sgl[q]) {
+      adc2_status r2 = gemm_rr(m, (int)d.ns, (int)d.ns, rq[q].xin, d.dim, false, h->M11, d.ns, false, rq[q].sout,
+                               d.dim, 1.0, false, st);
+      if (r2 != ADC2_OK) return r2;
+    } else {
+      k_zero_singles<<<grid_for(d.ns * m), 256, 0, st>>>(rq[q].sout, d.dim, d.ns, m);
+      ADC2_CHECK_LAUNCH();
+    }
+    if (dbl[q]) {
+      const int rows = m * d.nc;
+      k_sigma1_finish<<<grid_for((long)rows * d.nv, 256, 4096), 256, 0, st>>>(h->part, h->nsplit, h->Tp, m, d.nc,
+                                                                                d.no, d.nv, d.dim, rq[q].sout);
+      ADC2_CHECK_LAUNCH();
+    }
   }
   if ((rc = mark(8)) != ADC2_OK) return rc;
   if (prof) {
+    adc2_handle h = h0;
+    const Dims& d = h->d;
     ADC2_HIP(hipEventSynchronize(h->kev[8]));
-    const double nc_ = nc, no_ = no, nv_ = nv, na_ = naux, m_ = m;
+    const double nc_ = d.nc, no_ = d.no, nv_ = d.nv, na_ = d.naux, m_ = rq[0].m;
     const double heavy = 8.0 * m_ * nc_ * no_ * nv_ * nv_ * na_;
-    const double fs = sgl ? 1.0 : 0.0, fd = dbl ? 1.0 : 0.0;
+    const double fs = sgl[0] ? 1.0 : 0.0, fd = dbl[0] ? 1.0 : 0.0;
     const double fl[adc2_handle_s::NK] = {
         0.0,                                             // unpack (data movement)
         fd * heavy,                                      // Y-build GEMM
@@ -969,7 +1183,8 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
         fs * 8.0 * m_ * nc_ * no_ * nv_ * nv_ * nc_,     // pack + light sigma2 core term
         fd * 8.0 * m_ * nc_ * nv_ * nv_ * na_,           // back-contraction
         fs * 8.0 * m_ * (nc_ * nv_) * (nc_ * nv_)};      // M11 r1 + finish
-    const bool ran[adc2_handle_s::NK] = {dbl, dbl, dbl, sgl, sgl, sgl, dbl, true};
+    const bool ran[adc2_handle_s::NK] = {(bool)dbl[0], (bool)dbl[0], (bool)dbl[0], (bool)sgl[0],
+                                          (bool)sgl[0], (bool)sgl[0], (bool)dbl[0], true};
     for (int i = 0; i < adc2_handle_s::NK; ++i) {
       if (!ran[i]) continue;
       float ms = 0.f;

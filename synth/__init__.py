@@ -155,3 +155,19 @@ CONFIGS = {
 def config_system(name: str) -> System:
     c = CONFIGS[name]
     return make_system(c["nc"], c["no"], c["nv"], c["naux"], c["seed"], label=name)
+
+
+# Batching form: eight systems of uneven size, nc = 6, naux = 4 nv, 16 roots
+# each; system m drawn with seed 274510 + m.
+BATCH_C4 = [(20, 100), (80, 400), (35, 250), (60, 150), (25, 380), (70, 220), (45, 310), (55, 120)]
+
+
+def batch_systems(scale: float = 1.0, nc: int = 6) -> list:
+    """The batching workload; scale < 1 shrinks no and nv (naux = 4 nv kept)
+    for parity tests the oracle can follow."""
+    out = []
+    for m, (no, nv) in enumerate(BATCH_C4):
+        no_s = max(1, int(round(no * scale)))
+        nv_s = max(2, int(round(nv * scale)))
+        out.append(make_system(nc, no_s, nv_s, 4 * nv_s, 274510 + m, label=f"c4[{m}]"))
+    return out

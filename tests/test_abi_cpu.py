@@ -73,3 +73,36 @@ def test_binding_has_no_cpu_fallback(tmp_path):
             A.load(str(tmp_path / "missing.so"))
         finally:
             A._lib = A._lib_backup
+
+
+def test_batch_argument_errors_without_gpu(lib):
+    vp = ctypes.c_void_p
+    out = (vp * 2)(vp(5).value, vp(6).value)
+    mols = (A.Mol * 2)()
+    # sizes and NULLs are refused before any HIP call; out[] is cleared
+    assert lib.adc2_setup_batch(0, mols, 0, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(65, mols, 0, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(2, None, 0, None, out) == A.ADC2_ERR_ARG
+    assert out[0] is None and out[1] is None
+    assert lib.adc2_setup_batch(2, mols, 0, None, None) == A.ADC2_ERR_ARG
+    # a NULL system (L = eps = NULL) fails in adc2_setup and is named
+    assert lib.adc2_setup_batch(2, mols, 0, None, out) == A.ADC2_ERR_ARG
+    assert "system 0" in A.adc2_last_error()
+    hs = (vp * 2)(None, None)
+    ms = (ctypes.c_int * 2)(1, 1)
+    xs = (vp * 2)(vp(8).value, vp(16).value)
+    ss = (vp * 2)(vp(24).value, vp(32).value)
+    assert lib.adc2_sigma_batch(0, hs, ms, xs, ss, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_sigma_batch(2, hs, ms, xs, ss, None) == A.ADC2_ERR_ARG
+    assert "system 0" in A.adc2_last_error()
+    hs2 = (vp * 2)(vp(64).value, vp(64).value)   # never dereferenced: the repeat is refused first
+    assert lib.adc2_sigma_batch(2, hs2, ms, xs, ss, None) == A.ADC2_ERR_ARG
+    assert "twice" in A.adc2_last_error()
+    ms0 = (ctypes.c_int * 2)(1, 0)
+    hs3 = (vp * 2)(vp(64).value, vp(128).value)
+    assert lib.adc2_sigma_batch(2, hs3, ms0, xs, ss, None) == A.ADC2_ERR_ARG
+    om = (ctypes.c_double * 4)()
+    assert lib.adc2_davidson_batch(0, hs3, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs2, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs3, 2, None, None, None, None, None) == A.ADC2_ERR_ARG

@@ -1,0 +1,121 @@
+"""GPU parity of the batching form (adc2_setup_batch, adc2_sigma_batch,
+adc2_davidson_batch).
+
+A batched sigma runs the grouped heavy GEMMs (one launch over the ragged
+item list of all systems) and must equal separate adc2_sigma calls bit for
+bit; the batched solve must return, for every system, the roots of a solve on
+its own, and those roots must match the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_27451_amd as A
+from oracle import adc2 as O
+from synth import batch_systems, random_vectors
+
+pytestmark = pytest.mark.gpu
+
+FOLD = A.ADC2_SOLVER_FOLDED
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def setup(systems, prec):
+    print(f"[case] batch of {len(systems)} prec={prec} sizes={[(s.no, s.nv, s.naux) for s in systems]}", flush=True)
+    data = [(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux) for s in systems]
+    return A.adc2_setup_batch(data, prec)
+
+
+@pytest.mark.parametrize("prec", [A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3])
+def test_sigma_batch_equals_separate(prec):
+    systems = batch_systems(0.25)
+    hs = setup(systems, prec)
+    xs = [dev(random_vectors(900 + q, 1 + q % 3, h.dim)) for q, h in enumerate(hs)]
+    sb = A.adc2_sigma_batch(hs, xs)
+    for q, (h, x) in enumerate(zip(hs, xs)):
+        s1 = A.adc2_sigma(h, x)
+        torch.cuda.synchronize()
+        same = torch.equal(sb[q], s1)
+        if not same:
+            d = (sb[q] - s1).abs().max().item() / s1.abs().max().item()
+            print(f"  system {q}: max rel diff {d:.3e}", flush=True)
+        assert same, q
+    for h in hs:
+        h.close()
+
+
+def test_sigma_batch_mixed_precisions_vs_oracle():
+    """Handles in different precision forms in one batch: each form is grouped
+    separately; the FP64 system is checked against the oracle's sigma."""
+    systems = batch_systems(0.1)[:4]
+    data = [(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux) for s in systems]
+    hs = A.adc2_setup_batch(data, A.ADC2_FP64)
+    A.adc2_set_precision(hs[1], A.ADC2_C64)
+    A.adc2_set_precision(hs[2], A.ADC2_BF16X3)
+    A.adc2_set_precision(hs[3], A.ADC2_C64)
+    xs = [dev(random_vectors(950 + q, 2, h.dim)) for q, h in enumerate(hs)]
+    sb = A.adc2_sigma_batch(hs, xs)
+    for q in range(4):
+        assert torch.equal(sb[q], A.adc2_sigma(hs[q], xs[q])), q
+    s = systems[0]
+    o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    ref = o.sigma(xs[0].cpu())
+    err = ((sb[0].cpu() - ref).abs().max() / ref.abs().max()).item()
+    print(f"  fp64 batched sigma vs oracle {err:.2e}", flush=True)
+    assert err < 1e-11
+    for h in hs:
+        h.close()
+
+
+def check_batch_roots(systems, prec, solver, nroots, tol, oracle_idx):
+    hs = setup(systems, prec)
+    wb, Xb, infb = A.adc2_davidson_batch(hs, nroots, tol=tol, solver=solver)
+    for q, h in enumerate(hs):
+        w1, X1, inf1 = A.adc2_davidson(h, nroots, tol=tol, solver=solver)
+        print(f"  system {q}: batch {np.round(wb[q], 9)} its {infb[q]['iters']}  separate its {inf1['iters']}",
+              flush=True)
+        assert infb[q]["converged"] and inf1["converged"]
+        assert wb[q] == w1, (q, wb[q], w1)
+        assert torch.equal(Xb[q], X1), q
+    for q in oracle_idx:
+        s = systems[q]
+        sp = O.Spaces(s.nc, s.no, s.nv)
+        w_ref, _ = O.roots_folded(torch.from_numpy(s.L), torch.from_numpy(s.eps), sp, nroots, tol=1e-12)
+        err = np.abs(np.array(wb[q]) - np.asarray(w_ref)).max()
+        print(f"  system {q} vs oracle {err:.2e} Ha", flush=True)
+        assert err < (1e-9 if prec == A.ADC2_FP64 else 1e-4 / 27.211386245988)
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ADC2_FP64, A.ADC2_C64])
+def test_davidson_batch_folded_equals_separate_and_oracle(prec):
+    """Folded solver: systems 0-6 of the shrunken batch, whose four lowest
+    roots all lie at least 0.48 Ha inside the reach of the resolvent expansion
+    (0.05 of the half-width of the doubles spectrum below min D)."""
+    check_batch_roots(batch_systems(0.1)[:7], prec, FOLD, 4, 1e-8 if prec == A.ADC2_FP64 else 1e-5, (0, 3, 5))
+
+
+def test_davidson_batch_full_space_equals_separate_and_oracle():
+    """Full-space block Davidson through the same rendezvous, all eight
+    shrunken systems (system 7 has roots within 0.1 Ha of min D)."""
+    check_batch_roots(batch_systems(0.1), A.ADC2_FP64, A.ADC2_SOLVER_FULL, 3, 1e-8, (0, 7))
+
+
+def test_davidson_batch_reports_failing_system():
+    """A system whose roots are not all below the doubles threshold fails in
+    the folded solver; the batch names it and still solves the others."""
+    from synth import make_system
+    good = batch_systems(0.1)[0]
+    bad = make_system(1, 2, 3, 5, seed=7)   # its third root lies in the doubles band
+    hs = setup([good, bad], A.ADC2_FP64)
+    with pytest.raises(A.Adc2Error) as ei:
+        A.adc2_davidson_batch(hs, 3, tol=1e-8, solver=FOLD)
+    assert "system 1" in str(ei.value)
+    w1, _, _ = A.adc2_davidson(hs[0], 3, tol=1e-8, solver=FOLD)
+    assert len(w1) == 3
+    for h in hs:
+        h.close()
