@@ -122,15 +122,18 @@ def roofline_of(stats, peak, traffic):
 
 def run_batch(args, A, np, torch):
     """Batching form: the eight systems of the batch workload, 16 roots each,
-    complex64 heavy contractions with the folded solver to residual 1e-5 and an
-    FP64 Rayleigh polish; batched (adc2_setup_batch + adc2_davidson_batch)
+    complex64 heavy contractions with the folded solver and an FP64 Rayleigh
+    polish; batched (adc2_setup_batch + adc2_davidson_batch in both modes)
     and, for comparison, one system after the other."""
     from synth import batch_systems
     fold = A.ADC2_SOLVER_FOLDED
     nroots = args.nroots or 16
-    tol = args.tol_c64
+    tol = args.tol_batch
+    verbose = 1 if args.verbose else 0
     t = time.time()
     systems = batch_systems(1.0)
+    if args.batch_systems:
+        systems = [systems[int(i)] for i in args.batch_systems.split(",")]
     data = [(torch.from_numpy(s.L).cuda(), torch.from_numpy(s.eps).cuda(), s.nc, s.no, s.nv, s.naux)
             for s in systems]
     torch.cuda.synchronize()
@@ -142,60 +145,72 @@ def run_batch(args, A, np, torch):
         A.adc2_set_precision(h, A.ADC2_C64)
         return wp, rn
 
-    # batched
+    # warm-up (untimed): one solve of the smallest system, so that no timed leg pays first-call costs
+    qmin = min(range(len(data)), key=lambda q: systems[q].no * systems[q].nv ** 2)
+    h = A.adc2_setup(*data[qmin], prec=A.ADC2_C64)
+    A.adc2_davidson(h, nroots, tol=tol, solver=fold)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hs = A.adc2_setup_batch(data, A.ADC2_C64)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wb, Xb, infb = A.adc2_davidson_batch(hs, nroots, tol=tol, solver=fold)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    pol_b = [polish(h, X) for h, X in zip(hs, Xb)]
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    print(f"[bench] batched: setup {t1 - t0:.2f}s solve {t2 - t1:.2f}s polish {t3 - t2:.2f}s", file=sys.stderr,
-          flush=True)
-    sig_fl = sum(i["sigma_flops"] for i in infb)
-    for h in hs:
-        h.close()
-    del Xb
+    h.close()
     # one after the other
     seq = []
     t4 = time.perf_counter()
     for q, d in enumerate(data):
         ta = time.perf_counter()
         h = A.adc2_setup(*d, prec=A.ADC2_C64)
-        w, X, inf = A.adc2_davidson(h, nroots, tol=tol, solver=fold)
+        w, X, inf = A.adc2_davidson(h, nroots, tol=tol, solver=fold, verbose=verbose)
         wp, rn = polish(h, X)
         torch.cuda.synchronize()
-        seq.append((w, wp, rn, inf, time.perf_counter() - ta))
+        seq.append(dict(w=w, wp=wp, rn=rn, info=inf, s=time.perf_counter() - ta))
         h.close()
         del X
-        print(f"[bench] system {q} alone: {seq[-1][4]:.2f}s ({inf['iters']} it)", file=sys.stderr, flush=True)
+        print(f"[bench] system {q} alone: {seq[-1]['s']:.2f}s ({inf['iters']} it)", file=sys.stderr, flush=True)
     t5 = time.perf_counter()
-    same = all(wb[q] == seq[q][0] for q in range(len(data)))
+    sequential_s = t5 - t4
+    modes = {}
+    for name, mode in (("rounds", A.ADC2_BATCH_ROUNDS), ("streams", A.ADC2_BATCH_STREAMS)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hs = A.adc2_setup_batch(data, A.ADC2_C64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print(f"[bench] {name}: setup {t1 - t0:.2f}s", file=sys.stderr, flush=True)
+        wb, Xb, infb = A.adc2_davidson_batch(hs, nroots, tol=tol, solver=fold, verbose=verbose, mode=mode)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pol = [polish(h, X) for h, X in zip(hs, Xb)]
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        print(f"[bench] {name}: solve {t2 - t1:.2f}s polish {t3 - t2:.2f}s", file=sys.stderr, flush=True)
+        modes[name] = {
+            "total_s": round(t3 - t0, 3), "setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3),
+            "polish_s": round(t3 - t2, 3), "iterations": [i["iters"] for i in infb],
+            "speedup_vs_sequential": round(sequential_s / max(1e-9, t3 - t0), 3),
+            "roots_equal_sequential": bool(all(wb[q] == seq[q]["w"] for q in range(len(data)))),
+            "max_polished_resnorm": max(max(rn) for _, rn in pol),
+            "max_polish_shift_ev": max(float(np.abs(np.array(wp) - np.array(w)).max()) * HARTREE_EV
+                                       for (wp, _), w in zip(pol, wb)),
+        }
+        for h in hs:
+            h.close()
+        del Xb
+    best = min(modes, key=lambda k: modes[k]["total_s"])
     out = {
         "metric": "time to 16 roots of every system of the batch (batching form)",
-        "value": round(t3 - t0, 3),
+        "value": modes[best]["total_s"],
         "unit": "s",
         "n_gpus": 1,
         "higher_is_better": False,
         "dtype": "c64 contractions, f64 subspace",
         "data": "synthetic",
-        "config": {"workload": "batching form: 8 systems, nc=6, (no, nv) = " +
+        "config": {"workload": "batching form: " + str(len(systems)) + " systems, nc=6, (no, nv) = " +
                                ", ".join(f"({s.no},{s.nv})" for s in systems) + ", naux = 4 nv, "
                                f"{nroots} roots each, folded solver, complex64 tolerance {tol:g}, FP64 polish"},
-        "batched": {"setup_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3), "polish_s": round(t3 - t2, 3),
-                    "sigma_tflops_over_solve_wall": round(sig_fl / max(1e-9, t2 - t1) / 1e12, 3),
-                    "iterations": [i["iters"] for i in infb]},
-        "sequential_s": round(t5 - t4, 3),
-        "speedup": round((t5 - t4) / max(1e-9, t3 - t0), 3),
-        "roots_equal_sequential": bool(same),
-        "max_polished_resnorm": max(max(rn) for _, rn in pol_b),
-        "max_ev_shift_polish": max(float(np.abs(np.array(wp) - np.array(w)).max()) * HARTREE_EV
-                                   for (wp, _), w in zip(pol_b, wb)),
-        "omega_ha_polished": [list(wp) for wp, _ in pol_b],
+        "best_mode": best,
+        "modes": modes,
+        "sequential_s": round(sequential_s, 3),
+        "sequential_per_system_s": [round(r["s"], 3) for r in seq],
+        "sequential_iterations": [r["info"]["iters"] for r in seq],
+        "omega_ha_polished": [list(r["wp"]) for r in seq],
     }
     print(json.dumps(out), flush=True)
 
@@ -220,6 +235,11 @@ def main():
                     help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
                          "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
                          "one after the other; prints its own JSON line")
+    ap.add_argument("--tol-batch", type=float, default=5e-5,
+                    help="complex64 residual tolerance of the batch workload (its largest system's noise floor "
+                         "is ~2e-5)")
+    ap.add_argument("--batch-systems", default="",
+                    help="comma-separated indices of the batch systems to run (default: all eight)")
     ap.add_argument("--sigma-probe", action="store_true",
                     help="short run for hardware counters: 3 FP64, 3 complex64 and 3 split-BF16 sigma "
                          "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")

@@ -242,20 +242,27 @@ ADC2_API adc2_status adc2_sigma_batch(int nmol, const adc2_handle* hs, const int
 /*
  * adc2_davidson_batch -- adc2_davidson for nmol systems solved concurrently.
  * Each system runs its own solver (opt->solver, same options for all) on its
- * own host thread and HIP stream; whenever the solvers need sigma builds
- * they meet at a rendezvous and the pending requests of all systems still
- * iterating run as one batched sigma (adc2_sigma_batch).  A system that
- * converges (or fails) leaves the rendezvous and the others continue.  Each
- * system's iterates, and so its roots, equal those of a separate
- * adc2_davidson call.
+ * own host thread and HIP stream.
+ *   mode ADC2_BATCH_ROUNDS:  whenever the solvers need sigma builds they meet
+ *        at a rendezvous and the pending requests of all systems still
+ *        iterating run as one batched sigma (adc2_sigma_batch) on the given
+ *        stream; a system that converges (or fails) leaves the rendezvous.
+ *   mode ADC2_BATCH_STREAMS: no rendezvous; every system's sigma builds run
+ *        on its own stream and the GPU overlaps the streams (and one system's
+ *        host work with the others' kernels).
+ * In both modes each system's iterates, and so its roots, equal those of a
+ * separate adc2_davidson call.
  *   omega  host float64 [nmol][nroots];  X host [nmol] of dev pointers
  *   (complex128 [nroots][dim_i]) or NULL;  info host [nmol] or NULL.
  * Returns the first non-OK status in system order (every system's results
  * are still written; adc2_last_error names the system).  Synchronises the
  * stream; guesses are the default ones.
  */
+#define ADC2_BATCH_ROUNDS 0
+#define ADC2_BATCH_STREAMS 1
 ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nroots, const adc2_dav_opts* opt,
-                                         double* omega, void* const* X, adc2_dav_info* info, void* stream);
+                                         int mode, double* omega, void* const* X, adc2_dav_info* info,
+                                         void* stream);
 
 /* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
  * column (J,b)) into dev buffer dst.  Stream-ordered. */

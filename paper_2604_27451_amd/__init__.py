@@ -45,6 +45,8 @@ ADC2_BF16X3 = 2
 ADC2_MAX_ROOTS = 32
 ADC2_SOLVER_FULL = 0
 ADC2_SOLVER_FOLDED = 1
+ADC2_BATCH_ROUNDS = 0
+ADC2_BATCH_STREAMS = 1
 
 STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
@@ -135,7 +137,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_sigma_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp]
     lib.adc2_sigma_batch.restype = i
-    lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), ctypes.POINTER(d),
+    lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
     lib.adc2_destroy.argtypes = [vp]
@@ -289,7 +291,7 @@ def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):
 
 
 def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, want_vectors=True,
-                        verbose=0, stream=None, solver=ADC2_SOLVER_FOLDED):
+                        verbose=0, stream=None, solver=ADC2_SOLVER_FOLDED, mode=None):
     """Lowest nroots eigenpairs of every system of a batch, solved concurrently.
     Returns (omega [nmol][nroots] as lists, list of X or None, list of info dicts)."""
     import torch
@@ -300,7 +302,9 @@ def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess
     Xs = [torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") for h in hs] if want_vectors else None
     hp = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in hs])
     xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs]) if want_vectors else None
-    st = load().adc2_davidson_batch(n, hp, nroots, ctypes.byref(opts), omega, xp, infos, _stream_ptr(stream))
+    if mode is None:   # the faster of the two on the eight-system batch workload
+        mode = ADC2_BATCH_STREAMS
+    st = load().adc2_davidson_batch(n, hp, nroots, ctypes.byref(opts), mode, omega, xp, infos, _stream_ptr(stream))
     _check(st, "adc2_davidson_batch")
     om = [list(omega[q * nroots:(q + 1) * nroots]) for q in range(n)]
     return om, Xs, [infos[q].as_dict(nroots) for q in range(n)]

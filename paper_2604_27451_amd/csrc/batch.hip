@@ -7,11 +7,12 @@
 // (system, K-split, tile) item list (k_sigma.hip).
 //
 // Batched Davidson: one host thread and one HIP stream per system run the
-// ordinary solver.  Their sigma requests meet at a rendezvous: a request
-// waits until every system still iterating has one pending (or has left),
-// then the last arrival runs all pending requests as one sigma_multi on the
-// batch stream and releases the others.  Every system therefore sees exactly
-// the sigma results (and so the iterates) of a solve on its own.
+// ordinary solver.  In rounds mode their sigma requests meet at a rendezvous:
+// a request waits until every system still iterating has one pending (or has
+// left), then the last arrival runs all pending requests as one sigma_multi
+// on the batch stream and releases the others.  In streams mode each solver
+// keeps its sigma builds on its own stream.  Every system sees exactly the
+// sigma results (and so the iterates) of a solve on its own.
 #include <condition_variable>
 #include <mutex>
 #include <string>
@@ -126,8 +127,11 @@ ADC2_API adc2_status adc2_sigma_batch(int nmol, const adc2_handle* hs, const int
 }
 
 ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nroots, const adc2_dav_opts* opt,
-                                         double* omega, void* const* X, adc2_dav_info* info, void* stream) {
+                                         int mode, double* omega, void* const* X, adc2_dav_info* info,
+                                         void* stream) {
   if (nmol < 1 || nmol > 64 || !hs || !omega) return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: bad arguments");
+  if (mode != ADC2_BATCH_ROUNDS && mode != ADC2_BATCH_STREAMS)
+    return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: unknown mode");
   for (int i = 0; i < nmol; ++i) {
     if (!hs[i]) return bfail(ADC2_ERR_ARG, "adc2_davidson_batch: NULL handle");
     for (int j = 0; j < i; ++j)
@@ -151,12 +155,13 @@ ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nr
   rv.st = st;
   std::vector<adc2_status> rc(nmol, ADC2_OK);
   std::vector<std::string> msg(nmol);
-  for (int i = 0; i < nmol; ++i) {
-    adc2_handle h = hs[i];
-    hs[i]->sigma_hook = [&rv, h, i, &own](int m, const double2* xin, double2* sout, int parts, hipStream_t) {
-      return rv.submit(SigReq{h, m, xin, sout, parts}, own[i]);
-    };
-  }
+  if (mode == ADC2_BATCH_ROUNDS)
+    for (int i = 0; i < nmol; ++i) {
+      adc2_handle h = hs[i];
+      hs[i]->sigma_hook = [&rv, h, i, &own](int m, const double2* xin, double2* sout, int parts, hipStream_t) {
+        return rv.submit(SigReq{h, m, xin, sout, parts}, own[i]);
+      };
+    }
   std::vector<std::thread> th;
   th.reserve(nmol);
   for (int i = 0; i < nmol; ++i) {

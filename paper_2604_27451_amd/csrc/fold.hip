@@ -51,6 +51,7 @@ constexpr int FMB = 8;      // moments per workgroup
 constexpr int FTI = 32;     // largest row tile of the moment kernel
 constexpr int FSMAX = 64;   // largest search space
 constexpr int FCLAMP = 25;  // iterations a projected root may stay at the expansion limit
+constexpr int FSTALL = 40;  // iterations without a 20% drop of the largest residual before giving up
 
 __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -733,6 +734,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   std::vector<double> res(k, 1e300);
   bool have_omega = false, converged = false;
   int it = 0;
+  // stagnation: the largest residual has not dropped below 0.8 of its best
+  // value for FSTALL iterations (the precision form's noise floor)
+  double best_rmax = 1e300;
+  int best_it = 0;
   std::vector<cplx> x1((size_t)k * ns), r1((size_t)k * ns), mx2((size_t)k * ns);
   std::vector<double> nrm(k);
   const auto t_start = std::chrono::steady_clock::now();
@@ -935,7 +940,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     for (int j = 0; j < k; ++j) rmax = std::max(rmax, res[j]);
     tm_res += ms_since(tr0);
     if (verbose) {
-      fprintf(stderr, "[adc2 folded] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", it, s, rmax, om[0]);
+      fprintf(stderr, "[adc2 folded no=%d nv=%d] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", dd.no, dd.nv, it,
+              s, rmax, om[0]);
     }
     bool any_prov = false;
     for (int j = 0; j < k; ++j) any_prov = any_prov || prov[j];
@@ -944,6 +950,19 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       break;
     }
     if (it == max_iter) break;
+    if (rmax < 0.8 * best_rmax) {
+      best_rmax = rmax;
+      best_it = it;
+    } else if (!any_prov && it - best_it >= FSTALL) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "adc2_davidson (folded): residual stagnated at %.3e for %d iterations (tolerance %.1e is below "
+               "the noise floor of the sigma arithmetic)",
+               rmax, FSTALL, tol);
+      set_error(buf);
+      final_rc = ADC2_ERR_NOCONV;
+      break;
+    }
 
     // ---- new directions: diagonal preconditioner on the singles ----
     const auto tn0 = now();

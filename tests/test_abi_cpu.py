@@ -102,7 +102,9 @@ def test_batch_argument_errors_without_gpu(lib):
     hs3 = (vp * 2)(vp(64).value, vp(128).value)
     assert lib.adc2_sigma_batch(2, hs3, ms0, xs, ss, None) == A.ADC2_ERR_ARG
     om = (ctypes.c_double * 4)()
-    assert lib.adc2_davidson_batch(0, hs3, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
-    assert lib.adc2_davidson_batch(2, hs, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
-    assert lib.adc2_davidson_batch(2, hs2, 2, None, om, None, None, None) == A.ADC2_ERR_ARG
-    assert lib.adc2_davidson_batch(2, hs3, 2, None, None, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(0, hs3, 2, None, 0, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs, 2, None, 0, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs2, 2, None, 0, om, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs3, 2, None, 0, None, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_davidson_batch(2, hs3, 2, None, 7, om, None, None, None) == A.ADC2_ERR_ARG
+    assert "mode" in A.adc2_last_error()

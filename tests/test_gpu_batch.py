@@ -70,9 +70,9 @@ def test_sigma_batch_mixed_precisions_vs_oracle():
         h.close()
 
 
-def check_batch_roots(systems, prec, solver, nroots, tol, oracle_idx):
+def check_batch_roots(systems, prec, solver, nroots, tol, oracle_idx, mode=A.ADC2_BATCH_ROUNDS):
     hs = setup(systems, prec)
-    wb, Xb, infb = A.adc2_davidson_batch(hs, nroots, tol=tol, solver=solver)
+    wb, Xb, infb = A.adc2_davidson_batch(hs, nroots, tol=tol, solver=solver, mode=mode)
     for q, h in enumerate(hs):
         w1, X1, inf1 = A.adc2_davidson(h, nroots, tol=tol, solver=solver)
         print(f"  system {q}: batch {np.round(wb[q], 9)} its {infb[q]['iters']}  separate its {inf1['iters']}",
@@ -91,12 +91,14 @@ def check_batch_roots(systems, prec, solver, nroots, tol, oracle_idx):
         h.close()
 
 
-@pytest.mark.parametrize("prec", [A.ADC2_FP64, A.ADC2_C64])
-def test_davidson_batch_folded_equals_separate_and_oracle(prec):
+@pytest.mark.parametrize("prec,mode", [(A.ADC2_FP64, A.ADC2_BATCH_ROUNDS), (A.ADC2_C64, A.ADC2_BATCH_ROUNDS),
+                                       (A.ADC2_C64, A.ADC2_BATCH_STREAMS)])
+def test_davidson_batch_folded_equals_separate_and_oracle(prec, mode):
     """Folded solver: systems 0-6 of the shrunken batch, whose four lowest
     roots all lie at least 0.48 Ha inside the reach of the resolvent expansion
     (0.05 of the half-width of the doubles spectrum below min D)."""
-    check_batch_roots(batch_systems(0.1)[:7], prec, FOLD, 4, 1e-8 if prec == A.ADC2_FP64 else 1e-5, (0, 3, 5))
+    check_batch_roots(batch_systems(0.1)[:7], prec, FOLD, 4, 1e-8 if prec == A.ADC2_FP64 else 1e-5, (0, 3, 5),
+                      mode)
 
 
 def test_davidson_batch_full_space_equals_separate_and_oracle():
