@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--tol-mixed", type=float, default=1e-3)
     ap.add_argument("--tol-c64", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=400)
+    ap.add_argument("--max-subspace", type=int, default=0, help="search-space limit (0: the solver's default)")
+    ap.add_argument("--nguess", type=int, default=0, help="guess vectors (0: the solver's default)")
     ap.add_argument("--solver", choices=["folded", "full"], default="folded")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -292,6 +294,7 @@ def main():
     def solve(h, tol):
         A.adc2_profile(h, True)
         w, X, info = A.adc2_davidson(h, nroots, tol=tol, max_iter=args.max_iter, solver=solver,
+                                     max_subspace=args.max_subspace, nguess=args.nguess,
                                      verbose=1 if args.verbose else 0, raise_on_noconv=False)
         torch.cuda.synchronize()
         return w, X, info, A.adc2_kernel_stats(h)
