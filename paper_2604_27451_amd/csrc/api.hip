@@ -35,6 +35,10 @@ static void free_handle(adc2_handle h) {
   hipFree(h->LoT);
   hipFree(h->Lv32);
   hipFree(h->LvT32);
+  hipFree(h->LvB);
+  hipFree(h->LvTB);
+  hipFree(h->XB);
+  hipFree(h->RB);
   hipFree(h->eps);
   hipFree(h->M11);
   hipFree(h->diag);

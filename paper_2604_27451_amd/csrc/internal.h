@@ -55,6 +55,11 @@ struct adc2_handle_s {
   double2* LvT = nullptr;   // LoT + nc*nv*naux:   its valence rows (not a separate allocation)
   float2* Lv32 = nullptr;   // precision form: complex64 copy of the valence rows of Lvo
   float2* LvT32 = nullptr;  // precision form: complex64 copy of LvT
+  void* LvB = nullptr;      // split-BF16 variant: Lv32 and LvT32 in the blocked split layout (zgemmb.h)
+  void* LvTB = nullptr;
+  void* XB = nullptr;       // split-BF16 workspace: X and the unpacked doubles in the blocked split layout
+  void* RB = nullptr;
+  int wsb_m = 0;
   double* eps = nullptr;    // [n]
   double2* M11 = nullptr;   // [ns][ns]
   double* diag = nullptr;   // [dim]
@@ -110,6 +115,8 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st);
 adc2_status sigma_call(adc2_handle h, int m, const double2* X, double2* S, int parts, hipStream_t st);
 adc2_status build_lvt(adc2_handle h, hipStream_t st);
 adc2_status build_c64(adc2_handle h, hipStream_t st);
+adc2_status build_b3(adc2_handle h, hipStream_t st);
+adc2_status ensure_ws_b3(adc2_handle h, int m);
 adc2_status ensure_ws(adc2_handle h, int m);
 adc2_status unpack_weighted(adc2_handle h, int m, const double2* xin, const double* wts, hipStream_t st);
 adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);

@@ -28,6 +28,10 @@
 namespace adc2 {
 
 __host__ __device__ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
+  long g = (n + per - 1) / per;
+  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
+}
 
 // storage conversions of the precision form (complex64 operands, FP64 arithmetic around them)
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
@@ -337,24 +341,26 @@ __device__ __forceinline__ void ygemm_c64_item(BigSmemF (&s)[2], const float2* _
 }
 
 // Precision form, split-BF16 variant: the same two contractions on the BF16
-// matrix cores with hi/lo operand splitting (zgemmb.h), FP32 accumulation,
-// 512-thread workgroups (consumer waves 0-3 write the tile).
-__device__ __forceinline__ void zsig2_b3_item(BigSmemB (&s)[2], const float2* __restrict__ X32,
-                                              const float2* __restrict__ Lv32, int rows, int no, int nv, int naux,
+// matrix cores with hi/lo operands in the blocked split layout (zgemmb.h),
+// FP32 accumulation, 512-thread workgroups (consumer waves 0-3 write the
+// tile).  XB, LvB: sigma2 operands (rows (mI,a) and (j,b), K = naux); LvTB, RB:
+// Y-build operands (rows P and (mI,c), K = (j,d)).
+__device__ __forceinline__ void zsig2_b3_item(BigSmemB (&s)[2], const __bf16* __restrict__ XB,
+                                              const __bf16* __restrict__ LvB, int rows, int no, int nv, int naux,
                                               float2* __restrict__ Z, long lid) {
   const int ncols = no * nv;
   const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
-  const long lds = (long)naux * nv;
-  SrcBF A{X32, lds, nv, nv, rows, naux};
-  SrcBF B{Lv32, lds, nv, nv, ncols, naux};
+  const int nkc = (naux + BKB - 1) / BKB;
+  SrcBL A{(const char*)XB, nkc};
+  SrcBL B{(const char*)LvB, nkc};
   A.begin(threadIdx.x & 255, i0);
   B.begin(threadIdx.x & 255, j0);
   BigAccF acc;
   acc.zero();
-  big_mainloopB(s, A, B, 0, (naux + BKB - 1) / BKB, acc);
+  big_mainloopB(s, A, B, 0, nkc, acc);
   if (wave_id() >= 4) return;
   big_for_eachF(acc, [&](int r, int c, float2 v) {
     const int i = i0 + r, jc = j0 + c;
@@ -366,20 +372,19 @@ __device__ __forceinline__ void zsig2_b3_item(BigSmemB (&s)[2], const float2* __
   });
 }
 
-__device__ __forceinline__ void ygemm_b3_item(BigSmemB (&s)[2], const float2* __restrict__ LvT32,
-                                              const float2* __restrict__ Rt32, int rows, int no, int nv, int naux,
+__device__ __forceinline__ void ygemm_b3_item(BigSmemB (&s)[2], const __bf16* __restrict__ LvTB,
+                                              const __bf16* __restrict__ RB, int rows, int no, int nv, int naux,
                                               double2* __restrict__ Y, long lid, int split, int nsplit) {
   const int ncols = rows * nv;
   const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
   int bm, bn;
   big_tile_coords(lid, nbm, nbn, bm, bn);
   const int i0 = bm * BT, j0 = bn * BT;
-  const int K = no * nv;
-  SrcBF A{LvT32, 0, naux, naux, naux, K};
-  SrcBF B{Rt32, 0, ncols, ncols, ncols, K};
+  const int nchunks = (no * nv + BKB - 1) / BKB;
+  SrcBL A{(const char*)LvTB, nchunks};
+  SrcBL B{(const char*)RB, nchunks};
   A.begin(threadIdx.x & 255, i0);
   B.begin(threadIdx.x & 255, j0);
-  const int nchunks = (K + BKB - 1) / BKB;
   const int per = (nchunks + nsplit - 1) / nsplit;
   const int kc0 = split * per, kc1 = min(nchunks, kc0 + per);
   double2* Ys = Y + (long)split * ((long)rows * naux * nv);
@@ -396,6 +401,58 @@ __device__ __forceinline__ void ygemm_b3_item(BigSmemB (&s)[2], const float2* __
   });
 }
 
+// Split a K-major complex64 operand (element (k, row) at src[g*gstride + x +
+// k*ld], row = g*inner + x < R, k < K) into the blocked split layout of
+// zgemmb.h (rows padded to 128, k to 32, padding zero).  Thread t of a block's
+// 512 owns row r = (t / 4) % 128 and the k-group stored in 16-byte slot t % 4
+// of that row, so every plane store of a wave covers 16 whole 64-byte rows
+// (1 KB contiguous); the source reads of a wave are 4 runs of 16 rows.
+__global__ void k_split_pack(const float2* __restrict__ src, long gstride, long ld, int inner, int R, int K,
+                             int nrt, int nkc, __bf16* __restrict__ dst) {
+  const long total = (long)nrt * nkc * 512;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int slot = (int)(t & 3), r = (int)((t >> 2) & 127);
+    const long blk = t >> 9;
+    const int kc = (int)(blk % nkc), rt = (int)(blk / nkc);
+    const int row = rt * BT + r;
+    const int k0 = kc * BKB + 8 * (slot ^ ((r >> 1) & 3));
+    float re[8], im[8];
+    if (row < R) {
+      const int g = row / inner;
+      const float2* p = src + (long)g * gstride + (row - g * inner);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 v = k0 + e < K ? p[(long)(k0 + e) * ld] : make_float2(0.f, 0.f);
+        re[e] = v.x;
+        im[e] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) re[e] = im[e] = 0.f;
+    }
+    bf8 rh, rl, ih, il;
+    split8(re, rh, rl);
+    split8(im, ih, il);
+    const long o0 = split_block_offset(row, k0, 0, nkc);   // = plane-0 base of the block + r*32 + 8*slot
+    const long ps = (long)BT * BLDB;                      // plane stride
+    *(bf8*)(dst + o0) = rh;
+    *(bf8*)(dst + o0 + ps) = rl;
+    *(bf8*)(dst + o0 + 2 * ps) = ih;
+    *(bf8*)(dst + o0 + 3 * ps) = il;
+  }
+}
+
+static long split_bytes(long R, long K) { return (long)cdiv(R, BT) * cdiv(K, BKB) * BLOCK_BYTES; }
+
+static adc2_status split_pack(const float2* src, long gstride, long ld, int inner, long R, long K, __bf16* dst,
+                              hipStream_t st) {
+  const int nrt = cdiv(R, BT), nkc = cdiv(K, BKB);
+  const long total = (long)nrt * nkc * 512;
+  k_split_pack<<<grid_for(total, 256, 1L << 20), 256, 0, st>>>(src, gstride, ld, inner, (int)R, (int)K, nrt, nkc, dst);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
 __global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
                                                     int rows, int no, int nv, int naux, float2* __restrict__ Z) {
   __shared__ BigSmemF s[2];
@@ -410,18 +467,18 @@ __global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ Lv
   ygemm_c64_item(s, LvT32, Rt32, rows, no, nv, naux, Y, xcd_remap(blockIdx.x, nt), blockIdx.y, gridDim.y);
 }
 
-__global__ __launch_bounds__(512) void k_zsig2_b3(const float2* __restrict__ X32, const float2* __restrict__ Lv32,
+__global__ __launch_bounds__(512) void k_zsig2_b3(const __bf16* __restrict__ XB, const __bf16* __restrict__ LvB,
                                                    int rows, int no, int nv, int naux, float2* __restrict__ Z) {
   __shared__ BigSmemB s[2];
   const long nt = (long)((rows + BT - 1) / BT) * ((no * nv + BT - 1) / BT);
-  zsig2_b3_item(s, X32, Lv32, rows, no, nv, naux, Z, xcd_remap(blockIdx.x, nt));
+  zsig2_b3_item(s, XB, LvB, rows, no, nv, naux, Z, xcd_remap(blockIdx.x, nt));
 }
 
-__global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+__global__ __launch_bounds__(512) void k_ygemm_b3(const __bf16* __restrict__ LvTB, const __bf16* __restrict__ RB,
                                                    int rows, int no, int nv, int naux, double2* __restrict__ Y) {
   __shared__ BigSmemB s[2];
   const long nt = (long)((naux + BT - 1) / BT) * ((rows * nv + BT - 1) / BT);
-  ygemm_b3_item(s, LvT32, Rt32, rows, no, nv, naux, Y, xcd_remap(blockIdx.x, nt), blockIdx.y, gridDim.y);
+  ygemm_b3_item(s, LvTB, RB, rows, no, nv, naux, Y, xcd_remap(blockIdx.x, nt), blockIdx.y, gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,8 +490,8 @@ __global__ __launch_bounds__(512) void k_ygemm_b3(const float2* __restrict__ LvT
 // one XCD; the ragged sizes of the systems only change the item table.
 constexpr int GMAX = 16;   // systems per grouped launch
 struct GemmJob {
-  const float2* A;   // LvT32 (Y-build) or X32 (sigma2)
-  const float2* B;   // Rt32 (Y-build) or Lv32 (sigma2)
+  const void* A;     // Y-build: LvT32 (complex64) or LvTB (split);  sigma2: X32 or XB
+  const void* B;     // Y-build: Rt32 or RB;  sigma2: Lv32 or LvB
   void* C;           // Y (double2, nsplit partials) or Z (float2)
   int rows, no, nv, naux, nsplit;
   long ntile;        // output tiles of one K-split
@@ -463,9 +520,10 @@ __global__ __launch_bounds__(256) void k_gemm_c64_grouped(const GemmJobs J) {
     const int split = (int)(loc / g.ntile);
     const long lid = loc - (long)split * g.ntile;
     if (YBUILD)
-      ygemm_c64_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid, split, g.nsplit);
+      ygemm_c64_item(s, (const float2*)g.A, (const float2*)g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid,
+                     split, g.nsplit);
     else
-      zsig2_c64_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
+      zsig2_c64_item(s, (const float2*)g.A, (const float2*)g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
   }
 }
 
@@ -479,9 +537,10 @@ __global__ __launch_bounds__(512) void k_gemm_b3_grouped(const GemmJobs J) {
     const int split = (int)(loc / g.ntile);
     const long lid = loc - (long)split * g.ntile;
     if (YBUILD)
-      ygemm_b3_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid, split, g.nsplit);
+      ygemm_b3_item(s, (const __bf16*)g.A, (const __bf16*)g.B, g.rows, g.no, g.nv, g.naux, (double2*)g.C, lid,
+                    split, g.nsplit);
     else
-      zsig2_b3_item(s, g.A, g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
+      zsig2_b3_item(s, (const __bf16*)g.A, (const __bf16*)g.B, g.rows, g.no, g.nv, g.naux, (float2*)g.C, lid);
   }
 }
 
@@ -800,10 +859,6 @@ __global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, co
 }
 
 // ---------------------------------------------------------------------------
-static inline unsigned grid_for(long n, long per = 256, long cap = 16384) {
-  long g = (n + per - 1) / per;
-  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
-}
 
 adc2_status build_lvt(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
@@ -826,6 +881,34 @@ adc2_status build_c64(adc2_handle h, hipStream_t st) {
   ADC2_CHECK_LAUNCH();
   k_to_c64<<<grid_for(nlv), 256, 0, st>>>(h->LvT, nlv, h->LvT32);
   ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
+// Split-BF16 copies of the two static operands (blocked split layout).
+adc2_status build_b3(adc2_handle h, hipStream_t st) {
+  adc2_status rc = build_c64(h, st);
+  if (rc != ADC2_OK) return rc;
+  if (h->LvB && h->LvTB) return ADC2_OK;
+  const Dims& d = h->d;
+  const long K1 = d.naux, R1 = (long)d.no * d.nv;   // sigma2 B: rows (j,b), K = P
+  const long K2 = (long)d.no * d.nv, R2 = d.naux;   // Y-build A: rows P, K = (j,d)
+  ADC2_HIP(hipMalloc(&h->LvB, split_bytes(R1, K1)));
+  ADC2_HIP(hipMalloc(&h->LvTB, split_bytes(R2, K2)));
+  if ((rc = split_pack(h->Lv32, (long)d.naux * d.nv, d.nv, d.nv, R1, K1, (__bf16*)h->LvB, st)) != ADC2_OK) return rc;
+  return split_pack(h->LvT32, 0, d.naux, d.naux, R2, K2, (__bf16*)h->LvTB, st);
+}
+
+adc2_status ensure_ws_b3(adc2_handle h, int m) {
+  if (h->wsb_m >= m) return ADC2_OK;
+  hipFree(h->XB);
+  hipFree(h->RB);
+  h->XB = h->RB = nullptr;
+  h->wsb_m = 0;
+  const Dims& d = h->d;
+  const long rows = (long)m * d.nc * d.nv;
+  ADC2_HIP(hipMalloc(&h->XB, split_bytes(rows, d.naux)));
+  ADC2_HIP(hipMalloc(&h->RB, split_bytes(rows, (long)d.no * d.nv)));
+  h->wsb_m = m;
   return ADC2_OK;
 }
 
@@ -946,15 +1029,16 @@ static adc2_status grouped_gemm(int nreq, const SigReq* rq, const std::vector<ch
     g.no = d.no;
     g.nv = d.nv;
     g.naux = d.naux;
+    const bool split = prec == ADC2_BF16X3;
     if (ybuild) {
-      g.A = h->LvT32;
-      g.B = (const float2*)h->Zb;
+      g.A = split ? h->LvTB : (const void*)h->LvT32;
+      g.B = split ? h->RB : (const void*)h->Zb;
       g.C = h->Y;
       g.nsplit = h->ysplit;
       g.ntile = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
     } else {
-      g.A = (const float2*)h->X;
-      g.B = h->Lv32;
+      g.A = split ? h->XB : (const void*)h->X;
+      g.B = split ? h->LvB : (const void*)h->Lv32;
       g.C = h->Zb;
       g.nsplit = 1;
       g.ntile = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
@@ -979,22 +1063,10 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
   for (int q = 0; q < nreq; ++q) {
     adc2_handle h = rq[q].h;
     if ((rc = ensure_ws(h, rq[q].m)) != ADC2_OK) return rc;
-    const Dims& d = h->d;
-    const int nv = d.nv, naux = d.naux, rows = rq[q].m * d.nc;
     const bool b3 = h->prec == ADC2_BF16X3;
     const bool c64 = h->prec == ADC2_C64 || b3;   // complex64 operand copies
     if (c64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
-    if (b3) {
-      // the split-BF16 GEMMs address a tile's rows by 32-bit byte offsets from a
-      // workgroup base (grouped rows span at most (126 + nv) / nv groups) plus
-      // up to 15 k strides (the longest k stride: rows * nv), all in 32 bits
-      const double span_x = ((double)((126 + nv) / nv) * naux * nv + 17.0 * nv) * sizeof(float2);
-      const double span_r = 17.0 * rows * nv * sizeof(float2);
-      if (span_x >= 4294967296.0 || span_r >= 4294967296.0) {
-        set_error("split-BF16 sigma: operand row span exceeds 4 GiB; use fewer vectors per call");
-        return ADC2_ERR_ARG;
-      }
-    }
+    if (b3 && ((rc = build_b3(h, st)) != ADC2_OK || (rc = ensure_ws_b3(h, rq[q].m)) != ADC2_OK)) return rc;
   }
   adc2_handle h0 = rq[0].h;
   const bool prof = nreq == 1 && h0->profiling != 0;
@@ -1033,6 +1105,15 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
                                                                 nullptr);
     ADC2_CHECK_LAUNCH();
   }
+  for (int q = 0; q < nreq; ++q) {   // split-BF16: the unpacked doubles into the blocked split layout
+    adc2_handle h = rq[q].h;
+    if (!dbl[q] || h->prec != ADC2_BF16X3) continue;
+    const Dims& d = h->d;
+    const long ncols = (long)rq[q].m * d.nc * d.nv;
+    if ((rc = split_pack((const float2*)h->Zb, 0, ncols, (int)ncols, ncols, (long)d.no * d.nv, (__bf16*)h->RB, st)) !=
+        ADC2_OK)
+      return rc;
+  }
   if ((rc = mark(1)) != ADC2_OK) return rc;
   for (int prec : {ADC2_C64, ADC2_BF16X3})
     if (grouped(dbl, prec) && (rc = grouped_gemm(nreq, rq, dbl, prec, true, st)) != ADC2_OK) return rc;
@@ -1047,7 +1128,8 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
         const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
         dim3 grid((unsigned)nblk, ys);
         if (h->prec == ADC2_BF16X3)
-          k_ygemm_b3<<<grid, 512, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
+          k_ygemm_b3<<<grid, 512, 0, st>>>((const __bf16*)h->LvTB, (const __bf16*)h->RB, rows, d.no, d.nv, d.naux,
+                                           h->Y);
         else
           k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
       } else {
@@ -1094,6 +1176,14 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
       k_xbuild<double2><<<(unsigned)nblk, 256, 0, st>>>(rq[q].xin, d.dim, d.nc, d.nv, d.naux, rows, h->Lvv, h->X);
     ADC2_CHECK_LAUNCH();
   }
+  for (int q = 0; q < nreq; ++q) {   // split-BF16: X into the blocked split layout
+    adc2_handle h = rq[q].h;
+    if (!sgl[q] || h->prec != ADC2_BF16X3) continue;
+    const Dims& d = h->d;
+    if ((rc = split_pack((const float2*)h->X, (long)d.naux * d.nv, d.nv, d.nv, (long)rq[q].m * d.nc * d.nv, d.naux,
+                         (__bf16*)h->XB, st)) != ADC2_OK)
+      return rc;
+  }
   if ((rc = mark(4)) != ADC2_OK) return rc;
   for (int prec : {ADC2_C64, ADC2_BF16X3})
     if (grouped(sgl, prec) && (rc = grouped_gemm(nreq, rq, sgl, prec, false, st)) != ADC2_OK) return rc;
@@ -1105,8 +1195,8 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
     if (h->prec != ADC2_FP64) {
       const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
       if (h->prec == ADC2_BF16X3)
-        k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>((const float2*)h->X, h->Lv32, rows * d.nv, d.no, d.nv, d.naux,
-                                                     (float2*)h->Zb);
+        k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>((const __bf16*)h->XB, (const __bf16*)h->LvB, rows * d.nv, d.no,
+                                                     d.nv, d.naux, (float2*)h->Zb);
       else
         k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * d.nv, d.no, d.nv, d.naux,
                                                       (float2*)h->Zb);

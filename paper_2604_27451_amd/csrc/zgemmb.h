@@ -7,19 +7,20 @@
 // size 2^-16, is dropped).  A complex product uses four real products, so
 // twelve v_mfma_f32_16x16x32_bf16 per 16x16 block and 32-k step.
 //
+// The operands are split once, outside the GEMM, into a blocked layout that
+// is exactly the LDS tile (split_block_offset): for every 128-row tile and
+// 32-k chunk a 32 KB block of four planes (re hi, re lo, im hi, im lo) of
+// [128 rows][32 k] bf16, the 16-byte k-groups of a row permuted (kgrp),
+// rows and k zero-padded to whole tiles.
+//
 // 128 x 128 output tile per 512-thread workgroup of two roles.  Waves 0-3
 // (consumers) hold 64 x 64 of the tile each (4 x 4 blocks of 16 x 16) and
-// only read LDS fragments and issue MFMAs; waves 4-7 (producers) read the
-// K-major complex64 operands (contiguous along the output index), split them
-// and store them in LDS as four planes (re hi, re lo, im hi, im lo) of
-// [row][k] with k contiguous, so that a consumer lane's fragment (8
-// consecutive k of one row) is one 16-byte read.  With two waves per SIMD the
-// producers' vector ALU work runs beside the consumers' matrix work.  The
-// four 16-byte k-groups of a row are permuted (kgrp) so that the consecutive
-// rows one 16-byte read or write instruction touches fall on distinct banks.
-// Two LDS buffers: while the consumers multiply chunk
-// c, the producers stash chunk c+1 and load chunk c+3 (two chunks of global
-// loads in flight in registers); one barrier per chunk.
+// only read LDS fragments and issue MFMAs; waves 4-7 (producers) copy the
+// operand blocks into LDS with 16-byte loads and stores.  With two waves per
+// SIMD the producers' memory work runs beside the consumers' matrix work.
+// Two LDS buffers: while the consumers multiply chunk c, the producers store
+// chunk c+1 and load chunk c+3 (two chunks of global loads in flight in
+// registers); one barrier per chunk.
 //
 // Fragment layouts of v_mfma_f32_16x16x32_bf16 (checked on the device):
 //   A (16x32): lane l holds A[l % 16][8 (l / 16) + v], v = 0..7
@@ -50,86 +51,58 @@ struct BigSmemB {
 // no permutation or XOR with bits 2-3 gives 2- to 4-way conflicts.
 __device__ __forceinline__ int kgrp(int row, int g) { return 8 * (g ^ ((row >> 1) & 3)); }
 
-// round-to-nearest-even split of a float into bf16 hi and lo parts
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+
+// Position of element (k, row) of plane p in the blocked split layout, in
+// bf16 units; nkc = number of 32-k chunks (K padded).
+__host__ __device__ inline long split_block_offset(int row, int k, int p, int nkc) {
+  const int rt = row / BT, r = row % BT, kc = k / BKB, kk = k % BKB;
+  return (((long)rt * nkc + kc) * 4 + p) * (BT * BLDB) + (long)r * BLDB + 8 * ((kk >> 3) ^ ((r >> 1) & 3)) + (kk & 7);
 }
 
-// K-major complex64 source with grouped rows (row i = (g, x), x < inner,
-// element (k, i) at base[g*gstride + x + k*ld]).  Producer thread t (0..255)
-// stages row t % 128 of the tile and the 16 k of half t / 128 of the chunk.
-// The tile's first group g0 gives a workgroup-uniform base; a lane's row is a
-// 32-bit byte offset from it, and 16 k steps also fit in 32 bits (the
-// launcher checks both).  Rows past nrows read row nrows-1: they feed only
-// output rows or columns that are not written.  k past nk reads as zero.
-struct SrcBF {
-  const float2* base;
-  long gstride;
-  long ld;
-  int inner, nrows, nk;
-  const char* wbase;
-  unsigned offb;
-  int kh;
-  __device__ __forceinline__ void begin(int ptid, int i0) {
-    const int g0 = i0 / inner;
-    wbase = (const char*)(base + (long)g0 * gstride);
-    int i = i0 + (ptid & 127);
-    if (i >= nrows) i = nrows - 1;
-    const int g = i / inner;
-    offb = (unsigned)(((long)(g - g0) * gstride + (i - g * inner)) * (long)sizeof(float2));
-    kh = __builtin_amdgcn_readfirstlane(ptid >> 7);
-  }
-  // FULL: the caller guarantees that the chunk lies below nk (no clamping).
-  template <bool FULL = false>
-  __device__ __forceinline__ void load(int kc, fv2 (&r)[16]) const {
-    // raw buffer loads: uniform row base in the descriptor, lane offset in a
-    // VGPR, k step in the scalar offset (no per-load address arithmetic).  In
-    // general k is clamped to nk-1 and values past nk are replaced by 0.
-    const int k0 = kc * BKB + kh * 16;
-    const int kb = FULL ? k0 : min(k0, nk - 1);   // descriptor base row; scalar offsets are >= 0
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(wbase + (long)kb * ld * (long)sizeof(float2)), 0, -1, 0x00020000);
+// round-to-nearest-even split of 8 floats into bf16 hi and lo parts
+__device__ __forceinline__ void split8(const float (&x)[8], bf8& hi, bf8& lo) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int ee = FULL ? e : min(k0 + e, nk - 1) - kb;
-      const fv2 v = __builtin_bit_cast(fv2, __builtin_amdgcn_raw_buffer_load_b64(
-                                                rs, (int)offb, (int)(ee * ld * (long)sizeof(float2)), 0));
-      r[e] = FULL || k0 + e < nk ? v : (fv2){0.f, 0.f};
-    }
+  for (int v = 0; v < 8; v += 2) {
+    const fv2 xv = {x[v], x[v + 1]};
+    const bv2 h = __builtin_convertvector(xv, bv2);
+    const fv2 hf = __builtin_convertvector(h, fv2);
+    const bv2 l = __builtin_convertvector(xv - hf, bv2);
+    hi[v] = h[0];
+    hi[v + 1] = h[1];
+    lo[v] = l[0];
+    lo[v + 1] = l[1];
+  }
+}
+
+// Blocked split operand.  A chunk of one 128-row tile is 32 KB contiguous
+// (2048 16-byte segments, the LDS tile byte for byte); producer thread t
+// (0..255) moves segments t + 256 v, v = 0..7.
+constexpr int BLOCK_BYTES = 4 * BT * BLDB * 2;
+struct SrcBL {
+  const char* base;   // the operand's blocked array
+  int nkc;            // chunks per row tile
+  const char* tbase;  // this workgroup's row tile
+  int ptid;
+  typedef u4 Reg[8];
+  __device__ __forceinline__ void begin(int t, int i0) {
+    tbase = base + (long)(i0 / BT) * nkc * BLOCK_BYTES;
+    ptid = t;
+  }
+  __device__ __forceinline__ void load(int kc, Reg& r) const {
+    // raw buffer loads: the chunk's block in the descriptor, the lane's
+    // segment in the VGPR offset
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(tbase + (long)kc * BLOCK_BYTES), 0, BLOCK_BYTES, 0x00020000);
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      r[v] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rs, (ptid + 256 * v) * 16, 0, 0));
+  }
+  __device__ __forceinline__ void stash(__bf16 (*pl)[BT][BLDB], const Reg& r) const {
+    char* dst = (char*)&pl[0][0][0];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) *(u4*)(dst + (ptid + 256 * v) * 16) = r[v];
   }
 };
-
-// split of two floats (consecutive k) into packed bf16 hi and lo pairs
-__device__ __forceinline__ void split2(float x0, float x1, bv2& hi, bv2& lo) {
-  const fv2 x = {x0, x1};
-  hi = __builtin_convertvector(x, bv2);
-  const fv2 h = __builtin_convertvector(hi, fv2);
-  lo = __builtin_convertvector(x - h, bv2);
-}
-
-__device__ __forceinline__ void stash_bf(__bf16 (*pl)[BT][BLDB], const fv2 (&r)[16], int ptid) {
-  const int row = ptid & 127, k0 = (ptid >> 7) * 16;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    bf8 rh, rl, ih, il;
-#pragma unroll
-    for (int v = 0; v < 8; v += 2) {
-      bv2 a, b;
-      split2(r[8 * h + v].x, r[8 * h + v + 1].x, a, b);
-      rh[v] = a[0]; rh[v + 1] = a[1];
-      rl[v] = b[0]; rl[v + 1] = b[1];
-      split2(r[8 * h + v].y, r[8 * h + v + 1].y, a, b);
-      ih[v] = a[0]; ih[v + 1] = a[1];
-      il[v] = b[0]; il[v + 1] = b[1];
-    }
-    const int ko = kgrp(row, (k0 >> 3) + h);
-    *(bf8*)&pl[0][row][ko] = rh;
-    *(bf8*)&pl[1][row][ko] = rl;
-    *(bf8*)&pl[2][row][ko] = ih;
-    *(bf8*)&pl[3][row][ko] = il;
-  }
-}
 
 // sign flip of eight bf16 values (the sign bit of each half-word)
 __device__ __forceinline__ bf8 neg_bf8(bf8 x) {
@@ -210,46 +183,31 @@ __device__ __forceinline__ void big_mainloopB(BigSmemB (&s)[2], const SA& A, con
   if (kc0 >= kc1) return;
   const int w = wave_id();
   if (w >= 4) {
-    // producers: chunk c+1 is stashed while chunks c+2 and c+3 are in flight
+    // producers: chunk c+1 is stored while chunks c+2 and c+3 are in flight
     // in two register sets (set = chunk parity relative to kc0).  Chunk
-    // indices past kc1-1 are clamped to it: the extra loads and the stash into
+    // indices past kc1-1 are clamped to it: the extra loads and the store into
     // the buffer nobody reads after the last chunk keep the loop branch-free.
-    const int ptid = threadIdx.x - 256;
     const int kl = kc1 - 1;
-    fv2 ra0[16], rb0[16], ra1[16], rb1[16];
+    typename SA::Reg ra0, ra1;
+    typename SB::Reg rb0, rb1;
     A.load(kc0, ra0);
     B.load(kc0, rb0);
     A.load(min(kc0 + 1, kl), ra1);
     B.load(min(kc0 + 1, kl), rb1);
-    stash_bf(s[0].a, ra0, ptid);
-    stash_bf(s[0].b, rb0, ptid);
+    A.stash(s[0].a, ra0);
+    B.stash(s[0].b, rb0);
     A.load(min(kc0 + 2, kl), ra0);
     B.load(min(kc0 + 2, kl), rb0);
     lds_barrier();
-    auto step = [&](int c, fv2 (&ra)[16], fv2 (&rb)[16], int buf) {
-      __builtin_amdgcn_sched_barrier(0);   // keep this split below the previous barrier
-      stash_bf(s[buf].a, ra, ptid);
-      stash_bf(s[buf].b, rb, ptid);
+    auto step = [&](int c, typename SA::Reg& ra, typename SB::Reg& rb, int buf) {
+      __builtin_amdgcn_sched_barrier(0);   // keep this chunk's stores below the previous barrier
+      A.stash(s[buf].a, ra);
+      B.stash(s[buf].b, rb);
       A.load(min(c + 3, kl), ra);
       B.load(min(c + 3, kl), rb);
       lds_barrier();
     };
-    // steady state: chunks c+3 and c+4 lie below nk in both operands, so the
-    // loop body has no branch and two chunks of loads stay in flight
-    auto step_full = [&](int c, fv2 (&ra)[16], fv2 (&rb)[16], int buf) {
-      __builtin_amdgcn_sched_barrier(0);   // keep this split below the previous barrier
-      stash_bf(s[buf].a, ra, ptid);
-      stash_bf(s[buf].b, rb, ptid);
-      A.template load<true>(c + 3, ra);
-      B.template load<true>(c + 3, rb);
-      lds_barrier();
-    };
-    const int kfull = min(kc1, min(A.nk, B.nk) / BKB);   // chunks [0, kfull) lie below nk
     int c = kc0;
-    for (; c + 5 <= kfull; c += 2) {
-      step_full(c, ra1, rb1, 1);
-      step_full(c + 1, ra0, rb0, 0);
-    }
     for (; c + 1 < kc1; c += 2) {
       step(c, ra1, rb1, 1);
       step(c + 1, ra0, rb0, 0);
