@@ -215,6 +215,96 @@ def run_batch(args, A, np, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_fd(args, A, np, torch):
+    """Differentiation form at the c2 shape: d omega_k / dL and d omega_k / d eps
+    of the 10 lowest roots from the adjoint (adc2_omega_backward, one call per
+    root) against central finite differences of the eigenvalues, h = 1e-5, on
+    50 random Hermitian directions of L (unit Frobenius norm) and 10 random
+    directions of eps.  Each perturbed solve is the FP64 folded solver warm-
+    started from the unperturbed eigenvectors."""
+    from synth import config_system, random_hermitian_direction_device
+    fold = A.ADC2_SOLVER_FOLDED
+    ndir, nedir, hstep = 50, 10, 1e-5
+    sysm = config_system(args.config)
+    nc, no, nv, naux = sysm.nc, sysm.no, sysm.nv, sysm.naux
+    n = nc + no + nv
+    L = torch.from_numpy(sysm.L).cuda()
+    eps = torch.from_numpy(sysm.eps).cuda()
+    nroots = args.nroots or 10
+    tol = 1e-10
+    t0 = time.perf_counter()
+    h = A.adc2_setup(L, eps, nc, no, nv, naux)
+    w0, X0, inf0 = A.adc2_davidson(h, nroots, tol=tol, solver=fold)
+    print(f"[bench] fd: reference roots in {inf0['iters']} iterations", file=sys.stderr, flush=True)
+    G, GE = [], []
+    tb = time.perf_counter()
+    for k in range(nroots):
+        g = [0.0] * nroots
+        g[k] = 1.0
+        dL, de = A.adc2_omega_backward(h, X0, g)
+        G.append(dL)
+        GE.append(de)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - tb) / nroots
+    h.close()
+
+    def roots_at(Lp, ep):
+        hp = A.adc2_setup(Lp, ep, nc, no, nv, naux)
+        w, _, inf = A.adc2_davidson(hp, nroots, tol=tol, solver=fold, guess=X0, nguess=nroots, want_vectors=False)
+        hp.close()
+        return np.array(w), inf["iters"]
+
+    rows, iters = [], []
+    for d in range(ndir + nedir):
+        if d < ndir:
+            dL = random_hermitian_direction_device(27451 + 5000 + d, naux, n)
+            wp, ip = roots_at(L + hstep * dL, eps)
+            wm, im_ = roots_at(L - hstep * dL, eps)
+            ad = np.array([float(torch.sum(torch.conj(G[k]) * dL).real) for k in range(nroots)])
+            del dL
+        else:
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(27451 + 6000 + d)
+            de = torch.randn(n, generator=gen, device="cuda", dtype=torch.float64)
+            de = de / torch.linalg.vector_norm(de)
+            wp, ip = roots_at(L, eps + hstep * de)
+            wm, im_ = roots_at(L, eps - hstep * de)
+            ad = np.array([float(torch.dot(GE[k], de)) for k in range(nroots)])
+        fd = (wp - wm) / (2 * hstep)
+        rows.append((d < ndir, fd, ad))
+        iters += [ip, im_]
+        err = np.abs(fd - ad).max() / max(1e-300, np.abs(ad).max())
+        print(f"[bench] fd direction {d} ({'L' if d < ndir else 'eps'}): max rel dev {err:.2e} "
+              f"(|d omega| max {np.abs(ad).max():.3e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    def stats(is_l):
+        sel = [(fd, ad) for l, fd, ad in rows if l == is_l]
+        dev = [float(np.abs(fd - ad).max() / np.abs(ad).max()) for fd, ad in sel]
+        absd = [float(np.abs(fd - ad).max()) for fd, ad in sel]
+        return {"directions": len(sel), "max_rel_dev": max(dev), "median_rel_dev": float(np.median(dev)),
+                "max_abs_dev_ha": max(absd)}
+
+    out = {
+        "metric": "adjoint d omega/dL, d omega/d eps vs central finite differences (differentiation form)",
+        "value": stats(True)["max_rel_dev"],
+        "unit": "max relative deviation",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"CVS-ADC(2) {args.config}: nc={nc} no={no} nv={nv} naux={naux}, {nroots} roots, "
+                               f"{ndir} Hermitian L directions + {nedir} eps directions (unit norm), h = {hstep:g}, "
+                               "FP64 folded solves warm-started, tolerance 1e-10"},
+        "L_directions": stats(True),
+        "eps_directions": stats(False),
+        "adjoint_s_per_root": round(t_adj, 3),
+        "perturbed_solve_iterations": {"min": int(min(iters)), "max": int(max(iters))},
+        "wall_s": round(time.perf_counter() - t0, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,7 +323,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "fd"], default="single",
                     help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
                          "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
                          "one after the other; prints its own JSON line")
@@ -262,6 +352,9 @@ def main():
     A.load()
     if args.workload == "batch":
         run_batch(args, A, np, torch)
+        return
+    if args.workload == "fd":
+        run_fd(args, A, np, torch)
         return
     cfg = CONFIGS[args.config]
     nroots = args.nroots or cfg["nroots"]

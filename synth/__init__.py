@@ -171,3 +171,19 @@ def batch_systems(scale: float = 1.0, nc: int = 6) -> list:
         nv_s = max(2, int(round(nv * scale)))
         out.append(make_system(nc, no_s, nv_s, 4 * nv_s, 274510 + m, label=f"c4[{m}]"))
     return out
+
+
+def random_hermitian_direction_device(seed: int, naux: int, n: int, device="cuda"):
+    """A Hermitian-per-P direction dL of unit Frobenius norm drawn on the
+    device (torch generator seeded with seed): for directions at sizes where a
+    host draw would dominate the run time."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    re = torch.randn((naux, n, n), generator=g, device=device, dtype=torch.float64)
+    im = torch.randn((naux, n, n), generator=g, device=device, dtype=torch.float64)
+    a = torch.complex(re, im)
+    del re, im
+    h = 0.5 * (a + a.transpose(1, 2).conj())
+    del a
+    return h / torch.linalg.vector_norm(h)
