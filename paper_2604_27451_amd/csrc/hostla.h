@@ -1,6 +1,7 @@
 // hostla.h -- small dense host algebra of the folded eigensolver: a complex
-// Hermitian eigensolver (cyclic Jacobi) for the projected matrices (order
-// <= 64) and the Chebyshev coefficients of the resolvent 1/(x - t).
+// Hermitian eigensolver (Householder tridiagonalisation and implicit QL) for
+// the projected matrices (order <= 64) and the Chebyshev coefficients of the
+// resolvent 1/(x - t).
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -16,106 +17,173 @@ using cplx = std::complex<double>;
 // Eigen-decomposition of a Hermitian n x n matrix A (row-major).  On return
 // w[0..n) holds the eigenvalues in ascending order and Z (row-major, n x n)
 // the orthonormal eigenvectors as columns: A Z[:, i] = w[i] Z[:, i].
-// Cyclic Jacobi: each plane rotation R = [[c, s e], [-s conj(e), c]] with
-// e = a_pq / |a_pq| and t = s / c the smaller root of
-// t^2 + 2 theta t - 1 = 0, theta = (a_qq - a_pp) / (2 |a_pq|), zeroes a_pq.
+// Householder reduction to a real symmetric tridiagonal T = Q^H A Q, then the
+// implicit QL iteration with Wilkinson shifts on T (Bowdler, Martin, Reinsch
+// and Wilkinson 1968; eigenvectors accumulated in a real matrix), then the
+// back-transformation Z = Q Y.
+//   Reflector of step i (column i, rows i+1..n-1): H = I - tau v v^H with
+//   v[0] = 1, chosen so that H^H (alpha, x) = (beta, 0) with beta real,
+//   beta = -sign(Re alpha) |(alpha, x)|, tau = (beta - alpha) / beta,
+//   v[1:] = x / (alpha - beta); the trailing block is updated as
+//   A <- A - v w^H - w v^H with p = tau A v, w = p - (tau/2)(p^H v) v.
 inline void herm_eig(int n, const cplx* A, double* w, cplx* Z) {
+  if (n <= 0) return;
   std::vector<cplx> a(A, A + (size_t)n * n);
-  std::vector<cplx> z((size_t)n * n, cplx(0.0, 0.0));
-  for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
-  double diag2 = 0.0;
-  for (int i = 0; i < n; ++i) diag2 += std::norm(a[(size_t)i * n + i]);
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) off += std::norm(a[(size_t)p * n + q]);
-    if (off <= 1e-32 * std::max(diag2, 1e-300) || off == 0.0) break;
-    for (int p = 0; p < n; ++p) {
-      for (int q = p + 1; q < n; ++q) {
-        const cplx apq = a[(size_t)p * n + q];
-        const double g = std::abs(apq);
-        if (g == 0.0) continue;
-        const double app = a[(size_t)p * n + p].real(), aqq = a[(size_t)q * n + q].real();
-        if (g < 1e-300 + 1e-18 * (std::fabs(app) + std::fabs(aqq)) && sweep > 2) {
-          a[(size_t)p * n + q] = a[(size_t)q * n + p] = 0.0;
-          continue;
+  for (int i = 0; i < n; ++i) {          // Hermitian part, real diagonal
+    a[(size_t)i * n + i] = a[(size_t)i * n + i].real();
+    for (int j = i + 1; j < n; ++j) {
+      const cplx h = 0.5 * (a[(size_t)i * n + j] + std::conj(a[(size_t)j * n + i]));
+      a[(size_t)i * n + j] = h;
+      a[(size_t)j * n + i] = std::conj(h);
+    }
+  }
+  std::vector<double> d(n), e(n, 0.0);
+  std::vector<cplx> tau(n, cplx(0.0, 0.0)), V((size_t)n * n, cplx(0.0, 0.0));   // V column i = v_i
+  std::vector<cplx> p(n), wv(n), vc(n);
+  for (int i = 0; i + 1 < n; ++i) {
+    const int m = n - i - 1;               // length of the column below the diagonal
+    const cplx alpha = a[(size_t)(i + 1) * n + i];
+    double xn2 = 0.0;
+    for (int r = i + 2; r < n; ++r) xn2 += std::norm(a[(size_t)r * n + i]);
+    cplx t = 0.0;
+    double beta = alpha.real();
+    if (xn2 > 0.0 || alpha.imag() != 0.0) {
+      const double nrm = std::sqrt(std::norm(alpha) + xn2);
+      beta = alpha.real() >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      const cplx sc = 1.0 / (alpha - beta);
+      V[(size_t)(i + 1) * n + i] = 1.0;
+      for (int r = i + 2; r < n; ++r) V[(size_t)r * n + i] = a[(size_t)r * n + i] * sc;
+      // p = tau A22 v  (A22 = rows/cols i+1..n-1); the O(n^3) loops below
+      // spell out the complex arithmetic on the (re, im) pairs
+      for (int c = i + 1; c < n; ++c) vc[c] = V[(size_t)c * n + i];
+      for (int r = i + 1; r < n; ++r) {
+        const double* ar = reinterpret_cast<const double*>(&a[(size_t)r * n]);
+        const double* vv = reinterpret_cast<const double*>(vc.data());
+        double sr = 0.0, si = 0.0;
+        for (int c = i + 1; c < n; ++c) {
+          const double xr = ar[2 * c], xi = ar[2 * c + 1], yr = vv[2 * c], yi = vv[2 * c + 1];
+          sr += xr * yr - xi * yi;
+          si += xr * yi + xi * yr;
         }
-        const cplx e = apq / g;
-        const double th = (aqq - app) / (2.0 * g);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-        const cplx se = s * e, sce = s * std::conj(e);
-        // A <- A R   (columns p, q)
-        for (int i = 0; i < n; ++i) {
-          const cplx aip = a[(size_t)i * n + p], aiq = a[(size_t)i * n + q];
-          a[(size_t)i * n + p] = c * aip - sce * aiq;
-          a[(size_t)i * n + q] = se * aip + c * aiq;
+        p[r] = t * cplx(sr, si);
+      }
+      cplx pv = 0.0;                       // p^H v
+      for (int r = i + 1; r < n; ++r) pv += std::conj(p[r]) * V[(size_t)r * n + i];
+      const cplx half = -0.5 * t * pv;
+      for (int r = i + 1; r < n; ++r) wv[r] = p[r] + half * V[(size_t)r * n + i];
+      for (int r = i + 1; r < n; ++r) {
+        double* ar = reinterpret_cast<double*>(&a[(size_t)r * n]);
+        const double* ww = reinterpret_cast<const double*>(wv.data());
+        const double* vv = reinterpret_cast<const double*>(vc.data());
+        const double vr = vv[2 * r], vi = vv[2 * r + 1], wr = ww[2 * r], wi = ww[2 * r + 1];
+        for (int c = i + 1; c < n; ++c) {
+          // v_r conj(w_c) + w_r conj(v_c)
+          const double wcr = ww[2 * c], wci = ww[2 * c + 1], vcr = vv[2 * c], vci = vv[2 * c + 1];
+          ar[2 * c] -= vr * wcr + vi * wci + wr * vcr + wi * vci;
+          ar[2 * c + 1] -= vi * wcr - vr * wci + wi * vcr - wr * vci;
         }
-        // A <- R^H A (rows p, q)
-        for (int j = 0; j < n; ++j) {
-          const cplx apj = a[(size_t)p * n + j], aqj = a[(size_t)q * n + j];
-          a[(size_t)p * n + j] = c * apj - se * aqj;
-          a[(size_t)q * n + j] = sce * apj + c * aqj;
+      }
+    }
+    (void)m;
+    tau[i] = t;
+    d[i] = a[(size_t)i * n + i].real();
+    e[i] = beta;                           // T[i+1][i] = T[i][i+1]
+  }
+  d[n - 1] = a[(size_t)(n - 1) * n + (n - 1)].real();
+
+  // implicit QL on (d, e), e[i] coupling i and i+1; Y accumulates the rotations
+  std::vector<double> Y((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Y[(size_t)i * n + i] = 1.0;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-16 * dd) break;
+      }
+      if (m == l) break;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          break;
         }
-        a[(size_t)p * n + q] = a[(size_t)q * n + p] = 0.0;
-        a[(size_t)p * n + p] = a[(size_t)p * n + p].real();
-        a[(size_t)q * n + q] = a[(size_t)q * n + q].real();
-        // Z <- Z R
-        for (int i = 0; i < n; ++i) {
-          const cplx zip = z[(size_t)i * n + p], ziq = z[(size_t)i * n + q];
-          z[(size_t)i * n + p] = c * zip - sce * ziq;
-          z[(size_t)i * n + q] = se * zip + c * ziq;
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {       // rotate columns i and i+1 of Y
+          f = Y[(size_t)k * n + i + 1];
+          Y[(size_t)k * n + i + 1] = s * Y[(size_t)k * n + i] + c * f;
+          Y[(size_t)k * n + i] = c * Y[(size_t)k * n + i] - s * f;
         }
+      }
+      if (r == 0.0 && i >= l) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  // Z = Q Y, Q = H_0 H_1 ... H_{n-2}: apply the reflectors last to first
+  std::vector<cplx> X((size_t)n * n);
+  for (size_t q = 0; q < X.size(); ++q) X[q] = Y[q];
+  std::vector<double> acc(2 * n);
+  for (int i = n - 2; i >= 0; --i) {
+    if (tau[i] == cplx(0.0, 0.0)) continue;
+    // acc[c] = tau v^H X[:, c], then X -= v acc^T (row by row, contiguous)
+    std::fill(acc.begin(), acc.end(), 0.0);
+    for (int r = i + 1; r < n; ++r) {
+      const cplx v = V[(size_t)r * n + i];
+      const double vr = v.real(), vi = -v.imag();   // conj(v_r)
+      const double* xr = reinterpret_cast<const double*>(&X[(size_t)r * n]);
+      for (int c = 0; c < n; ++c) {
+        acc[2 * c] += vr * xr[2 * c] - vi * xr[2 * c + 1];
+        acc[2 * c + 1] += vr * xr[2 * c + 1] + vi * xr[2 * c];
+      }
+    }
+    const double tr = tau[i].real(), ti = tau[i].imag();
+    for (int c = 0; c < n; ++c) {
+      const double ar = acc[2 * c], ai = acc[2 * c + 1];
+      acc[2 * c] = tr * ar - ti * ai;
+      acc[2 * c + 1] = tr * ai + ti * ar;
+    }
+    for (int r = i + 1; r < n; ++r) {
+      const cplx v = V[(size_t)r * n + i];
+      const double vr = v.real(), vi = v.imag();
+      double* xr = reinterpret_cast<double*>(&X[(size_t)r * n]);
+      for (int c = 0; c < n; ++c) {
+        xr[2 * c] -= vr * acc[2 * c] - vi * acc[2 * c + 1];
+        xr[2 * c + 1] -= vr * acc[2 * c + 1] + vi * acc[2 * c];
       }
     }
   }
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
-  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a[(size_t)x * n + x].real() < a[(size_t)y * n + y].real(); });
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int i = 0; i < n; ++i) {
-    w[i] = a[(size_t)ord[i] * n + ord[i]].real();
-    for (int r = 0; r < n; ++r) Z[(size_t)r * n + i] = z[(size_t)r * n + ord[i]];
+    w[i] = d[ord[i]];
+    for (int r = 0; r < n; ++r) Z[(size_t)r * n + i] = X[(size_t)r * n + ord[i]];
   }
 }
 
-// Same, warm-started from an orthonormal basis Zp (columns, row-major n x n)
-// close to the eigenvectors: A is rotated into that basis, where it is nearly
-// diagonal, so the Jacobi sweeps converge in one or two passes.
+// Same contract, for a matrix close to diagonal in the basis Zp: the direct
+// solver above costs the same either way, so Zp is not needed.
 inline void herm_eig_warm(int n, const cplx* A, const cplx* Zp, double* w, cplx* Z) {
-  std::vector<cplx> T((size_t)n * n, cplx(0.0, 0.0)), B((size_t)n * n, cplx(0.0, 0.0)), Y((size_t)n * n);
-  for (int i = 0; i < n; ++i)          // T = A Zp
-    for (int l = 0; l < n; ++l) {
-      const cplx a = A[(size_t)i * n + l];
-      if (a == cplx(0.0, 0.0)) continue;
-      const cplx* zr = &Zp[(size_t)l * n];
-      cplx* tr = &T[(size_t)i * n];
-      for (int c = 0; c < n; ++c) tr[c] += a * zr[c];
-    }
-  for (int i = 0; i < n; ++i)          // B = Zp^H T
-    for (int r = 0; r < n; ++r) {
-      const cplx z = std::conj(Zp[(size_t)i * n + r]);
-      const cplx* tr = &T[(size_t)i * n];
-      cplx* br = &B[(size_t)r * n];
-      for (int c = 0; c < n; ++c) br[c] += z * tr[c];
-    }
-  for (int r = 0; r < n; ++r) {
-    B[(size_t)r * n + r] = B[(size_t)r * n + r].real();
-    for (int c = r + 1; c < n; ++c) {
-      const cplx a = 0.5 * (B[(size_t)r * n + c] + std::conj(B[(size_t)c * n + r]));
-      B[(size_t)r * n + c] = a;
-      B[(size_t)c * n + r] = std::conj(a);
-    }
-  }
-  herm_eig(n, B.data(), w, Y.data());
-  for (int i = 0; i < n; ++i) {        // Z = Zp Y
-    cplx* zr = &Z[(size_t)i * n];
-    for (int c = 0; c < n; ++c) zr[c] = 0.0;
-    for (int l = 0; l < n; ++l) {
-      const cplx zp = Zp[(size_t)i * n + l];
-      const cplx* yr = &Y[(size_t)l * n];
-      for (int c = 0; c < n; ++c) zr[c] += zp * yr[c];
-    }
-  }
+  (void)Zp;
+  herm_eig(n, A, w, Z);
 }
 
 // Chebyshev expansions of the resolvent for real |x| > 1 and t in [-1, 1]:
