@@ -8,8 +8,9 @@
 // The search space is kept in singles only, V = {v_i}, with U_i = M21 v_i
 // stored on the GPU.  The projected problem
 //   G(omega) = V^H M11 V + U^H (omega - D)^-1 U
-// is expanded in Chebyshev polynomials of D on [min D, max D]:
-//   (omega - D)^-1 = (1/h) sum_m b_m(x) T_m((D - c)/h),  x = (omega - c)/h,
+// is expanded in Chebyshev polynomials of tau(D), an affine image of
+// 1/(D - w0) with w0 below the roots (or of D itself):
+//   (omega - D)^-1 = sum_m g_m(omega) T_m(tau(D)),
 // so that K_m = U^H T_m U is computed once per basis vector on the GPU and
 // G(omega) for any omega < min D costs only host arithmetic.  Each root j
 // solves lambda_j(G(omega)) = omega by safeguarded Newton steps
@@ -64,7 +65,8 @@ __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / 
 template <int NB>
 __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
                                                     int qc, int ti, const double* __restrict__ D, double c,
-                                                    double ih, int nchb, int nmb, double2* __restrict__ part) {
+                                                    double ih, int inv, double w0, int nchb, int nmb,
+                                                    double2* __restrict__ part) {
   constexpr int NM = NB * FMB;
   __shared__ double2 ui[FTI][FCH + 1];
   __shared__ double2 uj[FGB][FCH + 1];
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U
     }
     if (tid < FCH) {   // T_m of this chunk's doubles energies
       const long ge = e0 + tid;
-      const double t = ge < nd ? (D[ge] - c) * ih : 0.0;
+      const double t = ge < nd ? ((inv ? 1.0 / (D[ge] - w0) : D[ge]) - c) * ih : 0.0;
       double t0 = 1.0, t1 = t;
       const int m0 = mb0 * FMB;
       for (int m = 0; m < m0 + NM; ++m) {
@@ -558,9 +560,21 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     Dmin = std::min(Dmin, hm[2 * b]);
     Dmax = std::max(Dmax, hm[2 * b + 1]);
   }
-  const double cc = 0.5 * (Dmin + Dmax);
-  const double hh = std::max(0.5 * (Dmax - Dmin), 1e-6 * std::max(1.0, std::fabs(cc)));
-  const double ih = 1.0 / hh;
+  // Expansion variable of the moments: the shifted inverse 1/(D - w0), with
+  // w0 below an estimate of the lowest root (the lower solution of
+  // omega = d11_e + nu_e / (omega - Dbar_e) over the singles e), needs far
+  // fewer terms than D itself; w0 is lowered, with all moments recomputed, if
+  // a root falls below w0 + 0.1 (Dmin - w0).  The linear variable remains
+  // for an estimate that is not below Dmin.
+  hostla::ResolventMap rmap = hostla::ResolventMap::linear(Dmin, Dmax);
+  double west = 1e300;
+  for (long e = 0; e < ns; ++e) {
+    const double a = d11[e], bb = pdb[e], nu = pnu[e];
+    const double r = nu > 0.0 ? 0.5 * ((a + bb) - std::sqrt((a - bb) * (a - bb) + 4.0 * nu)) : a;
+    west = std::min(west, r);
+  }
+  if (west < Dmin && std::isfinite(west))
+    rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, west - std::max(1.0, 0.5 * (Dmin - west)));
 
   // ---- host state ----
   std::vector<cplx> Vs((size_t)smax * ns), S1((size_t)smax * ns), H11((size_t)smax * smax);
@@ -588,7 +602,17 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   };
 
   // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 16 * mblocks
-  int mcomp = 3;                 // moment blocks held for every basis vector
+  // moment blocks held for every basis vector: with the shifted map, enough
+  // for the root estimate plus two terms (more are added on demand)
+  int mcomp = 3;
+  if (rmap.inv) {
+    std::vector<double> b(FMM), e(FMM), g(FMM), hq(FMM);
+    const int M = rmap.coeffs(west, FMM, b.data(), e.data(), g.data(), hq.data());
+    if (M > 0) mcomp = std::min(nmb, std::max(1, (M + 2 + FMB - 1) / FMB));
+  }
+  if (verbose)
+    fprintf(stderr, "[adc2 folded no=%d nv=%d] D in [%.6f, %.6f], root estimate %.6f, %s map w0 %.6f, %d moments\n",
+            dd.no, dd.nv, Dmin, Dmax, west, rmap.inv ? "shifted-inverse" : "linear", rmap.w0, FMB * mcomp);
   cplx* Kh = hK;
   double tm_cheb = 0.0;
   auto cheb_cols = [&](int srows, int j0, int q, int mblocks) -> adc2_status {
@@ -601,10 +625,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       const int nbw = std::min(cheb_nb, mblocks);
       dim3 g(nchb, ntile, (mblocks + nbw - 1) / nbw);
       switch (nbw) {
-        case 1: k_cheb_part<1><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
-        case 2: k_cheb_part<2><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
-        case 3: k_cheb_part<3><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
-        default: k_cheb_part<4><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, cc, ih, nchb, mblocks, part); break;
+        case 1: k_cheb_part<1><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
+        case 2: k_cheb_part<2><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
+        case 3: k_cheb_part<3><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
+        default: k_cheb_part<4><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
       }
       ADC2_CHECK_LAUNCH();
       const int mm_ = mblocks * FMB;
@@ -764,16 +788,17 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     for (int i = 0; i < s; ++i) T0 += K[(size_t)i * smax + i].real();
     const double zb = 0.5 * (-(lam_min - Dmin) + std::sqrt((lam_min - Dmin) * (lam_min - Dmin) + 4.0 * std::max(T0, 0.0))) + 1.0;
     const double lo0 = Dmin - zb;
-    // |x| >= 1.05: r = |x| - sqrt(x^2 - 1) < 0.73 and r^126 < 1e-17, so at most
-    // 126 Chebyshev terms; roots closer to min D than 0.05 of the half-width
-    // of the doubles spectrum are out of reach of this solver
-    const double hi0 = cc - 1.05 * hh;
+    // a pole at |x| >= 1.05 has r = |x| - sqrt(x^2 - 1) < 0.73 and r^126 < 1e-17,
+    // so at most 126 Chebyshev terms: with the shifted inverse, roots closer
+    // to min D than about 0.025 (min D - w0) are out of reach of this solver
+    double hi0 = rmap.reach(1.05);
+    double wlo = rmap.inv ? std::max(lo0, rmap.w0 + 0.1 * (Dmin - rmap.w0)) : lo0;   // lowest omega evaluated
     auto solve_root = [&](int j) {
       FoldRoot& R = roots[j];
-      double wv = have_omega ? R.omega : lo0;
-      if (!(wv > lo0 && wv < hi0)) wv = have_omega ? std::min(std::max(wv, lo0), hi0 - 1e-9 * std::fabs(hi0)) : lo0;
-      double lo = lo0, hi = hi0;
-      std::vector<double> b(FMM), e(FMM), w(s);
+      double wv = have_omega ? R.omega : wlo;
+      if (!(wv > wlo && wv < hi0)) wv = have_omega ? std::min(std::max(wv, wlo), hi0 - 1e-9 * std::fabs(hi0)) : wlo;
+      double lo = wlo, hi = hi0;
+      std::vector<double> b(FMM), e(FMM), w(s), gco(FMM), eco(FMM);
       std::vector<cplx> G((size_t)s * s), Z((size_t)s * s), Zp;
       // warm start from this root's last eigenvector basis, padded with the identity for the new vectors
       const int zs = R.Z.empty() ? 0 : (int)std::lround(std::sqrt((double)R.Z.size()));
@@ -785,7 +810,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       }
       R.status = 0;
       for (int nit = 0; nit < 80; ++nit) {
-        const int M = hostla::cheb_resolvent((wv - cc) * ih, FMM, b.data(), e.data());
+        // G = H11 + sum_m gco_m K_m,  |x2|^2 = y^H (sum_m eco_m K_m) y
+        const int M = rmap.coeffs(wv, FMM, b.data(), e.data(), gco.data(), eco.data());
         if (M < 0) {
           R.status = 2;
           return;
@@ -798,7 +824,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         for (int i = 0; i < s; ++i)
           for (int l = 0; l < s; ++l) {
             cplx a = H11[(size_t)i * smax + l];
-            for (int m = 0; m < M; ++m) a += (b[m] * ih) * K[((size_t)m * smax + i) * smax + l];
+            for (int m = 0; m < M; ++m) a += gco[m] * K[((size_t)m * smax + i) * smax + l];
             G[(size_t)i * s + l] = a;
           }
         for (int i = 0; i < s; ++i) {
@@ -812,7 +838,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         if (Zp.empty()) hostla::herm_eig(s, G.data(), w.data(), Z.data());
         else hostla::herm_eig_warm(s, G.data(), Zp.data(), w.data(), Z.data());
         Zp = Z;
-        // |x2|^2 = y^H E y,  E = (1/h^2) sum e_m K_m
+        // |x2|^2 = y^H E y,  E = sum eco_m K_m
         double n2 = 0.0;
         {
           std::vector<cplx> y(s);
@@ -822,12 +848,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
             cplx row = 0.0;
             for (int l = 0; l < s; ++l) {
               cplx kk = 0.0;
-              for (int m = 0; m < M; ++m) kk += e[m] * K[((size_t)m * smax + i) * smax + l];
+              for (int m = 0; m < M; ++m) kk += eco[m] * K[((size_t)m * smax + i) * smax + l];
               row += kk * y[l];
             }
             acc += std::conj(y[i]) * row;
           }
-          n2 = acc.real() * ih * ih;
+          n2 = acc.real();
         }
         const double f = w[j] - wv;
         if (f > 0.0) lo = std::max(lo, wv);
@@ -848,6 +874,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         wv = wn;
       }
       if (!(R.omega < hi0 - 1e-12 * std::fabs(hi0))) R.status = 1;
+      // the root lies below the lowest point the shifted map may evaluate
+      if (rmap.inv && wlo > lo0 && R.omega <= wlo + 1e-9 * std::max(1.0, std::fabs(wlo))) R.status = 4;
     };
     for (int attempt = 0; attempt < 4; ++attempt) {
       {
@@ -857,8 +885,21 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         for (auto& t : th) t.join();
       }
       int need = 0;
-      for (int j = 0; j < k; ++j)
+      bool below = false;
+      for (int j = 0; j < k; ++j) {
         if (roots[j].status == 3) need = std::max(need, roots[j].need);
+        if (roots[j].status == 4) below = true;
+      }
+      if (below) {
+        // a root below the shifted map's range: move the shift down (twice as
+        // far from min D) and recompute the moments of the whole space
+        rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, Dmin - 3.0 * (Dmin - rmap.w0));
+        hi0 = rmap.reach(1.05);
+        wlo = std::max(lo0, rmap.w0 + 0.1 * (Dmin - rmap.w0));
+        have_omega = false;
+        FD_TRY(cheb_cols(s, 0, s, mcomp));
+        continue;
+      }
       if (need == 0) break;
       // more Chebyshev moments: recompute them for the whole space
       mcomp = std::min(nmb, (need + FMB - 1) / FMB);
@@ -954,11 +995,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       best_rmax = rmax;
       best_it = it;
     } else if (!any_prov && it - best_it >= FSTALL) {
-      char buf[200];
+      char buf[320];
       snprintf(buf, sizeof buf,
                "adc2_davidson (folded): residual stagnated at %.3e for %d iterations (tolerance %.1e is below "
-               "the noise floor of the sigma arithmetic)",
-               rmax, FSTALL, tol);
+               "the noise floor of the sigma arithmetic, or a requested root lies too close to min D = %.6f for "
+               "the folded solver: use the full-space solver)",
+               rmax, FSTALL, tol, Dmin);
       set_error(buf);
       final_rc = ADC2_ERR_NOCONV;
       break;

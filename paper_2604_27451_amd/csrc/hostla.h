@@ -190,14 +190,14 @@ inline void herm_eig_warm(int n, const cplx* A, const cplx* Zp, double* w, cplx*
 //   1/(x - t)   = sum_m b[m] T_m(t),   1/(x - t)^2 = sum_m e[m] T_m(t).
 // With u = |x|, s = sqrt(u^2 - 1), r = u - s < 1 and sg = sign(x), the
 // generating function of the T_m gives b[m] = sg (m ? 2 : 1) (sg r)^m / s;
-// e = -db/dx.  Returns the number of terms after which r^m < 1e-17, or -1
-// if that exceeds mmax.
-inline int cheb_resolvent(double x, int mmax, double* b, double* e) {
+// e = -db/dx.  Returns the number of terms after which r^m < tol, or -1 if
+// that exceeds mmax.
+inline int cheb_resolvent(double x, int mmax, double* b, double* e, double tol = 1e-17) {
   const double sg = x > 0.0 ? 1.0 : -1.0;
   const double u = std::fabs(x);
   if (!(u > 1.0)) return -1;
   const double s = std::sqrt(u * u - 1.0), r = u - s;
-  int need = (int)std::ceil(std::log(1e-17) / std::log(r)) + 1;
+  int need = (int)std::ceil(std::log(tol) / std::log(r)) + 1;
   if (need < 2) need = 2;
   if (need > mmax) return -1;
   double rm = 1.0, sgm = 1.0;
@@ -211,6 +211,67 @@ inline int cheb_resolvent(double x, int mmax, double* b, double* e) {
   }
   return need;
 }
+
+// Chebyshev variable of the doubles energies D in [Dmin, Dmax] and the
+// expansion coefficients of the resolvent in it, for omega < Dmin:
+//   (omega - D)^-1 = sum_m g[m] T_m(tau(D)),  (omega - D)^-2 = sum_m h[m] T_m(tau(D)).
+// Linear: tau = (D - c) / hw, c and hw the centre and half-width of the
+// interval, and (omega - D)^-1 = (1/hw) / (x - tau), x = (omega - c) / hw.
+// Shifted inverse, w0 < Dmin: v = 1/(D - w0) maps the interval onto
+// [1/(Dmax - w0), 1/(Dmin - w0)] (centre c, half-width hw), and with
+// v* = 1/(omega - w0) the resolvent is v* - v*^2 / (v* - v), whose pole x =
+// (v* - c) / hw lies far outside [-1, 1] when w0 is well below omega, so the
+// series converges much faster.
+struct ResolventMap {
+  bool inv = false;
+  double c = 0.0, ih = 1.0, w0 = 0.0;   // tau = (v - c) * ih
+
+  static ResolventMap linear(double Dmin, double Dmax) {
+    ResolventMap r;
+    r.c = 0.5 * (Dmin + Dmax);
+    r.ih = 1.0 / std::max(0.5 * (Dmax - Dmin), 1e-6 * std::max(1.0, std::fabs(r.c)));
+    return r;
+  }
+  static ResolventMap shifted_inverse(double Dmin, double Dmax, double w0) {
+    ResolventMap r;
+    r.inv = true;
+    r.w0 = w0;
+    const double lo = 1.0 / (Dmax - w0), hi = 1.0 / (Dmin - w0);
+    r.c = 0.5 * (lo + hi);
+    r.ih = 1.0 / std::max(0.5 * (hi - lo), 1e-12 * hi);
+    return r;
+  }
+  double tau(double D) const { return ((inv ? 1.0 / (D - w0) : D) - c) * ih; }
+  // largest omega whose pole has |x| >= xmin
+  double reach(double xmin) const { return inv ? w0 + 1.0 / (c + xmin / ih) : c - xmin / ih; }
+  // g, h as above (b, e: work arrays); returns the number of terms, or -1 if
+  // more than mmax are needed or omega is not below the interval
+  int coeffs(double omega, int mmax, double* b, double* e, double* g, double* h) const {
+    if (!inv) {
+      const int M = cheb_resolvent((omega - c) * ih, mmax, b, e);
+      for (int m = 0; m < M; ++m) {
+        g[m] = b[m] * ih;
+        h[m] = e[m] * ih * ih;
+      }
+      return M;
+    }
+    if (!(omega > w0)) return -1;
+    const double vs = 1.0 / (omega - w0);
+    // the truncated tail is scaled by v*^2 / hw relative to the linear case
+    const int M = cheb_resolvent((vs - c) * ih, mmax, b, e, 1e-17 * std::min(1.0, c / vs));
+    // (omega - D)^-1 = v* - (v*^2/hw) sum b T;  (omega - D)^-2 = v*^2 - 2 (v*^3/hw) sum b T + (v*^4/hw^2) sum e T
+    const double g1 = vs * vs * ih, h1 = 2.0 * vs * vs * vs * ih, h2 = vs * vs * vs * vs * ih * ih;
+    for (int m = 0; m < M; ++m) {
+      g[m] = -g1 * b[m];
+      h[m] = -h1 * b[m] + h2 * e[m];
+    }
+    if (M > 0) {
+      g[0] += vs;
+      h[0] += vs * vs;
+    }
+    return M;
+  }
+};
 
 }  // namespace hostla
 }  // namespace adc2
