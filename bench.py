@@ -120,6 +120,44 @@ def roofline_of(stats, peak, traffic):
             "flops_per_launch": per_flops}
 
 
+# published MI355X figures next to which the probes are reported
+DATASHEET = {"mfma_f64": (78.6, "TFLOP/s"), "mfma_f32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
+             "valu_f64": (78.6, "TFLOP/s"), "hbm_read": (8000.0, "GB/s"), "hbm_copy": (8000.0, "GB/s")}
+
+
+def measure_peaks(A, names, reps=5, nbytes=8 << 30):
+    """Rates of the adc2_peak_probe microbenchmarks, with the datasheet value."""
+    kinds = {"mfma_f64": A.ADC2_PEAK_MFMA_F64, "mfma_f32": A.ADC2_PEAK_MFMA_F32,
+             "mfma_bf16": A.ADC2_PEAK_MFMA_BF16, "valu_f64": A.ADC2_PEAK_VALU_F64,
+             "hbm_read": A.ADC2_PEAK_HBM_READ, "hbm_copy": A.ADC2_PEAK_HBM_COPY}
+    out = {}
+    for n in names:
+        v = A.adc2_peak_probe(kinds[n], nbytes if n.startswith("hbm") else 0, reps)
+        ds, unit = DATASHEET[n]
+        out[n] = {"measured": round(v, 2), "datasheet": ds, "unit": unit, "frac_of_datasheet": round(v / ds, 4)}
+        print(f"[bench] peak {n}: {v:.1f} {unit} (datasheet {ds:g})", file=sys.stderr, flush=True)
+    return out
+
+
+def with_measured_peak(roof, measured):
+    """Adds the probe-measured peak (and the fraction of it) to a roofline record."""
+    roof = dict(roof)
+    roof["peak_measured"] = round(measured, 2)
+    roof["frac_of_measured"] = round(roof["achieved"] / measured, 4) if measured > 0 else None
+    return roof
+
+
+def run_peaks(args, A):
+    """Microbenchmarks of the rates the rooflines are quoted against."""
+    names = ["mfma_f64", "mfma_f32", "mfma_bf16", "valu_f64", "hbm_read", "hbm_copy"]
+    peaks = measure_peaks(A, names, reps=10)
+    print(json.dumps({"metric": "measured device peaks (adc2_peak_probe), 1 MI355X", "n_gpus": 1,
+                      "data": "synthetic", "config": {"workload": "peak microbenchmarks: dense MFMA "
+                                                      "(FP64 16x16x4, FP32 16x16x4, BF16 16x16x32), FP64 FMA, "
+                                                      "HBM read and copy over 8 GiB"},
+                      "peaks": peaks}), flush=True)
+
+
 def run_batch(args, A, np, torch):
     """Batching form: the eight systems of the batch workload, 16 roots each,
     complex64 heavy contractions with the folded solver and an FP64 Rayleigh
@@ -323,10 +361,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "fd"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "fd", "peaks"], default="single",
                     help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
                          "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
-                         "one after the other; prints its own JSON line")
+                         "one after the other; prints its own JSON line.  peaks: the device-rate "
+                         "microbenchmarks the rooflines are quoted against")
     ap.add_argument("--tol-batch", type=float, default=5e-5,
                     help="complex64 residual tolerance of the batch workload (its largest system's noise floor "
                          "is ~2e-5)")
@@ -355,6 +394,9 @@ def main():
         return
     if args.workload == "fd":
         run_fd(args, A, np, torch)
+        return
+    if args.workload == "peaks":
+        run_peaks(args, A)
         return
     cfg = CONFIGS[args.config]
     nroots = args.nroots or cfg["nroots"]
@@ -538,6 +580,15 @@ def main():
                                               f"denominators and subspace; tolerance {args.tol_c64:g}",
                                        PEAK_FP32_MFMA)
         out["mixed_c64"]["tol"] = args.tol_c64
+    # measured MFMA rates beside the published peaks (outside the timed steps)
+    pk = measure_peaks(A, ["mfma_f64"] + (["mfma_bf16"] if "mixed" in out else []) +
+                       (["mfma_f32"] if "mixed_c64" in out else []))
+    out["roofline"] = with_measured_peak(out["roofline"], pk["mfma_f64"]["measured"])
+    if "mixed" in out:
+        out["mixed"]["roofline"] = with_measured_peak(out["mixed"]["roofline"],
+                                                      pk["mfma_bf16"]["measured"] * 8.0 / 24.0)
+    if "mixed_c64" in out:
+        out["mixed_c64"]["roofline"] = with_measured_peak(out["mixed_c64"]["roofline"], pk["mfma_f32"]["measured"])
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)

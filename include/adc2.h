@@ -293,6 +293,31 @@ typedef struct {
 ADC2_API adc2_status adc2_profile(adc2_handle h, int enable);
 ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
 
+/*
+ * Peak probes: microbenchmarks of the device rates that roofline fractions
+ * are quoted against, run on the device current for the calling thread, on
+ * `stream`.  Not part of the method; a measurement utility.
+ *   ADC2_PEAK_MFMA_F64   v_mfma_f64_16x16x4_f64 (FP64 sigma GEMMs), TFLOP/s
+ *   ADC2_PEAK_MFMA_F32   v_mfma_f32_16x16x4_f32 (complex64 GEMMs), TFLOP/s
+ *   ADC2_PEAK_MFMA_BF16  v_mfma_f32_16x16x32_bf16 (split-BF16 GEMMs), TFLOP/s
+ *   ADC2_PEAK_VALU_F64   v_fma_f64 (folded-solver moments), TFLOP/s
+ *   ADC2_PEAK_HBM_READ   streaming 16-byte loads over `bytes`, GB/s
+ *   ADC2_PEAK_HBM_COPY   copy of `bytes` (read + write both counted), GB/s
+ * bytes: buffer size of the HBM probes (0 = 2 GiB; 64 MiB .. 64 GiB),
+ * ignored otherwise.  reps: timed launches (1..1000) after one warm-up; the
+ * best launch (HIP events) is returned in *rate (host).  The probe allocates
+ * and frees its own device buffers (up to 2 x bytes) and synchronises the
+ * stream.  Errors: ADC2_ERR_ARG for a NULL rate, unknown kind or sizes out of
+ * range; ADC2_ERR_OOM / ADC2_ERR_HIP from the runtime.
+ */
+#define ADC2_PEAK_MFMA_F64 0
+#define ADC2_PEAK_MFMA_F32 1
+#define ADC2_PEAK_MFMA_BF16 2
+#define ADC2_PEAK_VALU_F64 3
+#define ADC2_PEAK_HBM_READ 4
+#define ADC2_PEAK_HBM_COPY 5
+ADC2_API adc2_status adc2_peak_probe(int kind, size_t bytes, int reps, double* rate, void* stream);
+
 /* Release everything the handle owns.  NULL is accepted. */
 ADC2_API adc2_status adc2_destroy(adc2_handle h);
 

@@ -47,6 +47,12 @@ ADC2_SOLVER_FULL = 0
 ADC2_SOLVER_FOLDED = 1
 ADC2_BATCH_ROUNDS = 0
 ADC2_BATCH_STREAMS = 1
+ADC2_PEAK_MFMA_F64 = 0
+ADC2_PEAK_MFMA_F32 = 1
+ADC2_PEAK_MFMA_BF16 = 2
+ADC2_PEAK_VALU_F64 = 3
+ADC2_PEAK_HBM_READ = 4
+ADC2_PEAK_HBM_COPY = 5
 
 STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}
@@ -54,7 +60,7 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
-           "adc2_davidson_batch"]
+           "adc2_davidson_batch", "adc2_peak_probe"]
 
 
 class DavOpts(ctypes.Structure):
@@ -105,6 +111,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2604_27451_amd.build` "
                           "(there is no CPU fallback)")
+    # torch first: its HIP runtime (libamdhip64.so.7) is then the one the
+    # library's dependency of that name resolves to.  Loaded the other way
+    # round, the process holds two HIP and HSA runtimes and the library's
+    # own finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.adc2_setup.argtypes = [vp, vp, i, i, i, i, i, vp, ctypes.POINTER(vp)]
@@ -140,6 +151,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
+    lib.adc2_peak_probe.argtypes = [i, ctypes.c_size_t, i, ctypes.POINTER(d), vp]
+    lib.adc2_peak_probe.restype = i
     lib.adc2_destroy.argtypes = [vp]
     lib.adc2_destroy.restype = i
     lib.adc2_last_error.argtypes = []
@@ -422,6 +435,14 @@ def adc2_kernel_stats(h: Handle):
         raise Adc2Error(ADC2_ERR_ARG, "adc2_kernel_stats: NULL handle")
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops}
             for i in range(n)}
+
+
+def adc2_peak_probe(kind: int, nbytes: int = 0, reps: int = 5, stream=None) -> float:
+    """Measured device rate for one of the ADC2_PEAK_* kinds: TFLOP/s for the
+    MFMA and FMA probes, GB/s for the HBM probes."""
+    r = ctypes.c_double()
+    _check(load().adc2_peak_probe(kind, nbytes, reps, ctypes.byref(r), _stream_ptr(stream)), "adc2_peak_probe")
+    return r.value
 
 
 def adc2_destroy(h: Handle):

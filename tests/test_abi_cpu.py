@@ -63,6 +63,14 @@ def test_argument_errors_without_gpu(lib):
     g = (ctypes.c_double * 1)(1.0)
     assert lib.adc2_omega_backward(None, 1, None, g, None, None, None) == A.ADC2_ERR_ARG
     assert "NULL" in A.adc2_last_error()
+    # peak probes: argument checks come before any device call
+    r = ctypes.c_double(7.0)
+    assert lib.adc2_peak_probe(0, 0, 1, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_peak_probe(9, 0, 1, ctypes.byref(r), None) == A.ADC2_ERR_ARG and r.value == 0.0
+    assert "unknown kind" in A.adc2_last_error()
+    assert lib.adc2_peak_probe(A.ADC2_PEAK_MFMA_F64, 0, 0, ctypes.byref(r), None) == A.ADC2_ERR_ARG
+    assert lib.adc2_peak_probe(A.ADC2_PEAK_HBM_READ, 1 << 20, 1, ctypes.byref(r), None) == A.ADC2_ERR_ARG
+    assert "64 MiB" in A.adc2_last_error()
 
 
 def test_binding_has_no_cpu_fallback(tmp_path):
@@ -108,3 +116,18 @@ def test_batch_argument_errors_without_gpu(lib):
     assert lib.adc2_davidson_batch(2, hs3, 2, None, 0, None, None, None, None) == A.ADC2_ERR_ARG
     assert lib.adc2_davidson_batch(2, hs3, 2, None, 7, om, None, None, None) == A.ADC2_ERR_ARG
     assert "mode" in A.adc2_last_error()
+
+
+def test_one_hip_runtime_in_the_process():
+    """load() binds the library to torch's HIP runtime even when nothing else
+    imported torch first: a second runtime in the process (the library's
+    dependency resolved to another copy) sees no device."""
+    import subprocess
+    import sys
+    code = ("import paper_2604_27451_amd as A; A.load(); "
+            "m = open('/proc/self/maps').read().splitlines(); "
+            "print(len({l.split()[-1] for l in m if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
