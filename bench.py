@@ -158,6 +158,14 @@ def run_peaks(args, A):
                       "peaks": peaks}), flush=True)
 
 
+def heuristic_ysplit(s, m):
+    """The library's size rule for the Y-build K-split (used when no tuned
+    choice is set): enough splits for ~16 workgroups per CU, at most 8."""
+    bt = 128
+    ytiles = -(-s.naux // bt) * -(-(m * s.nc * s.nv) // bt)
+    return max(1, min(8, -(-(16 * 256) // ytiles)))
+
+
 def run_batch(args, A, np, torch):
     """Batching form: the eight systems of the batch workload, 16 roots each,
     complex64 heavy contractions with the folded solver and an FP64 Rayleigh
@@ -183,9 +191,29 @@ def run_batch(args, A, np, torch):
         A.adc2_set_precision(h, A.ADC2_C64)
         return wp, rn
 
+    # autotuner (untimed, one-time per shape): Y-build K-split of every system at m = nroots; later
+    # calls on a handle of the same shape take the choice from the in-process cache
+    tune = []
+    if not args.no_autotune:
+        for q, d in enumerate(data):
+            h = A.adc2_setup(*d, prec=A.ADC2_C64)
+            ta = time.perf_counter()
+            r = A.adc2_autotune(h, nroots)
+            r["s"] = round(time.perf_counter() - ta, 3)
+            r["heuristic_ysplit"] = h_ysplit = heuristic_ysplit(systems[q], nroots)
+            tune.append(r)
+            h.close()
+            print(f"[bench] tune system {q}: K-split {r['ysplit']} (heuristic {h_ysplit}), "
+                  + ", ".join(f"{k}: {v:.2f} ms" for k, v in r["ms"].items()), file=sys.stderr, flush=True)
+
+    def tuned(h):
+        if not args.no_autotune:
+            A.adc2_autotune(h, nroots)
+        return h
+
     # warm-up (untimed): one solve of the smallest system, so that no timed leg pays first-call costs
     qmin = min(range(len(data)), key=lambda q: systems[q].no * systems[q].nv ** 2)
-    h = A.adc2_setup(*data[qmin], prec=A.ADC2_C64)
+    h = tuned(A.adc2_setup(*data[qmin], prec=A.ADC2_C64))
     A.adc2_davidson(h, nroots, tol=tol, solver=fold)
     torch.cuda.synchronize()
     h.close()
@@ -194,7 +222,7 @@ def run_batch(args, A, np, torch):
     t4 = time.perf_counter()
     for q, d in enumerate(data):
         ta = time.perf_counter()
-        h = A.adc2_setup(*d, prec=A.ADC2_C64)
+        h = tuned(A.adc2_setup(*d, prec=A.ADC2_C64))
         w, X, inf = A.adc2_davidson(h, nroots, tol=tol, solver=fold, verbose=verbose)
         wp, rn = polish(h, X)
         torch.cuda.synchronize()
@@ -208,7 +236,7 @@ def run_batch(args, A, np, torch):
     for name, mode in (("rounds", A.ADC2_BATCH_ROUNDS), ("streams", A.ADC2_BATCH_STREAMS)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hs = A.adc2_setup_batch(data, A.ADC2_C64)
+        hs = [tuned(h) for h in A.adc2_setup_batch(data, A.ADC2_C64)]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         print(f"[bench] {name}: setup {t1 - t0:.2f}s", file=sys.stderr, flush=True)
@@ -249,6 +277,10 @@ def run_batch(args, A, np, torch):
         "sequential_per_system_s": [round(r["s"], 3) for r in seq],
         "sequential_iterations": [r["info"]["iters"] for r in seq],
         "omega_ha_polished": [list(r["wp"]) for r in seq],
+        "autotune": ({"m": nroots, "tune_s": round(sum(r["s"] for r in tune), 3),
+                      "systems": [{"ysplit": r["ysplit"], "heuristic_ysplit": r["heuristic_ysplit"],
+                                   "ms": {str(k): round(v, 3) for k, v in r["ms"].items()}} for r in tune]}
+                     if tune else None),
     }
     print(json.dumps(out), flush=True)
 
@@ -366,6 +398,8 @@ def main():
                          "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
                          "one after the other; prints its own JSON line.  peaks: the device-rate "
                          "microbenchmarks the rooflines are quoted against")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch workload: keep the size rule for the Y-build K-split instead of adc2_autotune")
     ap.add_argument("--tol-batch", type=float, default=5e-5,
                     help="complex64 residual tolerance of the batch workload (its largest system's noise floor "
                          "is ~2e-5)")

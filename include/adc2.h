@@ -294,6 +294,33 @@ ADC2_API adc2_status adc2_profile(adc2_handle h, int enable);
 ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
 
 /*
+ * Autotuner of the sigma build's dominant GEMM, the Y-build (M12 half of the
+ * sigma, Implementation section): its K-split count decides how many
+ * workgroups a launch has against extra partial traffic and a summation
+ * pass.  adc2_autotune times the Y-build of h's current precision form at
+ * block size m for the K-splits 1, 2, 3, 4, 6, 8, 12, 16 (those whose partial
+ * workspace stays under 8 GiB and that leave each split at least 64 of the
+ * no*nv contraction indices), one warm-up and three timed launches each, and
+ * fixes the fastest for h (for every later block size too).  A choice already
+ * made for the same (device, nc, no, nv, naux, m, form) in this process, or
+ * listed in the text file named by the environment variable ADC2_TUNE_CACHE,
+ * is reused without timing; new choices are appended to that file.
+ * Results of sigma builds differ between K-splits only by rounding.
+ * info (host, nullable) receives the choice, the candidates timed and their
+ * best times in ms (ncand = 0 and from_cache = 1 for a cached choice).
+ * Synchronises the stream; must not overlap other calls on h.  Errors:
+ * ADC2_ERR_ARG (NULL handle, m out of 1..4096), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ */
+typedef struct {
+  int ysplit;
+  int ncand;
+  int cand[8];
+  double ms[8];
+  int from_cache;
+} adc2_tune_info;
+ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_info* info, void* stream);
+
+/*
  * Peak probes: microbenchmarks of the device rates that roofline fractions
  * are quoted against, run on the device current for the calling thread, on
  * `stream`.  Not part of the method; a measurement utility.

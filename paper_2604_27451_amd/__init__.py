@@ -60,13 +60,18 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
-           "adc2_davidson_batch", "adc2_peak_probe"]
+           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune"]
 
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("solver", ctypes.c_int)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("ysplit", ctypes.c_int), ("ncand", ctypes.c_int), ("cand", ctypes.c_int * 8),
+                ("ms", ctypes.c_double * 8), ("from_cache", ctypes.c_int)]
 
 
 class Mol(ctypes.Structure):
@@ -151,6 +156,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
+    lib.adc2_autotune.argtypes = [vp, i, ctypes.POINTER(TuneInfo), vp]
+    lib.adc2_autotune.restype = i
     lib.adc2_peak_probe.argtypes = [i, ctypes.c_size_t, i, ctypes.POINTER(d), vp]
     lib.adc2_peak_probe.restype = i
     lib.adc2_destroy.argtypes = [vp]
@@ -435,6 +442,15 @@ def adc2_kernel_stats(h: Handle):
         raise Adc2Error(ADC2_ERR_ARG, "adc2_kernel_stats: NULL handle")
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops}
             for i in range(n)}
+
+
+def adc2_autotune(h: Handle, m: int, stream=None) -> dict:
+    """Times the Y-build K-split candidates of h at block size m and fixes the
+    fastest; returns {"ysplit", "from_cache", "ms": {split: ms}}."""
+    info = TuneInfo()
+    _check(load().adc2_autotune(h.ptr, m, ctypes.byref(info), _stream_ptr(stream)), "adc2_autotune")
+    return {"ysplit": info.ysplit, "from_cache": bool(info.from_cache),
+            "ms": {info.cand[c]: info.ms[c] for c in range(info.ncand)}}
 
 
 def adc2_peak_probe(kind: int, nbytes: int = 0, reps: int = 5, stream=None) -> float:

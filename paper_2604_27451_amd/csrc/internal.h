@@ -73,6 +73,7 @@ struct adc2_handle_s {
   double2* part = nullptr;  // split-K partials of the back-contraction
   int nsplit = 0;
   int ysplit = 1;           // K-splits of the Y-build GEMM
+  int ysplit_tuned = 0;     // K-split fixed by adc2_autotune (0: the size heuristic)
   int gemm3 = 0;            // heavy GEMMs: 0 = four-multiplication 128x128 (default), 1 = three-multiplication 128x64
   // folded-solver preconditioner (host, built on first use): per singles (K,c) the coupling
   // column norm sum_d |M21_{d,(Kc)}|^2 and its |M21|^2-weighted mean doubles energy
@@ -120,6 +121,11 @@ adc2_status ensure_ws_b3(adc2_handle h, int m);
 adc2_status ensure_ws(adc2_handle h, int m);
 adc2_status unpack_weighted(adc2_handle h, int m, const double2* xin, const double* wts, hipStream_t st);
 adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
+// Y-build GEMM of one request in the handle's form (h->ysplit partials) and the partial sum
+adc2_status ybuild_launch(adc2_handle h, int m, hipStream_t st);
+adc2_status ybuild_sum(adc2_handle h, int m, hipStream_t st);
+// bytes of an R x K operand in the blocked split-BF16 layout
+long split_bytes(long R, long K);
 
 // ---- setup pieces reused by the adjoint (k_setup.hip) ----
 // W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.

@@ -442,7 +442,7 @@ __global__ void k_split_pack(const float2* __restrict__ src, long gstride, long 
   }
 }
 
-static long split_bytes(long R, long K) { return (long)cdiv(R, BT) * cdiv(K, BKB) * BLOCK_BYTES; }
+long split_bytes(long R, long K) { return (long)cdiv(R, BT) * cdiv(K, BKB) * BLOCK_BYTES; }
 
 static adc2_status split_pack(const float2* src, long gstride, long ld, int inner, long R, long K, __bf16* dst,
                               hipStream_t st) {
@@ -929,6 +929,7 @@ adc2_status ensure_ws(adc2_handle h, int m) {
     const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, BT);
     int ys = (int)std::max<long>(1, std::min<long>(8, (16L * 256 + ytiles - 1) / ytiles));
     if (const char* v = getenv("ADC2_YSPLIT")) ys = std::max(1, std::min(16, atoi(v)));
+    if (h->ysplit_tuned > 0) ys = h->ysplit_tuned;   // adc2_autotune's choice
     h->ysplit = ys;
   }
   ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * d.naux * d.nv * h->ysplit));
@@ -994,6 +995,42 @@ adc2_status sigma_parts(adc2_handle h, int m, const double2* xin, double2* sout,
 adc2_status sigma_call(adc2_handle h, int m, const double2* xin, double2* sout, int parts, hipStream_t st) {
   if (h->sigma_hook) return h->sigma_hook(m, xin, sout, parts, st);
   return sigma_parts(h, m, xin, sout, parts, st);
+}
+
+// The Y-build GEMM of one request (m vectors) in the handle's precision form,
+// h->ysplit K-split partials into h->Y.
+adc2_status ybuild_launch(adc2_handle h, int m, hipStream_t st) {
+  const Dims& d = h->d;
+  const int rows = m * d.nc;
+  const int ys = h->ysplit;
+  if (h->prec != ADC2_FP64) {
+    const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
+    dim3 grid((unsigned)nblk, ys);
+    if (h->prec == ADC2_BF16X3)
+      k_ygemm_b3<<<grid, 512, 0, st>>>((const __bf16*)h->LvTB, (const __bf16*)h->RB, rows, d.no, d.nv, d.naux, h->Y);
+    else
+      k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
+  } else {
+    const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, h->gemm3 ? BT3N : BT);
+    dim3 grid((unsigned)nblk, ys);
+    if (h->gemm3)
+      k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
+    else
+      k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
+  }
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
+// Sum of the Y-build's K-split partials into the first one.
+adc2_status ybuild_sum(adc2_handle h, int m, hipStream_t st) {
+  const Dims& d = h->d;
+  if (h->ysplit > 1) {
+    const long len = (long)m * d.nc * d.naux * d.nv;
+    k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, h->ysplit);
+    ADC2_CHECK_LAUNCH();
+  }
+  return ADC2_OK;
 }
 
 // Launch the grouped heavy GEMM (Y-build if ybuild, else sigma2) of the
@@ -1120,33 +1157,8 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
   for (int q = 0; q < nreq; ++q) {
     if (!dbl[q]) continue;
     adc2_handle h = rq[q].h;
-    const Dims& d = h->d;
-    const int rows = rq[q].m * d.nc;
-    const int ys = h->ysplit;
-    if (!is_grouped(q)) {
-      if (h->prec != ADC2_FP64) {
-        const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, BT);
-        dim3 grid((unsigned)nblk, ys);
-        if (h->prec == ADC2_BF16X3)
-          k_ygemm_b3<<<grid, 512, 0, st>>>((const __bf16*)h->LvTB, (const __bf16*)h->RB, rows, d.no, d.nv, d.naux,
-                                           h->Y);
-        else
-          k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
-      } else {
-        const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, h->gemm3 ? BT3N : BT);
-        dim3 grid((unsigned)nblk, ys);
-        if (h->gemm3)
-          k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
-        else
-          k_ygemm<false><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
-      }
-      ADC2_CHECK_LAUNCH();
-    }
-    if (ys > 1) {
-      const long len = (long)rows * d.naux * d.nv;
-      k_ysum<<<grid_for(len), 256, 0, st>>>(h->Y, len, ys);
-      ADC2_CHECK_LAUNCH();
-    }
+    if (!is_grouped(q) && (rc = ybuild_launch(h, rq[q].m, st)) != ADC2_OK) return rc;
+    if ((rc = ybuild_sum(h, rq[q].m, st)) != ADC2_OK) return rc;
   }
   if ((rc = mark(2)) != ADC2_OK) return rc;
   for (int q = 0; q < nreq; ++q) {

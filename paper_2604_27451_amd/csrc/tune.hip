@@ -1,0 +1,173 @@
+// tune.hip -- autotuner of the sigma build's dominant GEMM.
+//
+// The Y-build contracts K = no*nv per output tile; its K-split (partials
+// summed afterwards) decides how many workgroups one launch has, against
+// the cost of the extra partial traffic and the summation.  The best split
+// depends on the system's shape, the block size and the precision form, so
+// adc2_autotune times every candidate on the device and keeps the fastest.
+// Choices are cached per (device, shape, block size, form) for the process
+// and, if ADC2_TUNE_CACHE names a file, across processes (one text line per
+// key, appended after each tuning).
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "internal.h"
+
+namespace adc2 {
+namespace {
+
+std::mutex tune_mu;
+std::map<std::string, int> tune_mem;   // key -> K-split
+bool tune_file_read = false;
+
+const int CANDS[] = {1, 2, 3, 4, 6, 8, 12, 16};
+constexpr int NCAND = sizeof(CANDS) / sizeof(CANDS[0]);
+constexpr double YMAX_BYTES = 8.0 * (1 << 30);   // Y partial workspace limit for the search
+
+std::string tune_key(adc2_handle h, int m) {
+  int dev = 0;
+  hipDeviceProp_t p;
+  std::string name = "gpu";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) name = p.gcnArchName;
+  for (char& c : name)
+    if (c == ' ') c = '_';
+  const Dims& d = h->d;
+  std::ostringstream k;
+  k << name << " nc=" << d.nc << " no=" << d.no << " nv=" << d.nv << " naux=" << d.naux << " m=" << m
+    << " prec=" << h->prec << " gemm3=" << h->gemm3;
+  return k.str();
+}
+
+// file lines: "<key> ysplit=<n>"
+void read_cache_file() {
+  if (tune_file_read) return;
+  tune_file_read = true;
+  const char* path = getenv("ADC2_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t p = line.rfind(" ysplit=");
+    if (p == std::string::npos) continue;
+    const int v = atoi(line.c_str() + p + 8);
+    if (v >= 1 && v <= 16) tune_mem[line.substr(0, p)] = v;
+  }
+}
+
+void append_cache_file(const std::string& key, int v) {
+  const char* path = getenv("ADC2_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << " ysplit=" << v << "\n";
+}
+
+adc2_status tfail(adc2_status s, const std::string& m) {
+  set_error("adc2_autotune: " + m);
+  return s;
+}
+
+}  // namespace
+}  // namespace adc2
+
+using namespace adc2;
+
+extern "C" ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_info* info, void* stream) {
+  if (!h) return tfail(ADC2_ERR_ARG, "NULL handle");
+  if (m < 1 || m > 4096) return tfail(ADC2_ERR_ARG, "m must be 1..4096");
+  hipStream_t st = (hipStream_t)stream;
+  adc2_tune_info loc;
+  adc2_tune_info& I = info ? *info : loc;
+  memset(&I, 0, sizeof(I));
+  const std::string key = tune_key(h, m);
+  {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    read_cache_file();
+    auto it = tune_mem.find(key);
+    if (it != tune_mem.end()) {
+      h->ysplit_tuned = it->second;
+      h->ws_m = 0;   // workspaces are re-sized for this split on the next sigma
+      I.ysplit = it->second;
+      I.from_cache = 1;
+      return ADC2_OK;
+    }
+  }
+  const Dims& d = h->d;
+  adc2_status rc;
+  if (h->prec != ADC2_FP64 && (rc = build_c64(h, st)) != ADC2_OK) return rc;
+  if (h->prec == ADC2_BF16X3 && (rc = build_b3(h, st)) != ADC2_OK) return rc;
+  const double ybytes = 16.0 * m * d.nc * (double)d.naux * d.nv;   // one partial of Y
+  const long kdim = (long)d.no * d.nv;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ADC2_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return tfail(ADC2_ERR_HIP, "hipEventCreate");
+  }
+  const int saved = h->ysplit_tuned;
+  int best = 0;
+  double best_ms = 1e300;
+  rc = ADC2_OK;
+  for (int c = 0; c < NCAND && rc == ADC2_OK; ++c) {
+    const int ys = CANDS[c];
+    if (ys > 1 && (ys * ybytes > YMAX_BYTES || (long)ys * 64 > kdim)) continue;
+    h->ysplit_tuned = ys;
+    h->ws_m = 0;
+    if ((rc = ensure_ws(h, m)) != ADC2_OK) break;
+    if (h->prec == ADC2_BF16X3 && (rc = ensure_ws_b3(h, m)) != ADC2_OK) break;
+    // defined operands (the timing does not depend on their values)
+    const size_t zb = (h->prec == ADC2_FP64 ? sizeof(double2) : sizeof(float2)) * (size_t)m * d.nc * d.no * d.nv * d.nv;
+    if (hipMemsetAsync(h->Zb, 0, zb, st) != hipSuccess) {
+      rc = tfail(ADC2_ERR_HIP, "hipMemsetAsync");
+      break;
+    }
+    if (h->prec == ADC2_BF16X3 &&
+        hipMemsetAsync(h->RB, 0, split_bytes((long)m * d.nc * d.nv, (long)d.no * d.nv), st) != hipSuccess) {
+      rc = tfail(ADC2_ERR_HIP, "hipMemsetAsync");
+      break;
+    }
+    double tmin = 1e300;
+    for (int r = 0; r < 4 && rc == ADC2_OK; ++r) {   // one warm-up, three timed
+      if (hipEventRecord(e0, st) != hipSuccess) rc = tfail(ADC2_ERR_HIP, "hipEventRecord");
+      if (rc == ADC2_OK) rc = ybuild_launch(h, m, st);
+      if (rc == ADC2_OK) rc = ybuild_sum(h, m, st);
+      if (rc == ADC2_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = tfail(ADC2_ERR_HIP, "timing events");
+      float ms = 0.f;
+      if (rc == ADC2_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = tfail(ADC2_ERR_HIP, "hipEventElapsedTime");
+      if (rc == ADC2_OK && r > 0) tmin = std::min(tmin, (double)ms);
+    }
+    if (rc != ADC2_OK) break;
+    if (I.ncand < 8) {
+      I.cand[I.ncand] = ys;
+      I.ms[I.ncand] = tmin;
+      ++I.ncand;
+    }
+    if (tmin < best_ms) {
+      best_ms = tmin;
+      best = ys;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != ADC2_OK || best == 0) {
+    h->ysplit_tuned = saved;
+    h->ws_m = 0;
+    return rc != ADC2_OK ? rc : tfail(ADC2_ERR_ARG, "no K-split candidate fits");
+  }
+  h->ysplit_tuned = best;
+  h->ws_m = 0;   // re-sized for the chosen split on the next sigma
+  I.ysplit = best;
+  {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_mem[key] = best;
+    append_cache_file(key, best);
+  }
+  return ADC2_OK;
+}
