@@ -80,6 +80,7 @@ typedef struct {
   int nguess;          /* initial guess vectors (0 -> 2k if k <= 8 else k)    */
   int verbose;         /* print one line per iteration to stderr              */
   int solver;          /* ADC2_SOLVER_FULL (0) or ADC2_SOLVER_FOLDED (1)      */
+  int follow;          /* 1: root following (full-space solver only), below  */
 } adc2_dav_opts;
 
 /* Eigensolvers of adc2_davidson.
@@ -146,6 +147,13 @@ ADC2_API adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, vo
  *   omega    host float64 [nroots], ascending.
  *   X        dev complex128 [nroots][dim] or NULL: normalised eigenvectors.
  *   info     host, may be NULL.
+ * Root following (opt->follow = 1, full-space solver): the root-specific
+ * Davidson the paper uses to keep each root matched to its guess (Hirao and
+ * Nakatsuji, cited in the Computational details).  Root j is, at every
+ * iteration, the Ritz pair whose vector overlaps most (|<g_j|x>|^2) with
+ * guess vector g_j, assigned greedily in decreasing order of overlap; omega
+ * and X are then in guess order, not ascending.  Needs guess with at least
+ * nroots vectors (ADC2_ERR_ARG otherwise, and with the folded solver).
  * Returns ADC2_ERR_NOCONV (with the best omega/X/info written) when max_iter
  * is reached; ADC2_ERR_NONFINITE when the iteration produced NaN/Inf.
  * Synchronises the stream.

@@ -66,7 +66,7 @@ EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_pr
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("solver", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("solver", ctypes.c_int), ("follow", ctypes.c_int)]
 
 
 class TuneInfo(ctypes.Structure):
@@ -248,9 +248,12 @@ def adc2_sigma(h: Handle, X, S=None, stream=None):
 
 
 def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, guess=None,
-                  want_vectors=True, verbose=0, stream=None, raise_on_noconv=True, solver=ADC2_SOLVER_FULL):
+                  want_vectors=True, verbose=0, stream=None, raise_on_noconv=True, solver=ADC2_SOLVER_FULL,
+                  follow=False):
+    """Eigenpairs of M.  follow=True: root j follows guess vector j (root-specific
+    Davidson; full-space solver; results in guess order)."""
     import torch
-    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver)
+    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver, 1 if follow else 0)
     info = DavInfo()
     omega = (ctypes.c_double * nroots)()
     X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None

@@ -342,12 +342,13 @@ namespace {
 
 struct DavWork {
   double2 *V = nullptr, *S = nullptr, *Xb = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr;
-  double2 *Vn = nullptr, *Sn = nullptr;
+  double2 *Vn = nullptr, *Sn = nullptr, *Ref = nullptr, *P = nullptr;
   double2 *G = nullptr, *Z = nullptr, *Gt = nullptr, *Ut = nullptr, *Cc = nullptr, *scratch = nullptr;
   double *theta = nullptr, *lam = nullptr, *npart = nullptr, *thact = nullptr;
   int *idx = nullptr, *count = nullptr;
   ~DavWork() {
     hipFree(V); hipFree(S); hipFree(Xb); hipFree(R); hipFree(T); hipFree(T2); hipFree(Vn); hipFree(Sn);
+    hipFree(Ref); hipFree(P);
     hipFree(G); hipFree(Z); hipFree(Gt); hipFree(Ut); hipFree(Cc); hipFree(scratch);
     hipFree(theta); hipFree(lam); hipFree(npart); hipFree(thact); hipFree(idx); hipFree(count);
   }
@@ -413,6 +414,9 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   nguess = (int)std::min<long>(nguess, d.ns);
   nguess = std::max(nguess, k);
   const int verbose = opt ? opt->verbose : 0;
+  const bool follow = opt && opt->follow != 0;
+  if (follow && (!guess || nguess < k))
+    return fail(ADC2_ERR_ARG, "adc2_davidson: root following needs at least nroots guess vectors");
   const int keep_max = std::min(std::min(2 * k, 32), max_sub - k);
   const int nblk = dav_nblk(dim);
 
@@ -438,6 +442,12 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   DAV_TRY(hipMalloc(&w.thact, sizeof(double) * 32));
   DAV_TRY(hipMalloc(&w.idx, sizeof(int) * LDG));
   DAV_TRY(hipMalloc(&w.count, sizeof(int)));
+  if (follow) {
+    // reference vectors of the followed roots: the first nroots guess vectors as given
+    DAV_TRY(hipMalloc(&w.Ref, sizeof(double2) * k * dim));
+    DAV_TRY(hipMalloc(&w.P, sizeof(double2) * LDG * LDG));
+    DAV_TRY(hipMemcpyAsync(w.Ref, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, st));
+  }
 
   double ms_sigma = 0.0;
   int n_sigma = 0;
@@ -479,10 +489,65 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   int s = g;
 
   std::vector<double> th(LDG), np(32 * nblk), rn(k);
+  std::vector<double2> hz((size_t)LDG * LDG), hp((size_t)LDG * LDG);
+  // Root following (root-specific Davidson of Hirao and Nakatsuji): root j is
+  // the Ritz pair whose vector overlaps most with reference vector j, taken
+  // greedily in decreasing order of overlap; the chosen columns of Z (and
+  // their Ritz values) are moved to the front in reference order, so the
+  // residual, restart and convergence steps below act on the followed roots.
+  auto follow_select = [&](int s_) -> adc2_status {
+    if ((rc = dav_gram(w.Ref, k, w.V, s_, dim, w.P, LDG, w.scratch, st)) != ADC2_OK) return rc;
+    DAV_TRY(hipMemcpyAsync(hz.data(), w.Z, sizeof(double2) * LDG * s_, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipMemcpyAsync(hp.data(), w.P, sizeof(double2) * LDG * k, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipMemcpyAsync(th.data(), w.theta, sizeof(double) * s_, hipMemcpyDeviceToHost, st));
+    DAV_TRY(hipStreamSynchronize(st));
+    std::vector<double> ov((size_t)k * s_);
+    for (int j = 0; j < k; ++j)
+      for (int l = 0; l < s_; ++l) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < s_; ++i) {
+          const double2 a = hp[(size_t)j * LDG + i], z = hz[(size_t)i * LDG + l];
+          re += a.x * z.x - a.y * z.y;
+          im += a.x * z.y + a.y * z.x;
+        }
+        ov[(size_t)j * s_ + l] = re * re + im * im;
+      }
+    std::vector<int> sel(k, -1);
+    std::vector<char> used(s_, 0);
+    for (int n = 0; n < k; ++n) {
+      int bj = -1, bl = -1;
+      double best = -1.0;
+      for (int j = 0; j < k; ++j) {
+        if (sel[j] >= 0) continue;
+        for (int l = 0; l < s_; ++l)
+          if (!used[l] && ov[(size_t)j * s_ + l] > best) {
+            best = ov[(size_t)j * s_ + l];
+            bj = j;
+            bl = l;
+          }
+      }
+      sel[bj] = bl;
+      used[bl] = 1;
+    }
+    std::vector<int> order(sel);
+    for (int l = 0; l < s_; ++l)
+      if (!used[l]) order.push_back(l);
+    std::vector<double2> z2((size_t)LDG * s_);
+    std::vector<double> th2(s_);
+    for (int c = 0; c < s_; ++c) {
+      th2[c] = th[order[c]];
+      for (int i = 0; i < s_; ++i) z2[(size_t)i * LDG + c] = hz[(size_t)i * LDG + order[c]];
+    }
+    DAV_TRY(hipMemcpyAsync(w.Z, z2.data(), sizeof(double2) * LDG * s_, hipMemcpyHostToDevice, st));
+    DAV_TRY(hipMemcpyAsync(w.theta, th2.data(), sizeof(double) * s_, hipMemcpyHostToDevice, st));
+    DAV_TRY(hipStreamSynchronize(st));   // host copies consumed before they go out of scope
+    return ADC2_OK;
+  };
   int it = 0;
   bool conv = false, nonfinite = false, stalled = false;
   for (it = 1; it <= max_iter; ++it) {
     if ((rc = dav_heevj(w.G, s, LDG, w.theta, w.Z, LDG, st)) != ADC2_OK) return rc;
+    if (follow && (rc = follow_select(s)) != ADC2_OK) return rc;
     if ((rc = dav_residual(w.V, w.S, s, w.Z, LDG, w.theta, k, dim, w.Xb, w.R, w.npart, nblk, st)) != ADC2_OK)
       return rc;
     DAV_TRY(hipMemcpyAsync(th.data(), w.theta, sizeof(double) * s, hipMemcpyDeviceToHost, st));

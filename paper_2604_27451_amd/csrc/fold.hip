@@ -402,6 +402,10 @@ static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
 
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
                           void* Xout, adc2_dav_info* info, hipStream_t st) {
+  if (opt && opt->follow) {
+    set_error("adc2_davidson: root following is provided by the full-space solver only");
+    return ADC2_ERR_ARG;
+  }
   const Dims& dd = h->d;
   const long ns = dd.ns, nd = dd.nd, dim = dd.dim;
   const double tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;

@@ -8,7 +8,7 @@ sign, a misplaced conjugate, a transposed operand):
       coupling, zeroth-order doubles block.
   P2  exact diagonalisation of the explicit matrix vs the oracle Davidson
       and vs the elimination of the diagonal doubles block (roots below
-      the doubles threshold).
+      the doubles threshold); the root-following selection rule.
   P3  Hermiticity, sigma linearity, matrix-free sigma == explicit matrix.
   P4  MP2 closed form vs the textbook closed-shell RMP2 formula.
   P5  nonrelativistic limit: real M, singlet/triplet multiplets, CIS limit
@@ -89,6 +89,27 @@ def test_p2_davidson_vs_exact():
     R = X @ M.T - w_dv[:, None] * X
     assert torch.linalg.vector_norm(R, dim=1).max().item() < 1e-8
     assert torch.allclose(X.conj() @ X.T, torch.eye(4, dtype=O.C128), atol=1e-10)
+
+
+def test_p2_root_following_selection_rule():
+    """roots_following picks, per reference, the eigenpair of largest overlap,
+    greedily without reuse.  Hand-made 4x4 case: a diagonal matrix, so the
+    eigenvectors are the unit vectors (no eigensolver arithmetic involved)."""
+    M = torch.diag(torch.tensor([1.0, 2.0, 3.0, 4.0], dtype=O.C128))
+    refs = torch.tensor([[0.1, 0.0, 0.9, 0.2],      # -> eigenvalue 3 (overlap 0.81)
+                         [0.0, 0.0, 0.8, 0.5],      # wants 3 too (0.64) but loses it -> 4 (0.25)
+                         [0.6, 0.5, 0.0, 0.0]], dtype=O.C128)   # -> 1 (0.36)
+    w, X = O.roots_following(M, refs)
+    assert w.tolist() == [3.0, 4.0, 1.0]
+    assert torch.equal(X.abs(), torch.eye(4, dtype=torch.float64)[:, [2, 3, 0]])
+    # exact eigenvectors of an ADC matrix as references give those eigenpairs back in reference order
+    s = make_system(1, 2, 5, 12, seed=4)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    Mx = a.matrix()
+    wn, vn = np.linalg.eigh(Mx.numpy())
+    pick = [5, 1, 8]
+    w2, _ = O.roots_following(Mx, torch.from_numpy(vn[:, pick].T.copy()))
+    assert np.abs(w2.numpy() - wn[pick]).max() < 1e-10
 
 
 def test_p2_folded_roots_vs_exact():
