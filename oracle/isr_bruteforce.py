@@ -164,6 +164,38 @@ class FockSpace:
         return outM, np.array(outE), resid
 
 
+def density_taylor(L, eps, nocc, nterms=3, degree=10, npts=17, lam_max=0.5):
+    """Taylor coefficients at lambda = 0 of the exact ground-state one-particle
+    density gamma_pq(lambda) = <Psi0(lambda)| a+_p a_q |Psi0(lambda)> (Psi0
+    normalised), read off by the same Chebyshev least-squares fit as the ISR
+    matrix.  Returns ([gamma^(0), gamma^(1), ...], fit residual)."""
+    fs = FockSpace(L, eps, nocc)
+    n = fs.n
+    k = np.arange(npts)
+    lams = lam_max * np.cos(np.pi * (k + 0.5) / npts)
+    G = []
+    for lam in lams:
+        _, psi, _ = fs.ground(lam)
+        g = np.empty((n, n), dtype=np.complex128)
+        for p in range(n):
+            for q in range(n):
+                g[p, q] = np.conj(psi) @ (fs.ad[p] @ (fs.a[q] @ psi))
+        G.append(g)
+    G = np.array(G)
+    x = lams / lam_max
+    Vm = np.polynomial.chebyshev.chebvander(x, degree)
+    coef = np.linalg.lstsq(Vm, G.reshape(npts, -1), rcond=None)[0]
+    resid = np.abs(Vm @ coef - G.reshape(npts, -1)).max()
+    out = [np.zeros((n, n), dtype=np.complex128) for _ in range(nterms)]
+    for d in range(degree + 1):
+        e = np.zeros(degree + 1)
+        e[d] = 1.0
+        mono = np.polynomial.chebyshev.cheb2poly(e)
+        for t in range(min(nterms, mono.size)):
+            out[t] = out[t] + (mono[t] / lam_max ** t) * coef[d].reshape(n, n)
+    return out, resid
+
+
 def _sym_orth(P):
     S = np.conj(P.T) @ P
     w, U = np.linalg.eigh(S)

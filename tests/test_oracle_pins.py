@@ -17,6 +17,9 @@ sign, a misplaced conjugate, a transposed operand):
       permutation of spinors inside a block, uniform shift of energies.
   P8  Hellmann-Feynman gradient vs central finite differences and the
       scaling identity.
+  FNS the MP2 virtual density (Eq. 15) vs the second-order coefficient of
+      the exact ground-state density; natural-spinor transform with nothing
+      dropped leaves the ADC roots and the MP2 energy unchanged.
 """
 import math
 
@@ -26,7 +29,7 @@ import torch
 
 from synth import make_system, make_spin_blocked
 from oracle import adc2 as O
-from oracle.isr_bruteforce import adc2_blocks
+from oracle.isr_bruteforce import adc2_blocks, density_taylor
 
 torch.set_num_threads(min(8, torch.get_num_threads()))
 
@@ -299,3 +302,43 @@ def test_p8_gradient_fd_and_scaling():
     rhs = (2 * (x1.conj() @ M1 @ x1).real + 4 * (x1.conj() @ M2 @ x1).real
            + 4 * (x1.conj() @ (M21.conj().T @ x2)).real)
     assert abs(lhs - float(rhs)) < 1e-10 * max(1.0, abs(lhs))
+
+
+# ---------------------------------------------------------------- FNS
+@pytest.mark.parametrize("shape,seed,sigma", [((1, 2, 3), 5, 0.12), ((2, 2, 3), 7, 0.15)])
+def test_fns_mp2_density_bruteforce(shape, seed, sigma):
+    """Eq. 15 is the lambda^2 coefficient of the exact ground-state density:
+    D_ab = <Psi0| a+_b a_a |Psi0>^(2) over virtual a, b (first order vanishes)."""
+    s = make_system(*shape, naux=6, seed=seed, sigma=sigma)
+    L, e, sp = _tensors(s)
+    D = O.mp2_density_vv(L, e, sp).numpy()
+    (g0, g1, g2), resid = density_taylor(s.L, s.eps, sp.o)
+    assert resid < 1e-9
+    o = sp.o
+    assert np.abs(g1).max() < 1e-9
+    assert np.abs(D - g2[o:, o:].T).max() <= 1e-7 * np.abs(D).max()
+    assert np.abs(D - D.conj().T).max() < 1e-15 and np.linalg.eigvalsh(D).min() > -1e-15
+
+
+def test_fns_keep_all_is_a_rotation():
+    """With every natural virtual kept, the semicanonical natural spinors are a
+    unitary rotation of the canonical virtuals with the same (diagonal) Fock
+    block, so the ADC roots and the MP2 energy do not change; with a threshold
+    the kept count is the number of occupations above it."""
+    s = make_system(2, 3, 8, 20, seed=17)
+    L, e, sp = _tensors(s)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    w0, _ = a.roots_exact(5)
+    Lp, ep, nvp, occ, U = O.frozen_natural_spinors(L, e, sp, -1.0)
+    assert nvp == s.nv
+    assert torch.allclose(U.conj().T @ U, torch.eye(s.nv, dtype=O.C128), atol=1e-12)
+    b = O.Adc2(Lp, ep, s.nc, s.no, nvp)
+    w1, _ = b.roots_exact(5)
+    assert torch.max(torch.abs(w1 - w0)).item() < 1e-10
+    assert abs(O.mp2_energy(Lp, ep, b.sp).item() - O.mp2_energy(L, e, sp).item()) < 1e-12
+    assert torch.allclose(Lp, Lp.conj().transpose(1, 2), atol=1e-14)
+    thr = float(occ[4] + occ[5]) / 2
+    Lt, et, nvt, _, Ut = O.frozen_natural_spinors(L, e, sp, thr)
+    assert nvt == 5 and Lt.shape == (s.naux, sp.o + 5, sp.o + 5)
+    F = Ut.conj().T @ torch.diag(e[sp.U]).to(O.C128) @ Ut
+    assert torch.allclose(F, torch.diag(et[sp.o:]).to(O.C128), atol=1e-12)
