@@ -302,6 +302,34 @@ ADC2_API adc2_status adc2_profile(adc2_handle h, int enable);
 ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
 
 /*
+ * adc2_fns -- frozen natural virtual spinors (paper, State-Average Frozen
+ * Natural Spinors: Eq. 15 and Eq. 17-20) from the MP2 virtual density of the
+ * system h was set up for:
+ *   D_ab = 1/2 sum_{c,i,j} <ac||ij><ij||bc> / (e^{ac}_{ij} e^{bc}_{ij}),
+ *   D V = V n;  V~ = natural virtuals with n >= threshold;
+ *   F_NS = V~^H diag(e_virt) V~ = Z~ e' Z~^H;  U = V~ Z~.
+ * The occupied spinors stay canonical.  The CIS(D) state average of Eq. 16
+ * is not included: D is its MP2 term.
+ *   L         dev complex128 [naux][n][n], the Cholesky vectors h was set up
+ *             with (the handle keeps only blocks of them).
+ *   threshold occupation cut (the paper's production value is 10^-4.5).
+ *   nv_out    host: the number nv' of kept virtual spinors.
+ *   occ       host float64 [nv] or NULL: all occupations n, descending.
+ *   L_out     dev complex128 with room for [naux][n'][n'] (n' = nc+no+nv' <=
+ *             n): the rotated vectors L'^P = W^H L^P W, W = blockdiag(1, U),
+ *             packed with stride n'; eps_out dev float64 with room for n':
+ *             occupied energies unchanged, then e'.  Both NULL: only nv_out
+ *             and occ are computed.
+ * A handle set up on (L_out, eps_out, nc, no, nv', naux) is the truncated
+ * problem; with every natural virtual kept its roots equal those of h.
+ * Synchronises the stream.  Errors: ADC2_ERR_ARG (NULL handle or nv_out,
+ * only one of L_out / eps_out, nothing above the threshold), ADC2_ERR_OOM,
+ * ADC2_ERR_HIP.  Work space: up to 2 GiB plus nv^2 and 2 n'n complex.
+ */
+ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double threshold, int* nv_out, double* occ,
+                              void* L_out, double* eps_out, void* stream);
+
+/*
  * Autotuner of the sigma build's dominant GEMM, the Y-build (M12 half of the
  * sigma, Implementation section): its K-split count decides how many
  * workgroups a launch has against extra partial traffic and a summation

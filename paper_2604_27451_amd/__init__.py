@@ -60,7 +60,7 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
-           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune"]
+           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns"]
 
 
 class DavOpts(ctypes.Structure):
@@ -156,6 +156,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
+    lib.adc2_fns.argtypes = [vp, vp, d, ctypes.POINTER(i), ctypes.POINTER(d), vp, vp, vp]
+    lib.adc2_fns.restype = i
     lib.adc2_autotune.argtypes = [vp, i, ctypes.POINTER(TuneInfo), vp]
     lib.adc2_autotune.restype = i
     lib.adc2_peak_probe.argtypes = [i, ctypes.c_size_t, i, ctypes.POINTER(d), vp]
@@ -445,6 +447,25 @@ def adc2_kernel_stats(h: Handle):
         raise Adc2Error(ADC2_ERR_ARG, "adc2_kernel_stats: NULL handle")
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops}
             for i in range(n)}
+
+
+def adc2_fns(h: Handle, L, threshold: float, stream=None):
+    """Frozen natural virtual spinors from the MP2 density of h's system.
+    Returns (L', eps', nv', occupations): the rotated Cholesky vectors and
+    energies of the truncated problem (nc, no, nv', naux)."""
+    import torch
+    _need(L, torch.complex128, "L")
+    n = h.nc + h.no + h.nv
+    occ = (ctypes.c_double * h.nv)()
+    nvp = ctypes.c_int()
+    Lout = torch.empty((h.naux * n * n,), dtype=torch.complex128, device="cuda")
+    eout = torch.empty((n,), dtype=torch.float64, device="cuda")
+    _check(load().adc2_fns(h.ptr, ctypes.c_void_p(L.data_ptr()), float(threshold), ctypes.byref(nvp), occ,
+                           ctypes.c_void_p(Lout.data_ptr()), ctypes.c_void_p(eout.data_ptr()), _stream_ptr(stream)),
+           "adc2_fns")
+    np_ = h.nc + h.no + nvp.value
+    Lp = Lout[:h.naux * np_ * np_].view(h.naux, np_, np_).clone()
+    return Lp, eout[:np_].clone(), nvp.value, list(occ)
 
 
 def adc2_autotune(h: Handle, m: int, stream=None) -> dict:

@@ -130,6 +130,9 @@ long split_bytes(long R, long K);
 // ---- setup pieces reused by the adjoint (k_setup.hip) ----
 // W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.
 adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st);
+// the same for a device list of pairs (k, l); epart holds npairs * nb(nb+1)/2 doubles, nb = ceil(nv / 64)
+adc2_status wbuild_pairs(adc2_handle h, const int2* dpairs, int npairs, double2* W, double* epart,
+                         hipStream_t st);
 
 // ---- large-tile FP64 GEMM of two K-major grouped operands (k_adjoint.hip) ----
 // C[s][i][j] = sum_{k in split s} A(k, i) B(k, j), A(k, i) = A[g*a_gstride + x + k*a_ld] with

@@ -457,6 +457,19 @@ static inline int grid_for(long n, int per = 256, int cap = 8192) {
 }
 
 // W for every occupied pair (k<l), in the same pair order as build_m11.
+// W for the npairs occupied pairs listed (device int2 (k, l), k < l) into
+// W[t][a][c]; epart: npairs * nb(nb+1)/2 doubles of MP2 energy partials.
+adc2_status wbuild_pairs(adc2_handle h, const int2* dpairs, int npairs, double2* W, double* epart,
+                         hipStream_t st) {
+  const Dims& d = h->d;
+  const int nb = (d.nv + TM - 1) / TM;
+  const long nwblk = (long)npairs * (nb * (nb + 1) / 2);
+  if (nwblk == 0) return ADC2_OK;
+  k_wbuild<<<(unsigned)nwblk, 256, 0, st>>>(h->Lvo, h->eps, dpairs, npairs, d.naux, d.nv, d.o, W, epart);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
 adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st) {
   const Dims& d = h->d;
   const int o = d.o, nv = d.nv;

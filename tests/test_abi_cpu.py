@@ -64,6 +64,9 @@ def test_argument_errors_without_gpu(lib):
     assert lib.adc2_omega_backward(None, 1, None, g, None, None, None) == A.ADC2_ERR_ARG
     assert "NULL" in A.adc2_last_error()
     assert lib.adc2_autotune(None, 1, None, None) == A.ADC2_ERR_ARG and "NULL" in A.adc2_last_error()
+    nvo = ctypes.c_int(5)
+    assert lib.adc2_fns(None, None, 1e-4, ctypes.byref(nvo), None, None, None, None) == A.ADC2_ERR_ARG
+    assert "NULL" in A.adc2_last_error()
     # peak probes: argument checks come before any device call
     r = ctypes.c_double(7.0)
     assert lib.adc2_peak_probe(0, 0, 1, None, None) == A.ADC2_ERR_ARG

@@ -1,0 +1,79 @@
+"""GPU parity of the frozen natural virtual spinors (adc2_fns, Eq. 15 and
+Eq. 17-20) against the oracle's mp2_density_vv / frozen_natural_spinors.
+
+Natural occupations and semicanonical energies must match element by
+element; the rotated Cholesky vectors are compared through |L'| (the phases
+of the new spinors are arbitrary) and through the ADC roots of the rotated
+problem: with every natural virtual kept they equal the canonical roots,
+with half of them kept they equal the oracle's roots of its own truncated
+problem.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_27451_amd as A
+from oracle import adc2 as O
+from synth import make_system
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def fns_case(s, thr, nroots):
+    L, e = dev(s.L), dev(s.eps)
+    h = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    Lp, ep, nvp, occ = A.adc2_fns(h, L, thr)
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    Lo, eo, nvo, occo, _ = O.frozen_natural_spinors(O.as_c128(s.L), O.as_f64(s.eps), sp, thr)
+    print(f"[case] fns {(s.nc, s.no, s.nv, s.naux)} threshold {thr:g}: kept {nvp} (oracle {nvo})", flush=True)
+    assert nvp == nvo
+    occ = np.array(occ)
+    eo_occ = occo.numpy()
+    assert np.abs(occ - eo_occ).max() <= 1e-12 * np.abs(eo_occ).max()
+    assert np.abs(ep.cpu().numpy() - eo.numpy()).max() < 1e-12 * np.abs(eo.numpy()).max()
+    dl = (Lp.cpu().abs() - Lo.abs()).abs().max().item()
+    print(f"  occupations, energies match; max ||L'| - |L'_oracle|| {dl:.2e}", flush=True)
+    assert dl < 1e-12
+    hp = A.adc2_setup(Lp, ep, s.nc, s.no, nvp, s.naux)
+    w, _, inf = A.adc2_davidson(hp, nroots, tol=1e-9)
+    hp.close()
+    h.close()
+    return np.array(w), (Lo, eo, nvo)
+
+
+def test_fns_keep_all_roots_unchanged():
+    s = make_system(2, 4, 14, 30, seed=41)
+    w, _ = fns_case(s, -1.0, 4)
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    w0, _ = a.roots_exact(4)
+    err = np.abs(w - w0.numpy()).max()
+    print(f"  roots in the rotated basis vs canonical {err:.2e} Ha", flush=True)
+    assert err < 1e-9
+
+
+def test_fns_truncated_matches_oracle():
+    s = make_system(2, 4, 16, 30, seed=43)
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    D = O.mp2_density_vv(O.as_c128(s.L), O.as_f64(s.eps), sp)
+    occ = np.sort(np.linalg.eigvalsh(D.numpy()))[::-1]
+    thr = float(np.sqrt(occ[7] * occ[8]))
+    w, (Lo, eo, nvo) = fns_case(s, thr, 4)
+    assert nvo == 8
+    b = O.Adc2(Lo, eo, s.nc, s.no, nvo)
+    wt, _ = b.roots_exact(4)
+    err = np.abs(w - wt.numpy()).max()
+    print(f"  truncated roots vs oracle {err:.2e} Ha", flush=True)
+    assert err < 1e-9
+
+
+def test_fns_occupations_only_and_errors():
+    s = make_system(1, 3, 10, 20, seed=5)
+    L, e = dev(s.L), dev(s.eps)
+    h = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    with pytest.raises(A.Adc2Error):
+        A.adc2_fns(h, L, 1e6)          # nothing above the threshold
+    h.close()
