@@ -164,6 +164,51 @@ class FockSpace:
         return outM, np.array(outE), resid
 
 
+def transition_taylor(L, eps, nocc, d, nterms=3, degree=10, npts=17, lam_max=0.5):
+    """Taylor coefficients at lambda = 0 of the modified transition moments
+    F_I(lambda) = <Psi~_I| D |Psi0> (Theory section: transition properties)
+    of the one-particle operator D = sum_pq d_pq a+_p a_q, over the
+    intermediate states [singles | doubles] of isr_matrix.  Returns
+    ([F^(0), F^(1), ...], fit residual)."""
+    fs = FockSpace(L, eps, nocc)
+    n = fs.n
+    dim = 1 << n
+    Dop = np.zeros((dim, dim), dtype=np.complex128)
+    for p in range(n):
+        for q in range(n):
+            if d[p][q] != 0:
+                Dop += d[p][q] * (fs.ad[p] @ fs.a[q])
+    singles, doubles = fs.excitations()
+    k = np.arange(npts)
+    lams = lam_max * np.cos(np.pi * (k + 0.5) / npts)
+    Fs = []
+    for lam in lams:
+        _, psi, _ = fs.ground(lam)
+        P1 = np.stack([fs.ad[a] @ (fs.a[i] @ psi) for (i, a) in singles], axis=1)
+        P2 = np.stack([fs.ad[a] @ (fs.ad[b] @ (fs.a[i] @ (fs.a[j] @ psi)))
+                       for (i, j, a, b) in doubles], axis=1)
+        P1 = P1 - np.outer(psi, np.conj(psi) @ P1)
+        T1 = _sym_orth(P1)
+        lower = np.concatenate([psi[:, None], T1], axis=1)
+        P2 = P2 - lower @ (np.conj(lower.T) @ P2)
+        T2 = _sym_orth(P2)
+        T = np.concatenate([T1, T2], axis=1)
+        Fs.append(np.conj(T.T) @ (Dop @ psi))
+    Fs = np.array(Fs)
+    x = lams / lam_max
+    Vm = np.polynomial.chebyshev.chebvander(x, degree)
+    coef = np.linalg.lstsq(Vm, Fs, rcond=None)[0]
+    resid = np.abs(Vm @ coef - Fs).max()
+    out = [np.zeros(Fs.shape[1], dtype=np.complex128) for _ in range(nterms)]
+    for dd in range(degree + 1):
+        e = np.zeros(degree + 1)
+        e[dd] = 1.0
+        mono = np.polynomial.chebyshev.cheb2poly(e)
+        for t in range(min(nterms, mono.size)):
+            out[t] = out[t] + (mono[t] / lam_max ** t) * coef[dd]
+    return out, resid, singles, doubles
+
+
 def density_taylor(L, eps, nocc, nterms=3, degree=10, npts=17, lam_max=0.5):
     """Taylor coefficients at lambda = 0 of the exact ground-state one-particle
     density gamma_pq(lambda) = <Psi0(lambda)| a+_p a_q |Psi0(lambda)> (Psi0

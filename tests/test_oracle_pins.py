@@ -17,6 +17,9 @@ sign, a misplaced conjugate, a transposed operand):
       permutation of spinors inside a block, uniform shift of energies.
   P8  Hellmann-Feynman gradient vs central finite differences and the
       scaling identity.
+  TM  transition moments F_I = <Psi~_I|D|Psi0> through first order vs the
+      brute-force intermediate states; the spin selection rule (triplets
+      dark) in the nonrelativistic limit.
   FNS the MP2 virtual density (Eq. 15) vs the second-order coefficient of
       the exact ground-state density; natural-spinor transform with nothing
       dropped leaves the ADC roots and the MP2 energy unchanged.
@@ -29,7 +32,7 @@ import torch
 
 from synth import make_system, make_spin_blocked
 from oracle import adc2 as O
-from oracle.isr_bruteforce import adc2_blocks, density_taylor
+from oracle.isr_bruteforce import adc2_blocks, density_taylor, transition_taylor
 
 torch.set_num_threads(min(8, torch.get_num_threads()))
 
@@ -342,3 +345,72 @@ def test_fns_keep_all_is_a_rotation():
     assert nvt == 5 and Lt.shape == (s.naux, sp.o + 5, sp.o + 5)
     F = Ut.conj().T @ torch.diag(e[sp.U]).to(O.C128) @ Ut
     assert torch.allclose(F, torch.diag(et[sp.o:]).to(O.C128), atol=1e-12)
+
+
+# ---------------------------------------------------------------- TM
+def _hermitian(n, seed):
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return 0.5 * (d + d.conj().T)
+
+
+@pytest.mark.parametrize("shape,seed,sigma", [((1, 2, 3), 5, 0.12), ((2, 2, 3), 7, 0.15), ((1, 3, 3), 11, 0.10)])
+def test_tm_first_order_bruteforce(shape, seed, sigma):
+    """Zeroth plus first order of F_I(lambda) from the intermediate states
+    constructed by brute force equals transition_moments on the CVS rows
+    (doubles basis a+_a a+_b a_j a_I = -1 x the brute-force a+_a a+_b a_I a_j)."""
+    s = make_system(*shape, naux=6, seed=seed, sigma=sigma)
+    L, e, sp = _tensors(s)
+    d = _hermitian(sp.n, 3 + seed)
+    (F0, F1, F2), resid, singles, doubles = transition_taylor(s.L, s.eps, sp.o, d)
+    assert resid < 1e-9
+    ns = len(singles)
+    nc = sp.nc
+    cvs_s = [k for k, (i, a) in enumerate(singles) if i < nc]
+    cvs_d = [ns + k for k, (i, j, a, b) in enumerate(doubles) if i < nc <= j]
+    ref = np.concatenate([(F0 + F1)[cvs_s], -(F0 + F1)[cvs_d]])
+    # brute-force singles are ordered (i, a) with i outer; doubles (i<j, a<b): the CVS order of the vector layout
+    got = O.transition_moments(L, e, sp, d).numpy()
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
+    # the second order is not part of it: it is a genuine correction of these inputs
+    assert np.abs(F2[cvs_s]).max() > 1e-4 * np.abs(ref).max()
+
+
+def test_tm_spin_selection_rule():
+    """Nonrelativistic limit with a spin-free dipole: every triplet state has
+    zero transition moment, singlets do not (spin is conserved by F at each
+    order); oscillator strengths follow f = 2/3 w |T|^2."""
+    sb = make_spin_blocked(1, 2, 4, 12, seed=9, sigma=0.1)
+    L, e, sp = _tensors(sb)
+    a = O.Adc2(sb.L, sb.eps, sb.nc, sb.no, sb.nv)
+    M = a.matrix()
+    w, v = torch.linalg.eigh(M)
+    n_sp = sp.n // 2
+    dip = []
+    for c in range(3):
+        rng = np.random.default_rng(40 + c)
+        x = rng.standard_normal((n_sp, n_sp))
+        x = x + x.T
+        dd = np.zeros((sp.n, sp.n))
+        for sg in range(2):
+            idx = 2 * np.arange(n_sp) + sg
+            dd[np.ix_(idx, idx)] = x
+        dip.append(dd)
+    dip = np.array(dip)
+    k = 12
+    T, f = O.oscillator_strengths(L, e, sp, dip, v[:, :k].T, w[:k])
+    sizes = _multiplets(w[:k].numpy(), 1e-9)
+    pos = 0
+    n_dark = n_bright = 0
+    for sz in sizes:
+        blk = f[pos:pos + sz].numpy()
+        if sz == 3:
+            assert blk.max() < 1e-20 * max(1.0, float(f.max()))
+            n_dark += 1
+        else:
+            assert sz == 1 and blk[0] > 1e-8
+            n_bright += 1
+        pos += sz
+    assert n_dark >= 1 and n_bright >= 1
+    assert torch.allclose(f, (2.0 / 3.0) * w[:k] * (T.abs() ** 2).sum(1), rtol=1e-14)
