@@ -147,6 +147,33 @@ def with_measured_peak(roof, measured):
     return roof
 
 
+def run_transition(args, A, np, torch):
+    """Transition dipole moments and oscillator strengths (first-order F) of
+    the FP64 roots of the configuration, with synthetic dipole integrals."""
+    from synth import CONFIGS, config_system, dipole_integrals
+    s = config_system(args.config)
+    nroots = args.nroots or CONFIGS[args.config]["nroots"]
+    L, e = torch.from_numpy(s.L).cuda(), torch.from_numpy(s.eps).cuda()
+    dip = torch.from_numpy(dipole_integrals(27451, s.nc + s.no + s.nv)).cuda()
+    h = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    w, X, inf = A.adc2_davidson(h, nroots, tol=args.tol, solver=A.ADC2_SOLVER_FOLDED)
+    A.adc2_transition(h, dip, X[:1], w[:1])          # warm-up (first-call costs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, f = A.adc2_transition(h, dip, X, w)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] transition moments of {nroots} roots: {dt:.3f}s", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "transition moments and oscillator strengths, time", "value": round(dt, 4),
+                      "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"CVS-ADC(2) {args.config}: nc={s.nc} no={s.no} nv={s.nv} "
+                                             f"naux={s.naux}, {nroots} FP64 roots, first-order F, 3 dipole "
+                                             "components"},
+                      "omega_ha": list(w), "oscillator_strengths": [float(x) for x in f],
+                      "abs_T": [[float(abs(t)) for t in row] for row in T]}), flush=True)
+    h.close()
+
+
 def run_peaks(args, A):
     """Microbenchmarks of the rates the rooflines are quoted against."""
     names = ["mfma_f64", "mfma_f32", "mfma_bf16", "valu_f64", "hbm_read", "hbm_copy"]
@@ -393,7 +420,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "fd", "peaks"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "fd", "peaks", "transition"], default="single",
                     help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
                          "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
                          "one after the other; prints its own JSON line.  peaks: the device-rate "
@@ -431,6 +458,9 @@ def main():
         return
     if args.workload == "peaks":
         run_peaks(args, A)
+        return
+    if args.workload == "transition":
+        run_transition(args, A, np, torch)
         return
     cfg = CONFIGS[args.config]
     nroots = args.nroots or cfg["nroots"]

@@ -302,6 +302,27 @@ ADC2_API adc2_status adc2_profile(adc2_handle h, int enable);
 ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
 
 /*
+ * adc2_transition -- transition dipole moments and oscillator strengths
+ * (paper, Theory section, transition properties):
+ *   T_n = X_n^H F,  F_I = <Psi~_I| D |Psi0>,  f_n = (2/3) omega_n sum_x |T_n^x|^2,
+ * for the three Cartesian components of a one-particle operator
+ * D = sum_pq d_pq a+_p a_q.  F is built through first order in the
+ * Moller-Plesset expansion (singles: zeroth and first order; doubles: first
+ * order); its second-order terms are not included.
+ *   dip    dev complex128 [3][n][n], d^x, d^y, d^z (Hermitian), spinor order
+ *          of the setup.
+ *   X      dev complex128 [nroots][dim], normalised eigenvectors (e.g. from
+ *          adc2_davidson); omega host float64 [nroots].
+ *   T      host complex128 [nroots][3]; f host float64 [nroots].
+ * Work space: the MP2 amplitudes of every occupied pair (o(o-1)/2 nv^2
+ * complex), F (3 dim complex) and small buffers, allocated and freed here.
+ * Synchronises the stream.  Errors: ADC2_ERR_ARG (NULL argument, nroots out
+ * of 1..ADC2_MAX_ROOTS), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ */
+ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, int nroots, const void* X, const double* omega,
+                                     void* T, double* f, void* stream);
+
+/*
  * adc2_fns -- frozen natural virtual spinors (paper, State-Average Frozen
  * Natural Spinors: Eq. 15 and Eq. 17-20) from the MP2 virtual density of the
  * system h was set up for:

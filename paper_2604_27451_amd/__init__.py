@@ -60,7 +60,7 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
-           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns"]
+           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns", "adc2_transition"]
 
 
 class DavOpts(ctypes.Structure):
@@ -156,6 +156,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
+    lib.adc2_transition.argtypes = [vp, vp, i, vp, ctypes.POINTER(d), vp, ctypes.POINTER(d), vp]
+    lib.adc2_transition.restype = i
     lib.adc2_fns.argtypes = [vp, vp, d, ctypes.POINTER(i), ctypes.POINTER(d), vp, vp, vp]
     lib.adc2_fns.restype = i
     lib.adc2_autotune.argtypes = [vp, i, ctypes.POINTER(TuneInfo), vp]
@@ -447,6 +449,22 @@ def adc2_kernel_stats(h: Handle):
         raise Adc2Error(ADC2_ERR_ARG, "adc2_kernel_stats: NULL handle")
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops}
             for i in range(n)}
+
+
+def adc2_transition(h: Handle, dip, X, omega, stream=None):
+    """Transition dipole moments T [k][3] (complex) and oscillator strengths
+    f [k] of the eigenpairs (X, omega); dip: [3][n][n] complex128 on the GPU."""
+    import numpy as np
+    import torch
+    _need(dip, torch.complex128, "dip")
+    _need(X, torch.complex128, "X")
+    k = X.shape[0]
+    om = (ctypes.c_double * k)(*[float(w) for w in omega])
+    T = np.zeros((k, 3), dtype=np.complex128)
+    f = (ctypes.c_double * k)()
+    _check(load().adc2_transition(h.ptr, ctypes.c_void_p(dip.data_ptr()), k, ctypes.c_void_p(X.data_ptr()), om,
+                                  ctypes.c_void_p(T.ctypes.data), f, _stream_ptr(stream)), "adc2_transition")
+    return T, np.array(f[:])
 
 
 def adc2_fns(h: Handle, L, threshold: float, stream=None):

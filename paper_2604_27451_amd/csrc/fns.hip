@@ -38,6 +38,20 @@ __global__ void k_tau(double2* __restrict__ W, const int2* __restrict__ pairs, i
   }
 }
 
+}  // namespace
+
+// W[t][a][c] -> tau = W / (e_a + e_c - e_k - e_l) in place for the device
+// pair list (k, l) of t < npairs
+adc2_status tau_from_w(double2* W, const int2* dpairs, int npairs, const double* eps, int o, int nv, hipStream_t st) {
+  const long tot = (long)npairs * nv * nv;
+  if (tot == 0) return ADC2_OK;
+  k_tau<<<(unsigned)std::min<long>(16384, (tot + 255) / 256), 256, 0, st>>>(W, dpairs, npairs, eps, o, nv);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
+}
+
+namespace {
+
 adc2_status ffail(adc2_status s, const std::string& m) {
   set_error("adc2_fns: " + m);
   return s;
@@ -101,9 +115,10 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
         msg = adc2_last_error();
         break;
       }
-      const long tot = (long)cnt * nv2;
-      k_tau<<<(unsigned)std::min<long>(16384, (tot + 255) / 256), 256, 0, st>>>(Wc, dpairs + p0, cnt, h->eps, o, nv);
-      if (!hip(hipGetLastError(), "k_tau")) break;
+      if ((rc = tau_from_w(Wc, dpairs + p0, cnt, h->eps, o, nv, st)) != ADC2_OK) {
+        msg = adc2_last_error();
+        break;
+      }
       for (int t = 0; t < cnt && rc == ADC2_OK; ++t) {
         const double2* tp = Wc + (long)t * nv2;
         if ((rc = gemm_rr(nv, nv, nv, tp, nv, false, tp, nv, true, Dd, nv, 1.0, true, st)) != ADC2_OK)

@@ -124,6 +124,8 @@ adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
 // Y-build GEMM of one request in the handle's form (h->ysplit partials) and the partial sum
 adc2_status ybuild_launch(adc2_handle h, int m, hipStream_t st);
 adc2_status ybuild_sum(adc2_handle h, int m, hipStream_t st);
+// MP2 amplitudes in place: W[t][a][c] /= e_a + e_c - e_k - e_l for the device pair list (k, l) (fns.hip)
+adc2_status tau_from_w(double2* W, const int2* dpairs, int npairs, const double* eps, int o, int nv, hipStream_t st);
 // bytes of an R x K operand in the blocked split-BF16 layout
 long split_bytes(long R, long K);
 

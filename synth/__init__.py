@@ -129,6 +129,14 @@ def random_vectors(seed: int, m: int, dim: int) -> np.ndarray:
     return (v / math.sqrt(2.0)).astype(np.complex128)
 
 
+def dipole_integrals(seed: int, n: int, scale: float = 0.5) -> np.ndarray:
+    """Stand-in spinor dipole integrals d^x, d^y, d^z: [3][n][n] complex
+    Hermitian, entries of size ~scale (atomic units)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 5]))
+    a = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
+    return np.ascontiguousarray(0.5 * scale * (a + np.conj(np.transpose(a, (0, 2, 1)))), dtype=np.complex128)
+
+
 def random_hermitian_direction(seed: int, naux: int, n: int) -> np.ndarray:
     """A Hermitian-per-P direction dL of unit Frobenius norm."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))

@@ -1,0 +1,93 @@
+"""GPU parity of the transition moments and oscillator strengths
+(adc2_transition) against the oracle's transition_moments /
+oscillator_strengths (first-order F, Theory section).
+
+T = X^H F is linear in X, so random vectors as well as eigenvectors probe F
+element by element in projection: 8 random directions x 3 Cartesian
+components, and the 4 lowest eigenvectors with their oscillator strengths.
+In the nonrelativistic limit with a spin-free dipole every triplet root is
+dark on the GPU as well.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_27451_amd as A
+from oracle import adc2 as O
+from synth import dipole_integrals, make_spin_blocked, make_system, random_vectors
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("shape,seed", [((2, 4, 14, 30), 51), ((1, 3, 17, 24), 52)])
+def test_transition_parity(shape, seed):
+    s = make_system(*shape, seed=seed)
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    dip = dipole_integrals(seed, sp.n)
+    print(f"[case] transition moments {shape}", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    Fo = O.transition_moments(O.as_c128(s.L), O.as_f64(s.eps), sp, dip).numpy()   # [3][dim]
+    # random directions
+    Xr = random_vectors(seed, 8, h.dim)
+    T, f = A.adc2_transition(h, dev(dip), dev(Xr), [1.0] * 8)
+    Tref = Xr.conj() @ Fo.T
+    err = np.abs(T - Tref).max() / np.abs(Tref).max()
+    print(f"  random directions: max rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+    # eigenvectors and oscillator strengths
+    w, X, inf = A.adc2_davidson(h, 4, tol=1e-10)
+    T, f = A.adc2_transition(h, dev(dip), X, w)
+    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w)
+    ef = np.abs(f - fr.numpy()).max() / np.abs(fr.numpy()).max()
+    print(f"  roots {np.round(w, 6)} f {np.round(f, 6)}  rel err {ef:.2e}", flush=True)
+    assert np.abs(T - Tr.numpy()).max() < 1e-12 * np.abs(Tr.numpy()).max()
+    assert ef < 1e-12
+    h.close()
+
+
+def test_transition_spin_selection_rule():
+    sb = make_spin_blocked(1, 2, 4, 12, seed=9, sigma=0.1)
+    sp = O.Spaces(sb.nc, sb.no, sb.nv)
+    n_sp = sp.n // 2
+    rng = np.random.default_rng(44)
+    dip = np.zeros((3, sp.n, sp.n), dtype=np.complex128)
+    for c in range(3):
+        x = rng.standard_normal((n_sp, n_sp))
+        x = x + x.T
+        for sg in range(2):
+            idx = 2 * np.arange(n_sp) + sg
+            dip[c][np.ix_(idx, idx)] = x
+    h = A.adc2_setup(dev(sb.L), dev(sb.eps), sb.nc, sb.no, sb.nv, sb.naux)
+    w, X, inf = A.adc2_davidson(h, 8, tol=1e-10)
+    T, f = A.adc2_transition(h, dev(dip), X, w)
+    h.close()
+    w = np.array(w)
+    groups, cur = [], [0]
+    for i in range(1, len(w)):
+        if w[i] - w[cur[-1]] < 1e-7:
+            cur.append(i)
+        else:
+            groups.append(cur)
+            cur = [i]
+    groups.append(cur)
+    print(f"[case] spin selection: roots {np.round(w, 6)} f {f}", flush=True)
+    dark = [g for g in groups if len(g) == 3]
+    bright = [g for g in groups if len(g) == 1 and g[0] < len(w) - 1]
+    assert dark and bright
+    for g in dark:
+        assert f[g].max() < 1e-18 * max(1.0, f.max())
+    assert max(f[g[0]] for g in bright) > 1e-6
+
+
+def test_transition_argument_errors():
+    s = make_system(1, 2, 5, 12, seed=4)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    dip = dev(dipole_integrals(1, s.nc + s.no + s.nv))
+    X = torch.zeros(33, h.dim, dtype=torch.complex128, device="cuda")
+    with pytest.raises(A.Adc2Error):
+        A.adc2_transition(h, dip, X, [1.0] * 33)
+    h.close()
