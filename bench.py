@@ -343,6 +343,24 @@ def run_fd(args, A, np, torch):
         GE.append(de)
     torch.cuda.synchronize()
     t_adj = (time.perf_counter() - tb) / nroots
+    # complex64 leg: eigenvectors from the complex64 solve (tolerance 1e-5), the
+    # same adjoint (FP64 arithmetic) on them, against the FP64 gradient
+    A.adc2_set_precision(h, A.ADC2_C64)
+    wc, Xc, infc = A.adc2_davidson(h, nroots, tol=1e-5, solver=fold)
+    A.adc2_set_precision(h, A.ADC2_FP64)
+    Gc, GEc = [], []
+    for k in range(nroots):
+        g = [0.0] * nroots
+        g[k] = 1.0
+        dL, de = A.adc2_omega_backward(h, Xc, g)
+        Gc.append(dL)
+        GEc.append(de)
+    c64_rel = [float(torch.linalg.vector_norm(Gc[k] - G[k]) / torch.linalg.vector_norm(G[k])) for k in range(nroots)]
+    c64_rel_e = [float(torch.linalg.vector_norm(GEc[k] - GE[k]) / torch.linalg.vector_norm(GE[k]))
+                 for k in range(nroots)]
+    print(f"[bench] fd: complex64 eigenvectors ({infc['iters']} it): gradient rel. dev. vs FP64 "
+          f"L {max(c64_rel):.2e}, eps {max(c64_rel_e):.2e}", file=sys.stderr, flush=True)
+    del Xc
     h.close()
 
     def roots_at(Lp, ep):
@@ -351,13 +369,14 @@ def run_fd(args, A, np, torch):
         hp.close()
         return np.array(w), inf["iters"]
 
-    rows, iters = [], []
+    rows, rows_c, iters = [], [], []
     for d in range(ndir + nedir):
         if d < ndir:
             dL = random_hermitian_direction_device(27451 + 5000 + d, naux, n)
             wp, ip = roots_at(L + hstep * dL, eps)
             wm, im_ = roots_at(L - hstep * dL, eps)
             ad = np.array([float(torch.sum(torch.conj(G[k]) * dL).real) for k in range(nroots)])
+            adc = np.array([float(torch.sum(torch.conj(Gc[k]) * dL).real) for k in range(nroots)])
             del dL
         else:
             gen = torch.Generator(device="cuda")
@@ -367,15 +386,17 @@ def run_fd(args, A, np, torch):
             wp, ip = roots_at(L, eps + hstep * de)
             wm, im_ = roots_at(L, eps - hstep * de)
             ad = np.array([float(torch.dot(GE[k], de)) for k in range(nroots)])
+            adc = np.array([float(torch.dot(GEc[k], de)) for k in range(nroots)])
         fd = (wp - wm) / (2 * hstep)
         rows.append((d < ndir, fd, ad))
+        rows_c.append((d < ndir, fd, adc))
         iters += [ip, im_]
         err = np.abs(fd - ad).max() / max(1e-300, np.abs(ad).max())
         print(f"[bench] fd direction {d} ({'L' if d < ndir else 'eps'}): max rel dev {err:.2e} "
               f"(|d omega| max {np.abs(ad).max():.3e})", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
-    def stats(is_l):
+    def stats(is_l, rows=rows):
         sel = [(fd, ad) for l, fd, ad in rows if l == is_l]
         dev = [float(np.abs(fd - ad).max() / np.abs(ad).max()) for fd, ad in sel]
         absd = [float(np.abs(fd - ad).max()) for fd, ad in sel]
@@ -397,6 +418,11 @@ def run_fd(args, A, np, torch):
         "eps_directions": stats(False),
         "adjoint_s_per_root": round(t_adj, 3),
         "perturbed_solve_iterations": {"min": int(min(iters)), "max": int(max(iters))},
+        "complex64": {"eigenvectors": "complex64 folded solve, tolerance 1e-5; adjoint in FP64 arithmetic",
+                      "iterations": infc["iters"],
+                      "max_rel_dev_vs_fp64_gradient_L": max(c64_rel),
+                      "max_rel_dev_vs_fp64_gradient_eps": max(c64_rel_e),
+                      "L_directions": stats(True, rows_c), "eps_directions": stats(False, rows_c)},
         "wall_s": round(time.perf_counter() - t0, 1),
     }
     print(json.dumps(out), flush=True)
