@@ -445,6 +445,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the FP64 solve started from split-BF16 vectors (FP64 roots through the precision form)")
+    ap.add_argument("--tol-refine", type=float, default=1e-4,
+                    help="split-BF16 tolerance before the FP64 continuation")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", choices=["single", "batch", "fd", "peaks", "transition"], default="single",
                     help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
@@ -553,12 +557,33 @@ def main():
                 t5 = time.perf_counter()
                 r[tag] = dict(solve_s=t4 - t3, polish_s=t5 - t4, w=wm, wp=wp, rn_polish=rn, info=infom, ks=ksm)
                 del Xm
+            if not args.no_refined:
+                # FP64 roots through the precision form: split-BF16 solve to tol_refine, then the
+                # FP64 folded solve to the FP64 tolerance started from those vectors
+                t6 = time.perf_counter()
+                A.adc2_set_precision(h, A.ADC2_BF16X3)
+                wb, Xb, infb, _ = solve(h, args.tol_refine)
+                A.adc2_set_precision(h, A.ADC2_FP64)
+                t7 = time.perf_counter()
+                wr, Xr, infr = A.adc2_davidson(h, nroots, tol=args.tol, max_iter=args.max_iter, solver=solver,
+                                               max_subspace=args.max_subspace, guess=Xb, nguess=nroots,
+                                               raise_on_noconv=False)
+                torch.cuda.synchronize()
+                t8 = time.perf_counter()
+                r["refined"] = dict(mixed_s=t7 - t6, fp64_s=t8 - t7, w=wr, it_mixed=infb["iters"],
+                                    it_fp64=infr["iters"], converged=infr["converged"],
+                                    max_resnorm=max(infr["resnorm"]))
+                del Xb, Xr
         h.close()
         r["wall_s"] = time.perf_counter() - t0
         msg = (f"[bench] step {i} ({'timed' if timed else 'warmup'}): setup {r['setup_s']:.3f}s "
                f"fp64 {r['fp64_solve_s']:.2f}s ({info64['iters']} it, max|r| {max(info64['resnorm']):.1e})")
         if "adjoint_s" in r:
             msg += f" adjoint {r['adjoint_s']:.2f}s"
+        if "refined" in r:
+            m = r["refined"]
+            msg += (f" fp64-via-b3 {m['mixed_s'] + m['fp64_s']:.2f}s ({m['it_mixed']}+{m['it_fp64']} it, max|dw| "
+                    f"{np.abs(np.array(m['w']) - np.array(w64)).max():.1e} Ha)")
         for tag in ("b3", "c64"):
             if tag in r:
                 m = r[tag]
@@ -665,6 +690,21 @@ def main():
                                          "FP64 setup, denominators and subspace; tolerance "
                                          f"{args.tol_mixed:g}", PEAK_BF16X3)
         out["mixed"]["tol"] = args.tol_mixed
+    if "refined" in last:
+        m = last["refined"]
+        out["fp64_via_mixed"] = {
+            "what": f"split-BF16 folded solve to {args.tol_refine:g}, then the FP64 folded solve to {args.tol:g} "
+                    "started from its vectors",
+            "time_to_roots_s": round(float(np.mean([r["setup_s"] + r["refined"]["mixed_s"] + r["refined"]["fp64_s"]
+                                                    for r in res])), 3),
+            "mixed_s": round(float(np.mean([r["refined"]["mixed_s"] for r in res])), 3),
+            "fp64_s": round(float(np.mean([r["refined"]["fp64_s"] for r in res])), 3),
+            "iterations": [m["it_mixed"], m["it_fp64"]], "converged": m["converged"],
+            "max_resnorm": m["max_resnorm"],
+            "max_abs_dev_from_fp64_roots_ha": float(np.abs(np.array(m["w"]) - w64).max()),
+            "speedup_vs_fp64": round(out["time_to_roots_s"] / max(1e-9, float(np.mean(
+                [r["setup_s"] + r["refined"]["mixed_s"] + r["refined"]["fp64_s"] for r in res]))), 3),
+        }
     if "c64" in last:
         out["mixed_c64"] = mixed_block("c64", "complex64 operands, FP32 MFMA accumulation; FP64 setup, "
                                               f"denominators and subspace; tolerance {args.tol_c64:g}",
