@@ -445,6 +445,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 leg of the precision form")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the FP64 solve started from split-BF16 vectors (FP64 roots through the precision form)")
     ap.add_argument("--tol-refine", type=float, default=1e-4,
@@ -546,7 +547,8 @@ def main():
             del dL, de
         del X64
         if not args.no_mixed:
-            for tag, prec, tol in (("b3", A.ADC2_BF16X3, args.tol_mixed), ("c64", A.ADC2_C64, args.tol_c64)):
+            legs = [("b3", A.ADC2_BF16X3, args.tol_mixed)] + ([] if args.no_c64 else [("c64", A.ADC2_C64, args.tol_c64)])
+            for tag, prec, tol in legs:
                 t3 = time.perf_counter()
                 A.adc2_set_precision(h, prec)
                 wm, Xm, infom, ksm = solve(h, tol)
