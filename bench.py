@@ -65,7 +65,7 @@ def f_sigma(nc, no, nv, naux):
     return 8.0 * (2.0 * nc * no * nv * nv * naux + 2.0 * nc * nv * nv * naux + (nc * nv) ** 2)
 
 
-def cpu_baseline(sysm, nj: int = 4):
+def cpu_baseline(sysm, nj: int = 8):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     the sigma build (integral blocks + product) for one vector of this system
     restricted to its first nj valence spinors."""
