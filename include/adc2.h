@@ -81,6 +81,7 @@ typedef struct {
   int verbose;         /* print one line per iteration to stderr              */
   int solver;          /* ADC2_SOLVER_FULL (0) or ADC2_SOLVER_FOLDED (1)      */
   int follow;          /* 1: root following (full-space solver only), below  */
+  double mixed_tol;    /* > 0: two-stage solve through split-BF16, below     */
 } adc2_dav_opts;
 
 /* Eigensolvers of adc2_davidson.
@@ -147,6 +148,12 @@ ADC2_API adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, vo
  *   omega    host float64 [nroots], ascending.
  *   X        dev complex128 [nroots][dim] or NULL: normalised eigenvectors.
  *   info     host, may be NULL.
+ * Two-stage solve (opt->mixed_tol > 0, handle in ADC2_FP64): the roots are
+ * first solved with split-BF16 sigma builds to residual mixed_tol, then by
+ * the FP64 solver to tol started from those vectors; the results are FP64
+ * roots (the precision form's arithmetic never reaches them).  info sums
+ * both stages; the handle is left in ADC2_FP64.  mixed_tol must exceed
+ * tol (ADC2_ERR_ARG otherwise, and with root following).
  * Root following (opt->follow = 1, full-space solver): the root-specific
  * Davidson the paper uses to keep each root matched to its guess (Hirao and
  * Nakatsuji, cited in the Computational details).  Root j is, at every

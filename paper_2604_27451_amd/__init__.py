@@ -66,7 +66,8 @@ EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_pr
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("nguess", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("solver", ctypes.c_int), ("follow", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("solver", ctypes.c_int), ("follow", ctypes.c_int),
+                ("mixed_tol", ctypes.c_double)]
 
 
 class TuneInfo(ctypes.Structure):
@@ -253,11 +254,12 @@ def adc2_sigma(h: Handle, X, S=None, stream=None):
 
 def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, guess=None,
                   want_vectors=True, verbose=0, stream=None, raise_on_noconv=True, solver=ADC2_SOLVER_FULL,
-                  follow=False):
+                  follow=False, mixed_tol=0.0):
     """Eigenpairs of M.  follow=True: root j follows guess vector j (root-specific
-    Davidson; full-space solver; results in guess order)."""
+    Davidson; full-space solver; results in guess order).  mixed_tol > 0: solve
+    with split-BF16 sigma builds to mixed_tol first, then in FP64 to tol."""
     import torch
-    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver, 1 if follow else 0)
+    opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver, 1 if follow else 0, float(mixed_tol))
     info = DavInfo()
     omega = (ctypes.c_double * nroots)()
     X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None

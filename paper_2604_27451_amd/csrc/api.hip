@@ -391,6 +391,44 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
                           double* omega, void* Xout, adc2_dav_info* info, void* stream) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!h || !omega) return fail(ADC2_ERR_ARG, "adc2_davidson: bad arguments");
+  if (opt && opt->mixed_tol > 0.0) {
+    // two stages: split-BF16 sigma builds to mixed_tol, then FP64 from those vectors
+    const double tol = opt->tol > 0 ? opt->tol : 1e-8;
+    if (opt->follow) return fail(ADC2_ERR_ARG, "adc2_davidson: the two-stage solve does not follow roots");
+    if (!(opt->mixed_tol > tol)) return fail(ADC2_ERR_ARG, "adc2_davidson: mixed_tol must exceed tol");
+    if (h->prec != ADC2_FP64) return fail(ADC2_ERR_ARG, "adc2_davidson: the two-stage solve needs an FP64 handle");
+    if (nroots <= 0 || nroots > ADC2_MAX_ROOTS) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..32");
+    hipStream_t st = (hipStream_t)stream;
+    double2* Xm = nullptr;
+    if (hipMalloc(&Xm, sizeof(double2) * (size_t)nroots * h->d.dim) != hipSuccess)
+      return fail(ADC2_ERR_OOM, "adc2_davidson: no memory for the first-stage vectors");
+    adc2_dav_opts o1 = *opt;
+    o1.mixed_tol = 0.0;
+    o1.tol = opt->mixed_tol;
+    adc2_dav_info i1{}, i2{};
+    h->prec = ADC2_BF16X3;
+    adc2_status r = adc2_davidson(h, nroots, &o1, guess, omega, Xm, &i1, stream);
+    h->prec = ADC2_FP64;
+    if (r == ADC2_OK || r == ADC2_ERR_NOCONV) {   // a first stage short of mixed_tol still seeds the second
+      adc2_dav_opts o2 = *opt;
+      o2.mixed_tol = 0.0;
+      o2.nguess = nroots;
+      r = adc2_davidson(h, nroots, &o2, Xm, omega, Xout, &i2, stream);
+    }
+    const std::string msg = r == ADC2_OK ? std::string() : std::string(adc2_last_error());
+    (void)hipStreamSynchronize(st);
+    hipFree(Xm);
+    if (info) {
+      *info = i2;
+      info->iters = i1.iters + i2.iters;
+      info->n_sigma = i1.n_sigma + i2.n_sigma;
+      info->ms_sigma = i1.ms_sigma + i2.ms_sigma;
+      info->sigma_flops = i1.sigma_flops + i2.sigma_flops;
+      info->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (r != ADC2_OK) return fail(r, msg);
+    return ADC2_OK;
+  }
   if (opt && opt->solver == ADC2_SOLVER_FOLDED) {
     if (nroots <= 0 || nroots > ADC2_MAX_ROOTS) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..32");
     return fold_davidson(h, nroots, opt, guess, omega, Xout, info, (hipStream_t)stream);
