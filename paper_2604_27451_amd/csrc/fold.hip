@@ -164,18 +164,19 @@ __global__ __launch_bounds__(256) void k_fold_x2(const double2* __restrict__ U, 
   __syncthreads();
   for (long d = blockIdx.x * (long)blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
     const double Dd = D[d];
-    for (int jb = 0; jb < q; jb += 8) {
-      double2 acc[8];
+    // 16 roots per pass: one read of U for up to 16 roots
+    for (int jb = 0; jb < q; jb += 16) {
+      double2 acc[16];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
+      for (int k = 0; k < 16; ++k) acc[k] = make_double2(0.0, 0.0);
       for (int i = 0; i < s; ++i) {
         const double2 u = U[(long)i * ldu + d];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < 16; ++k)
           if (jb + k < q) acc[k] = cadd(acc[k], cmul(u, ys[i * 32 + jb + k]));
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
+      for (int k = 0; k < 16; ++k)
         if (jb + k < q) out[(long)(jb + k) * ldo + d] = cscale(acc[k], 1.0 / (oms[jb + k] - Dd));
     }
   }
@@ -183,11 +184,11 @@ __global__ __launch_bounds__(256) void k_fold_x2(const double2* __restrict__ U, 
 
 // In place U_j <- sum_{i<s} U_i C[i][j] for j < q <= s <= 64; one workgroup
 // per 64 doubles, the block of U staged in LDS before any row is rewritten.
+// C (s x q, row-major) is read with wave-uniform addresses, so only the U
+// block occupies LDS (two workgroups per CU fit).
 __global__ __launch_bounds__(256) void k_fold_rotate(double2* __restrict__ U, long ldu, long nd, int s,
                                                       const double2* __restrict__ C, int q) {
-  __shared__ double2 cs[FSMAX * FSMAX];
   __shared__ double2 us[FSMAX][65];
-  for (int t = threadIdx.x; t < s * q; t += blockDim.x) cs[(t / q) * FSMAX + t % q] = C[t];
   const long d0 = (long)blockIdx.x * 64;
   for (int t = threadIdx.x; t < s * 64; t += blockDim.x) {
     const int i = t / 64, e = t % 64;
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_fold_rotate(double2* __restrict__ U, lo
   if (d0 + e < nd) {
     for (int j = jg; j < q; j += 4) {
       double2 a = make_double2(0.0, 0.0);
-      for (int i = 0; i < s; ++i) a = cadd(a, cmul(us[i][e], cs[i * FSMAX + j]));
+      for (int i = 0; i < s; ++i) a = cadd(a, cmul(us[i][e], C[i * q + j]));
       U[(long)j * ldu + d0 + e] = a;
     }
   }
