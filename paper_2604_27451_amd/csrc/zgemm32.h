@@ -15,7 +15,11 @@ namespace adc2 {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int FLDP = BT + 1;   // padded LDS row (floats)
+// Padded LDS row (floats).  A fragment read (and a stash of a K-major
+// operand) touches 4 consecutive k rows x 16 consecutive floats per wave; a
+// row stride of 16 mod 32 banks puts the four rows on disjoint banks (the
+// stride BT + 1 made them overlap: half of the LDS cycles were conflicts).
+constexpr int FLDP = BT + 16;
 
 struct BigSmemF {
   float a_re[BK][FLDP];
