@@ -70,6 +70,31 @@ def test_fns_truncated_matches_oracle():
     assert err < 1e-9
 
 
+def test_fns_truncated_c1_folded_roots():
+    """nc=6, no=10, nv=40, naux=150 truncated to the 20 most occupied natural
+    virtuals: the folded solver on the GPU's rotated problem against the
+    oracle's Davidson on the oracle's rotated problem."""
+    from synth import config_system
+    s = config_system("c1")
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    D = O.mp2_density_vv(O.as_c128(s.L), O.as_f64(s.eps), sp)
+    occ = np.sort(np.linalg.eigvalsh(D.numpy()))[::-1]
+    thr = float(np.sqrt(occ[19] * occ[20]))
+    L, e = dev(s.L), dev(s.eps)
+    h = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    Lp, ep, nvp, _ = A.adc2_fns(h, L, thr)
+    h.close()
+    assert nvp == 20
+    hp = A.adc2_setup(Lp, ep, s.nc, s.no, nvp, s.naux)
+    w, _, inf = A.adc2_davidson(hp, 4, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
+    hp.close()
+    Lo, eo, nvo, _, _ = O.frozen_natural_spinors(O.as_c128(s.L), O.as_f64(s.eps), sp, thr)
+    wo, _, info = O.Adc2(Lo, eo, s.nc, s.no, nvo).roots(4, tol=1e-10)
+    err = np.abs(np.array(w) - np.asarray(wo)).max()
+    print(f"[case] fns c1 -> nv' = {nvp}: roots {np.round(w, 6)} vs oracle {err:.2e} Ha", flush=True)
+    assert err < 1e-8
+
+
 def test_fns_occupations_only_and_errors():
     s = make_system(1, 3, 10, 20, seed=5)
     L, e = dev(s.L), dev(s.eps)

@@ -49,6 +49,25 @@ def test_transition_parity(shape, seed):
     h.close()
 
 
+def test_transition_with_folded_eigenvectors_c1():
+    """Eigenvectors of the folded solver (doubles rebuilt from the singles) at
+    nc=6, no=10, nv=40, naux=150: GPU transition moments against the oracle's
+    with the same vectors."""
+    from synth import config_system
+    s = config_system("c1")
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    dip = dipole_integrals(7, sp.n)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    w, X, inf = A.adc2_davidson(h, 4, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
+    T, f = A.adc2_transition(h, dev(dip), X, w)
+    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w)
+    err = np.abs(T - Tr.numpy()).max() / np.abs(Tr.numpy()).max()
+    print(f"[case] folded c1: f {np.round(f, 5)} rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+    assert np.abs(f - fr.numpy()).max() < 1e-12 * np.abs(fr.numpy()).max()
+    h.close()
+
+
 def test_transition_spin_selection_rule():
     sb = make_spin_blocked(1, 2, 4, 12, seed=9, sigma=0.1)
     sp = O.Spaces(sb.nc, sb.no, sb.nv)
