@@ -30,7 +30,7 @@ def test_transition_parity(shape, seed):
     dip = dipole_integrals(seed, sp.n)
     print(f"[case] transition moments {shape}", flush=True)
     h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
-    Fo = O.transition_moments(O.as_c128(s.L), O.as_f64(s.eps), sp, dip).numpy()   # [3][dim]
+    Fo = O.transition_moments(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, order=1).numpy()   # [3][dim]
     # random directions
     Xr = random_vectors(seed, 8, h.dim)
     T, f = A.adc2_transition(h, dev(dip), dev(Xr), [1.0] * 8)
@@ -41,7 +41,7 @@ def test_transition_parity(shape, seed):
     # eigenvectors and oscillator strengths
     w, X, inf = A.adc2_davidson(h, 4, tol=1e-10)
     T, f = A.adc2_transition(h, dev(dip), X, w)
-    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w)
+    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w, order=1)
     ef = np.abs(f - fr.numpy()).max() / np.abs(fr.numpy()).max()
     print(f"  roots {np.round(w, 6)} f {np.round(f, 6)}  rel err {ef:.2e}", flush=True)
     assert np.abs(T - Tr.numpy()).max() < 1e-12 * np.abs(Tr.numpy()).max()
@@ -60,7 +60,7 @@ def test_transition_with_folded_eigenvectors_c1():
     h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
     w, X, inf = A.adc2_davidson(h, 4, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
     T, f = A.adc2_transition(h, dev(dip), X, w)
-    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w)
+    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w, order=1)
     err = np.abs(T - Tr.numpy()).max() / np.abs(Tr.numpy()).max()
     print(f"[case] folded c1: f {np.round(f, 5)} rel err {err:.2e}", flush=True)
     assert err < 1e-12

@@ -17,9 +17,10 @@ sign, a misplaced conjugate, a transposed operand):
       permutation of spinors inside a block, uniform shift of energies.
   P8  Hellmann-Feynman gradient vs central finite differences and the
       scaling identity.
-  TM  transition moments F_I = <Psi~_I|D|Psi0> through first order vs the
-      brute-force intermediate states; the spin selection rule (triplets
-      dark) in the nonrelativistic limit.
+  TM  transition moments F_I = <Psi~_I|D|Psi0> through first order, and the
+      singles through second order, vs the brute-force intermediate states;
+      invariance under D -> D + c 1; the spin selection rule (triplets dark)
+      in the nonrelativistic limit.
   FNS the MP2 virtual density (Eq. 15) vs the second-order coefficient of
       the exact ground-state density; natural-spinor transform with nothing
       dropped leaves the ADC roots and the MP2 energy unchanged.
@@ -370,11 +371,64 @@ def test_tm_first_order_bruteforce(shape, seed, sigma):
     cvs_d = [ns + k for k, (i, j, a, b) in enumerate(doubles) if i < nc <= j]
     ref = np.concatenate([(F0 + F1)[cvs_s], -(F0 + F1)[cvs_d]])
     # brute-force singles are ordered (i, a) with i outer; doubles (i<j, a<b): the CVS order of the vector layout
-    got = O.transition_moments(L, e, sp, d).numpy()
+    got = O.transition_moments(L, e, sp, d, order=1).numpy()
     assert got.shape == ref.shape
     assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
     # the second order is not part of it: it is a genuine correction of these inputs
     assert np.abs(F2[cvs_s]).max() > 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape,seed,sigma", [((1, 2, 3), 5, 0.15), ((2, 1, 3), 7, 0.15), ((1, 2, 4), 11, 0.15),
+                                              ((2, 2, 3), 13, 0.12)])
+def test_tm_second_order_bruteforce(shape, seed, sigma):
+    """Singles through second order: the lambda^2 coefficient of F_I(lambda)
+    from the brute-force intermediate states (core rows of the full singles
+    class) equals second_order_singles, and transition_moments(order=2) is
+    F^(0) + F^(1) + F^(2) on the singles rows and F^(0) + F^(1) on the doubles
+    rows.  Each of the six second-order terms is of the size of the whole
+    here, so a dropped term, a wrong sign or a transposed index fails."""
+    s = make_system(*shape, naux=6, seed=seed, sigma=sigma, core=(-3.0, -2.5))
+    L, e, sp = _tensors(s)
+    d = _hermitian(sp.n, 17 + seed)
+    (F0, F1, F2), resid, singles, doubles = transition_taylor(s.L, s.eps, sp.o, d)
+    assert resid < 1e-9
+    ns = len(singles)
+    cvs_s = [k for k, (i, a) in enumerate(singles) if i < sp.nc]
+    cvs_d = [ns + k for k, (i, j, a, b) in enumerate(doubles) if i < sp.nc <= j]
+    # the lambda^2 coefficient of a degree-10 fit on |lambda| <= 0.5 carries
+    # about resid / 0.5^2 of fit error: 5e-9 absolute, while the terms below
+    # are each above 1e-5
+    f2 = O.second_order_singles(L, e, sp, d).reshape(-1).numpy()
+    assert np.abs(f2 - F2[cvs_s]).max() <= 5e-9
+    ref = np.concatenate([(F0 + F1 + F2)[cvs_s], -(F0 + F1)[cvs_d]])
+    got = O.transition_moments(L, e, sp, d, order=2).numpy()
+    assert np.abs(got - ref).max() <= 5e-9
+    # every term matters on these inputs: drop each in turn and the pin fails
+    tau = O.mp2_amplitudes(L, e, sp)
+    sa, u = O.second_order_amplitudes(L, e, sp)
+    dd = torch.as_tensor(d).to(O.C128)
+    C, O_, U = sp.C, sp.O, sp.U
+    dvo = dd[U][:, O_]
+    terms = [torch.einsum("ab,ib->ia", dd[U][:, U], sa), -torch.einsum("ji,ja->ia", dd[O_][:, O_], sa),
+             torch.einsum("jb,abij->ia", dd[O_][:, U], u),
+             -0.25 * torch.einsum("ac,ci->ia", torch.einsum("abkl,cbkl->ac", tau, tau.conj()), dvo),
+             -0.25 * torch.einsum("ak,ik->ia", dvo, torch.einsum("cdil,cdkl->ik", tau, tau.conj())),
+             0.5 * torch.einsum("iakc,ck->ia", torch.einsum("abil,cbkl->iakc", tau, tau.conj()), dvo)]
+    for t in terms:
+        assert float(t[C].abs().max()) > 1e-5
+
+
+def test_tm_second_order_shift_invariance():
+    """F_I = <Psi~_I|D|Psi0> is unchanged by D -> D + c 1, since every
+    intermediate state is orthogonal to Psi0: the two singles-amplitude terms
+    of the second order cancel exactly for d = 1."""
+    s = make_system(2, 3, 4, 8, seed=23, sigma=0.15, core=(-3.0, -2.5))
+    L, e, sp = _tensors(s)
+    d = _hermitian(sp.n, 29)
+    f = O.transition_moments(L, e, sp, d, order=2)
+    g = O.transition_moments(L, e, sp, d + 0.7 * np.eye(sp.n), order=2)
+    assert torch.allclose(f, g, rtol=0, atol=1e-13 * float(f.abs().max()))
+    assert float(O.second_order_singles(L, e, sp, np.eye(sp.n)).abs().max()) < 1e-14
 
 
 def test_tm_spin_selection_rule():
