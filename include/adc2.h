@@ -313,21 +313,30 @@ ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
  * (paper, Theory section, transition properties):
  *   T_n = X_n^H F,  F_I = <Psi~_I| D |Psi0>,  f_n = (2/3) omega_n sum_x |T_n^x|^2,
  * for the three Cartesian components of a one-particle operator
- * D = sum_pq d_pq a+_p a_q.  F is built through first order in the
- * Moller-Plesset expansion (singles: zeroth and first order; doubles: first
- * order); its second-order terms are not included.
+ * D = sum_pq d_pq a+_p a_q.  F in the Moller-Plesset expansion of that
+ * definition: singles through `order` (1: zeroth and first; 2: also the
+ * second, the order of the paper's transition density), doubles through
+ * first order (their second order reaches T only at third order).  The
+ * second-order singles hold the second-order ground-state singles and
+ * doubles amplitudes (particle and hole ladders, ring terms) and the pair
+ * densities; the intermediate states are the core rows of the full singles
+ * class.
  *   dip    dev complex128 [3][n][n], d^x, d^y, d^z (Hermitian), spinor order
  *          of the setup.
  *   X      dev complex128 [nroots][dim], normalised eigenvectors (e.g. from
  *          adc2_davidson); omega host float64 [nroots].
+ *   order  1 or 2.
  *   T      host complex128 [nroots][3]; f host float64 [nroots].
  * Work space: the MP2 amplitudes of every occupied pair (o(o-1)/2 nv^2
- * complex), F (3 dim complex) and small buffers, allocated and freed here.
+ * complex), F (3 dim complex) and small buffers; order 2 adds up to three
+ * o^2 nv^2 arrays (amplitudes of every ordered pair, (kj|bc) twice) and
+ * 2 naux nv^2 + nc o nv^2; all allocated and freed here.  The particle
+ * ladder costs 2 nc o naux nv^3 complex multiply-adds (FP64 MFMA).
  * Synchronises the stream.  Errors: ADC2_ERR_ARG (NULL argument, nroots out
- * of 1..ADC2_MAX_ROOTS), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ * of 1..ADC2_MAX_ROOTS, order not 1 or 2), ADC2_ERR_OOM, ADC2_ERR_HIP.
  */
 ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, int nroots, const void* X, const double* omega,
-                                     void* T, double* f, void* stream);
+                                     int order, void* T, double* f, void* stream);
 
 /*
  * adc2_fns -- frozen natural virtual spinors (paper, State-Average Frozen

@@ -157,7 +157,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
-    lib.adc2_transition.argtypes = [vp, vp, i, vp, ctypes.POINTER(d), vp, ctypes.POINTER(d), vp]
+    lib.adc2_transition.argtypes = [vp, vp, i, vp, ctypes.POINTER(d), i, vp, ctypes.POINTER(d), vp]
     lib.adc2_transition.restype = i
     lib.adc2_fns.argtypes = [vp, vp, d, ctypes.POINTER(i), ctypes.POINTER(d), vp, vp, vp]
     lib.adc2_fns.restype = i
@@ -453,9 +453,10 @@ def adc2_kernel_stats(h: Handle):
             for i in range(n)}
 
 
-def adc2_transition(h: Handle, dip, X, omega, stream=None):
+def adc2_transition(h: Handle, dip, X, omega, order: int = 2, stream=None):
     """Transition dipole moments T [k][3] (complex) and oscillator strengths
-    f [k] of the eigenpairs (X, omega); dip: [3][n][n] complex128 on the GPU."""
+    f [k] of the eigenpairs (X, omega); dip: [3][n][n] complex128 on the GPU;
+    order: the singles of F through first (1) or second (2) order."""
     import numpy as np
     import torch
     _need(dip, torch.complex128, "dip")
@@ -465,7 +466,8 @@ def adc2_transition(h: Handle, dip, X, omega, stream=None):
     T = np.zeros((k, 3), dtype=np.complex128)
     f = (ctypes.c_double * k)()
     _check(load().adc2_transition(h.ptr, ctypes.c_void_p(dip.data_ptr()), k, ctypes.c_void_p(X.data_ptr()), om,
-                                  ctypes.c_void_p(T.ctypes.data), f, _stream_ptr(stream)), "adc2_transition")
+                                  int(order), ctypes.c_void_p(T.ctypes.data), f, _stream_ptr(stream)),
+           "adc2_transition")
     return T, np.array(f[:])
 
 

@@ -3,14 +3,31 @@
 // F_I = <Psi~_I| D |Psi0> for the three Cartesian components of a dipole
 // operator D = sum_pq d_pq a+_p a_q, and f_n = (2/3) omega_n |T_n|^2.
 //
-// F is built through first order in the Moller-Plesset expansion:
-//   singles (I, a):  F = d_aI - sum_{j in O, b} tau^{ab}_{Ij} d_jb
-//   doubles (I, j, a<b) in the basis a+_a a+_b a_j a_I |Phi0>:
+// F in the Moller-Plesset expansion (the paper builds the transition density
+// through second order and prints no expressions; these are the orders of the
+// definition):
+//   singles (I, a):  F = d_aI - sum_{j in O, b} tau^{ab}_{Ij} d_jb  (+ F2, order 2)
+//   doubles (I, j, a<b) in the basis a+_a a+_b a_j a_I |Phi0>, first order
+//   (their second order reaches T only at third order):
 //     F = -[ (d_vv tau_Ij - (d_vv tau_Ij)^T)_{ab}
 //            - sum_{k in O} (d_kI tau^{ab}_{kj} + d_kj tau^{ab}_{Ik}) ]
 // (tau_Ij antisymmetric, so tau_Ij d_vv^T = -(d_vv tau_Ij)^T), with the MP2
 // amplitudes tau of every occupied pair from the setup's W-build.  The
-// second-order terms of F are not included.
+// second-order singles F2 (tm_second_order below):
+//   F2_Ia = sum_b d_ab s_Ib - sum_j d_jI s_ja + sum_{jb} d_jb u^{ab}_{Ij}
+//           - 1/4 sum_c rho_ac d_cI - 1/4 sum_k d_ak sigma_Ik
+//           + 1/2 sum_{lb} tau^{ab}_{Il} h_lb,   h_lb = sum_{kc} conj(tau^{cb}_{kl}) d_ck,
+// s and u the second-order singles and doubles amplitudes of the ground state,
+//   s_ia = (N1_ia - N2_ia) / (e_a - e_i),
+//     N1_ia = sum_{P,b} Z^P_ib L^P_ab,  N2_ia = sum_{P,j} L^P_ji Z^P_ja,
+//     Z^P_ib = sum_{jc} tau^{bc}_{ij} L^P_jc,
+//   u^{ab}_{Ij} = [ sum_{P,c,d} L^P_ac tau^{cd}_{Ij} L^P_bd      (particle ladder)
+//                 + sum_{k<l} <kl||Ij> tau^{ab}_{kl}            (hole ladder)
+//                 + P(Ij) P(ab) r^{ab}_{Ij} ] / D^{ab}_{Ij},
+//     r^{ab}_{ij} = sum_P Z^P_ia L^P_bj - sum_{kc} tau^{ac}_{ik} (kj|bc),
+// and the pair densities rho_ac = sum_{klb} tau^{ab}_{kl} conj(tau^{cb}_{kl}),
+// sigma_ik = sum_{lcd} tau^{cd}_{il} conj(tau^{cd}_{kl}); j, k, l over every
+// occupied spinor.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -81,19 +98,373 @@ __global__ __launch_bounds__(256) void k_tm_doubles(const double2* __restrict__ 
   }
 }
 
+
+// dst[b][a][c] = src[a][b][c] (conjugated if CONJ); A, B, C the extents of src
+template <bool CONJ>
+__global__ void k_swap12(const double2* __restrict__ src, long A, long B, long C, double2* __restrict__ dst) {
+  const long total = A * B * C;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e % C, ba = e / C;
+    const long a = ba % A, b = ba / A;
+    double2 v = src[(a * B + b) * C + c];
+    if (CONJ) v.y = -v.y;
+    dst[e] = v;
+  }
+}
+
+// dst[c][r] = src[r][c] for an R x Cc matrix, 32 x 32 tiles through LDS
+__global__ __launch_bounds__(256) void k_transpose(const double2* __restrict__ src, long R, long Cc,
+                                                    double2* __restrict__ dst) {
+  __shared__ double2 t[32][33];
+  const long tilesC = (Cc + 31) / 32;
+  const long tr = blockIdx.x / tilesC, tc = blockIdx.x - tr * tilesC;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const long r = tr * 32 + k, c = tc * 32 + tx;
+    t[k][tx] = (r < R && c < Cc) ? src[r * Cc + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const long c = tc * 32 + k, r = tr * 32 + tx;
+    if (r < R && c < Cc) dst[c * R + r] = t[tx][k];
+  }
+}
+
+// Tph[j][a][k][c] = tau^{ac}_{jk} over every ordered occupied pair (0 for j == k)
+__global__ void k_build_tph(const double2* __restrict__ tau, int o, int nv, double2* __restrict__ Tph) {
+  const long nv2 = (long)nv * nv, total = (long)o * nv * o * nv;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int c = (int)(e % nv);
+    long r = e / nv;
+    const int k = (int)(r % o);
+    r /= o;
+    const int a = (int)(r % nv), j = (int)(r / nv);
+    Tph[e] = tau_at(tau, j, k, o, nv2, (long)a * nv + c);
+  }
+}
+
+// G[p][(I, j)] = <kl||Ij> = sum_P (L^P_kI L^P_lj - L^P_kj L^P_lI) for the pair p = (k < l)
+__global__ void k_oooo(const double2* __restrict__ Loo, int naux, int o, int nc, const int2* __restrict__ pairs,
+                       int npairs, double2* __restrict__ G) {
+  const long total = (long)npairs * nc * o;
+  const long oo = (long)o * o;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int j = (int)(e % o);
+    const long t = e / o;
+    const int I = (int)(t % nc), p = (int)(t / nc);
+    const int k = pairs[p].x, l = pairs[p].y;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int P = 0; P < naux; ++P) {
+      const double2* L = Loo + (long)P * oo;
+      const double2 x = cmul(L[(long)k * o + I], L[(long)l * o + j]);
+      const double2 y = cmul(L[(long)k * o + j], L[(long)l * o + I]);
+      acc.x += x.x - y.x;
+      acc.y += x.y - y.y;
+    }
+    G[e] = acc;
+  }
+}
+
+// dst[e] += alpha * sum_s part[s][e], e < n
+__global__ void k_sum_parts(const double2* __restrict__ part, int nsplit, long n, double alpha,
+                            double2* __restrict__ dst) {
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    double2 a = make_double2(0.0, 0.0);
+    for (int q = 0; q < nsplit; ++q) a = cadd(a, part[(long)q * n + e]);
+    dst[e].x += alpha * a.x;
+    dst[e].y += alpha * a.y;
+  }
+}
+
+// Nt[j][a][b] += R[a][j][b] - R[b][j][a] - Rp[j][a][b] + Rp[j][b][a]  (one core I)
+__global__ void k_ring_add(const double2* __restrict__ R, const double2* __restrict__ Rp, int o, int nv,
+                           double2* __restrict__ Nt) {
+  const long nv2 = (long)nv * nv, total = (long)o * nv2, onv = (long)o * nv;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int b = (int)(e % nv);
+    const long r = e / nv;
+    const int a = (int)(r % nv), j = (int)(r / nv);
+    const double2 x1 = R[(long)a * onv + (long)j * nv + b], x2 = R[(long)b * onv + (long)j * nv + a];
+    const double2 y1 = Rp[((long)j * nv + a) * nv + b], y2 = Rp[((long)j * nv + b) * nv + a];
+    Nt[e].x += x1.x - x2.x - y1.x + y2.x;
+    Nt[e].y += x1.y - x2.y - y1.y + y2.y;
+  }
+}
+
+// u[I][j][a][b] = Nt / (e_a + e_b - e_I - e_j), 0 for j == I
+__global__ void k_u_divide(double2* __restrict__ Nt, const double* __restrict__ eps, int nc, int o, int nv) {
+  const long nv2 = (long)nv * nv, total = (long)nc * o * nv2;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int b = (int)(e % nv);
+    const long r = e / nv;
+    const int a = (int)(r % nv);
+    const long q = r / nv;
+    const int j = (int)(q % o), I = (int)(q / o);
+    if (j == I) {
+      Nt[e] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double w = 1.0 / (eps[o + a] + eps[o + b] - eps[I] - eps[j]);
+    Nt[e].x *= w;
+    Nt[e].y *= w;
+  }
+}
+
+// s[i][a] = (N1[i][a] - N2T[a][i]) / (e_a - e_i)
+__global__ void k_singles_amp(const double2* __restrict__ N1, const double2* __restrict__ N2T,
+                              const double* __restrict__ eps, int o, int nv, double2* __restrict__ s) {
+  const long total = (long)o * nv;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int a = (int)(e % nv), i = (int)(e / nv);
+    const double w = 1.0 / (eps[o + a] - eps[i]);
+    const double2 x = N1[e], y = N2T[(long)a * o + i];
+    s[e] = make_double2((x.x - y.x) * w, (x.y - y.y) * w);
+  }
+}
+
+// wdc[comp][(k, c)] = d^comp_{ck}
+__global__ void k_dvo_rows(const double2* __restrict__ dip, int o, int nv, int n, double2* __restrict__ wdc) {
+  const long onv = (long)o * nv, total = 3 * onv;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const int comp = (int)(e / onv);
+    const long r = e - comp * onv;
+    const int k = (int)(r / nv), c = (int)(r % nv);
+    wdc[e] = dip[(long)comp * n * n + (long)(o + c) * n + k];
+  }
+}
+
+// F2 of one (component, I, a), added to the singles row of F; one workgroup each
+__global__ __launch_bounds__(256) void k_f2_assemble(const double2* __restrict__ u, const double2* __restrict__ sa,
+                                                      const double2* __restrict__ rho,
+                                                      const double2* __restrict__ sig,
+                                                      const double2* __restrict__ f2p,
+                                                      const double2* __restrict__ dip, int nc, int o, int nv, int n,
+                                                      long dim, double2* __restrict__ F) {
+  __shared__ double2 red[256];
+  const int blk = blockIdx.x;
+  const int comp = blk / (nc * nv), r = blk - comp * nc * nv;
+  const int I = r / nv, a = r - I * nv;
+  const long nv2 = (long)nv * nv;
+  const double2* d = dip + (long)comp * n * n;
+  double2 acc = make_double2(0.0, 0.0);
+  // sum_{jb} d_jb u^{ab}_{Ij}
+  for (long e = threadIdx.x; e < (long)o * nv; e += 256) {
+    const int j = (int)(e / nv), b = (int)(e - (long)j * nv);
+    acc = cadd(acc, cmul(d[(long)j * n + o + b], u[((long)I * o + j) * nv2 + (long)a * nv + b]));
+  }
+  // sum_b d_ab s_Ib - 1/4 sum_c rho_ac d_cI
+  for (int b = threadIdx.x; b < nv; b += 256) {
+    acc = cadd(acc, cmul(d[(long)(o + a) * n + o + b], sa[(long)I * nv + b]));
+    const double2 t = cmul(rho[(long)a * nv + b], d[(long)(o + b) * n + I]);
+    acc.x -= 0.25 * t.x;
+    acc.y -= 0.25 * t.y;
+  }
+  // - sum_j d_jI s_ja - 1/4 sum_k d_ak sigma_Ik
+  for (int j = threadIdx.x; j < o; j += 256) {
+    const double2 t = cmul(d[(long)j * n + I], sa[(long)j * nv + a]);
+    const double2 q = cmul(d[(long)(o + a) * n + j], sig[(long)I * o + j]);
+    acc.x -= t.x + 0.25 * q.x;
+    acc.y -= t.y + 0.25 * q.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double2 t = f2p[((long)I * nv + a) * 3 + comp];
+    double2* out = F + (long)comp * dim + (long)I * nv + a;
+    out->x += red[0].x + t.x;
+    out->y += red[0].y + t.y;
+  }
+}
+
+unsigned grid_for(long n) { return (unsigned)std::max<long>(1, std::min<long>(8192, (n + 255) / 256)); }
+
 adc2_status tfail(adc2_status s, const std::string& m) {
   set_error("adc2_transition: " + m);
   return s;
 }
 
 }  // namespace
+
+// Second-order singles F2 of the three components, added to the singles rows
+// of F (expressions in the file header).  tau: the pair amplitudes of every
+// occupied pair (k < l) in row-major pair order, dpairs their (k, l) list.
+// Work space (freed here): Tph and (kj|bc) twice, o^2 nv^2 complex each, the
+// Lvv transposes 2 naux nv^2, the ladder's U naux nv^2, u nc o nv^2.
+adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpairs, int npairs,
+                            const double2* dip, double2* F, hipStream_t st) {
+  const Dims& d = h->d;
+  const int nc = d.nc, o = d.o, nv = d.nv, n = d.n, naux = d.naux;
+  const long nv2 = (long)nv * nv, onv = (long)o * nv, dim = d.dim;
+  std::vector<void*> bufs;
+  auto release = [&]() {
+    hipStreamSynchronize(st);
+    for (void* q : bufs) hipFree(q);
+    bufs.clear();
+  };
+  auto alloc = [&](double2** q, long count) -> adc2_status {
+    const hipError_t e = hipMalloc((void**)q, sizeof(double2) * std::max<long>(count, 1));
+    if (e != hipSuccess) {
+      set_error(std::string("adc2_transition: hipMalloc: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+    }
+    bufs.push_back(*q);
+    return ADC2_OK;
+  };
+  auto drop = [&](double2* q) {   // free one buffer early (after the stream has finished with it)
+    hipStreamSynchronize(st);
+    hipFree(q);
+    bufs.erase(std::remove(bufs.begin(), bufs.end(), (void*)q), bufs.end());
+  };
+  auto launched = [&](const char* what) -> adc2_status {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return ADC2_OK;
+    set_error(std::string("adc2_transition: ") + what + ": " + hipGetErrorString(e));
+    return ADC2_ERR_HIP;
+  };
+#define T2_TRY(x)                    \
+  do {                               \
+    const adc2_status r_ = (x);      \
+    if (r_ != ADC2_OK) {             \
+      release();                     \
+      return r_;                     \
+    }                                \
+  } while (0)
+
+  // tau over every ordered pair, [j][a][k][c]
+  double2 *Tph, *LovP, *ZT;
+  T2_TRY(alloc(&Tph, onv * onv));
+  k_build_tph<<<grid_for(onv * onv), 256, 0, st>>>(tau, o, nv, Tph);
+  T2_TRY(launched("k_build_tph"));
+  // Z^P_ib at ZT[i][b][P] = sum_{(j,c)} Tph[i][b][(j,c)] L^P_jc, L^P_jc = conj(Lvo[j][P][c]) at LovP[P][(j,c)]
+  T2_TRY(alloc(&LovP, (long)naux * onv));
+  T2_TRY(alloc(&ZT, onv * naux));
+  k_swap12<true><<<grid_for((long)naux * onv), 256, 0, st>>>(h->Lvo, o, naux, nv, LovP);
+  T2_TRY(launched("k_swap12"));
+  T2_TRY(gemm_rr((int)onv, naux, (int)onv, Tph, onv, false, LovP, onv, false, ZT, naux, 1.0, false, st));
+  drop(LovP);
+  // second-order singles amplitudes
+  double2 *LvvT, *N1, *ZA, *LooK, *N2T, *sa;
+  T2_TRY(alloc(&LvvT, nv2 * naux));      // [a][b][P] = L^P_ab
+  T2_TRY(alloc(&N1, onv));
+  T2_TRY(alloc(&ZA, onv * naux));
+  T2_TRY(alloc(&LooK, (long)o * o * naux));   // [k][j][P] = L^P_kj
+  T2_TRY(alloc(&N2T, onv));
+  T2_TRY(alloc(&sa, onv));
+  const long lvv_tiles = ((naux + 31) / 32) * ((nv2 + 31) / 32);
+  k_transpose<<<(unsigned)lvv_tiles, 256, 0, st>>>(h->Lvv, naux, nv2, LvvT);
+  T2_TRY(launched("k_transpose"));
+  const long loo_tiles = ((naux + 31) / 32) * (((long)o * o + 31) / 32);
+  k_transpose<<<(unsigned)loo_tiles, 256, 0, st>>>(h->Loo, naux, (long)o * o, LooK);
+  T2_TRY(launched("k_transpose"));
+  T2_TRY(gemm_rr(o, nv, (int)(nv * (long)naux), ZT, nv * (long)naux, false, LvvT, nv * (long)naux, false, N1, nv,
+                 1.0, false, st));
+  k_swap12<false><<<grid_for(onv * naux), 256, 0, st>>>(ZT, o, nv, naux, ZA);
+  T2_TRY(launched("k_swap12"));
+  T2_TRY(gemm_rr(nv, o, (int)((long)o * naux), ZA, (long)o * naux, false, LooK, (long)o * naux, true, N2T, o, 1.0,
+                 false, st));
+  k_singles_amp<<<grid_for(onv), 256, 0, st>>>(N1, N2T, h->eps, o, nv, sa);
+  T2_TRY(launched("k_singles_amp"));
+  drop(ZA);
+  drop(N1);
+  drop(N2T);
+  // (kj|bc) at P1[(j,b)][(k,c)]
+  double2 *Koovv, *P1;
+  T2_TRY(alloc(&Koovv, (long)o * o * nv2));
+  T2_TRY(gemm_rr(o * o, (int)nv2, naux, LooK, naux, false, LvvT, naux, false, Koovv, nv2, 1.0, false, st));
+  drop(LvvT);
+  drop(LooK);
+  T2_TRY(alloc(&P1, (long)o * o * nv2));
+  k_swap12<false><<<grid_for((long)o * o * nv2), 256, 0, st>>>(Koovv, o, onv, nv, P1);
+  T2_TRY(launched("k_swap12"));
+  drop(Koovv);
+  // numerators of u for the pairs (I, j): hole ladder first (it writes Nt)
+  double2 *Nt, *G;
+  T2_TRY(alloc(&Nt, (long)nc * o * nv2));
+  T2_TRY(alloc(&G, (long)npairs * nc * o));
+  k_oooo<<<grid_for((long)npairs * nc * o), 256, 0, st>>>(h->Loo, naux, o, nc, dpairs, npairs, G);
+  T2_TRY(launched("k_oooo"));
+  T2_TRY(bgemm_kmajor(G, 0, (long)nc * o, nc * o, tau, 0, nv2, (int)nv2, nc * o, (int)nv2, npairs, 1, Nt, st));
+  drop(G);
+  // ring terms, one core I at a time
+  double2 *R, *Rp;
+  T2_TRY(alloc(&R, nv * onv));
+  T2_TRY(alloc(&Rp, onv * nv));
+  for (int I = 0; I < nc; ++I) {
+    T2_TRY(gemm_rr(nv, (int)onv, naux, ZT + (long)I * nv * naux, naux, false, h->LoT, naux, true, R, onv, 1.0, false,
+                   st));
+    T2_TRY(gemm_rr(nv, (int)onv, (int)onv, Tph + (long)I * nv * onv, onv, false, P1, onv, false, R, onv, -1.0, true,
+                   st));
+    T2_TRY(gemm_rr((int)onv, nv, naux, ZT, naux, false, h->LoT + (long)I * nv * naux, naux, true, Rp, nv, 1.0, false,
+                   st));
+    T2_TRY(gemm_rr((int)onv, nv, (int)onv, Tph, onv, false, P1 + (long)I * nv * onv, onv, false, Rp, nv, -1.0, true,
+                   st));
+    k_ring_add<<<grid_for((long)o * nv2), 256, 0, st>>>(R, Rp, o, nv, Nt + (long)I * o * nv2);
+    T2_TRY(launched("k_ring_add"));
+  }
+  drop(R);
+  drop(Rp);
+  drop(P1);
+  drop(ZT);
+  // particle ladder sum_{P,c,d} L^P_ac tau^{cd}_{Ij} L^P_bd through LB[d][P][b] = conj(Lvv[P][d][b]) = L^P_bd:
+  //   U[d][(P,a)] = sum_c tau^{cd} LB[c][(P,a)],  ladder[a][b] = sum_{(d,P)} U[(d,P)][a] LB[(d,P)][b]
+  double2 *LB, *U, *part;
+  const long Kl = (long)nv * naux;
+  const int tiles = ((nv + 127) / 128) * ((nv + 127) / 128);
+  const int nsplit = (int)std::max<long>(1, std::min<long>(std::max(1, 1024 / tiles), Kl / 256));
+  T2_TRY(alloc(&LB, nv2 * naux));
+  T2_TRY(alloc(&U, nv2 * naux));
+  T2_TRY(alloc(&part, (long)nsplit * nv2));
+  k_swap12<true><<<grid_for(nv2 * naux), 256, 0, st>>>(h->Lvv, naux, nv, nv, LB);
+  T2_TRY(launched("k_swap12"));
+  for (int I = 0; I < nc; ++I)
+    for (int j = 0; j < o; ++j) {
+      if (j == I) continue;
+      const int k = std::min(I, j), l = std::max(I, j);
+      const long p = (long)k * o - (long)k * (k + 1) / 2 + (l - k - 1);
+      const double sgn = I < j ? 1.0 : -1.0;
+      T2_TRY(bgemm_kmajor(tau + p * nv2, 0, nv, nv, LB, 0, Kl, (int)Kl, nv, (int)Kl, nv, 1, U, st));
+      T2_TRY(bgemm_kmajor(U, 0, nv, nv, LB, 0, nv, nv, nv, nv, (int)Kl, nsplit, part, st));
+      k_sum_parts<<<grid_for(nv2), 256, 0, st>>>(part, nsplit, nv2, sgn, Nt + ((long)I * o + j) * nv2);
+      T2_TRY(launched("k_sum_parts"));
+    }
+  drop(LB);
+  drop(U);
+  drop(part);
+  k_u_divide<<<grid_for((long)nc * o * nv2), 256, 0, st>>>(Nt, h->eps, nc, o, nv);
+  T2_TRY(launched("k_u_divide"));
+  // pair densities and the particle-hole term
+  double2 *rho, *sig, *wdc, *hb, *f2p;
+  T2_TRY(alloc(&rho, nv2));
+  T2_TRY(alloc(&sig, (long)nc * o));
+  T2_TRY(alloc(&wdc, 3 * onv));
+  T2_TRY(alloc(&hb, 3 * onv));
+  T2_TRY(alloc(&f2p, (long)nc * nv * 3));
+  for (int k = 0; k < o; ++k)
+    T2_TRY(gemm_rr(nv, nv, (int)onv, Tph + (long)k * nv * onv, onv, false, Tph + (long)k * nv * onv, onv, true, rho,
+                   nv, 1.0, k > 0, st));
+  T2_TRY(gemm_rr(nc, o, (int)(nv * onv), Tph, nv * onv, false, Tph, nv * onv, true, sig, o, 1.0, false, st));
+  k_dvo_rows<<<grid_for(3 * onv), 256, 0, st>>>(dip, o, nv, n, wdc);
+  T2_TRY(launched("k_dvo_rows"));
+  T2_TRY(gemm_rr(3, (int)onv, (int)onv, wdc, onv, false, Tph, onv, true, hb, onv, 1.0, false, st));
+  T2_TRY(gemm_rr(nc * nv, 3, (int)onv, Tph, onv, false, hb, onv, false, f2p, 3, 0.5, false, st));
+  k_f2_assemble<<<(unsigned)(3 * nc * nv), 256, 0, st>>>(Nt, sa, rho, sig, f2p, dip, nc, o, nv, n, dim, F);
+  T2_TRY(launched("k_f2_assemble"));
+  release();
+#undef T2_TRY
+  return ADC2_OK;
+}
 }  // namespace adc2
 
 using namespace adc2;
 
 extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, int nroots, const void* X,
-                                                const double* omega, void* T, double* f, void* stream) {
+                                                const double* omega, int order, void* T, double* f, void* stream) {
   if (!h || !dip || !X || !omega || !T || !f) return tfail(ADC2_ERR_ARG, "NULL argument");
+  if (order != 1 && order != 2) return tfail(ADC2_ERR_ARG, "order must be 1 or 2");
   if (nroots < 1 || nroots > ADC2_MAX_ROOTS) return tfail(ADC2_ERR_ARG, "nroots must be in 1..ADC2_MAX_ROOTS");
   hipStream_t st = (hipStream_t)stream;
   const Dims& d = h->d;
@@ -142,6 +513,7 @@ extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, 
     k_tm_singles<<<(unsigned)(3 * nc * nv), 256, 0, st>>>(tau, dp, nc, o, nv, n, dim, F);
     hip(hipGetLastError(), "k_tm_singles");
   }
+  if (rc == ADC2_OK && npairs > 0 && order == 2) status(tm_second_order(h, tau, dpairs, npairs, dp, F, st));
   const unsigned gd = (unsigned)std::min<long>(4096, (nv2 + 255) / 256);
   for (int c = 0; c < 3 && rc == ADC2_OK && npairs > 0; ++c) {
     const double2* dc = dp + (long)c * n * n;

@@ -64,7 +64,7 @@ def test_argument_errors_without_gpu(lib):
     assert lib.adc2_omega_backward(None, 1, None, g, None, None, None) == A.ADC2_ERR_ARG
     assert "NULL" in A.adc2_last_error()
     assert lib.adc2_autotune(None, 1, None, None) == A.ADC2_ERR_ARG and "NULL" in A.adc2_last_error()
-    assert lib.adc2_transition(None, None, 1, None, None, None, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_transition(None, None, 1, None, None, 2, None, None, None) == A.ADC2_ERR_ARG
     nvo = ctypes.c_int(5)
     assert lib.adc2_fns(None, None, 1e-4, ctypes.byref(nvo), None, None, None, None) == A.ADC2_ERR_ARG
     assert "NULL" in A.adc2_last_error()

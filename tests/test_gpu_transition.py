@@ -1,12 +1,20 @@
 """GPU parity of the transition moments and oscillator strengths
 (adc2_transition) against the oracle's transition_moments /
-oscillator_strengths (first-order F, Theory section).
+oscillator_strengths (Theory section), singles of F through second order
+(the default) and through first order.
 
 T = X^H F is linear in X, so random vectors as well as eigenvectors probe F
 element by element in projection: 8 random directions x 3 Cartesian
 components, and the 4 lowest eigenvectors with their oscillator strengths.
 In the nonrelativistic limit with a spin-free dipole every triplet root is
 dark on the GPU as well.
+
+Tolerance: both sides are FP64; the second-order terms are sums over up to
+naux nv (ladder) or o nv (ring, densities) products of O(1e-2) values, whose
+rounding differs between the GEMMs and the oracle's einsum.  Relative
+1e-11 of max |T| covers a random-walk error of sqrt(K) 1.1e-16 with a wide
+margin and is far below the second-order part itself (checked to be above
+1e-4 of max |T|).
 """
 import numpy as np
 import pytest
@@ -23,29 +31,33 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("shape,seed", [((2, 4, 14, 30), 51), ((1, 3, 17, 24), 52)])
+@pytest.mark.parametrize("shape,seed", [((2, 4, 14, 30), 51), ((1, 3, 17, 24), 52), ((3, 2, 11, 20), 53)])
 def test_transition_parity(shape, seed):
     s = make_system(*shape, seed=seed)
     sp = O.Spaces(s.nc, s.no, s.nv)
     dip = dipole_integrals(seed, sp.n)
     print(f"[case] transition moments {shape}", flush=True)
     h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
-    Fo = O.transition_moments(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, order=1).numpy()   # [3][dim]
-    # random directions
+    L, e = O.as_c128(s.L), O.as_f64(s.eps)
     Xr = random_vectors(seed, 8, h.dim)
-    T, f = A.adc2_transition(h, dev(dip), dev(Xr), [1.0] * 8)
-    Tref = Xr.conj() @ Fo.T
-    err = np.abs(T - Tref).max() / np.abs(Tref).max()
-    print(f"  random directions: max rel err {err:.2e}", flush=True)
-    assert err < 1e-12
+    for order, tol in ((1, 1e-12), (2, 1e-11)):
+        Fo = O.transition_moments(L, e, sp, dip, order=order).numpy()   # [3][dim]
+        T, f = A.adc2_transition(h, dev(dip), dev(Xr), [1.0] * 8, order=order)
+        Tref = Xr.conj() @ Fo.T
+        err = np.abs(T - Tref).max() / np.abs(Tref).max()
+        print(f"  order {order} random directions: max rel err {err:.2e}", flush=True)
+        assert err < tol
+    # the second order is a real part of these T
+    F1 = O.transition_moments(L, e, sp, dip, order=1).numpy()
+    assert np.abs(Tref - Xr.conj() @ F1.T).max() > 1e-4 * np.abs(Tref).max()
     # eigenvectors and oscillator strengths
     w, X, inf = A.adc2_davidson(h, 4, tol=1e-10)
     T, f = A.adc2_transition(h, dev(dip), X, w)
-    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w, order=1)
+    Tr, fr = O.oscillator_strengths(L, e, sp, dip, X.cpu(), w)
     ef = np.abs(f - fr.numpy()).max() / np.abs(fr.numpy()).max()
     print(f"  roots {np.round(w, 6)} f {np.round(f, 6)}  rel err {ef:.2e}", flush=True)
-    assert np.abs(T - Tr.numpy()).max() < 1e-12 * np.abs(Tr.numpy()).max()
-    assert ef < 1e-12
+    assert np.abs(T - Tr.numpy()).max() < 1e-11 * np.abs(Tr.numpy()).max()
+    assert ef < 1e-11
     h.close()
 
 
@@ -60,11 +72,11 @@ def test_transition_with_folded_eigenvectors_c1():
     h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
     w, X, inf = A.adc2_davidson(h, 4, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
     T, f = A.adc2_transition(h, dev(dip), X, w)
-    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w, order=1)
+    Tr, fr = O.oscillator_strengths(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, X.cpu(), w)
     err = np.abs(T - Tr.numpy()).max() / np.abs(Tr.numpy()).max()
     print(f"[case] folded c1: f {np.round(f, 5)} rel err {err:.2e}", flush=True)
-    assert err < 1e-12
-    assert np.abs(f - fr.numpy()).max() < 1e-12 * np.abs(fr.numpy()).max()
+    assert err < 1e-11
+    assert np.abs(f - fr.numpy()).max() < 1e-11 * np.abs(fr.numpy()).max()
     h.close()
 
 
@@ -109,4 +121,6 @@ def test_transition_argument_errors():
     X = torch.zeros(33, h.dim, dtype=torch.complex128, device="cuda")
     with pytest.raises(A.Adc2Error):
         A.adc2_transition(h, dip, X, [1.0] * 33)
+    with pytest.raises(A.Adc2Error):
+        A.adc2_transition(h, dip, X[:2], [1.0] * 2, order=3)
     h.close()
