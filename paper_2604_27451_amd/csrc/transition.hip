@@ -280,6 +280,52 @@ __global__ __launch_bounds__(256) void k_f2_assemble(const double2* __restrict__
   }
 }
 
+// part[sl][I][k] = sum over slice sl of e < K of Tph[I][e] conj(Tph[k][e]) (rows of length K);
+// grid (o, nsl), one workgroup per (k, slice)
+__global__ __launch_bounds__(256) void k_sigma_part(const double2* __restrict__ Tph, long K, int nc, int o, int nsl,
+                                                     double2* __restrict__ part) {
+  __shared__ double2 red[8][256];
+  const int k = blockIdx.x, sl = blockIdx.y;
+  const long per = (K + nsl - 1) / nsl;
+  const long e0 = (long)sl * per, e1 = e0 + per < K ? e0 + per : K;
+  const double2* rk = Tph + (long)k * K;
+  for (int I0 = 0; I0 < nc; I0 += 8) {
+    double2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (long e = e0 + threadIdx.x; e < e1; e += 256) {
+      const double2 v = rk[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (I0 + q >= nc) break;
+        const double2 u = Tph[(long)(I0 + q) * K + e];
+        acc[q].x += u.x * v.x + u.y * v.y;   // u conj(v)
+        acc[q].y += u.y * v.x - u.x * v.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = cadd(red[q][threadIdx.x], red[q][threadIdx.x + st]);
+      __syncthreads();
+    }
+    if (threadIdx.x < 8 && I0 + (int)threadIdx.x < nc)
+      part[((long)sl * nc + I0 + threadIdx.x) * o + k] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// dst[e] = conj(src[e])
+__global__ void k_conj(const double2* __restrict__ src, long n, double2* __restrict__ dst) {
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    const double2 v = src[e];
+    dst[e] = make_double2(v.x, -v.y);
+  }
+}
+
 unsigned grid_for(long n) { return (unsigned)std::max<long>(1, std::min<long>(8192, (n + 255) / 256)); }
 
 adc2_status tfail(adc2_status s, const std::string& m) {
@@ -324,6 +370,11 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
     if (e == hipSuccess) return ADC2_OK;
     set_error(std::string("adc2_transition: ") + what + ": " + hipGetErrorString(e));
     return ADC2_ERR_HIP;
+  };
+  auto hip_ok = [&](hipError_t e) -> adc2_status {
+    if (e == hipSuccess) return ADC2_OK;
+    set_error(std::string("adc2_transition: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
   };
 #define T2_TRY(x)                    \
   do {                               \
@@ -413,24 +464,40 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   //   U[d][(P,a)] = sum_c tau^{cd} LB[c][(P,a)],  ladder[a][b] = sum_{(d,P)} U[(d,P)][a] LB[(d,P)][b]
   double2 *LB, *U, *part;
   const long Kl = (long)nv * naux;
-  const int tiles = ((nv + 127) / 128) * ((nv + 127) / 128);
-  const int nsplit = (int)std::max<long>(1, std::min<long>(std::max(1, 1024 / tiles), Kl / 256));
+  constexpr int PB = 8;   // ladder pairs per launch
+  auto nsplit_for = [&](int nb) {   // K-splits that bring a launch to about 1024 workgroups
+    const int tiles = ((nb * nv + 127) / 128) * ((nv + 127) / 128);
+    return (int)std::max<long>(1, std::min<long>(std::max(1, 1024 / tiles), Kl / 256));
+  };
+  const int nsplit1 = nsplit_for(1);
+  const int pbu = std::min(PB, std::max(1, o - 1));
+  long part_len = 0;
+  for (int nb = 1; nb <= pbu; ++nb) part_len = std::max(part_len, (long)nsplit_for(nb) * nb * nv2);
   T2_TRY(alloc(&LB, nv2 * naux));
-  T2_TRY(alloc(&U, nv2 * naux));
-  T2_TRY(alloc(&part, (long)nsplit * nv2));
+  T2_TRY(alloc(&U, (long)pbu * nv2 * naux));
+  T2_TRY(alloc(&part, part_len));
   k_swap12<true><<<grid_for(nv2 * naux), 256, 0, st>>>(h->Lvv, naux, nv, nv, LB);
   T2_TRY(launched("k_swap12"));
-  for (int I = 0; I < nc; ++I)
-    for (int j = 0; j < o; ++j) {
-      if (j == I) continue;
-      const int k = std::min(I, j), l = std::max(I, j);
-      const long p = (long)k * o - (long)k * (k + 1) / 2 + (l - k - 1);
-      const double sgn = I < j ? 1.0 : -1.0;
+  // pairs (I, j > I) lie consecutively in the pair order: up to PB of them per launch pair
+  // (their rows (pair, d) / (pair, a) as groups of nv); pairs (I, j < I) one at a time, sign -1
+  for (int I = 0; I < nc; ++I) {
+    for (int j = 0; j < I; ++j) {
+      const long p = (long)j * o - (long)j * (j + 1) / 2 + (I - j - 1);
       T2_TRY(bgemm_kmajor(tau + p * nv2, 0, nv, nv, LB, 0, Kl, (int)Kl, nv, (int)Kl, nv, 1, U, st));
-      T2_TRY(bgemm_kmajor(U, 0, nv, nv, LB, 0, nv, nv, nv, nv, (int)Kl, nsplit, part, st));
-      k_sum_parts<<<grid_for(nv2), 256, 0, st>>>(part, nsplit, nv2, sgn, Nt + ((long)I * o + j) * nv2);
+      T2_TRY(bgemm_kmajor(U, 0, nv, nv, LB, 0, nv, nv, nv, nv, (int)Kl, nsplit1, part, st));
+      k_sum_parts<<<grid_for(nv2), 256, 0, st>>>(part, nsplit1, nv2, -1.0, Nt + ((long)I * o + j) * nv2);
       T2_TRY(launched("k_sum_parts"));
     }
+    for (int j0 = I + 1; j0 < o; j0 += PB) {
+      const int nb = std::min(PB, o - j0);
+      const long p0 = (long)I * o - (long)I * (I + 1) / 2 + (j0 - I - 1);
+      const int nsb = nsplit_for(nb);
+      T2_TRY(bgemm_kmajor(tau + p0 * nv2, nv2, nv, nv, LB, 0, Kl, (int)Kl, nb * nv, (int)Kl, nv, 1, U, st));
+      T2_TRY(bgemm_kmajor(U, nv * Kl, nv, nv, LB, 0, nv, nv, nb * nv, nv, (int)Kl, nsb, part, st));
+      k_sum_parts<<<grid_for(nb * nv2), 256, 0, st>>>(part, nsb, nb * nv2, 1.0, Nt + ((long)I * o + j0) * nv2);
+      T2_TRY(launched("k_sum_parts"));
+    }
+  }
   drop(LB);
   drop(U);
   drop(part);
@@ -443,10 +510,35 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   T2_TRY(alloc(&wdc, 3 * onv));
   T2_TRY(alloc(&hb, 3 * onv));
   T2_TRY(alloc(&f2p, (long)nc * nv * 3));
-  for (int k = 0; k < o; ++k)
-    T2_TRY(gemm_rr(nv, nv, (int)onv, Tph + (long)k * nv * onv, onv, false, Tph + (long)k * nv * onv, onv, true, rho,
-                   nv, 1.0, k > 0, st));
-  T2_TRY(gemm_rr(nc, o, (int)(nv * onv), Tph, nv * onv, false, Tph, nv * onv, true, sig, o, 1.0, false, st));
+  {
+    // rho_ac = 2 sum_{(p, b)} tau_p[b][a] conj(tau_p[b][c]) over the pairs p = (k < l): split-K GEMM of
+    // the K-major rows (p, b) against their conjugate
+    double2 *tc, *rpart;
+    const long Kr = (long)npairs * nv;
+    const int nsr = (int)std::max<long>(1, std::min<long>(std::max(1, 1024 / (((nv + 127) / 128) * ((nv + 127) / 128))),
+                                                          Kr / 256));
+    T2_TRY(alloc(&tc, (long)npairs * nv2));
+    T2_TRY(alloc(&rpart, (long)nsr * nv2));
+    k_conj<<<grid_for((long)npairs * nv2), 256, 0, st>>>(tau, (long)npairs * nv2, tc);
+    T2_TRY(launched("k_conj"));
+    T2_TRY(bgemm_kmajor(tau, 0, nv, nv, tc, 0, nv, nv, nv, nv, (int)Kr, nsr, rpart, st));
+    T2_TRY(hip_ok(hipMemsetAsync(rho, 0, sizeof(double2) * nv2, st)));
+    k_sum_parts<<<grid_for(nv2), 256, 0, st>>>(rpart, nsr, nv2, 2.0, rho);
+    T2_TRY(launched("k_sum_parts"));
+    drop(tc);
+    drop(rpart);
+    // sigma_Ik over slices of the rows of Tph
+    double2* spart;
+    const long Ks = nv * onv;
+    const int nsl = (int)std::max<long>(1, std::min<long>(64, Ks / 4096));
+    T2_TRY(alloc(&spart, (long)nsl * nc * o));
+    k_sigma_part<<<dim3(o, nsl), 256, 0, st>>>(Tph, Ks, nc, o, nsl, spart);
+    T2_TRY(launched("k_sigma_part"));
+    T2_TRY(hip_ok(hipMemsetAsync(sig, 0, sizeof(double2) * nc * o, st)));
+    k_sum_parts<<<grid_for((long)nc * o), 256, 0, st>>>(spart, nsl, (long)nc * o, 1.0, sig);
+    T2_TRY(launched("k_sum_parts"));
+    drop(spart);
+  }
   k_dvo_rows<<<grid_for(3 * onv), 256, 0, st>>>(dip, o, nv, n, wdc);
   T2_TRY(launched("k_dvo_rows"));
   T2_TRY(gemm_rr(3, (int)onv, (int)onv, wdc, onv, false, Tph, onv, true, hb, onv, 1.0, false, st));
