@@ -124,3 +124,28 @@ def test_transition_argument_errors():
     with pytest.raises(A.Adc2Error):
         A.adc2_transition(h, dip, X[:2], [1.0] * 2, order=3)
     h.close()
+
+
+def test_transition_c2_shift_invariance():
+    """nc=6, no=60, nv=300, naux=1500, second order, 4 random directions.
+    Every intermediate state is orthogonal to Psi0, so T is unchanged by
+    d -> d + c 1 at any size: at second order this needs the two
+    singles-amplitude terms to cancel to rounding across the whole
+    occupied space, and the remaining terms to see no diagonal of d.  The
+    second-order part itself is checked to be present."""
+    from synth import config_system
+    s = config_system("c2")
+    n = s.nc + s.no + s.nv
+    print(f"[case] transition c2 shift invariance", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    dip = dipole_integrals(11, n)
+    X = dev(random_vectors(12, 4, h.dim))
+    T1, _ = A.adc2_transition(h, dev(dip), X, [1.0] * 4, order=1)
+    T2, _ = A.adc2_transition(h, dev(dip), X, [1.0] * 4, order=2)
+    Ts, _ = A.adc2_transition(h, dev(dip + 0.7 * np.eye(n)[None]), X, [1.0] * 4, order=2)
+    h.close()
+    err = np.abs(Ts - T2).max() / np.abs(T2).max()
+    print(f"  shift: rel change {err:.2e}; second-order part {np.abs(T2 - T1).max() / np.abs(T2).max():.2e}",
+          flush=True)
+    assert err < 1e-12
+    assert np.abs(T2 - T1).max() > 1e-3 * np.abs(T2).max()
