@@ -460,47 +460,38 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   drop(Rp);
   drop(P1);
   drop(ZT);
-  // particle ladder sum_{P,c,d} L^P_ac tau^{cd}_{Ij} L^P_bd through LB[d][P][b] = conj(Lvv[P][d][b]) = L^P_bd:
-  //   U[d][(P,a)] = sum_c tau^{cd} LB[c][(P,a)],  ladder[a][b] = sum_{(d,P)} U[(d,P)][a] LB[(d,P)][b]
-  double2 *LB, *U, *part;
-  const long Kl = (long)nv * naux;
-  constexpr int PB = 8;   // ladder pairs per launch
-  auto nsplit_for = [&](int nb) {   // K-splits that bring a launch to about 1024 workgroups
-    const int tiles = ((nb * nv + 127) / 128) * ((nv + 127) / 128);
-    return (int)std::max<long>(1, std::min<long>(std::max(1, 1024 / tiles), Kl / 256));
-  };
-  const int nsplit1 = nsplit_for(1);
-  const int pbu = std::min(PB, std::max(1, o - 1));
-  long part_len = 0;
-  for (int nb = 1; nb <= pbu; ++nb) part_len = std::max(part_len, (long)nsplit_for(nb) * nb * nv2);
-  T2_TRY(alloc(&LB, nv2 * naux));
-  T2_TRY(alloc(&U, (long)pbu * nv2 * naux));
-  T2_TRY(alloc(&part, part_len));
-  k_swap12<true><<<grid_for(nv2 * naux), 256, 0, st>>>(h->Lvv, naux, nv, nv, LB);
-  T2_TRY(launched("k_swap12"));
-  // pairs (I, j > I) lie consecutively in the pair order: up to PB of them per launch pair
-  // (their rows (pair, d) / (pair, a) as groups of nv); pairs (I, j < I) one at a time, sign -1
-  for (int I = 0; I < nc; ++I) {
-    for (int j = 0; j < I; ++j) {
-      const long p = (long)j * o - (long)j * (j + 1) / 2 + (I - j - 1);
-      T2_TRY(bgemm_kmajor(tau + p * nv2, 0, nv, nv, LB, 0, Kl, (int)Kl, nv, (int)Kl, nv, 1, U, st));
-      T2_TRY(bgemm_kmajor(U, 0, nv, nv, LB, 0, nv, nv, nv, nv, (int)Kl, nsplit1, part, st));
-      k_sum_parts<<<grid_for(nv2), 256, 0, st>>>(part, nsplit1, nv2, -1.0, Nt + ((long)I * o + j) * nv2);
-      T2_TRY(launched("k_sum_parts"));
+  // particle ladder sum_{c,d} (ac|bd) tau^{cd}_{Ij} for every pair (I, j), in blocks of ab a-values:
+  //   V[(a,c)][(b,d)] = sum_P L^P_ac L^P_bd   (K-major GEMM over P)
+  //   W[a][b][(c,d)]  = V[a][c][b][d]          (per-a swap of c and b)
+  //   Nt[(I,j)][a][b] += sum_{(c,d)} tau^{cd}_{Ij} W[(a,b)][(c,d)]
+  // with the signed amplitudes of the pairs (I, j) gathered as TIj[(I,j)][(c,d)] from Tph.
+  {
+    double2 *TIj, *V, *W;
+    const int ab = std::min(nv, 16);
+    T2_TRY(alloc(&TIj, (long)nc * o * nv2));
+    for (int I = 0; I < nc; ++I) {
+      k_swap12<false><<<grid_for(onv * nv), 256, 0, st>>>(Tph + (long)I * nv * onv, nv, o, nv,
+                                                          TIj + (long)I * o * nv2);
+      T2_TRY(launched("k_swap12"));
     }
-    for (int j0 = I + 1; j0 < o; j0 += PB) {
-      const int nb = std::min(PB, o - j0);
-      const long p0 = (long)I * o - (long)I * (I + 1) / 2 + (j0 - I - 1);
-      const int nsb = nsplit_for(nb);
-      T2_TRY(bgemm_kmajor(tau + p0 * nv2, nv2, nv, nv, LB, 0, Kl, (int)Kl, nb * nv, (int)Kl, nv, 1, U, st));
-      T2_TRY(bgemm_kmajor(U, nv * Kl, nv, nv, LB, 0, nv, nv, nb * nv, nv, (int)Kl, nsb, part, st));
-      k_sum_parts<<<grid_for(nb * nv2), 256, 0, st>>>(part, nsb, nb * nv2, 1.0, Nt + ((long)I * o + j0) * nv2);
-      T2_TRY(launched("k_sum_parts"));
+    T2_TRY(alloc(&V, (long)ab * nv * nv2));
+    T2_TRY(alloc(&W, (long)ab * nv * nv2));
+    for (int a0 = 0; a0 < nv; a0 += ab) {
+      const int na = std::min(ab, nv - a0);
+      T2_TRY(bgemm_kmajor(h->Lvv + (long)a0 * nv, 0, nv2, na * nv, h->Lvv, 0, nv2, (int)nv2, na * nv, (int)nv2, naux,
+                          1, V, st));
+      k_swap12<false><<<grid_for((long)na * nv * nv2), 256, 0, st>>>(V, (long)na * nv, nv, nv, W);
+      T2_TRY(launched("k_swap12"));
+      // W as [a][c][b][d] -> [a][b][c][d]: the swap above exchanged (a,c) with b; restore a as the outer index
+      k_swap12<false><<<grid_for((long)na * nv * nv2), 256, 0, st>>>(W, nv, na, nv * (long)nv, V);
+      T2_TRY(launched("k_swap12"));
+      T2_TRY(gemm_rr(nc * o, na * nv, (int)nv2, TIj, nv2, false, V, nv2, false, Nt + (long)a0 * nv, nv2, 1.0, true,
+                     st));
     }
+    drop(TIj);
+    drop(V);
+    drop(W);
   }
-  drop(LB);
-  drop(U);
-  drop(part);
   k_u_divide<<<grid_for((long)nc * o * nv2), 256, 0, st>>>(Nt, h->eps, nc, o, nv);
   T2_TRY(launched("k_u_divide"));
   // pair densities and the particle-hole term
