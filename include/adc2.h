@@ -329,9 +329,11 @@ ADC2_API int adc2_kernel_stats(adc2_handle h, adc2_kstat* out, int max);
  *   T      host complex128 [nroots][3]; f host float64 [nroots].
  * Work space: the MP2 amplitudes of every occupied pair (o(o-1)/2 nv^2
  * complex), F (3 dim complex) and small buffers; order 2 adds up to three
- * o^2 nv^2 arrays (amplitudes of every ordered pair, (kj|bc) twice) and
- * 2 naux nv^2 + nc o nv^2; all allocated and freed here.  The particle
- * ladder costs 2 nc o naux nv^3 complex multiply-adds (FP64 MFMA).
+ * o^2 nv^2 arrays (amplitudes of every ordered pair, (kj|bc) twice), the
+ * (ac|bd) integrals of up to 32 a-values twice (at most 2 x 16 GiB) and
+ * naux nv^2 + 2 nc o nv^2; all allocated and freed here (about 35 GB at
+ * nc=6, no=60, nv=300; ADC2_ERR_OOM where it does not fit).  The particle
+ * ladder costs naux nv^4 + nc o nv^4 complex multiply-adds (FP64 MFMA).
  * Synchronises the stream.  Errors: ADC2_ERR_ARG (NULL argument, nroots out
  * of 1..ADC2_MAX_ROOTS, order not 1 or 2), ADC2_ERR_OOM, ADC2_ERR_HIP.
  */

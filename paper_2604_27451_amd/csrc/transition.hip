@@ -467,7 +467,9 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   // with the signed amplitudes of the pairs (I, j) gathered as TIj[(I,j)][(c,d)] from Tph.
   {
     double2 *TIj, *V, *W;
-    const int ab = std::min(nv, 16);
+    // a-values per block: up to 32, each of V and W under 16 GiB
+    const long per_a = (long)nv * nv2 * (long)sizeof(double2);
+    const int ab = (int)std::max<long>(1, std::min<long>(std::min(nv, 32), (16L << 30) / per_a));
     T2_TRY(alloc(&TIj, (long)nc * o * nv2));
     for (int I = 0; I < nc; ++I) {
       k_swap12<false><<<grid_for(onv * nv), 256, 0, st>>>(Tph + (long)I * nv * onv, nv, o, nv,
