@@ -61,6 +61,27 @@ def test_transition_parity(shape, seed):
     h.close()
 
 
+@pytest.mark.parametrize("shape,seed", [((1, 1, 3, 5), 61), ((2, 1, 5, 9), 62), ((3, 1, 2, 6), 63)])
+def test_transition_tiny_shapes(shape, seed):
+    """Edge shapes of the second-order path: a single occupied pair
+    (o = 2), more core than valence spinors, two virtuals (one virtual
+    pair); random directions only."""
+    s = make_system(*shape, seed=seed)
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    dip = dipole_integrals(seed, sp.n)
+    print(f"[case] transition tiny {shape}", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    Xr = random_vectors(seed, 3, h.dim)
+    for order in (1, 2):
+        Fo = O.transition_moments(O.as_c128(s.L), O.as_f64(s.eps), sp, dip, order=order).numpy()
+        T, _ = A.adc2_transition(h, dev(dip), dev(Xr), [1.0] * 3, order=order)
+        Tref = Xr.conj() @ Fo.T
+        err = np.abs(T - Tref).max() / np.abs(Tref).max()
+        print(f"  order {order}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-11
+    h.close()
+
+
 def test_transition_with_folded_eigenvectors_c1():
     """Eigenvectors of the folded solver (doubles rebuilt from the singles) at
     nc=6, no=10, nv=40, naux=150: GPU transition moments against the oracle's
