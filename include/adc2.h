@@ -107,6 +107,27 @@ typedef struct {
 } adc2_dav_info;
 
 /*
+ * Device-memory callbacks, optional in adc2_setup / adc2_setup_batch.  With
+ * them, every device buffer of a handle -- its integral blocks and sigma work
+ * spaces, and the per-call work spaces of the entry points that take the
+ * handle (solvers, adjoint, transition moments, natural spinors, autotuner)
+ * -- comes from alloc(bytes, ctx) and goes back through release(ptr, ctx), so
+ * that a caching allocator (PyTorch's, for instance) can back it.  alloc
+ * returns NULL when it cannot serve the request (reported as ADC2_ERR_OOM);
+ * the returned memory must be device memory of the current device, aligned
+ * to 256 bytes.  The library waits for the device to be idle before each
+ * release, as hipFree does.  NULL, or alloc == NULL, selects hipMalloc and
+ * hipFree.  The struct is copied at setup; ctx must stay valid for the
+ * handle's lifetime.  Pinned host staging buffers and the handle-free
+ * adc2_peak_probe still use the HIP allocators.
+ */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, void* ctx);
+  void* ctx;
+} adc2_alloc;
+
+/*
  * adc2_setup -- build a handle for one system.
  *   L     dev, complex128 [naux][n][n]; each L[P] must be Hermitian
  *         (L[P][q][p] = conj(L[P][p][q])); read only during the call.
@@ -115,6 +136,7 @@ typedef struct {
  *         occupied denominator must be nonzero.
  *   nc, no, nv, naux  > 0 (nv >= 2).
  *   prec  adc2_precision: arithmetic of the sigma build (setup is always FP64).
+ *   alloc optional device-memory callbacks (above), NULL for hipMalloc.
  * Work done (stream-ordered, then synchronised): slicing L into the
  * virtual-virtual, virtual-occupied and occupied-occupied blocks; the MP2
  * amplitudes tau = <ac||kl> / D^{ac}_{kl} over all occupied k,l (denominators
@@ -125,7 +147,7 @@ typedef struct {
  * On error *out is set to NULL and nothing is leaked.
  */
 ADC2_API adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
-                       int naux, int prec, void* stream, adc2_handle* out);
+                       int naux, int prec, const adc2_alloc* alloc, void* stream, adc2_handle* out);
 
 /* Vector length nc*nv + nc*no*nv*(nv-1)/2 (0 for a NULL handle). */
 ADC2_API size_t adc2_dim(adc2_handle h);
@@ -234,13 +256,14 @@ typedef struct {
 
 /*
  * adc2_setup_batch -- adc2_setup for nmol systems (1..64) with one precision.
+ *   alloc  optional device-memory callbacks shared by every handle (NULL: hipMalloc).
  *   mols   host [nmol]; out host [nmol] receives the handles (each released
  *          with adc2_destroy).  On error every handle already built is
  *          destroyed, out[] is set to NULL and the failing system's index is
  *          named in adc2_last_error.  Synchronises the stream.
  */
-ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, void* stream,
-                                      adc2_handle* out);
+ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, const adc2_alloc* alloc,
+                                      void* stream, adc2_handle* out);
 
 /*
  * adc2_sigma_batch -- S_i = M_i X_i for nmol systems in one batched launch

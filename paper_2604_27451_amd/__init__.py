@@ -100,6 +100,34 @@ class KStat(ctypes.Structure):
                 ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Alloc(ctypes.Structure):
+    """adc2_alloc: device-memory callbacks of a handle."""
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def torch_allocator():
+    """Device-memory callbacks backed by PyTorch's caching allocator (on the
+    current device and stream): pass as alloc= to adc2_setup /
+    adc2_setup_batch.  A request the allocator cannot serve returns NULL,
+    which the library reports as ADC2_ERR_OOM."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _release(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Alloc(_ALLOC_FN(_alloc), _RELEASE_FN(_release), None)
+
+
 class Adc2Error(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -124,7 +152,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
-    lib.adc2_setup.argtypes = [vp, vp, i, i, i, i, i, vp, ctypes.POINTER(vp)]
+    lib.adc2_setup.argtypes = [vp, vp, i, i, i, i, i, ctypes.POINTER(Alloc), vp, ctypes.POINTER(vp)]
     lib.adc2_setup.restype = i
     lib.adc2_dim.argtypes = [vp]
     lib.adc2_dim.restype = ctypes.c_size_t
@@ -149,7 +177,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_profile.restype = i
     lib.adc2_kernel_stats.argtypes = [vp, ctypes.POINTER(KStat), i]
     lib.adc2_kernel_stats.restype = i
-    lib.adc2_setup_batch.argtypes = [i, ctypes.POINTER(Mol), i, vp, ctypes.POINTER(vp)]
+    lib.adc2_setup_batch.argtypes = [i, ctypes.POINTER(Mol), i, ctypes.POINTER(Alloc), vp, ctypes.POINTER(vp)]
     lib.adc2_setup_batch.restype = i
     lib.adc2_sigma_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp]
@@ -199,8 +227,9 @@ def _need(t, dtype, what):
 
 
 class Handle:
-    def __init__(self, ptr, nc, no, nv, naux):
+    def __init__(self, ptr, nc, no, nv, naux, alloc=None):
         self.ptr = ptr
+        self.alloc = alloc          # keeps the callbacks alive while the handle lives
         self.nc, self.no, self.nv, self.naux = nc, no, nv, naux
         self.dim = int(load().adc2_dim(ptr))
         self.ns = nc * nv
@@ -217,7 +246,9 @@ class Handle:
             pass
 
 
-def adc2_setup(L, eps, nc, no, nv, naux, prec=ADC2_FP64, stream=None) -> Handle:
+def adc2_setup(L, eps, nc, no, nv, naux, prec=ADC2_FP64, stream=None, alloc=None) -> Handle:
+    """Handle of one system.  alloc: None (hipMalloc), "torch" (PyTorch's
+    caching allocator) or an Alloc of one's own."""
     import torch
     _need(L, torch.complex128, "L")
     _need(eps, torch.float64, "eps")
@@ -225,10 +256,12 @@ def adc2_setup(L, eps, nc, no, nv, naux, prec=ADC2_FP64, stream=None) -> Handle:
     if tuple(L.shape) != (naux, n, n) or tuple(eps.shape) != (n,):
         raise ValueError("L must be [naux][n][n] and eps [n]")
     out = ctypes.c_void_p()
+    al = torch_allocator() if alloc == "torch" else alloc
     st = load().adc2_setup(ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(eps.data_ptr()),
-                           nc, no, nv, naux, prec, _stream_ptr(stream), ctypes.byref(out))
+                           nc, no, nv, naux, prec, ctypes.byref(al) if al is not None else None,
+                           _stream_ptr(stream), ctypes.byref(out))
     _check(st, "adc2_setup")
-    return Handle(out, nc, no, nv, naux)
+    return Handle(out, nc, no, nv, naux, al)
 
 
 def adc2_dim(h: Handle) -> int:
@@ -279,8 +312,9 @@ def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, ngues
     return res
 
 
-def adc2_setup_batch(systems, prec=ADC2_FP64, stream=None):
-    """Handles for a batch of systems; systems is a list of (L, eps, nc, no, nv, naux)."""
+def adc2_setup_batch(systems, prec=ADC2_FP64, stream=None, alloc=None):
+    """Handles for a batch of systems; systems is a list of (L, eps, nc, no, nv, naux);
+    alloc as in adc2_setup."""
     import torch
     n = len(systems)
     mols = (Mol * n)()
@@ -292,8 +326,10 @@ def adc2_setup_batch(systems, prec=ADC2_FP64, stream=None):
             raise ValueError(f"system {q}: L must be [naux][n][n] and eps [n]")
         mols[q] = Mol(L.data_ptr(), eps.data_ptr(), nc, no, nv, naux)
     out = (ctypes.c_void_p * n)()
-    _check(load().adc2_setup_batch(n, mols, prec, _stream_ptr(stream), out), "adc2_setup_batch")
-    return [Handle(ctypes.c_void_p(out[q]), *systems[q][2:6]) for q in range(n)]
+    al = torch_allocator() if alloc == "torch" else alloc
+    _check(load().adc2_setup_batch(n, mols, prec, ctypes.byref(al) if al is not None else None,
+                                   _stream_ptr(stream), out), "adc2_setup_batch")
+    return [Handle(ctypes.c_void_p(out[q]), *systems[q][2:6], alloc=al) for q in range(n)]
 
 
 def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):

@@ -28,25 +28,25 @@ static adc2_status fail(adc2_status st, const std::string& msg) {
 
 static void free_handle(adc2_handle h) {
   if (!h) return;
-  hipFree(h->Lvv);
-  hipFree(h->Lvo);
-  hipFree(h->Loo);
-  hipFree(h->Vt);
-  hipFree(h->LoT);
-  hipFree(h->Lv32);
-  hipFree(h->LvT32);
-  hipFree(h->LvB);
-  hipFree(h->LvTB);
-  hipFree(h->XB);
-  hipFree(h->RB);
-  hipFree(h->eps);
-  hipFree(h->M11);
-  hipFree(h->diag);
-  hipFree(h->X);
-  hipFree(h->Y);
-  hipFree(h->part);
-  hipFree(h->Zb);
-  hipFree(h->Tp);
+  dfree(h, h->Lvv);
+  dfree(h, h->Lvo);
+  dfree(h, h->Loo);
+  dfree(h, h->Vt);
+  dfree(h, h->LoT);
+  dfree(h, h->Lv32);
+  dfree(h, h->LvT32);
+  dfree(h, h->LvB);
+  dfree(h, h->LvTB);
+  dfree(h, h->XB);
+  dfree(h, h->RB);
+  dfree(h, h->eps);
+  dfree(h, h->M11);
+  dfree(h, h->diag);
+  dfree(h, h->X);
+  dfree(h, h->Y);
+  dfree(h, h->part);
+  dfree(h, h->Zb);
+  dfree(h, h->Tp);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (int i = 0; i <= adc2_handle_s::NK; ++i)
@@ -110,6 +110,30 @@ __global__ void k_gather_theta(const double* __restrict__ th, const int* __restr
 
 using namespace adc2;
 
+namespace adc2 {
+
+hipError_t dmalloc_raw(adc2_handle h, void** p, size_t bytes) {
+  if (!h || !h->alloc.alloc) return hipMalloc(p, bytes);
+  if (bytes == 0) {          // as hipMalloc: success, no memory
+    *p = nullptr;
+    return hipSuccess;
+  }
+  *p = h->alloc.alloc(bytes, h->alloc.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dfree(adc2_handle h, void* p) {
+  if (!p) return;
+  if (!h || !h->alloc.alloc) {
+    hipFree(p);
+    return;
+  }
+  hipDeviceSynchronize();
+  h->alloc.release(p, h->alloc.ctx);
+}
+
+}  // namespace adc2
+
 extern "C" {
 
 const char* adc2_last_error(void) { return g_last_error.c_str(); }
@@ -122,7 +146,7 @@ adc2_status adc2_destroy(adc2_handle h) {
 }
 
 adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv, int naux, int prec,
-                       void* stream, adc2_handle* out) {
+                       const adc2_alloc* alloc, void* stream, adc2_handle* out) {
   if (!out) return fail(ADC2_ERR_ARG, "adc2_setup: out is NULL");
   *out = nullptr;
   if (!L || !eps) return fail(ADC2_ERR_ARG, "adc2_setup: L or eps is NULL");
@@ -146,6 +170,13 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
   d.dim = d.ns + d.nd;
   d.nocc_pair = (long)d.o * (d.o - 1) / 2;
   h->prec = prec;
+  if (alloc && alloc->alloc) {
+    if (!alloc->release) {
+      delete h;
+      return fail(ADC2_ERR_ARG, "adc2_setup: alloc callbacks need both alloc and release");
+    }
+    h->alloc = *alloc;
+  }
   if (const char* v = getenv("ADC2_ZGEMM")) h->gemm3 = (strcmp(v, "3m") == 0) ? 1 : 0;
 #define SETUP_TRY(call)                                                           \
   do {                                                                            \
@@ -165,13 +196,13 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
       free_handle(h);
       return fail(ADC2_ERR_NONFINITE, "adc2_setup: non-finite spinor energy");
     }
-  SETUP_TRY(hipMalloc(&h->Lvv, sizeof(double2) * (size_t)naux * nv * nv));
-  SETUP_TRY(hipMalloc(&h->Lvo, sizeof(double2) * (size_t)d.o * naux * nv));
-  SETUP_TRY(hipMalloc(&h->Loo, sizeof(double2) * (size_t)naux * d.o * d.o));
-  SETUP_TRY(hipMalloc(&h->Vt, sizeof(double2) * (size_t)nc * no * nc * nv));
-  SETUP_TRY(hipMalloc(&h->eps, sizeof(double) * d.n));
-  SETUP_TRY(hipMalloc(&h->M11, sizeof(double2) * (size_t)d.ns * d.ns));
-  SETUP_TRY(hipMalloc(&h->diag, sizeof(double) * (size_t)d.dim));
+  SETUP_TRY(dmalloc(h, &h->Lvv, sizeof(double2) * (size_t)naux * nv * nv));
+  SETUP_TRY(dmalloc(h, &h->Lvo, sizeof(double2) * (size_t)d.o * naux * nv));
+  SETUP_TRY(dmalloc(h, &h->Loo, sizeof(double2) * (size_t)naux * d.o * d.o));
+  SETUP_TRY(dmalloc(h, &h->Vt, sizeof(double2) * (size_t)nc * no * nc * nv));
+  SETUP_TRY(dmalloc(h, &h->eps, sizeof(double) * d.n));
+  SETUP_TRY(dmalloc(h, &h->M11, sizeof(double2) * (size_t)d.ns * d.ns));
+  SETUP_TRY(dmalloc(h, &h->diag, sizeof(double) * (size_t)d.dim));
   SETUP_TRY(hipEventCreate(&h->ev0));
   SETUP_TRY(hipEventCreate(&h->ev1));
   SETUP_TRY(hipMemcpyAsync(h->eps, eps, sizeof(double) * d.n, hipMemcpyDeviceToDevice, st));
@@ -231,7 +262,7 @@ adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, do
   std::vector<double> hp(32 * (size_t)nblk);
   auto done = [&](adc2_status r) {
     h->prec = saved;
-    hipFree(S); hipFree(G); hipFree(scr); hipFree(w); hipFree(np);
+    dfree(h, S); dfree(h, G); dfree(h, scr); dfree(h, w); dfree(h, np);
     return r;
   };
 #define RQ_TRY(call)                                                            \
@@ -242,11 +273,11 @@ adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* omega, do
       return done(e_ == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP);     \
     }                                                                           \
   } while (0)
-  RQ_TRY(hipMalloc(&S, sizeof(double2) * k * dim));
-  RQ_TRY(hipMalloc(&G, sizeof(double2) * 2 * 32 * 32));
-  RQ_TRY(hipMalloc(&scr, sizeof(double2) * 256 * (long)nblk * 16 * 4));
-  RQ_TRY(hipMalloc(&w, sizeof(double) * 32));
-  RQ_TRY(hipMalloc(&np, sizeof(double) * 32 * nblk));
+  RQ_TRY(dmalloc(h, &S, sizeof(double2) * k * dim));
+  RQ_TRY(dmalloc(h, &G, sizeof(double2) * 2 * 32 * 32));
+  RQ_TRY(dmalloc(h, &scr, sizeof(double2) * 256 * (long)nblk * 16 * 4));
+  RQ_TRY(dmalloc(h, &w, sizeof(double) * 32));
+  RQ_TRY(dmalloc(h, &np, sizeof(double) * 32 * nblk));
   h->prec = ADC2_FP64;
   if ((rc = sigma_fp64(h, k, (const double2*)X, S, st)) != ADC2_OK) return done(rc);
   if ((rc = dav_gram((const double2*)X, k, S, k, dim, G, 32, scr, st)) != ADC2_OK) return done(rc);
@@ -341,16 +372,17 @@ adc2_status adc2_mp2_energy(adc2_handle h, double* e) {
 namespace {
 
 struct DavWork {
+  adc2_handle h = nullptr;   // owner of the allocations (its callbacks, if any)
   double2 *V = nullptr, *S = nullptr, *Xb = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr;
   double2 *Vn = nullptr, *Sn = nullptr, *Ref = nullptr, *P = nullptr;
   double2 *G = nullptr, *Z = nullptr, *Gt = nullptr, *Ut = nullptr, *Cc = nullptr, *scratch = nullptr;
   double *theta = nullptr, *lam = nullptr, *npart = nullptr, *thact = nullptr;
   int *idx = nullptr, *count = nullptr;
   ~DavWork() {
-    hipFree(V); hipFree(S); hipFree(Xb); hipFree(R); hipFree(T); hipFree(T2); hipFree(Vn); hipFree(Sn);
-    hipFree(Ref); hipFree(P);
-    hipFree(G); hipFree(Z); hipFree(Gt); hipFree(Ut); hipFree(Cc); hipFree(scratch);
-    hipFree(theta); hipFree(lam); hipFree(npart); hipFree(thact); hipFree(idx); hipFree(count);
+    dfree(h, V); dfree(h, S); dfree(h, Xb); dfree(h, R); dfree(h, T); dfree(h, T2); dfree(h, Vn); dfree(h, Sn);
+    dfree(h, Ref); dfree(h, P);
+    dfree(h, G); dfree(h, Z); dfree(h, Gt); dfree(h, Ut); dfree(h, Cc); dfree(h, scratch);
+    dfree(h, theta); dfree(h, lam); dfree(h, npart); dfree(h, thact); dfree(h, idx); dfree(h, count);
   }
 };
 
@@ -400,7 +432,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     if (nroots <= 0 || nroots > ADC2_MAX_ROOTS) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..32");
     hipStream_t st = (hipStream_t)stream;
     double2* Xm = nullptr;
-    if (hipMalloc(&Xm, sizeof(double2) * (size_t)nroots * h->d.dim) != hipSuccess)
+    if (dmalloc(h, &Xm, sizeof(double2) * (size_t)nroots * h->d.dim) != hipSuccess)
       return fail(ADC2_ERR_OOM, "adc2_davidson: no memory for the first-stage vectors");
     adc2_dav_opts o1 = *opt;
     o1.mixed_tol = 0.0;
@@ -417,7 +449,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     }
     const std::string msg = r == ADC2_OK ? std::string() : std::string(adc2_last_error());
     (void)hipStreamSynchronize(st);
-    hipFree(Xm);
+    dfree(h, Xm);
     if (info) {
       *info = i2;
       info->iters = i1.iters + i2.iters;
@@ -459,31 +491,32 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   const int nblk = dav_nblk(dim);
 
   DavWork w;
+  w.h = h;
 #define DAV_TRY(call) ADC2_HIP(call)
-  DAV_TRY(hipMalloc(&w.V, sizeof(double2) * max_sub * dim));
-  DAV_TRY(hipMalloc(&w.S, sizeof(double2) * max_sub * dim));
-  DAV_TRY(hipMalloc(&w.Xb, sizeof(double2) * k * dim));
-  DAV_TRY(hipMalloc(&w.R, sizeof(double2) * k * dim));
-  DAV_TRY(hipMalloc(&w.T, sizeof(double2) * std::max(k, nguess) * dim));
-  DAV_TRY(hipMalloc(&w.T2, sizeof(double2) * std::max(k, nguess) * dim));
-  DAV_TRY(hipMalloc(&w.Vn, sizeof(double2) * keep_max * dim));
-  DAV_TRY(hipMalloc(&w.Sn, sizeof(double2) * keep_max * dim));
-  DAV_TRY(hipMalloc(&w.G, sizeof(double2) * LDG * LDG));
-  DAV_TRY(hipMalloc(&w.Z, sizeof(double2) * LDG * LDG));
-  DAV_TRY(hipMalloc(&w.Gt, sizeof(double2) * LDG * LDG));
-  DAV_TRY(hipMalloc(&w.Ut, sizeof(double2) * LDG * LDG));
-  DAV_TRY(hipMalloc(&w.Cc, sizeof(double2) * LDG * 32));
-  DAV_TRY(hipMalloc(&w.scratch, sizeof(double2) * 256 * (long)nblk * 16 * 4));
-  DAV_TRY(hipMalloc(&w.theta, sizeof(double) * LDG));
-  DAV_TRY(hipMalloc(&w.lam, sizeof(double) * LDG));
-  DAV_TRY(hipMalloc(&w.npart, sizeof(double) * 32 * nblk));
-  DAV_TRY(hipMalloc(&w.thact, sizeof(double) * 32));
-  DAV_TRY(hipMalloc(&w.idx, sizeof(int) * LDG));
-  DAV_TRY(hipMalloc(&w.count, sizeof(int)));
+  DAV_TRY(dmalloc(h, &w.V, sizeof(double2) * max_sub * dim));
+  DAV_TRY(dmalloc(h, &w.S, sizeof(double2) * max_sub * dim));
+  DAV_TRY(dmalloc(h, &w.Xb, sizeof(double2) * k * dim));
+  DAV_TRY(dmalloc(h, &w.R, sizeof(double2) * k * dim));
+  DAV_TRY(dmalloc(h, &w.T, sizeof(double2) * std::max(k, nguess) * dim));
+  DAV_TRY(dmalloc(h, &w.T2, sizeof(double2) * std::max(k, nguess) * dim));
+  DAV_TRY(dmalloc(h, &w.Vn, sizeof(double2) * keep_max * dim));
+  DAV_TRY(dmalloc(h, &w.Sn, sizeof(double2) * keep_max * dim));
+  DAV_TRY(dmalloc(h, &w.G, sizeof(double2) * LDG * LDG));
+  DAV_TRY(dmalloc(h, &w.Z, sizeof(double2) * LDG * LDG));
+  DAV_TRY(dmalloc(h, &w.Gt, sizeof(double2) * LDG * LDG));
+  DAV_TRY(dmalloc(h, &w.Ut, sizeof(double2) * LDG * LDG));
+  DAV_TRY(dmalloc(h, &w.Cc, sizeof(double2) * LDG * 32));
+  DAV_TRY(dmalloc(h, &w.scratch, sizeof(double2) * 256 * (long)nblk * 16 * 4));
+  DAV_TRY(dmalloc(h, &w.theta, sizeof(double) * LDG));
+  DAV_TRY(dmalloc(h, &w.lam, sizeof(double) * LDG));
+  DAV_TRY(dmalloc(h, &w.npart, sizeof(double) * 32 * nblk));
+  DAV_TRY(dmalloc(h, &w.thact, sizeof(double) * 32));
+  DAV_TRY(dmalloc(h, &w.idx, sizeof(int) * LDG));
+  DAV_TRY(dmalloc(h, &w.count, sizeof(int)));
   if (follow) {
     // reference vectors of the followed roots: the first nroots guess vectors as given
-    DAV_TRY(hipMalloc(&w.Ref, sizeof(double2) * k * dim));
-    DAV_TRY(hipMalloc(&w.P, sizeof(double2) * LDG * LDG));
+    DAV_TRY(dmalloc(h, &w.Ref, sizeof(double2) * k * dim));
+    DAV_TRY(dmalloc(h, &w.P, sizeof(double2) * LDG * LDG));
     DAV_TRY(hipMemcpyAsync(w.Ref, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, st));
   }
 

@@ -91,14 +91,15 @@ using namespace adc2;
 
 extern "C" {
 
-ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, void* stream, adc2_handle* out) {
+ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, const adc2_alloc* alloc, void* stream,
+                                      adc2_handle* out) {
   if (!out) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: out is NULL");
   if (nmol < 1 || nmol > 64) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: nmol must be 1..64");
   for (int i = 0; i < nmol; ++i) out[i] = nullptr;
   if (!mols) return bfail(ADC2_ERR_ARG, "adc2_setup_batch: mols is NULL");
   for (int i = 0; i < nmol; ++i) {
     const adc2_mol& mo = mols[i];
-    adc2_status r = adc2_setup(mo.L, mo.eps, mo.nc, mo.no, mo.nv, mo.naux, prec, stream, &out[i]);
+    adc2_status r = adc2_setup(mo.L, mo.eps, mo.nc, mo.no, mo.nv, mo.naux, prec, alloc, stream, &out[i]);
     if (r != ADC2_OK) {
       const std::string m = std::string("adc2_setup_batch: system ") + std::to_string(i) + ": " + adc2_last_error();
       for (int j = 0; j < i; ++j) {

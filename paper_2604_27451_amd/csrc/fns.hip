@@ -92,21 +92,21 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
     return rc == ADC2_OK;
   };
   auto cleanup = [&]() {
-    hipFree(dpairs);
-    hipFree(Wc);
-    hipFree(Dd);
-    hipFree(WT);
-    hipFree(YT);
-    hipFree(epart);
+    dfree(h, dpairs);
+    dfree(h, Wc);
+    dfree(h, Dd);
+    dfree(h, WT);
+    dfree(h, YT);
+    dfree(h, epart);
   };
 
   // ---- D (Eq. 15) ----
-  hip(hipMalloc(&Dd, sizeof(double2) * nv2), "hipMalloc");
+  hip(dmalloc(h, &Dd, sizeof(double2) * nv2), "hipMalloc");
   if (rc == ADC2_OK) hip(hipMemsetAsync(Dd, 0, sizeof(double2) * nv2, st), "hipMemsetAsync");
   if (npairs > 0 && rc == ADC2_OK) {
-    hip(hipMalloc(&dpairs, sizeof(int2) * npairs), "hipMalloc");
-    if (rc == ADC2_OK) hip(hipMalloc(&Wc, sizeof(double2) * chunk * nv2), "hipMalloc");
-    if (rc == ADC2_OK) hip(hipMalloc(&epart, sizeof(double) * (long)chunk * (nb * (nb + 1) / 2)), "hipMalloc");
+    hip(dmalloc(h, &dpairs, sizeof(int2) * npairs), "hipMalloc");
+    if (rc == ADC2_OK) hip(dmalloc(h, &Wc, sizeof(double2) * chunk * nv2), "hipMalloc");
+    if (rc == ADC2_OK) hip(dmalloc(h, &epart, sizeof(double) * (long)chunk * (nb * (nb + 1) / 2)), "hipMalloc");
     if (rc == ADC2_OK)
       hip(hipMemcpyAsync(dpairs, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     for (int p0 = 0; p0 < npairs && rc == ADC2_OK; p0 += chunk) {
@@ -131,7 +131,7 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
     hip(hipMemcpyAsync(D.data(), Dd, sizeof(double2) * nv2, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     hip(hipStreamSynchronize(st), "hipStreamSynchronize");
   }
-  hipFree(Wc);
+  dfree(h, Wc);
   Wc = nullptr;
   if (rc != ADC2_OK) {
     cleanup();
@@ -200,8 +200,8 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
   for (int j = 0; j < keep; ++j) he[o + j] = ep[j];
 
   // ---- L'^P = W^H L^P W:  YT = W^T (L^P)^T,  L'^P = conj(W^T) YT^T ----
-  if (rc == ADC2_OK) hip(hipMalloc(&WT, sizeof(double2) * np * n), "hipMalloc");
-  if (rc == ADC2_OK) hip(hipMalloc(&YT, sizeof(double2) * np * n), "hipMalloc");
+  if (rc == ADC2_OK) hip(dmalloc(h, &WT, sizeof(double2) * np * n), "hipMalloc");
+  if (rc == ADC2_OK) hip(dmalloc(h, &YT, sizeof(double2) * np * n), "hipMalloc");
   if (rc == ADC2_OK)
     hip(hipMemcpyAsync(WT, hWT.data(), sizeof(double2) * np * n, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
   if (rc == ADC2_OK)

@@ -344,8 +344,8 @@ static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
   std::vector<double> eps(d.n);
   std::vector<double2> Vt((size_t)nc * no * nc * nv);
   std::vector<double> hnm(2 * nv);
-  hipError_t e = hipMalloc(&C, sizeof(double2) * nv2 * nv);
-  if (e == hipSuccess) e = hipMalloc(&nm, sizeof(double) * 2 * nv);
+  hipError_t e = dmalloc(h, &C, sizeof(double2) * nv2 * nv);
+  if (e == hipSuccess) e = dmalloc(h, &nm, sizeof(double) * 2 * nv);
   if (e == hipSuccess) e = hipMemsetAsync(nm, 0, sizeof(double) * 2 * nv, st);
   if (e == hipSuccess) e = hipMemcpy(eps.data(), h->eps, sizeof(double) * d.n, hipMemcpyDeviceToHost);
   adc2_status rc = ADC2_OK;
@@ -361,8 +361,8 @@ static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
   if (e == hipSuccess && rc == ADC2_OK) e = hipMemcpy(hnm.data(), nm, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost);
   if (e == hipSuccess && rc == ADC2_OK)
     e = hipMemcpy(Vt.data(), h->Vt, sizeof(double2) * Vt.size(), hipMemcpyDeviceToHost);
-  hipFree(C);
-  hipFree(nm);
+  dfree(h, C);
+  dfree(h, nm);
   if (rc != ADC2_OK) return rc;
   if (e != hipSuccess) {
     set_error(std::string("adc2_davidson (folded): preconditioner: ") + hipGetErrorString(e));
@@ -429,7 +429,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   std::vector<void*> owned;
   std::vector<void*>* pinned_list = nullptr;
   auto release = [&]() {
-    for (void* p : owned) hipFree(p);
+    for (void* p : owned) dfree(h, p);
     owned.clear();
     if (pinned_list) {
       for (void* p : *pinned_list) hipHostFree(p);
@@ -437,7 +437,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     }
   };
   auto dalloc = [&](void** p, size_t bytes) -> adc2_status {
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    hipError_t e = dmalloc(h, p, std::max<size_t>(bytes, 16));
     if (e != hipSuccess) {
       set_error(std::string("adc2_davidson (folded): hipMalloc: ") + hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;

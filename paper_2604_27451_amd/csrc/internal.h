@@ -24,6 +24,15 @@ void set_error(const std::string& msg);
 
 #define ADC2_CHECK_LAUNCH() ADC2_HIP(hipGetLastError())
 
+// Device memory of a handle: through its callbacks when set, else hipMalloc / hipFree
+// (dfree waits for the device first, as hipFree does; NULL is ignored).
+hipError_t dmalloc_raw(adc2_handle h, void** p, size_t bytes);
+void dfree(adc2_handle h, void* p);
+template <class T>
+inline hipError_t dmalloc(adc2_handle h, T** p, size_t bytes) {
+  return dmalloc_raw(h, reinterpret_cast<void**>(p), bytes);
+}
+
 // Sizes of one system.
 struct Dims {
   int nc, no, nv, naux;
@@ -46,6 +55,7 @@ struct DevBuf {
 struct adc2_handle_s {
   adc2::Dims d;
   int prec = 0;
+  adc2_alloc alloc{};       // device-memory callbacks (alloc == NULL: hipMalloc / hipFree)
   // integral blocks
   double2* Lvv = nullptr;   // [naux][nv][nv]      L^P_{ac}
   double2* Lvo = nullptr;   // [o][naux][nv]       L^P_{a k}  (k occupied)

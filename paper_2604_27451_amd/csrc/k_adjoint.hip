@@ -904,12 +904,12 @@ adc2_status omega_backward(adc2_handle h, int m, const double2* X, const double*
 
   std::vector<void*> owned;
   auto release = [&]() {
-    for (void* p : owned) hipFree(p);
+    for (void* p : owned) dfree(h, p);
     owned.clear();
   };
   auto alloc = [&](void** p, size_t bytes) -> adc2_status {
     *p = nullptr;
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    hipError_t e = dmalloc(h, p, std::max<size_t>(bytes, 16));
     if (e != hipSuccess) {
       set_error(std::string("adc2_omega_backward: hipMalloc: ") + hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
@@ -1032,8 +1032,8 @@ adc2_status omega_backward(adc2_handle h, int m, const double2* X, const double*
                                                       hvo + (long)nc * naux * nv);
     BW_HIP(hipGetLastError());
     BW_HIP(hipStreamSynchronize(st));
-    hipFree(Rn);
-    hipFree(C);
+    dfree(h, Rn);
+    dfree(h, C);
     owned.erase(std::remove(owned.begin(), owned.end(), (void*)Rn), owned.end());
     owned.erase(std::remove(owned.begin(), owned.end(), (void*)C), owned.end());
   }
@@ -1059,8 +1059,8 @@ adc2_status omega_backward(adc2_handle h, int m, const double2* X, const double*
     k_efill<<<(unsigned)(npairs * cdv(nv, ET)), 256, 0, st>>>(WT, PQ, PQG, h->eps, nc, o, nv, npairs, Ef, hr);
     BW_HIP(hipGetLastError());
     BW_HIP(hipStreamSynchronize(st));
-    hipFree(WT);
-    hipFree(PQ);
+    dfree(h, WT);
+    dfree(h, PQ);
     owned.erase(std::remove(owned.begin(), owned.end(), (void*)WT), owned.end());
     owned.erase(std::remove(owned.begin(), owned.end(), (void*)PQ), owned.end());
     // hvo[k][P][a] += 8 sum_{(l,c)} LoT[(l,c)][P] Ef[k][l][c][a]

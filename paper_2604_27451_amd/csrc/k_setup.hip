@@ -482,16 +482,16 @@ adc2_status wbuild(adc2_handle h, double2* W, hipStream_t st) {
   const long nwblk = (long)npairs * (nb * (nb + 1) / 2);
   int2* dpairs = nullptr;
   double* epart = nullptr;
-  hipError_t e = hipMalloc(&dpairs, sizeof(int2) * npairs);
-  if (e == hipSuccess) e = hipMalloc(&epart, sizeof(double) * nwblk);
+  hipError_t e = dmalloc(h, &dpairs, sizeof(int2) * npairs);
+  if (e == hipSuccess) e = dmalloc(h, &epart, sizeof(double) * nwblk);
   if (e == hipSuccess) e = hipMemcpyAsync(dpairs, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     k_wbuild<<<(unsigned)nwblk, 256, 0, st>>>(h->Lvo, h->eps, dpairs, npairs, d.naux, nv, o, W, epart);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(dpairs);
-  hipFree(epart);
+  dfree(h, dpairs);
+  dfree(h, epart);
   if (e != hipSuccess) {
     set_error(std::string("wbuild: ") + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
@@ -552,8 +552,8 @@ adc2_status build_m11(adc2_handle h, hipStream_t st) {
   const size_t part_len = std::max((size_t)nsplit_i, (size_t)(nc * nc * nsplit_iii)) * nv2;
 
   auto cleanup = [&]() {
-    hipFree(dpairs); hipFree(dpidx); hipFree(dent); hipFree(dsgn); hipFree(doff);
-    hipFree(W); hipFree(part); hipFree(Bm); hipFree(E); hipFree(G2); hipFree(qpart); hipFree(epart);
+    dfree(h, dpairs); dfree(h, dpidx); dfree(h, dent); dfree(h, dsgn); dfree(h, doff);
+    dfree(h, W); dfree(h, part); dfree(h, Bm); dfree(h, E); dfree(h, G2); dfree(h, qpart); dfree(h, epart);
   };
 #define SETUP_HIP(call)                                                            \
   do {                                                                             \
@@ -566,18 +566,18 @@ adc2_status build_m11(adc2_handle h, hipStream_t st) {
     }                                                                              \
   } while (0)
 
-  SETUP_HIP(hipMalloc(&dpairs, sizeof(int2) * std::max(1, npairs)));
-  SETUP_HIP(hipMalloc(&dpidx, sizeof(int) * o * o));
-  SETUP_HIP(hipMalloc(&dent, sizeof(int4) * std::max<size_t>(1, ent.size())));
-  SETUP_HIP(hipMalloc(&dsgn, sizeof(double) * std::max<size_t>(1, sgn.size())));
-  SETUP_HIP(hipMalloc(&doff, sizeof(int) * off.size()));
-  SETUP_HIP(hipMalloc(&W, sizeof(double2) * std::max<long>(1, (long)npairs * nv2)));
-  SETUP_HIP(hipMalloc(&part, sizeof(double2) * part_len));
-  SETUP_HIP(hipMalloc(&Bm, sizeof(double2) * nv2));
-  SETUP_HIP(hipMalloc(&E, sizeof(double2) * nc * nc * nv2));
-  SETUP_HIP(hipMalloc(&G2, sizeof(double2) * nc * nc * nv2));
-  SETUP_HIP(hipMalloc(&qpart, sizeof(double2) * nc * nc * o));
-  SETUP_HIP(hipMalloc(&epart, sizeof(double) * std::max<long>(1, nwblk)));
+  SETUP_HIP(dmalloc(h, &dpairs, sizeof(int2) * std::max(1, npairs)));
+  SETUP_HIP(dmalloc(h, &dpidx, sizeof(int) * o * o));
+  SETUP_HIP(dmalloc(h, &dent, sizeof(int4) * std::max<size_t>(1, ent.size())));
+  SETUP_HIP(dmalloc(h, &dsgn, sizeof(double) * std::max<size_t>(1, sgn.size())));
+  SETUP_HIP(dmalloc(h, &doff, sizeof(int) * off.size()));
+  SETUP_HIP(dmalloc(h, &W, sizeof(double2) * std::max<long>(1, (long)npairs * nv2)));
+  SETUP_HIP(dmalloc(h, &part, sizeof(double2) * part_len));
+  SETUP_HIP(dmalloc(h, &Bm, sizeof(double2) * nv2));
+  SETUP_HIP(dmalloc(h, &E, sizeof(double2) * nc * nc * nv2));
+  SETUP_HIP(dmalloc(h, &G2, sizeof(double2) * nc * nc * nv2));
+  SETUP_HIP(dmalloc(h, &qpart, sizeof(double2) * nc * nc * o));
+  SETUP_HIP(dmalloc(h, &epart, sizeof(double) * std::max<long>(1, nwblk)));
   SETUP_HIP(hipMemcpyAsync(dpairs, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, st));
   SETUP_HIP(hipMemcpyAsync(dpidx, pidx.data(), sizeof(int) * o * o, hipMemcpyHostToDevice, st));
   SETUP_HIP(hipMemcpyAsync(dent, ent.data(), sizeof(int4) * ent.size(), hipMemcpyHostToDevice, st));

@@ -863,7 +863,7 @@ __global__ void k_sigma1_finish(const double2* __restrict__ part, int nsplit, co
 adc2_status build_lvt(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
   if (h->LoT) return ADC2_OK;
-  ADC2_HIP(hipMalloc(&h->LoT, sizeof(double2) * (long)d.o * d.nv * d.naux));
+  ADC2_HIP(dmalloc(h, &h->LoT, sizeof(double2) * (long)d.o * d.nv * d.naux));
   h->LvT = h->LoT + (long)d.nc * d.nv * d.naux;
   const long nblk = (long)d.o * cdiv(d.nv, UT) * cdiv(d.naux, UT);
   k_lvo_transpose<<<(unsigned)nblk, 256, 0, st>>>(h->Lvo, d.nv, d.naux, h->LoT);
@@ -875,8 +875,8 @@ adc2_status build_c64(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
   if (h->Lv32 && h->LvT32) return ADC2_OK;
   const long nlv = (long)d.no * d.naux * d.nv;
-  ADC2_HIP(hipMalloc(&h->Lv32, sizeof(float2) * nlv));
-  ADC2_HIP(hipMalloc(&h->LvT32, sizeof(float2) * nlv));
+  ADC2_HIP(dmalloc(h, &h->Lv32, sizeof(float2) * nlv));
+  ADC2_HIP(dmalloc(h, &h->LvT32, sizeof(float2) * nlv));
   k_to_c64<<<grid_for(nlv), 256, 0, st>>>(h->Lvo + (long)d.nc * d.naux * d.nv, nlv, h->Lv32);
   ADC2_CHECK_LAUNCH();
   k_to_c64<<<grid_for(nlv), 256, 0, st>>>(h->LvT, nlv, h->LvT32);
@@ -892,22 +892,22 @@ adc2_status build_b3(adc2_handle h, hipStream_t st) {
   const Dims& d = h->d;
   const long K1 = d.naux, R1 = (long)d.no * d.nv;   // sigma2 B: rows (j,b), K = P
   const long K2 = (long)d.no * d.nv, R2 = d.naux;   // Y-build A: rows P, K = (j,d)
-  ADC2_HIP(hipMalloc(&h->LvB, split_bytes(R1, K1)));
-  ADC2_HIP(hipMalloc(&h->LvTB, split_bytes(R2, K2)));
+  ADC2_HIP(dmalloc(h, &h->LvB, split_bytes(R1, K1)));
+  ADC2_HIP(dmalloc(h, &h->LvTB, split_bytes(R2, K2)));
   if ((rc = split_pack(h->Lv32, (long)d.naux * d.nv, d.nv, d.nv, R1, K1, (__bf16*)h->LvB, st)) != ADC2_OK) return rc;
   return split_pack(h->LvT32, 0, d.naux, d.naux, R2, K2, (__bf16*)h->LvTB, st);
 }
 
 adc2_status ensure_ws_b3(adc2_handle h, int m) {
   if (h->wsb_m >= m) return ADC2_OK;
-  hipFree(h->XB);
-  hipFree(h->RB);
+  dfree(h, h->XB);
+  dfree(h, h->RB);
   h->XB = h->RB = nullptr;
   h->wsb_m = 0;
   const Dims& d = h->d;
   const long rows = (long)m * d.nc * d.nv;
-  ADC2_HIP(hipMalloc(&h->XB, split_bytes(rows, d.naux)));
-  ADC2_HIP(hipMalloc(&h->RB, split_bytes(rows, (long)d.no * d.nv)));
+  ADC2_HIP(dmalloc(h, &h->XB, split_bytes(rows, d.naux)));
+  ADC2_HIP(dmalloc(h, &h->RB, split_bytes(rows, (long)d.no * d.nv)));
   h->wsb_m = m;
   return ADC2_OK;
 }
@@ -915,15 +915,15 @@ adc2_status ensure_ws_b3(adc2_handle h, int m) {
 adc2_status ensure_ws(adc2_handle h, int m) {
   if (h->ws_m >= m) return ADC2_OK;
   const Dims& d = h->d;
-  hipFree(h->X);
-  hipFree(h->Y);
-  hipFree(h->part);
-  hipFree(h->Zb);
-  hipFree(h->Tp);
+  dfree(h, h->X);
+  dfree(h, h->Y);
+  dfree(h, h->part);
+  dfree(h, h->Zb);
+  dfree(h, h->Tp);
   h->X = h->Y = h->part = h->Zb = h->Tp = nullptr;
   h->ws_m = 0;
   const long rows = (long)m * d.nc;
-  ADC2_HIP(hipMalloc(&h->X, sizeof(double2) * rows * d.naux * d.nv));
+  ADC2_HIP(dmalloc(h, &h->X, sizeof(double2) * rows * d.naux * d.nv));
   {
     // split the Y-build over K so that the long-K tiles fill the GPU
     const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, BT);
@@ -932,15 +932,15 @@ adc2_status ensure_ws(adc2_handle h, int m) {
     if (h->ysplit_tuned > 0) ys = h->ysplit_tuned;   // adc2_autotune's choice
     h->ysplit = ys;
   }
-  ADC2_HIP(hipMalloc(&h->Y, sizeof(double2) * rows * d.naux * d.nv * h->ysplit));
-  ADC2_HIP(hipMalloc(&h->Zb, sizeof(double2) * rows * d.no * (long)d.nv * d.nv));
+  ADC2_HIP(dmalloc(h, &h->Y, sizeof(double2) * rows * d.naux * d.nv * h->ysplit));
+  ADC2_HIP(dmalloc(h, &h->Zb, sizeof(double2) * rows * d.no * (long)d.nv * d.nv));
   const int njg = (d.no + LJG - 1) / LJG;
-  ADC2_HIP(hipMalloc(&h->Tp, sizeof(double2) * rows * njg * d.nc * d.nv));
+  ADC2_HIP(dmalloc(h, &h->Tp, sizeof(double2) * rows * njg * d.nc * d.nv));
   const int nbi = cdiv(rows, TM), nba = cdiv(d.nv, TN);
   int nsplit = std::max(1, std::min(256, 2048 / std::max(1, nbi * nba)));
   nsplit = std::min(nsplit, d.naux);
   h->nsplit = nsplit;
-  ADC2_HIP(hipMalloc(&h->part, sizeof(double2) * nsplit * rows * d.nv));
+  ADC2_HIP(dmalloc(h, &h->part, sizeof(double2) * nsplit * rows * d.nv));
   h->ws_m = m;
   return ADC2_OK;
 }

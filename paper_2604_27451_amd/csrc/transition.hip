@@ -348,11 +348,11 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   std::vector<void*> bufs;
   auto release = [&]() {
     hipStreamSynchronize(st);
-    for (void* q : bufs) hipFree(q);
+    for (void* q : bufs) dfree(h, q);
     bufs.clear();
   };
   auto alloc = [&](double2** q, long count) -> adc2_status {
-    const hipError_t e = hipMalloc((void**)q, sizeof(double2) * std::max<long>(count, 1));
+    const hipError_t e = dmalloc(h, (void**)q, sizeof(double2) * std::max<long>(count, 1));
     if (e != hipSuccess) {
       set_error(std::string("adc2_transition: hipMalloc: ") + hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
@@ -362,7 +362,7 @@ adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpair
   };
   auto drop = [&](double2* q) {   // free one buffer early (after the stream has finished with it)
     hipStreamSynchronize(st);
-    hipFree(q);
+    dfree(h, q);
     bufs.erase(std::remove(bufs.begin(), bufs.end(), (void*)q), bufs.end());
   };
   auto launched = [&](const char* what) -> adc2_status {
@@ -579,14 +579,14 @@ extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, 
   };
   const int nblk = dav_nblk(dim);
   const int ntile = ((nroots + 15) / 16) * 1;
-  hip(hipMalloc(&F, sizeof(double2) * 3 * dim), "hipMalloc");
+  hip(dmalloc(h, &F, sizeof(double2) * 3 * dim), "hipMalloc");
   if (npairs > 0) {
-    hip(hipMalloc(&tau, sizeof(double2) * npairs * nv2), "hipMalloc");
-    hip(hipMalloc(&dpairs, sizeof(int2) * npairs), "hipMalloc");
+    hip(dmalloc(h, &tau, sizeof(double2) * npairs * nv2), "hipMalloc");
+    hip(dmalloc(h, &dpairs, sizeof(int2) * npairs), "hipMalloc");
   }
-  hip(hipMalloc(&Ab, sizeof(double2) * nv2), "hipMalloc");
-  hip(hipMalloc(&G, sizeof(double2) * nroots * 3), "hipMalloc");
-  hip(hipMalloc(&scr, sizeof(double2) * 256 * (long)nblk * ntile), "hipMalloc");
+  hip(dmalloc(h, &Ab, sizeof(double2) * nv2), "hipMalloc");
+  hip(dmalloc(h, &G, sizeof(double2) * nroots * 3), "hipMalloc");
+  hip(dmalloc(h, &scr, sizeof(double2) * 256 * (long)nblk * ntile), "hipMalloc");
   if (rc == ADC2_OK && npairs > 0) {
     hip(hipMemcpyAsync(dpairs, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     if (status(wbuild(h, tau, st))) status(tau_from_w(tau, dpairs, npairs, h->eps, o, nv, st));
@@ -623,12 +623,12 @@ extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, 
     rc = ADC2_ERR_HIP;
     msg = "hipStreamSynchronize";
   }
-  hipFree(F);
-  hipFree(tau);
-  hipFree(dpairs);
-  hipFree(Ab);
-  hipFree(G);
-  hipFree(scr);
+  dfree(h, F);
+  dfree(h, tau);
+  dfree(h, dpairs);
+  dfree(h, Ab);
+  dfree(h, G);
+  dfree(h, scr);
   if (rc != ADC2_OK) return tfail(rc, msg);
   double2* To = (double2*)T;
   for (int k = 0; k < nroots; ++k) {

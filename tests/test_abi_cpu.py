@@ -40,15 +40,19 @@ def test_exports_visible_in_dynamic_table():
 
 def test_argument_errors_without_gpu(lib):
     out = ctypes.c_void_p(123)
-    st = lib.adc2_setup(None, None, 1, 1, 2, 1, 0, None, ctypes.byref(out))
+    st = lib.adc2_setup(None, None, 1, 1, 2, 1, 0, None, None, ctypes.byref(out))
     assert st == A.ADC2_ERR_ARG
     assert out.value is None
     assert "NULL" in A.adc2_last_error()
-    st = lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 0, 1, 2, 1, 0, None, ctypes.byref(out))
+    st = lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 0, 1, 2, 1, 0, None, None, ctypes.byref(out))
     assert st == A.ADC2_ERR_ARG
-    st = lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, 2, 1, 7, None, ctypes.byref(out))
+    st = lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, 2, 1, 7, None, None, ctypes.byref(out))
     assert st == A.ADC2_ERR_ARG and "precision" in A.adc2_last_error()
-    assert lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, 2, 1, 0, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, 2, 1, 0, None, None, None) == A.ADC2_ERR_ARG
+    # allocator callbacks need both functions (checked before any HIP call)
+    half = A.Alloc(A._ALLOC_FN(lambda n, c: None), A._RELEASE_FN(), None)
+    assert lib.adc2_setup(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, 2, 1, 0, ctypes.byref(half), None,
+                          ctypes.byref(out)) == A.ADC2_ERR_ARG
     assert lib.adc2_dim(None) == 0
     assert lib.adc2_destroy(None) == A.ADC2_OK
     assert lib.adc2_sigma(None, 1, None, None, None) == A.ADC2_ERR_ARG
@@ -93,13 +97,13 @@ def test_batch_argument_errors_without_gpu(lib):
     out = (vp * 2)(vp(5).value, vp(6).value)
     mols = (A.Mol * 2)()
     # sizes and NULLs are refused before any HIP call; out[] is cleared
-    assert lib.adc2_setup_batch(0, mols, 0, None, out) == A.ADC2_ERR_ARG
-    assert lib.adc2_setup_batch(65, mols, 0, None, out) == A.ADC2_ERR_ARG
-    assert lib.adc2_setup_batch(2, None, 0, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(0, mols, 0, None, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(65, mols, 0, None, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(2, None, 0, None, None, out) == A.ADC2_ERR_ARG
     assert out[0] is None and out[1] is None
-    assert lib.adc2_setup_batch(2, mols, 0, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(2, mols, 0, None, None, None) == A.ADC2_ERR_ARG
     # a NULL system (L = eps = NULL) fails in adc2_setup and is named
-    assert lib.adc2_setup_batch(2, mols, 0, None, out) == A.ADC2_ERR_ARG
+    assert lib.adc2_setup_batch(2, mols, 0, None, None, out) == A.ADC2_ERR_ARG
     assert "system 0" in A.adc2_last_error()
     hs = (vp * 2)(None, None)
     ms = (ctypes.c_int * 2)(1, 1)
