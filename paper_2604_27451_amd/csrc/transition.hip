@@ -21,7 +21,7 @@
 //   s_ia = (N1_ia - N2_ia) / (e_a - e_i),
 //     N1_ia = sum_{P,b} Z^P_ib L^P_ab,  N2_ia = sum_{P,j} L^P_ji Z^P_ja,
 //     Z^P_ib = sum_{jc} tau^{bc}_{ij} L^P_jc,
-//   u^{ab}_{Ij} = [ sum_{P,c,d} L^P_ac tau^{cd}_{Ij} L^P_bd      (particle ladder)
+//   u^{ab}_{Ij} = [ sum_{c,d} (ac|bd) tau^{cd}_{Ij}               (particle ladder)
 //                 + sum_{k<l} <kl||Ij> tau^{ab}_{kl}            (hole ladder)
 //                 + P(Ij) P(ab) r^{ab}_{Ij} ] / D^{ab}_{Ij},
 //     r^{ab}_{ij} = sum_P Z^P_ia L^P_bj - sum_{kc} tau^{ac}_{ik} (kj|bc),
@@ -339,7 +339,8 @@ adc2_status tfail(adc2_status s, const std::string& m) {
 // of F (expressions in the file header).  tau: the pair amplitudes of every
 // occupied pair (k < l) in row-major pair order, dpairs their (k, l) list.
 // Work space (freed here): Tph and (kj|bc) twice, o^2 nv^2 complex each, the
-// Lvv transposes 2 naux nv^2, the ladder's U naux nv^2, u nc o nv^2.
+// Lvv transpose naux nv^2, two (ac|bd) blocks of up to 32 a-values (each at
+// most 16 GiB), the pair amplitudes and u of the pairs (I, j), nc o nv^2 each.
 adc2_status tm_second_order(adc2_handle h, const double2* tau, const int2* dpairs, int npairs,
                             const double2* dip, double2* F, hipStream_t st) {
   const Dims& d = h->d;
