@@ -476,8 +476,8 @@ def main():
                          "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over the valence index is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -212,8 +212,8 @@ ADC2_API adc2_status adc2_rayleigh(adc2_handle h, int k, const void* X, double* 
                                    void* stream);
 
 /*
- * adc2_omega_backward -- adjoint of the eigenvalues (spec differentiation
- * form; Hellmann-Feynman theorem applied to the Hermitian eigenproblem of
+ * adc2_omega_backward -- adjoint of the eigenvalues (differentiation form;
+ * Hellmann-Feynman theorem applied to the Hermitian eigenproblem of
  * Eq. 11 with M through second order, Eq. 12).  For vectors x_k and weights
  * g_k it returns the gradient of
  *     f(L, eps) = sum_k g_k x_k^H M(L, eps) x_k / (x_k^H x_k)
