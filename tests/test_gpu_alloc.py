@@ -76,3 +76,32 @@ def test_refusing_allocator_is_oom():
         A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux, alloc=al)
     assert ei.value.status == A.ADC2_ERR_OOM
     assert len(calls) == 1
+
+
+def test_torch_allocator_other_entry_points():
+    """Natural spinors, the autotuner and the batched setup / solve on
+    handles backed by PyTorch's allocator agree with hipMalloc handles."""
+    s = make_system(1, 3, 12, 24, seed=73)
+    print("[case] torch allocator: fns, autotune, batch", flush=True)
+    L, e = dev(s.L), dev(s.eps)
+    ha = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    ht = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux, alloc="torch")
+    Fa = A.adc2_fns(ha, L, 1e-3)
+    Ft = A.adc2_fns(ht, L, 1e-3)
+    assert Fa[2] == Ft[2] and torch.equal(Fa[0], Ft[0]) and torch.equal(Fa[1], Ft[1])
+    ra, rt = A.adc2_autotune(ha, 2), A.adc2_autotune(ht, 2)
+    assert ra["ysplit"] >= 1 and rt["ysplit"] >= 1
+    x = dev(random_vectors(9, 2, ha.dim))
+    assert torch.equal(A.adc2_sigma(ha, x), A.adc2_sigma(ht, x))
+    ha.close()
+    ht.close()
+    s2 = make_system(1, 2, 9, 18, seed=74)
+    systems = [(L, e, s.nc, s.no, s.nv, s.naux), (dev(s2.L), dev(s2.eps), s2.nc, s2.no, s2.nv, s2.naux)]
+    hb = A.adc2_setup_batch(systems)
+    hbt = A.adc2_setup_batch(systems, alloc="torch")
+    wa, _, _ = A.adc2_davidson_batch(hb, 2, tol=1e-9)
+    wt, _, _ = A.adc2_davidson_batch(hbt, 2, tol=1e-9)
+    for q in range(2):
+        assert np.abs(np.array(wa[q]) - np.array(wt[q])).max() < 1e-12
+    for hh in hb + hbt:
+        hh.close()
