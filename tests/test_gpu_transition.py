@@ -170,3 +170,41 @@ def test_transition_c2_shift_invariance():
           flush=True)
     assert err < 1e-12
     assert np.abs(T2 - T1).max() > 1e-3 * np.abs(T2).max()
+
+
+def test_transition_spin_selection_rule_larger():
+    """The selection rule at order 2 on a nonrelativistic system whose GEMMs
+    span ragged tiles (nc=6, no=20, nv=160 spinors, naux=160): every triplet
+    root is dark to rounding, the singlets are not."""
+    sb = make_spin_blocked(3, 10, 80, 160, seed=19, sigma=0.05)
+    sp = O.Spaces(sb.nc, sb.no, sb.nv)
+    n_sp = sp.n // 2
+    rng = np.random.default_rng(45)
+    dip = np.zeros((3, sp.n, sp.n), dtype=np.complex128)
+    for c in range(3):
+        x = rng.standard_normal((n_sp, n_sp))
+        x = x + x.T
+        for sg in range(2):
+            idx = 2 * np.arange(n_sp) + sg
+            dip[c][np.ix_(idx, idx)] = x
+    print("[case] spin selection rule, nc=6 no=20 nv=160", flush=True)
+    h = A.adc2_setup(dev(sb.L), dev(sb.eps), sb.nc, sb.no, sb.nv, sb.naux)
+    w, X, inf = A.adc2_davidson(h, 8, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
+    T, f = A.adc2_transition(h, dev(dip), X, w, order=2)
+    h.close()
+    w = np.array(w)
+    groups, cur = [], [0]
+    for i in range(1, len(w)):
+        if w[i] - w[cur[-1]] < 1e-7:
+            cur.append(i)
+        else:
+            groups.append(cur)
+            cur = [i]
+    groups.append(cur)
+    print(f"  roots {np.round(w, 6)} f {f}", flush=True)
+    dark = [g for g in groups if len(g) == 3]
+    bright = [g for g in groups if len(g) == 1 and g[0] < len(w) - 1]
+    assert dark and bright
+    for g in dark:
+        assert f[g].max() < 1e-18 * max(1.0, f.max())     # measured <= 3e-21
+    assert max(f[g[0]] for g in bright) > 1e-6
