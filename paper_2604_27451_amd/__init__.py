@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadc2.so")
@@ -240,6 +241,11 @@ class Handle:
             self.ptr = None
 
     def __del__(self):
+        # at interpreter shutdown a handle whose memory belongs to PyTorch's
+        # allocator is left to the process exit: its release callbacks would
+        # call into a torch that may already be torn down
+        if self.alloc is not None and sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
