@@ -122,14 +122,16 @@ def roofline_of(stats, peak, traffic):
 
 # published MI355X figures next to which the probes are reported
 DATASHEET = {"mfma_f64": (78.6, "TFLOP/s"), "mfma_f32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
-             "valu_f64": (78.6, "TFLOP/s"), "hbm_read": (8000.0, "GB/s"), "hbm_copy": (8000.0, "GB/s")}
+             "valu_f64": (78.6, "TFLOP/s"), "hbm_read": (8000.0, "GB/s"), "hbm_copy": (8000.0, "GB/s"),
+             "mfma_f64_rand": (78.6, "TFLOP/s"), "mfma_bf16_rand": (2500.0, "TFLOP/s")}
 
 
 def measure_peaks(A, names, reps=5, nbytes=8 << 30):
     """Rates of the adc2_peak_probe microbenchmarks, with the datasheet value."""
     kinds = {"mfma_f64": A.ADC2_PEAK_MFMA_F64, "mfma_f32": A.ADC2_PEAK_MFMA_F32,
              "mfma_bf16": A.ADC2_PEAK_MFMA_BF16, "valu_f64": A.ADC2_PEAK_VALU_F64,
-             "hbm_read": A.ADC2_PEAK_HBM_READ, "hbm_copy": A.ADC2_PEAK_HBM_COPY}
+             "hbm_read": A.ADC2_PEAK_HBM_READ, "hbm_copy": A.ADC2_PEAK_HBM_COPY,
+             "mfma_f64_rand": A.ADC2_PEAK_MFMA_F64_RAND, "mfma_bf16_rand": A.ADC2_PEAK_MFMA_BF16_RAND}
     out = {}
     for n in names:
         v = A.adc2_peak_probe(kinds[n], nbytes if n.startswith("hbm") else 0, reps)
@@ -184,7 +186,8 @@ def run_transition(args, A, np, torch):
 
 def run_peaks(args, A):
     """Microbenchmarks of the rates the rooflines are quoted against."""
-    names = ["mfma_f64", "mfma_f32", "mfma_bf16", "valu_f64", "hbm_read", "hbm_copy"]
+    names = ["mfma_f64", "mfma_f32", "mfma_bf16", "valu_f64", "hbm_read", "hbm_copy", "mfma_f64_rand",
+             "mfma_bf16_rand"]
     peaks = measure_peaks(A, names, reps=10)
     print(json.dumps({"metric": "measured device peaks (adc2_peak_probe), 1 MI355X", "n_gpus": 1,
                       "data": "synthetic", "config": {"workload": "peak microbenchmarks: dense MFMA "
@@ -715,12 +718,18 @@ def main():
                                        PEAK_FP32_MFMA)
         out["mixed_c64"]["tol"] = args.tol_c64
     # measured MFMA rates beside the published peaks (outside the timed steps)
-    pk = measure_peaks(A, ["mfma_f64"] + (["mfma_bf16"] if "mixed" in out else []) +
+    pk = measure_peaks(A, ["mfma_f64", "mfma_f64_rand"] +
+                       (["mfma_bf16", "mfma_bf16_rand"] if "mixed" in out else []) +
                        (["mfma_f32"] if "mixed_c64" in out else []))
     out["roofline"] = with_measured_peak(out["roofline"], pk["mfma_f64"]["measured"])
+    out["roofline"]["peak_measured_random_operands"] = pk["mfma_f64_rand"]["measured"]
     if "mixed" in out:
         out["mixed"]["roofline"] = with_measured_peak(out["mixed"]["roofline"],
                                                       pk["mfma_bf16"]["measured"] * 8.0 / 24.0)
+        # the same instruction on data-like operands: the rate the power limit allows
+        rnd = pk["mfma_bf16_rand"]["measured"] * 8.0 / 24.0
+        out["mixed"]["roofline"]["peak_measured_random_operands"] = round(rnd, 2)
+        out["mixed"]["roofline"]["frac_of_random_operands"] = round(out["mixed"]["roofline"]["achieved"] / rnd, 4)
     if "mixed_c64" in out:
         out["mixed_c64"]["roofline"] = with_measured_peak(out["mixed_c64"]["roofline"], pk["mfma_f32"]["measured"])
     cpu = None

@@ -398,7 +398,8 @@ ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double threshold, in
  * pass.  adc2_autotune times the Y-build of h's current precision form at
  * block size m for the K-splits 1, 2, 3, 4, 6, 8, 12, 16 (those whose partial
  * workspace stays under 8 GiB and that leave each split at least 64 of the
- * no*nv contraction indices), one warm-up and three timed launches each, and
+ * no*nv contraction indices), one warm-up and three timed launches each on
+ * uniform random operands (the matrix cores run measurably faster on zeros), and
  * fixes the fastest for h (for every later block size too).  A choice already
  * made for the same (device, nc, no, nv, naux, m, form) in this process, or
  * listed in the text file named by the environment variable ADC2_TUNE_CACHE,
@@ -428,6 +429,12 @@ ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_info* info, v
  *   ADC2_PEAK_VALU_F64   v_fma_f64 (folded-solver moments), TFLOP/s
  *   ADC2_PEAK_HBM_READ   streaming 16-byte loads over `bytes`, GB/s
  *   ADC2_PEAK_HBM_COPY   copy of `bytes` (read + write both counted), GB/s
+ *   ADC2_PEAK_MFMA_F64_RAND, ADC2_PEAK_MFMA_BF16_RAND  the FP64 and BF16 MFMA
+ *                        probes with per-lane pseudo-random operands (uniform
+ *                        in [-1, 1), four registers of each side cycled):
+ *                        the rate with data-like switching activity, which
+ *                        the power limit may hold below the constant-operand
+ *                        rate, TFLOP/s
  * bytes: buffer size of the HBM probes (0 = 2 GiB; 64 MiB .. 64 GiB),
  * ignored otherwise.  reps: timed launches (1..1000) after one warm-up; the
  * best launch (HIP events) is returned in *rate (host).  The probe allocates
@@ -441,6 +448,8 @@ ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_info* info, v
 #define ADC2_PEAK_VALU_F64 3
 #define ADC2_PEAK_HBM_READ 4
 #define ADC2_PEAK_HBM_COPY 5
+#define ADC2_PEAK_MFMA_F64_RAND 6
+#define ADC2_PEAK_MFMA_BF16_RAND 7
 ADC2_API adc2_status adc2_peak_probe(int kind, size_t bytes, int reps, double* rate, void* stream);
 
 /* Release everything the handle owns.  NULL is accepted. */

@@ -54,6 +54,8 @@ ADC2_PEAK_MFMA_BF16 = 2
 ADC2_PEAK_VALU_F64 = 3
 ADC2_PEAK_HBM_READ = 4
 ADC2_PEAK_HBM_COPY = 5
+ADC2_PEAK_MFMA_F64_RAND = 6
+ADC2_PEAK_MFMA_BF16_RAND = 7
 
 STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3: "ADC2_ERR_OOM",
                 4: "ADC2_ERR_HIP", 5: "ADC2_ERR_NOCONV", 6: "ADC2_ERR_NONFINITE"}

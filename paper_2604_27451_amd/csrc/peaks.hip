@@ -1,7 +1,8 @@
 // peaks.hip -- microbenchmarks of the device rates the rooflines are quoted
 // against: dense MFMA throughput of the three instructions the sigma GEMMs
-// issue (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32), FP64 vector FMA (the
-// Chebyshev moment kernel), and HBM streaming read and copy bandwidth.
+// issue (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32), with constant and with
+// pseudo-random operands, FP64 vector FMA (the Chebyshev moment kernel), and
+// HBM streaming read and copy bandwidth.
 //
 // MFMA and FMA probes keep CH independent accumulator chains per wave, so
 // that issue rate, not latency, bounds them, and touch memory only to store
@@ -42,6 +43,68 @@ __global__ __launch_bounds__(256) void k_peak_mfma_f64(double a, double b, int i
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < CH; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// Pseudo-random operands: a 32-bit integer hash of (block, lane, slot) mapped
+// to [-1, 1).  The probes below feed each lane its own values and cycle four
+// operand registers of each side through the chains, so that consecutive
+// MFMAs see different, data-like bit patterns (the constant-operand probes
+// above measure the matrix cores at minimal switching activity).
+__device__ __forceinline__ float hash_unit(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return (float)(x >> 8) * (1.0f / 8388608.0f) - 1.0f;
+}
+
+__global__ __launch_bounds__(256) void k_peak_mfma_f64_rand(int iters, double* __restrict__ out) {
+  const unsigned base = (blockIdx.x * 256u + threadIdx.x) * 16u;
+  double av[4], bv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    av[q] = (double)hash_unit(base + q) + 1e-9 * hash_unit(base + 8 + q);
+    bv[q] = (double)hash_unit(base + 4 + q) + 1e-9 * hash_unit(base + 12 + q);
+  }
+  pd4 acc[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c & 3], bv[(c >> 2) & 3], pd4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+  for (int it = 1; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c & 3], bv[(c >> 2) & 3], acc[c], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_peak_mfma_bf16_rand(int iters, double* __restrict__ out) {
+  const unsigned base = (blockIdx.x * 256u + threadIdx.x) * 64u;
+  pb8 av[4], bv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      av[q][i] = (__bf16)hash_unit(base + q * 8 + i);
+      bv[q][i] = (__bf16)hash_unit(base + 32 + q * 8 + i);
+    }
+  pf4 acc[CHB];
+#pragma unroll
+  for (int c = 0; c < CHB; ++c)
+    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[c & 3], bv[(c >> 2) & 3], pf4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  for (int it = 1; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < CHB; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[c & 3], bv[(c >> 2) & 3], acc[c], 0, 0, 0);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < CHB; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
   out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
@@ -139,7 +202,7 @@ using namespace adc2;
 extern "C" ADC2_API adc2_status adc2_peak_probe(int kind, size_t bytes, int reps, double* rate, void* stream) {
   if (!rate) return pfail(ADC2_ERR_ARG, "rate is NULL");
   *rate = 0.0;
-  if (kind < ADC2_PEAK_MFMA_F64 || kind > ADC2_PEAK_HBM_COPY) return pfail(ADC2_ERR_ARG, "unknown kind");
+  if (kind < ADC2_PEAK_MFMA_F64 || kind > ADC2_PEAK_MFMA_BF16_RAND) return pfail(ADC2_ERR_ARG, "unknown kind");
   if (reps < 1 || reps > 1000) return pfail(ADC2_ERR_ARG, "reps must be 1..1000");
   const bool hbm = kind == ADC2_PEAK_HBM_READ || kind == ADC2_PEAK_HBM_COPY;
   if (hbm) {
@@ -178,6 +241,8 @@ extern "C" ADC2_API adc2_status adc2_peak_probe(int kind, size_t bytes, int reps
     case ADC2_PEAK_MFMA_F64: iters = 4096; work = waves * iters * CH * (16.0 * 16 * 4 * 2); break;
     case ADC2_PEAK_MFMA_F32: iters = 8192; work = waves * iters * CH * (16.0 * 16 * 4 * 2); break;
     case ADC2_PEAK_MFMA_BF16: iters = 8192; work = waves * iters * CHB * (16.0 * 16 * 32 * 2); break;
+    case ADC2_PEAK_MFMA_F64_RAND: iters = 4096; work = waves * iters * CH * (16.0 * 16 * 4 * 2); break;
+    case ADC2_PEAK_MFMA_BF16_RAND: iters = 8192; work = waves * iters * CHB * (16.0 * 16 * 32 * 2); break;
     case ADC2_PEAK_VALU_F64: iters = 65536; work = waves * 64.0 * iters * CH * 2.0; break;
     case ADC2_PEAK_HBM_READ: work = (double)bytes; break;
     default: work = 2.0 * (double)bytes; break;
@@ -187,6 +252,8 @@ extern "C" ADC2_API adc2_status adc2_peak_probe(int kind, size_t bytes, int reps
       case ADC2_PEAK_MFMA_F64: k_peak_mfma_f64<<<PGRID, 256, 0, st>>>(1.0000001, 0.9999999, iters, (double*)out); break;
       case ADC2_PEAK_MFMA_F32: k_peak_mfma_f32<<<PGRID, 256, 0, st>>>(1.0001f, 0.9999f, iters, (double*)out); break;
       case ADC2_PEAK_MFMA_BF16: k_peak_mfma_bf16<<<PGRID, 256, 0, st>>>(0.01f, 0.02f, iters, (double*)out); break;
+      case ADC2_PEAK_MFMA_F64_RAND: k_peak_mfma_f64_rand<<<PGRID, 256, 0, st>>>(iters, (double*)out); break;
+      case ADC2_PEAK_MFMA_BF16_RAND: k_peak_mfma_bf16_rand<<<PGRID, 256, 0, st>>>(iters, (double*)out); break;
       case ADC2_PEAK_VALU_F64: k_peak_fma_f64<<<PGRID, 256, 0, st>>>(0.9999999, 1e-7, iters, (double*)out); break;
       case ADC2_PEAK_HBM_READ: k_peak_read<<<PGRID, 256, 0, st>>>((const pu4*)in, bytes / 16, (pu4*)out); break;
       default: k_peak_copy<<<PGRID, 256, 0, st>>>((const pu4*)in, bytes / 16, (pu4*)out); break;

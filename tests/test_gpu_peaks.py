@@ -10,7 +10,8 @@ import paper_2604_27451_amd as A
 pytestmark = pytest.mark.gpu
 
 DATASHEET = {A.ADC2_PEAK_MFMA_F64: 78.6, A.ADC2_PEAK_MFMA_F32: 157.3, A.ADC2_PEAK_MFMA_BF16: 2500.0,
-             A.ADC2_PEAK_VALU_F64: 78.6, A.ADC2_PEAK_HBM_READ: 8000.0, A.ADC2_PEAK_HBM_COPY: 8000.0}
+             A.ADC2_PEAK_VALU_F64: 78.6, A.ADC2_PEAK_HBM_READ: 8000.0, A.ADC2_PEAK_HBM_COPY: 8000.0,
+             A.ADC2_PEAK_MFMA_F64_RAND: 78.6, A.ADC2_PEAK_MFMA_BF16_RAND: 2500.0}
 
 
 @pytest.mark.parametrize("kind", sorted(DATASHEET))
