@@ -105,3 +105,24 @@ def test_torch_allocator_other_entry_points():
         assert np.abs(np.array(wa[q]) - np.array(wt[q])).max() < 1e-12
     for hh in hb + hbt:
         hh.close()
+
+
+def test_torch_allocator_precision_forms_and_two_stage():
+    """The complex64 and split-BF16 operand copies and work spaces (built on
+    first use) and the two-stage solve (split-BF16 then FP64, nested solver
+    calls) on a handle backed by PyTorch's allocator."""
+    s = make_system(2, 3, 16, 32, seed=75)
+    print("[case] torch allocator: precision forms, two-stage", flush=True)
+    L, e = dev(s.L), dev(s.eps)
+    ha = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux)
+    ht = A.adc2_setup(L, e, s.nc, s.no, s.nv, s.naux, alloc="torch")
+    x = dev(random_vectors(11, 4, ha.dim))
+    for prec in (A.ADC2_C64, A.ADC2_BF16X3, A.ADC2_FP64):
+        A.adc2_set_precision(ha, prec)
+        A.adc2_set_precision(ht, prec)
+        assert torch.equal(A.adc2_sigma(ha, x), A.adc2_sigma(ht, x)), prec
+    wa, _, _ = A.adc2_davidson(ha, 3, tol=1e-9, mixed_tol=1e-4)
+    wt, _, _ = A.adc2_davidson(ht, 3, tol=1e-9, mixed_tol=1e-4)
+    assert np.abs(np.array(wa) - np.array(wt)).max() < 1e-12
+    ha.close()
+    ht.close()
