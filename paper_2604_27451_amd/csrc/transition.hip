@@ -76,16 +76,22 @@ __global__ __launch_bounds__(256) void k_tm_singles(const double2* __restrict__ 
   }
 }
 
-// doubles of one (component, I, j): A = d_vv tau_Ij, out = F block of (I, j), a < b packed
-__global__ __launch_bounds__(256) void k_tm_doubles(const double2* __restrict__ A, const double2* __restrict__ tau,
-                                                     const double2* __restrict__ d, int I, int jg, int o, int nv,
-                                                     int n, double2* __restrict__ out) {
+// doubles of one (component, I) and every valence j = nc + blockIdx.y:
+// A_j[a][b] = (d_vv tau_Ij)[a][b] at Ab[a * lda + j' * nv + b] (j' = blockIdx.y),
+// out = F blocks of (I, nc..o-1) in order, a < b packed
+__global__ __launch_bounds__(256) void k_tm_doubles(const double2* __restrict__ Ab, long lda,
+                                                     const double2* __restrict__ tau,
+                                                     const double2* __restrict__ d, int I, int nc, int o, int nv,
+                                                     int n, long npair, double2* __restrict__ out0) {
   const long nv2 = (long)nv * nv;
+  const int jv = blockIdx.y, jg = nc + jv;
+  const double2* A = Ab + (long)jv * nv;
+  double2* out = out0 + (long)jv * npair;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < nv2; e += (long)gridDim.x * 256) {
     const int a = (int)(e / nv), b = (int)(e - (long)a * nv);
     if (a >= b) continue;
     const long ab = (long)a * nv + b;
-    const double2 x = A[ab], y = A[(long)b * nv + a];
+    const double2 x = A[(long)a * lda + b], y = A[(long)b * lda + a];
     double2 s = make_double2(x.x - y.x, x.y - y.y);
     for (int k = 0; k < o; ++k) {
       const double2 t1 = cmul(d[(long)k * n + I], tau_at(tau, k, jg, o, nv2, ab));
@@ -585,7 +591,7 @@ extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, 
     hip(dmalloc(h, &tau, sizeof(double2) * npairs * nv2), "hipMalloc");
     hip(dmalloc(h, &dpairs, sizeof(int2) * npairs), "hipMalloc");
   }
-  hip(dmalloc(h, &Ab, sizeof(double2) * nv2), "hipMalloc");
+  hip(dmalloc(h, &Ab, sizeof(double2) * nv * (long)no * nv), "hipMalloc");
   hip(dmalloc(h, &G, sizeof(double2) * nroots * 3), "hipMalloc");
   hip(dmalloc(h, &scr, sizeof(double2) * 256 * (long)nblk * ntile), "hipMalloc");
   if (rc == ADC2_OK && npairs > 0) {
@@ -601,19 +607,21 @@ extern "C" ADC2_API adc2_status adc2_transition(adc2_handle h, const void* dip, 
   }
   if (rc == ADC2_OK && npairs > 0 && order == 2) status(tm_second_order(h, tau, dpairs, npairs, dp, F, st));
   const unsigned gd = (unsigned)std::min<long>(4096, (nv2 + 255) / 256);
+  const long lda = (long)no * nv;
   for (int c = 0; c < 3 && rc == ADC2_OK && npairs > 0; ++c) {
     const double2* dc = dp + (long)c * n * n;
-    for (int I = 0; I < nc && rc == ADC2_OK; ++I)
-      for (int j = 0; j < no && rc == ADC2_OK; ++j) {
-        const int jg = nc + j;
-        const double2* tIj = tau + ((long)I * o - (long)I * (I + 1) / 2 + (jg - I - 1)) * nv2;
-        // A = d_vv tau_Ij  (B given transposed: tau_Ij^T = -tau_Ij)
-        if (!status(gemm_rr(nv, nv, nv, dc + (long)o * n + o, n, false, tIj, nv, false, Ab, nv, -1.0, false, st)))
-          break;
-        k_tm_doubles<<<gd, 256, 0, st>>>(Ab, tau, dc, I, jg, o, nv, n,
-                                         F + (long)c * dim + ns + ((long)I * no + j) * d.npair);
-        hip(hipGetLastError(), "k_tm_doubles");
-      }
+    for (int I = 0; I < nc && rc == ADC2_OK; ++I) {
+      // the pairs (I, j) of the valence j > I follow each other in pair order:
+      // Ab[a][(j', b)] = sum_c d_ac tau^{cb}_{Ij} for all of them in one GEMM
+      // (B given transposed: tau_Ij^T = -tau_Ij)
+      const double2* tI = tau + ((long)I * o - (long)I * (I + 1) / 2 + (nc - I - 1)) * nv2;
+      if (!status(gemm_rr(nv, (int)lda, nv, dc + (long)o * n + o, n, false, tI, nv, false, Ab, lda, -1.0, false,
+                          st)))
+        break;
+      k_tm_doubles<<<dim3(gd, no), 256, 0, st>>>(Ab, lda, tau, dc, I, nc, o, nv, n, d.npair,
+                                                 F + (long)c * dim + ns + (long)I * no * d.npair);
+      hip(hipGetLastError(), "k_tm_doubles");
+    }
   }
   // T[k][c] = X_k^H F_c
   if (rc == ADC2_OK) status(dav_gram((const double2*)X, nroots, F, 3, dim, G, 3, scr, st));
