@@ -418,6 +418,44 @@ def test_tm_second_order_bruteforce(shape, seed, sigma):
         assert float(t[C].abs().max()) > 1e-5
 
 
+@pytest.mark.parametrize("shape,seed", [((1, 2, 3), 5), ((2, 2, 3), 13)])
+def test_second_order_amplitudes_from_wavefunction(shape, seed):
+    """The exact ground state Psi0(lambda) of the brute-force Fock space,
+    expanded in lambda: its first-order doubles coefficients are -tau, its
+    second-order singles and doubles coefficients are s and u of
+    second_order_amplitudes (each of the ladder, ring and singles terms is a
+    sizeable part of them on these inputs)."""
+    from oracle.isr_bruteforce import FockSpace
+    s = make_system(*shape, naux=6, seed=seed, sigma=0.15, core=(-3.0, -2.5))
+    L, e, sp = _tensors(s)
+    o = sp.o
+    fs = FockSpace(s.L, s.eps, o)
+    singles, doubles = fs.excitations()
+    ref = np.zeros(1 << fs.n)
+    ref[fs.ref] = 1.0
+    phi1 = np.stack([fs.ad[a] @ (fs.a[i] @ ref) for (i, a) in singles], axis=1)
+    phi2 = np.stack([fs.ad[a] @ (fs.ad[b] @ (fs.a[j] @ (fs.a[i] @ ref))) for (i, j, a, b) in doubles], axis=1)
+    npts, deg, lm = 17, 10, 0.5
+    lams = lm * np.cos(np.pi * (np.arange(npts) + 0.5) / npts)
+    C = np.array([np.concatenate([phi1.T @ psi, phi2.T @ psi]) for psi in (fs.ground(x)[1] for x in lams)])
+    coef = np.linalg.lstsq(np.polynomial.chebyshev.chebvander(lams / lm, deg), C, rcond=None)[0]
+    taylor = [np.zeros(C.shape[1], dtype=complex) for _ in range(3)]
+    for dd in range(deg + 1):
+        mono = np.polynomial.chebyshev.cheb2poly(np.eye(deg + 1)[dd])
+        for t in range(min(3, mono.size)):
+            taylor[t] = taylor[t] + mono[t] / lm ** t * coef[dd]
+    ns = len(singles)
+    tau = O.mp2_amplitudes(L, e, sp).numpy()
+    sa, u = (x.numpy() for x in O.second_order_amplitudes(L, e, sp))
+    t1 = np.array([tau[a - o, b - o, i, j] for (i, j, a, b) in doubles])
+    s2 = np.array([sa[i, a - o] for (i, a) in singles])
+    u2 = np.array([u[a - o, b - o, i, j] for (i, j, a, b) in doubles])
+    assert np.abs(taylor[1][:ns]).max() < 1e-9                     # no first-order singles
+    assert np.abs(taylor[1][ns:] + t1).max() < 1e-9
+    assert np.abs(taylor[2][:ns] - s2).max() < 5e-9 and np.abs(s2).max() > 1e-4
+    assert np.abs(taylor[2][ns:] - u2).max() < 5e-9 and np.abs(u2).max() > 1e-4
+
+
 def test_tm_second_order_shift_invariance():
     """F_I = <Psi~_I|D|Psi0> is unchanged by D -> D + c 1, since every
     intermediate state is orthogonal to Psi0: the two singles-amplitude terms
