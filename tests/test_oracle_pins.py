@@ -506,3 +506,55 @@ def test_tm_spin_selection_rule():
         pos += sz
     assert n_dark >= 1 and n_bright >= 1
     assert torch.allclose(f, (2.0 / 3.0) * w[:k] * (T.abs() ** 2).sum(1), rtol=1e-14)
+
+
+def test_tm_second_order_terms_by_fit():
+    """How the second-order singles terms were found: the lambda^2
+    coefficient of F from the brute-force intermediate states is fitted by
+    least squares over 16 candidate contractions (the singles and doubles
+    second-order amplitude pieces, the pair densities and particle-hole
+    terms over all or only core k).  The fit returns the coefficients of
+    second_order_singles exactly (1/2, -1/2, -1/2, 1/2, 1/2, 1/2, 1, -1/4,
+    -1/4, 1/2) and zero for the six other candidates."""
+    rows, rhs = [], []
+    for shape, seed in [((1, 2, 3), 5), ((2, 1, 3), 7), ((1, 2, 4), 11)]:
+        s = make_system(*shape, naux=6, seed=seed, sigma=0.15, core=(-3.0, -2.5))
+        L, e, sp = _tensors(s)
+        o = sp.o
+        d = _hermitian(sp.n, 100 * seed)
+        (_, _, F2), resid, singles, _ = transition_taylor(s.L, s.eps, o, d)
+        assert resid < 1e-9
+        O_, U = sp.O, sp.U
+        dd = torch.as_tensor(d).to(O.C128)
+        dvv, doo, dov, dvo = dd[U][:, U], dd[O_][:, O_], dd[O_][:, U], dd[U][:, O_]
+        tau = O.mp2_amplitudes(L, e, sp)
+        Dia = e[U][None, :] - e[O_][:, None]
+        s1 = torch.einsum("ajbc,bcij->ia", O.asym(L, U, O_, U, U), tau) / Dia
+        s2 = torch.einsum("jkib,abjk->ia", O.asym(L, O_, O_, O_, U), tau) / Dia
+        D = O.denom(e, sp, U, U, O_, O_)
+        pp = torch.einsum("abcd,cdij->abij", O.asym(L, U, U, U, U), tau) / D
+        hh = torch.einsum("klij,abkl->abij", O.asym(L, O_, O_, O_, O_), tau) / D
+        r = torch.einsum("kbcj,acik->abij", O.asym(L, O_, U, U, O_), tau)
+        ring = (r - r.permute(1, 0, 2, 3) - r.permute(0, 1, 3, 2) + r.permute(1, 0, 3, 2)) / D
+        rho = torch.einsum("abkl,cbkl->ac", tau, tau.conj())
+        sig = torch.einsum("cdil,cdkl->ik", tau, tau.conj())
+        P = torch.einsum("abil,cbkl->iakc", tau, tau.conj())
+        Q = torch.einsum("abkl,cbil->iakc", tau, tau.conj())
+        mc = torch.zeros(o, dtype=O.C128)
+        mc[:sp.nc] = 1.0
+        cand = [torch.einsum("ab,ib->ia", dvv, s1), torch.einsum("ab,ib->ia", dvv, s2),
+                torch.einsum("ji,ja->ia", doo, s1), torch.einsum("ji,ja->ia", doo, s2),
+                torch.einsum("jb,abij->ia", dov, pp), torch.einsum("jb,abij->ia", dov, hh),
+                torch.einsum("jb,abij->ia", dov, ring), torch.einsum("ac,ci->ia", rho, dvo),
+                torch.einsum("ak,ik->ia", dvo, sig), torch.einsum("iakc,ck->ia", P, dvo),
+                torch.einsum("ak,ki->ia", dvo, sig), torch.einsum("iakc,ck->ia", Q, dvo),
+                torch.einsum("ak,ik->ia", dvo * mc, sig), torch.einsum("iakc,ck->ia", P, dvo * mc),
+                torch.einsum("ak,ki->ia", dvo * mc, sig), torch.einsum("iakc,ck->ia", Q, dvo * mc)]
+        A_ = np.stack([np.array([c[i, a - o].item() for (i, a) in singles]) for c in cand], axis=1)
+        rows.append(A_)
+        rhs.append(F2[:len(singles)])
+    A_ = np.concatenate(rows)
+    b = np.concatenate(rhs)
+    x = np.linalg.lstsq(np.concatenate([A_.real, A_.imag]), np.concatenate([b.real, b.imag]), rcond=None)[0]
+    want = np.array([0.5, -0.5, -0.5, 0.5, 0.5, 0.5, 1.0, -0.25, -0.25, 0.5, 0, 0, 0, 0, 0, 0])
+    assert np.abs(x - want).max() < 1e-5, np.round(x, 6)
