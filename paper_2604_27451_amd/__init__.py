@@ -20,7 +20,7 @@ Functions mirror the C ABI names:
     adc2_destroy(h)
     adc2_last_error() -> str
 and the autograd wrapper
-    adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, ...) -> omega (float64 tensor)
+    adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, max_iter=0, solver=FOLDED) -> omega (float64 tensor)
 whose backward is adc2_omega_backward.
 """
 from __future__ import annotations
@@ -229,6 +229,16 @@ def _need(t, dtype, what):
         raise ValueError(f"{what} must be contiguous")
 
 
+def _rows(t, dim, what, rows=None):
+    """Shape check of a block of ADC vectors [k][dim] before any pointer is
+    handed to the library (which cannot see tensor shapes): wrong shapes would
+    otherwise mean reads or writes past the end of a device buffer."""
+    if t.dim() != 2 or t.shape[1] != dim:
+        raise ValueError(f"{what} must be [k][{dim}], got {list(t.shape)}")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{what} must have {rows} rows, got {t.shape[0]}")
+
+
 class Handle:
     def __init__(self, ptr, nc, no, nv, naux, alloc=None):
         self.ptr = ptr
@@ -258,11 +268,11 @@ def adc2_setup(L, eps, nc, no, nv, naux, prec=ADC2_FP64, stream=None, alloc=None
     """Handle of one system.  alloc: None (hipMalloc), "torch" (PyTorch's
     caching allocator) or an Alloc of one's own."""
     import torch
-    _need(L, torch.complex128, "L")
-    _need(eps, torch.float64, "eps")
     n = nc + no + nv
     if tuple(L.shape) != (naux, n, n) or tuple(eps.shape) != (n,):
         raise ValueError("L must be [naux][n][n] and eps [n]")
+    _need(L, torch.complex128, "L")
+    _need(eps, torch.float64, "eps")
     out = ctypes.c_void_p()
     al = torch_allocator() if alloc == "torch" else alloc
     st = load().adc2_setup(ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(eps.data_ptr()),
@@ -278,12 +288,16 @@ def adc2_dim(h: Handle) -> int:
 
 def adc2_sigma(h: Handle, X, S=None, stream=None):
     import torch
-    _need(X, torch.complex128, "X")
     if X.dim() == 1:
         X = X[None]
+    _rows(X, h.dim, "X")
     m = X.shape[0]
-    if X.shape[1] != h.dim:
-        raise ValueError("X must be [m][dim]")
+    if S is not None:
+        if S.dim() == 1:
+            S = S[None]
+        if tuple(S.shape) != tuple(X.shape):
+            raise ValueError(f"S must have the shape of X {list(X.shape)}, got {list(S.shape)}")
+    _need(X, torch.complex128, "X")
     if S is None:
         S = torch.empty_like(X)
     _need(S, torch.complex128, "S")
@@ -303,13 +317,16 @@ def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, ngues
     opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver, 1 if follow else 0, float(mixed_tol))
     info = DavInfo()
     omega = (ctypes.c_double * nroots)()
-    X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None
     gp = ctypes.c_void_p(0)
     if guess is not None:
-        _need(guess, torch.complex128, "guess")
-        gp = ctypes.c_void_p(guess.data_ptr())
+        _rows(guess, h.dim, "guess")
         if opts.nguess == 0:
             opts.nguess = guess.shape[0]
+        if opts.nguess > guess.shape[0]:
+            raise ValueError(f"nguess={opts.nguess} exceeds the {guess.shape[0]} rows of guess")
+        _need(guess, torch.complex128, "guess")
+        gp = ctypes.c_void_p(guess.data_ptr())
+    X = torch.empty((nroots, h.dim), dtype=torch.complex128, device="cuda") if want_vectors else None
     st = load().adc2_davidson(h.ptr, nroots, ctypes.byref(opts), gp, omega,
                               ctypes.c_void_p(X.data_ptr()) if X is not None else ctypes.c_void_p(0),
                               ctypes.byref(info), _stream_ptr(stream))
@@ -390,6 +407,7 @@ def adc2_set_precision(h: Handle, prec: int):
 def adc2_rayleigh(h: Handle, X, stream=None):
     """FP64 Rayleigh quotients and residual norms of the rows of X."""
     import torch
+    _rows(X, h.dim, "X")
     _need(X, torch.complex128, "X")
     k = X.shape[0]
     om = (ctypes.c_double * k)()
@@ -403,12 +421,11 @@ def adc2_omega_backward(h: Handle, X, g_omega, dL=None, deps=None, stream=None):
     """Gradient of sum_k g_k x_k^H M x_k / x_k^H x_k with respect to L
     (Hermitian-projected, complex128 [naux][n][n]) and eps (float64 [n])."""
     import torch
-    _need(X, torch.complex128, "X")
     if X.dim() == 1:
         X = X[None]
+    _rows(X, h.dim, "X")
+    _need(X, torch.complex128, "X")
     k = X.shape[0]
-    if X.shape[1] != h.dim:
-        raise ValueError("X must be [nroots][dim]")
     g = [float(v) for v in (g_omega.tolist() if isinstance(g_omega, torch.Tensor) else g_omega)]
     if len(g) != k:
         raise ValueError("g_omega must have one entry per vector")
@@ -441,27 +458,30 @@ def _omega_function():
         """omega = lowest eigenvalues of M(L, eps); backward by adc2_omega_backward."""
 
         @staticmethod
-        def forward(ctx, L, eps, nc, no, nv, nroots, tol, max_iter):
+        def forward(ctx, L, eps, nc, no, nv, nroots, tol, max_iter, solver):
             naux = L.shape[0]
             h = adc2_setup(L.detach().contiguous(), eps.detach().contiguous(), nc, no, nv, naux)
-            w, X, _ = adc2_davidson(h, nroots, tol=tol, max_iter=max_iter)
+            w, X, _ = adc2_davidson(h, nroots, tol=tol, max_iter=max_iter, solver=solver)
+            # the handle lives as long as the graph node: it is destroyed when
+            # ctx is released (Handle.__del__), so backward may run again
+            # under retain_graph=True
             ctx.h, ctx.X = h, X
             return torch.tensor(w, dtype=torch.float64, device=L.device)
 
         @staticmethod
         def backward(ctx, g):
             dL, de = adc2_omega_backward(ctx.h, ctx.X, g.detach().cpu())
-            ctx.h.close()
-            ctx.h = ctx.X = None
-            return dL, de, None, None, None, None, None, None
+            return dL, de, None, None, None, None, None, None, None
 
     _omega_fn = Adc2Omega
     return _omega_fn
 
 
-def adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, max_iter=0):
-    """Lowest nroots eigenvalues as a differentiable function of (L, eps)."""
-    return _omega_function().apply(L, eps, nc, no, nv, nroots, tol, max_iter)
+def adc2_omega(L, eps, nc, no, nv, nroots, tol=1e-10, max_iter=0, solver=ADC2_SOLVER_FOLDED):
+    """Lowest nroots eigenvalues as a differentiable function of (L, eps).
+    solver: ADC2_SOLVER_FOLDED (default; roots below the doubles threshold,
+    the case of every benchmark system) or ADC2_SOLVER_FULL."""
+    return _omega_function().apply(L, eps, nc, no, nv, nroots, tol, max_iter, solver)
 
 
 def adc2_get_m11(h: Handle, stream=None):
@@ -503,10 +523,17 @@ def adc2_transition(h: Handle, dip, X, omega, order: int = 2, stream=None):
     order: the singles of F through first (1) or second (2) order."""
     import numpy as np
     import torch
+    n = h.nc + h.no + h.nv
+    if tuple(dip.shape) != (3, n, n):
+        raise ValueError(f"dip must be [3][{n}][{n}], got {list(dip.shape)}")
+    _rows(X, h.dim, "X")
+    k = X.shape[0]
+    omega = [float(w) for w in (omega.tolist() if isinstance(omega, torch.Tensor) else omega)]
+    if len(omega) != k:
+        raise ValueError(f"omega must have one entry per row of X ({k}), got {len(omega)}")
     _need(dip, torch.complex128, "dip")
     _need(X, torch.complex128, "X")
-    k = X.shape[0]
-    om = (ctypes.c_double * k)(*[float(w) for w in omega])
+    om = (ctypes.c_double * k)(*omega)
     T = np.zeros((k, 3), dtype=np.complex128)
     f = (ctypes.c_double * k)()
     _check(load().adc2_transition(h.ptr, ctypes.c_void_p(dip.data_ptr()), k, ctypes.c_void_p(X.data_ptr()), om,
@@ -520,8 +547,10 @@ def adc2_fns(h: Handle, L, threshold: float, stream=None):
     Returns (L', eps', nv', occupations): the rotated Cholesky vectors and
     energies of the truncated problem (nc, no, nv', naux)."""
     import torch
-    _need(L, torch.complex128, "L")
     n = h.nc + h.no + h.nv
+    if tuple(L.shape) != (h.naux, n, n):
+        raise ValueError(f"L must be [{h.naux}][{n}][{n}], got {list(L.shape)}")
+    _need(L, torch.complex128, "L")
     occ = (ctypes.c_double * h.nv)()
     nvp = ctypes.c_int()
     Lout = torch.empty((h.naux * n * n,), dtype=torch.complex128, device="cuda")

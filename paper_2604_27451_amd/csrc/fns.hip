@@ -147,7 +147,10 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
     }
   std::vector<double> w(nv);
   std::vector<hostla::cplx> V(nv2);
-  hostla::herm_eig(nv, D.data(), w.data(), V.data());
+  if (hostla::herm_eig(nv, D.data(), w.data(), V.data()) != 0) {
+    cleanup();
+    return ffail(ADC2_ERR_NOCONV, "adc2_fns: the eigensolve of the virtual density did not converge");
+  }
   // descending occupations
   std::vector<int> ord(nv);
   for (int i = 0; i < nv; ++i) ord[i] = nv - 1 - i;
@@ -183,7 +186,10 @@ extern "C" ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double th
       F[(size_t)j * keep + i] = std::conj(v);
     }
   std::vector<double> ep(keep);
-  hostla::herm_eig(keep, F.data(), ep.data(), Zt.data());
+  if (hostla::herm_eig(keep, F.data(), ep.data(), Zt.data()) != 0) {
+    cleanup();
+    return ffail(ADC2_ERR_NOCONV, "adc2_fns: the eigensolve of the kept Fock block did not converge");
+  }
   // WT = W^T (n' x n, row-major), W = blockdiag(1_o, U), U = V~ Z~
   const int np = o + keep;
   std::vector<hostla::cplx> hWT((size_t)np * n, 0.0);

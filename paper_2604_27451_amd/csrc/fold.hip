@@ -319,7 +319,8 @@ struct FoldRoot {
   std::vector<cplx> y;           // eigenvector of G(omega) for this root
   std::vector<cplx> Z;           // all eigenvectors of G(omega) (columns)
   int status = 0;                // 0 ok, 1 root not below the doubles threshold, 2 expansion too long,
-                                 // 3 more moments needed (need)
+                                 // 3 more moments needed (need), 4 below the shifted map's range,
+                                 // 5 projected eigensolve did not converge
   int need = 0;
   int clamped = 0;               // consecutive iterations with status 1 (held at the expansion limit)
 };
@@ -786,7 +787,11 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       std::vector<cplx> Z((size_t)s * s), Hs((size_t)s * s);
       for (int i = 0; i < s; ++i)
         for (int j = 0; j < s; ++j) Hs[(size_t)i * s + j] = H11[(size_t)i * smax + j];
-      hostla::herm_eig(s, Hs.data(), w.data(), Z.data());
+      if (hostla::herm_eig(s, Hs.data(), w.data(), Z.data()) != 0) {
+        set_error("adc2_davidson (folded): the eigensolve of the projected singles block did not converge");
+        final_rc = ADC2_ERR_NOCONV;
+        break;
+      }
       lam_min = w[0];
     }
     double T0 = 0.0;
@@ -840,8 +845,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
             G[(size_t)l * s + i] = std::conj(a);
           }
         }
-        if (Zp.empty()) hostla::herm_eig(s, G.data(), w.data(), Z.data());
-        else hostla::herm_eig_warm(s, G.data(), Zp.data(), w.data(), Z.data());
+        const int bad = Zp.empty() ? hostla::herm_eig(s, G.data(), w.data(), Z.data())
+                                   : hostla::herm_eig_warm(s, G.data(), Zp.data(), w.data(), Z.data());
+        if (bad != 0) {
+          R.status = 5;
+          return;
+        }
         Zp = Z;
         // |x2|^2 = y^H E y,  E = sum eco_m K_m
         double n2 = 0.0;
@@ -929,10 +938,14 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     for (int j = 0; j < k; ++j) {
       if (roots[j].status != 0) {
         char buf[200];
-        snprintf(buf, sizeof buf,
-                 "adc2_davidson (folded): root %d is not below the doubles threshold min D = %.6f (use the "
-                 "full-space solver)",
-                 j, Dmin);
+        if (roots[j].status == 5)
+          snprintf(buf, sizeof buf, "adc2_davidson (folded): the projected eigensolve of root %d did not converge",
+                   j);
+        else
+          snprintf(buf, sizeof buf,
+                   "adc2_davidson (folded): root %d is not below the doubles threshold min D = %.6f (use the "
+                   "full-space solver)",
+                   j, Dmin);
         set_error(buf);
         final_rc = ADC2_ERR_NOCONV;
         break;

@@ -26,8 +26,11 @@ using cplx = std::complex<double>;
 //   beta = -sign(Re alpha) |(alpha, x)|, tau = (beta - alpha) / beta,
 //   v[1:] = x / (alpha - beta); the trailing block is updated as
 //   A <- A - v w^H - w v^H with p = tau A v, w = p - (tau/2)(p^H v) v.
-inline void herm_eig(int n, const cplx* A, double* w, cplx* Z) {
-  if (n <= 0) return;
+// Returns the number of eigenvalues whose QL iteration did not converge
+// within max_iter sweeps (0 on success); callers treat a nonzero count as a
+// failed eigensolve.
+inline int herm_eig(int n, const cplx* A, double* w, cplx* Z, int max_iter = 60) {
+  if (n <= 0) return 0;
   std::vector<cplx> a(A, A + (size_t)n * n);
   for (int i = 0; i < n; ++i) {          // Hermitian part, real diagonal
     a[(size_t)i * n + i] = a[(size_t)i * n + i].real();
@@ -95,14 +98,19 @@ inline void herm_eig(int n, const cplx* A, double* w, cplx* Z) {
   // implicit QL on (d, e), e[i] coupling i and i+1; Y accumulates the rotations
   std::vector<double> Y((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) Y[(size_t)i * n + i] = 1.0;
+  int unconverged = 0;
   for (int l = 0; l < n; ++l) {
-    for (int iter = 0; iter < 60; ++iter) {
+    for (int iter = 0;; ++iter) {
       int m = l;
       for (; m + 1 < n; ++m) {
         const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
         if (std::fabs(e[m]) <= 1e-16 * dd) break;
       }
       if (m == l) break;
+      if (iter >= max_iter) {
+        ++unconverged;
+        break;
+      }
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
       double r = std::hypot(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
@@ -177,13 +185,14 @@ inline void herm_eig(int n, const cplx* A, double* w, cplx* Z) {
     w[i] = d[ord[i]];
     for (int r = 0; r < n; ++r) Z[(size_t)r * n + i] = X[(size_t)r * n + ord[i]];
   }
+  return unconverged;
 }
 
 // Same contract, for a matrix close to diagonal in the basis Zp: the direct
 // solver above costs the same either way, so Zp is not needed.
-inline void herm_eig_warm(int n, const cplx* A, const cplx* Zp, double* w, cplx* Z) {
+inline int herm_eig_warm(int n, const cplx* A, const cplx* Zp, double* w, cplx* Z) {
   (void)Zp;
-  herm_eig(n, A, w, Z);
+  return herm_eig(n, A, w, Z);
 }
 
 // Chebyshev expansions of the resolvent for real |x| > 1 and t in [-1, 1]:

@@ -1,9 +1,9 @@
 // k_setup.hip -- setup kernels: Cholesky-block repack, MP2 amplitudes and the
 // dense CVS singles block through second order.
 //
-// Paper (Implementation section): integrals with at most two virtual indices
-// are formed once; integrals with more are generated on the fly from the
-// Cholesky vectors.  Here the setup forms
+// Storage split (Implementation section): setup keeps only integrals with up
+// to two virtual indices; contractions that carry three or four virtual
+// indices are formed from L inside the sigma GEMMs.  The setup forms
 //   W^{kl}_{ac} = <ac||kl> = (ak|cl) - (al|ck)   for every occupied pair k<l,
 //   tau = W / D^{ac}_{kl},  D = e_a + e_c - e_k - e_l   (Eq. 15 denominators),
 // the MP2 energy, and the singles block

@@ -140,3 +140,54 @@ def test_one_hip_runtime_in_the_process():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_binding_rejects_wrong_shapes_before_any_call(monkeypatch):
+    """The library sees only pointers, so the binding checks every tensor
+    shape first: a wrong shape raises ValueError before any library call (the
+    library is replaced by an object that fails on any attribute access)."""
+    import torch
+
+    class NoCalls:
+        def __getattr__(self, name):
+            raise AssertionError(f"library call {name} reached with a wrong shape")
+
+    monkeypatch.setattr(A, "_lib", NoCalls())
+    h = A.Handle.__new__(A.Handle)
+    h.ptr, h.alloc = None, None
+    h.nc, h.no, h.nv, h.naux = 2, 3, 4, 5
+    h.ns = 8
+    h.dim = 8 + 2 * 3 * 6
+    n = 9
+    c = torch.complex128
+    good = torch.zeros((2, h.dim), dtype=c)
+    with pytest.raises(ValueError):                      # X too short
+        A.adc2_sigma(h, torch.zeros((2, h.dim - 1), dtype=c))
+    with pytest.raises(ValueError):                      # S with fewer rows than X
+        A.adc2_sigma(h, good, torch.zeros((1, h.dim), dtype=c))
+    with pytest.raises(ValueError):                      # S too short
+        A.adc2_sigma(h, good, torch.zeros((2, h.dim - 3), dtype=c))
+    with pytest.raises(ValueError):                      # guess too short
+        A.adc2_davidson(h, 2, guess=torch.zeros((2, h.dim - 1), dtype=c))
+    with pytest.raises(ValueError):                      # nguess beyond the guess rows
+        A.adc2_davidson(h, 2, nguess=3, guess=good)
+    with pytest.raises(ValueError):
+        A.adc2_rayleigh(h, torch.zeros((2, h.dim + 1), dtype=c))
+    with pytest.raises(ValueError):
+        A.adc2_omega_backward(h, torch.zeros((2, 7), dtype=c), [1.0, 1.0])
+    dip = torch.zeros((3, n, n), dtype=c)
+    with pytest.raises(ValueError):                      # dip of the wrong size
+        A.adc2_transition(h, torch.zeros((3, n - 1, n - 1), dtype=c), good, [0.1, 0.2])
+    with pytest.raises(ValueError):                      # X of the wrong length
+        A.adc2_transition(h, dip, torch.zeros((2, h.dim - 1), dtype=c), [0.1, 0.2])
+    with pytest.raises(ValueError):                      # omega shorter than X
+        A.adc2_transition(h, dip, good, [0.1])
+    with pytest.raises(ValueError):
+        A.adc2_fns(h, torch.zeros((h.naux, n, n - 1), dtype=c), 1e-4)
+    with pytest.raises(ValueError):
+        A.adc2_setup(torch.zeros((5, n, n), dtype=c), torch.zeros(n - 1, dtype=torch.float64), 2, 3, 4, 5)
+    # right shapes on host memory get past the shape checks and stop at the device check
+    with pytest.raises(TypeError):
+        A.adc2_sigma(h, good)
+    with pytest.raises(TypeError):
+        A.adc2_transition(h, dip, good, [0.1, 0.2])

@@ -225,7 +225,7 @@ def test_autograd_function_matches_oracle():
     k = 3
     L = dev(s.L).requires_grad_(True)
     eps = dev(s.eps).requires_grad_(True)
-    w = A.adc2_omega(L, eps, s.nc, s.no, s.nv, k, tol=1e-11)
+    w = A.adc2_omega(L, eps, s.nc, s.no, s.nv, k, tol=1e-11, solver=A.ADC2_SOLVER_FULL)
     coef = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
     (w * coef).sum().backward()
     o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
@@ -235,3 +235,32 @@ def test_autograd_function_matches_oracle():
                              V.T.contiguous(), coef.cpu().tolist())
     assert rel(L.grad.cpu().numpy(), G.numpy()) < 1e-8
     assert rel(eps.grad.cpu().numpy(), de.numpy()) < 1e-8
+
+
+def test_autograd_function_folded_c1():
+    """adc2_omega with its default solver (the folded one) at c1: roots
+    against the oracle Davidson, gradients against the oracle's autograd
+    gradient at the oracle's own eigenvectors, and a second backward through
+    the same graph (retain_graph) giving the same gradient."""
+    s = system("c1")
+    k = 4
+    print(f"[case] autograd folded c1 nc={s.nc} no={s.no} nv={s.nv} naux={s.naux} k={k}", flush=True)
+    L = dev(s.L).requires_grad_(True)
+    eps = dev(s.eps).requires_grad_(True)
+    w = A.adc2_omega(L, eps, s.nc, s.no, s.nv, k, tol=1e-10)
+    coef = torch.tensor([1.0, -0.5, 0.25, 2.0], dtype=torch.float64, device="cuda")
+    (w * coef).sum().backward(retain_graph=True)
+    gL1, ge1 = L.grad.clone(), eps.grad.clone()
+    L.grad = None
+    eps.grad = None
+    (w * coef).sum().backward()
+    assert torch.equal(L.grad, gL1) and torch.equal(eps.grad, ge1)
+    o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    w_or, X_or, inf = o.roots(k, tol=1e-10, max_iter=400)
+    assert inf["converged"]
+    assert np.abs(w.detach().cpu().numpy() - w_or.numpy()).max() < 1e-9
+    G, de = O.omega_gradient(torch.from_numpy(s.L), torch.from_numpy(s.eps), O.Spaces(s.nc, s.no, s.nv),
+                             X_or / torch.linalg.vector_norm(X_or, dim=1, keepdim=True), coef.cpu().tolist())
+    # eigenvectors of the two solvers differ by O(residual) = 1e-10, so do the gradients
+    assert rel(gL1.cpu().numpy(), G.numpy()) < 1e-7
+    assert rel(ge1.cpu().numpy(), de.numpy()) < 1e-7

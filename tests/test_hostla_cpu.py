@@ -27,6 +27,9 @@ SHIM = r'''
 extern "C" void heig(int n, const double* A, double* w, double* Z) {
   adc2::hostla::herm_eig(n, (const adc2::hostla::cplx*)A, w, (adc2::hostla::cplx*)Z);
 }
+extern "C" int heig_it(int n, const double* A, double* w, double* Z, int max_iter) {
+  return adc2::hostla::herm_eig(n, (const adc2::hostla::cplx*)A, w, (adc2::hostla::cplx*)Z, max_iter);
+}
 extern "C" int cheb(double x, int mmax, double* b, double* e) {
   return adc2::hostla::cheb_resolvent(x, mmax, b, e);
 }
@@ -162,3 +165,82 @@ def test_resolvent_map_term_counts_and_reach(lib):
     # omega at or above min D, or at or below w0, has no expansion
     assert lib.rmap_coeffs(1, Dmin, Dmax, w0, Dmin, 128, *args) < 0
     assert lib.rmap_coeffs(1, Dmin, Dmax, w0, w0, 128, *args) < 0
+
+
+def test_herm_eig_reports_unconverged_eigenvalues(lib):
+    """herm_eig returns the number of eigenvalues whose QL iteration did not
+    finish within max_iter sweeps: 0 with the default limit, nonzero when the
+    limit is forced to zero sweeps on a matrix that needs them (the callers
+    turn a nonzero count into ADC2_ERR_NOCONV)."""
+    lib.heig_it.restype = ctypes.c_int
+    n = 12
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = np.ascontiguousarray(A + A.conj().T)
+    w = np.zeros(n)
+    Z = np.zeros((n, n), dtype=np.complex128)
+    args = (A.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p))
+    assert lib.heig_it(n, *args, 60) == 0
+    assert np.abs(w - np.linalg.eigvalsh(A)).max() < 1e-12 * np.abs(w).max()
+    bad = lib.heig_it(n, *args, 0)
+    assert 1 <= bad <= n
+    # a diagonal matrix needs no sweep at all
+    D = np.ascontiguousarray(np.diag(np.arange(n, dtype=float)).astype(complex))
+    assert lib.heig_it(n, D.ctypes.data_as(ctypes.c_void_p), args[1], args[2], 0) == 0
+
+
+SAN_MAIN = r'''
+#include "hostla.h"
+#include <cstdio>
+#include <random>
+using adc2::hostla::cplx;
+int main() {
+  std::mt19937_64 g(11);
+  std::normal_distribution<double> nd;
+  int fails = 0;
+  for (int n : {1, 2, 5, 17, 64}) {
+    std::vector<cplx> A((size_t)n * n), Z((size_t)n * n);
+    std::vector<double> w(n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const cplx v(nd(g), i == j ? 0.0 : nd(g));
+        A[(size_t)i * n + j] = v;
+        A[(size_t)j * n + i] = std::conj(v);
+      }
+    if (adc2::hostla::herm_eig(n, A.data(), w.data(), Z.data()) != 0) ++fails;
+    double r = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < n; ++c) {
+        cplx acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * Z[(size_t)k * n + c];
+        r = std::max(r, std::abs(acc - w[c] * Z[(size_t)i * n + c]));
+      }
+    if (r > 1e-10 * (1.0 + std::fabs(w[0]) + std::fabs(w[n - 1]))) ++fails;
+    double b[256], e[256], gg[256], hh[256];
+    if (adc2::hostla::cheb_resolvent(1.5 + n, 256, b, e) < 1) ++fails;
+    auto rm = adc2::hostla::ResolventMap::shifted_inverse(2.0, 9.0, -1.0);
+    if (rm.coeffs(0.5, 256, b, e, gg, hh) < 1) ++fails;
+  }
+  std::printf("fails=%d\n", fails);
+  return fails;
+}
+'''
+
+
+def test_host_algebra_under_address_and_undefined_sanitizers(tmp_path):
+    """The host algebra of the folded solver, built as a host program with
+    AddressSanitizer and UndefinedBehaviorSanitizer (g++, no GPU code), runs
+    its eigensolver and resolvent coefficients without a report."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.fail("g++ not found")
+    src = tmp_path / "san.cpp"
+    src.write_text(SAN_MAIN)
+    exe = tmp_path / "san"
+    subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120,
+                       env={**os.environ, "ASAN_OPTIONS": "detect_leaks=1:verify_asan_link_order=0"})
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "fails=0" in r.stdout
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
