@@ -241,6 +241,27 @@ def density_taylor(L, eps, nocc, nterms=3, degree=10, npts=17, lam_max=0.5):
     return out, resid
 
 
+def determinant_doubles_block(L, eps, nc, no, nv):
+    """Matrix of the fluctuation potential V_N between the CVS doubly
+    excited determinants a+_a a+_b a_j a_I |Phi0> (I core, j valence, a<b),
+    minus its reference expectation value <Phi0|V_N|Phi0> (the first-order
+    energy, subtracted with E0 in M = H - E0), straight from the Fock-space
+    operators: the first-order doubles block with no intermediate-state
+    construction and no fit."""
+    o = nc + no
+    fs = FockSpace(L, eps, o)
+    ref = np.zeros(1 << fs.n, dtype=np.complex128)
+    ref[fs.ref] = 1.0
+    vecs = []
+    for I in range(nc):
+        for j in range(nc, o):
+            for a, b in itertools.combinations(range(o, fs.n), 2):
+                vecs.append(fs.ad[a] @ (fs.ad[b] @ (fs.a[j] @ (fs.a[I] @ ref))))
+    T = np.stack(vecs, axis=1)
+    e1 = np.conj(ref) @ fs.V @ ref
+    return np.conj(T.T) @ fs.V @ T - e1 * np.eye(T.shape[1])
+
+
 def _sym_orth(P):
     S = np.conj(P.T) @ P
     w, U = np.linalg.eigh(S)
@@ -257,6 +278,7 @@ def adc2_blocks(L, eps, nc, no, nv, **fit):
       M21_cvs  : first-order coupling rows (I, j valence, a<b) in the basis
                  a+_a a+_b a_j a_I |Phi0> (= -1 x the a+_a a+_b a_I a_j state)
       M22_cvs  : zeroth-order doubles block on the same rows
+      M22x_cvs : first-order doubles block on the same rows (ADC(2)-x)
       E_mp2    : second-order ground-state energy (lambda^2 coefficient)
       fit_resid: max residual of the polynomial fit
     """
@@ -274,7 +296,10 @@ def adc2_blocks(L, eps, nc, no, nv, **fit):
     M21 = (M0 + M1)[ns:, :ns]
     M21_cvs = sign * M21[np.ix_(cvs_d, cvs_s)]
     M22_cvs = M0[ns:, ns:][np.ix_(cvs_d, cvs_d)]
+    # first-order doubles block (the extension of ADC(2)-x); the basis sign
+    # of the doubles rows cancels between bra and ket
+    M22x_cvs = M1[ns:, ns:][np.ix_(cvs_d, cvs_d)]
     return {"M11_full": M11_full, "M11_cvs": M11_cvs, "M21_cvs": M21_cvs,
-            "M22_cvs": M22_cvs, "E_mp2": E[2], "E1": E[1], "E0": E[0],
+            "M22_cvs": M22_cvs, "M22x_cvs": M22x_cvs, "E_mp2": E[2], "E1": E[1], "E0": E[0],
             "fit_resid": resid, "orders": (M0, M1, M2), "singles": singles,
             "doubles": doubles}
