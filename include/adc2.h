@@ -161,6 +161,30 @@ ADC2_API size_t adc2_dim(adc2_handle h);
 ADC2_API adc2_status adc2_sigma(adc2_handle h, int m, const void* X, void* S, void* stream);
 
 /*
+ * adc2_sigma_noalloc -- adc2_sigma (FP64 form) that allocates nothing.
+ * For callers that cannot allocate device memory during the call: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The caller passes X and S as for adc2_sigma; the sigma's work
+ * spaces (the X-build output, the Y-build partials, the unpacked doubles and
+ * the light and back-contraction partials) come from one static device
+ * array of 128 MiB that the library holds on every device it runs on until
+ * the process ends, instead of the handle's buffers.  No hipMalloc, hipFree
+ * or other allocating call is made.  The array is shared by every call on a
+ * device and keeps the last call's contents; no kernel of the sigma reads
+ * scratch memory it has not written in the same call.  Calls that overlap on
+ * one device (concurrent streams or threads) race on the array and must not
+ * be issued.  Results equal adc2_sigma's in the FP64 form: the same kernels
+ * with the same split counts.
+ *   m  >= 1; the work spaces of m vectors must fit the array: about
+ *      16 m nc (naux nv (1 + ysplit) + no nv^2) bytes (c1: nc=6, no=10,
+ *      nv=40, naux=150 fits m up to about 16).
+ * Errors: ADC2_ERR_ARG (NULL, m < 1, S aliasing X, a handle in a precision
+ * form, sizes above the maximum, with the bytes needed in the message),
+ * ADC2_ERR_HIP.  Stream-ordered, asynchronous.
+ */
+ADC2_API adc2_status adc2_sigma_noalloc(adc2_handle h, int m, const void* X, void* S, void* stream);
+
+/*
  * adc2_davidson -- lowest nroots eigenpairs of M by block Davidson (FP64).
  *   nroots   1..ADC2_MAX_ROOTS.
  *   opt      may be NULL (tol 1e-8, defaults above).

@@ -9,6 +9,7 @@ Functions mirror the C ABI names:
     adc2_setup(L, eps, nc, no, nv, naux, prec=0) -> Handle
     adc2_dim(h)
     adc2_sigma(h, X, S=None) -> S
+    adc2_sigma_noalloc(h, X, S) -> S
     adc2_davidson(h, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0,
                   guess=None, want_vectors=True, verbose=0) -> (omega, X, info)
     adc2_set_precision(h, prec)
@@ -63,7 +64,8 @@ STATUS_NAMES = {0: "ADC2_OK", 1: "ADC2_ERR_ARG", 2: "ADC2_ERR_NOT_HERMITIAN", 3:
 EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_precision",
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
-           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns", "adc2_transition"]
+           "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns", "adc2_transition",
+           "adc2_sigma_noalloc"]
 
 
 class DavOpts(ctypes.Structure):
@@ -161,6 +163,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_dim.restype = ctypes.c_size_t
     lib.adc2_sigma.argtypes = [vp, i, vp, vp, vp]
     lib.adc2_sigma.restype = i
+    lib.adc2_sigma_noalloc.argtypes = [vp, i, vp, vp, vp]
+    lib.adc2_sigma_noalloc.restype = i
     lib.adc2_davidson.argtypes = [vp, i, ctypes.POINTER(DavOpts), vp, ctypes.POINTER(d), vp,
                                   ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson.restype = i
@@ -304,6 +308,25 @@ def adc2_sigma(h: Handle, X, S=None, stream=None):
     st = load().adc2_sigma(h.ptr, m, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(S.data_ptr()),
                            _stream_ptr(stream))
     _check(st, "adc2_sigma")
+    return S
+
+
+def adc2_sigma_noalloc(h: Handle, X, S, stream=None):
+    """S = M X (FP64 form) with the library's static scratch array for the
+    work spaces: no device allocation inside the call (S must be given)."""
+    import torch
+    if X.dim() == 1:
+        X = X[None]
+    if S.dim() == 1:
+        S = S[None]
+    _rows(X, h.dim, "X")
+    if tuple(S.shape) != tuple(X.shape):
+        raise ValueError(f"S must have the shape of X {list(X.shape)}, got {list(S.shape)}")
+    _need(X, torch.complex128, "X")
+    _need(S, torch.complex128, "S")
+    st = load().adc2_sigma_noalloc(h.ptr, X.shape[0], ctypes.c_void_p(X.data_ptr()),
+                                   ctypes.c_void_p(S.data_ptr()), _stream_ptr(stream))
+    _check(st, "adc2_sigma_noalloc")
     return S
 
 

@@ -19,6 +19,8 @@
 #include <cstdlib>
 #include <vector>
 
+#include <mutex>
+
 #include "internal.h"
 #include "tile.h"
 #include "zgemm.h"
@@ -912,9 +914,43 @@ adc2_status ensure_ws_b3(adc2_handle h, int m) {
   return ADC2_OK;
 }
 
+// Sizes of the FP64 sigma work spaces for a block of m vectors and the two
+// split counts that go with them.
+struct WsPlan {
+  int ysplit, nsplit;
+  size_t x, y, zb, tp, part;   // bytes of h->X, h->Y, h->Zb, h->Tp, h->part
+};
+
+// ys, ns > 0 impose the split counts instead of choosing them.
+static WsPlan ws_plan(adc2_handle h, int m, int ys = 0, int ns = 0) {
+  const Dims& d = h->d;
+  WsPlan p;
+  const long rows = (long)m * d.nc;
+  if (ys <= 0) {
+    // split the Y-build over K so that the long-K tiles fill the GPU
+    const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, BT);
+    ys = (int)std::max<long>(1, std::min<long>(8, (16L * 256 + ytiles - 1) / ytiles));
+    if (const char* v = getenv("ADC2_YSPLIT")) ys = std::max(1, std::min(16, atoi(v)));
+    if (h->ysplit_tuned > 0) ys = h->ysplit_tuned;   // adc2_autotune's choice
+  }
+  p.ysplit = ys;
+  if (ns <= 0) {
+    const int nbi = cdiv(rows, TM), nba = cdiv(d.nv, TN);
+    ns = std::max(1, std::min(256, 2048 / std::max(1, nbi * nba)));
+    ns = std::min(ns, d.naux);
+  }
+  p.nsplit = ns;
+  const int njg = (d.no + LJG - 1) / LJG;
+  p.x = sizeof(double2) * rows * d.naux * d.nv;
+  p.y = sizeof(double2) * rows * d.naux * d.nv * p.ysplit;
+  p.zb = sizeof(double2) * rows * d.no * (long)d.nv * d.nv;
+  p.tp = sizeof(double2) * rows * njg * d.nc * d.nv;
+  p.part = sizeof(double2) * p.nsplit * rows * d.nv;
+  return p;
+}
+
 adc2_status ensure_ws(adc2_handle h, int m) {
   if (h->ws_m >= m) return ADC2_OK;
-  const Dims& d = h->d;
   dfree(h, h->X);
   dfree(h, h->Y);
   dfree(h, h->part);
@@ -922,25 +958,14 @@ adc2_status ensure_ws(adc2_handle h, int m) {
   dfree(h, h->Tp);
   h->X = h->Y = h->part = h->Zb = h->Tp = nullptr;
   h->ws_m = 0;
-  const long rows = (long)m * d.nc;
-  ADC2_HIP(dmalloc(h, &h->X, sizeof(double2) * rows * d.naux * d.nv));
-  {
-    // split the Y-build over K so that the long-K tiles fill the GPU
-    const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, BT);
-    int ys = (int)std::max<long>(1, std::min<long>(8, (16L * 256 + ytiles - 1) / ytiles));
-    if (const char* v = getenv("ADC2_YSPLIT")) ys = std::max(1, std::min(16, atoi(v)));
-    if (h->ysplit_tuned > 0) ys = h->ysplit_tuned;   // adc2_autotune's choice
-    h->ysplit = ys;
-  }
-  ADC2_HIP(dmalloc(h, &h->Y, sizeof(double2) * rows * d.naux * d.nv * h->ysplit));
-  ADC2_HIP(dmalloc(h, &h->Zb, sizeof(double2) * rows * d.no * (long)d.nv * d.nv));
-  const int njg = (d.no + LJG - 1) / LJG;
-  ADC2_HIP(dmalloc(h, &h->Tp, sizeof(double2) * rows * njg * d.nc * d.nv));
-  const int nbi = cdiv(rows, TM), nba = cdiv(d.nv, TN);
-  int nsplit = std::max(1, std::min(256, 2048 / std::max(1, nbi * nba)));
-  nsplit = std::min(nsplit, d.naux);
-  h->nsplit = nsplit;
-  ADC2_HIP(dmalloc(h, &h->part, sizeof(double2) * nsplit * rows * d.nv));
+  const WsPlan p = ws_plan(h, m);
+  h->ysplit = p.ysplit;
+  h->nsplit = p.nsplit;
+  ADC2_HIP(dmalloc(h, &h->X, p.x));
+  ADC2_HIP(dmalloc(h, &h->Y, p.y));
+  ADC2_HIP(dmalloc(h, &h->Zb, p.zb));
+  ADC2_HIP(dmalloc(h, &h->Tp, p.tp));
+  ADC2_HIP(dmalloc(h, &h->part, p.part));
   h->ws_m = m;
   return ADC2_OK;
 }
@@ -1300,3 +1325,122 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
 }
 
 }  // namespace adc2
+
+// ---------------------------------------------------------------------------
+// Sigma without device allocation: the FP64 sigma build of adc2_sigma with its
+// work spaces (X, Y, unpacked doubles, light partials, back-contraction
+// partials) carved from one static device array instead of the handle's
+// buffers.  The array is a fixed part of the code object, so each device the
+// library runs on holds one copy until the process ends; the host reaches it
+// only through the address hipGetSymbolAddress returns for the current
+// device (the array's own name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+namespace adc2 {
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+}  // namespace adc2
+
+static __device__ __align__(256) unsigned char scratch[adc2::NOALLOC_SCRATCH_BYTES];
+
+namespace adc2 {
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static adc2_status scratch_address(void** out) {
+  int dev = 0;
+  ADC2_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    set_error("adc2_sigma_noalloc: device index out of range");
+    return ADC2_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    ADC2_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("adc2_sigma_noalloc: hipGetSymbolAddress returned NULL");
+      return ADC2_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADC2_OK;
+}
+
+// The plan of a no-allocation sigma: the split counts adc2_sigma would use
+// on this handle now (those of its current work spaces when they already
+// hold m vectors), so that both give the same result.
+static WsPlan noalloc_plan(adc2_handle h, int m) {
+  return h->ws_m >= m ? ws_plan(h, m, h->ysplit, h->nsplit) : ws_plan(h, m);
+}
+
+static size_t plan_bytes(const WsPlan& p) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(p.x) + al(p.y) + al(p.zb) + al(p.tp) + al(p.part);
+}
+
+}  // namespace adc2
+
+extern "C" adc2_status adc2_sigma_noalloc(adc2_handle h, int m, const void* X, void* S, void* stream) {
+  using namespace adc2;
+  if (!h || !X || !S || m <= 0) {
+    set_error("adc2_sigma_noalloc: bad arguments");
+    return ADC2_ERR_ARG;
+  }
+  if (X == S) {
+    set_error("adc2_sigma_noalloc: S must not alias X");
+    return ADC2_ERR_ARG;
+  }
+  if (h->prec != ADC2_FP64) {
+    set_error("adc2_sigma_noalloc: only the FP64 form (the handle is in a precision form)");
+    return ADC2_ERR_ARG;
+  }
+  const WsPlan p = noalloc_plan(h, m);
+  const size_t need = plan_bytes(p);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "adc2_sigma_noalloc: m=%d needs %zu bytes of scratch, above its maximum of %zu bytes "
+             "(use adc2_sigma)",
+             m, need, NOALLOC_SCRATCH_BYTES);
+    set_error(buf);
+    return ADC2_ERR_ARG;
+  }
+  void* base = nullptr;
+  adc2_status rc = scratch_address(&base);
+  if (rc != ADC2_OK) return rc;
+  // point the handle's work spaces into the scratch for this call only; the
+  // kernels take these addresses as arguments at launch
+  double2 *sX = h->X, *sY = h->Y, *sZb = h->Zb, *sTp = h->Tp, *spart = h->part;
+  const int sws = h->ws_m, sys = h->ysplit, sns = h->nsplit;
+  unsigned char* q = static_cast<unsigned char*>(base);
+  auto take = [&](size_t b) {
+    double2* r = reinterpret_cast<double2*>(q);
+    q += (b + 255) & ~size_t(255);
+    return r;
+  };
+  h->X = take(p.x);
+  h->Y = take(p.y);
+  h->Zb = take(p.zb);
+  h->Tp = take(p.tp);
+  h->part = take(p.part);
+  h->ws_m = m;
+  h->ysplit = p.ysplit;
+  h->nsplit = p.nsplit;
+  rc = sigma_parts(h, m, static_cast<const double2*>(X), static_cast<double2*>(S),
+                   SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN, static_cast<hipStream_t>(stream));
+  h->X = sX;
+  h->Y = sY;
+  h->Zb = sZb;
+  h->Tp = sTp;
+  h->part = spart;
+  h->ws_m = sws;
+  h->ysplit = sys;
+  h->nsplit = sns;
+  return rc;
+}
+
