@@ -224,6 +224,30 @@ ADC2_API adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opt
 ADC2_API adc2_status adc2_set_precision(adc2_handle h, int prec);
 
 /*
+ * adc2_set_method -- the scheme of M for subsequent sigma builds, solves and
+ * diagonals of the handle.
+ *   ADC2_METHOD_ADC2   (default) CVS-ADC(2): doubles block diag(D), zeroth order.
+ *   ADC2_METHOD_ADC2X  CVS-ADC(2)-x, the extended scheme the paper's
+ *     Conclusions name as the next step: the doubles block also carries its
+ *     first-order part, the fluctuation potential between the doubly excited
+ *     determinants (particle ladder <ab||cd>, hole ladder <Kk||Ij>, and the
+ *     ring terms <kb||cj> (k, j valence) and <Kb||cI> (K, I core) that the
+ *     core-valence separation leaves).  The singles block and the coupling
+ *     are those of ADC(2).
+ * Selecting ADC(2)-x forms its integral blocks once (FP64, stream-ordered,
+ * then synchronised): npair^2 + (nc no)^2 + (no nv)^2 + (nc nv)^2 complex
+ * values, npair = nv(nv-1)/2 (32 GB at nv = 300); ADC2_ERR_OOM with the size
+ * in the message above 64 GiB.  Its sigma terms run in FP64 on the MFMA
+ * whatever the precision form.  Under ADC(2)-x the folded solver (which needs
+ * a diagonal doubles block) and adc2_omega_backward return ADC2_ERR_ARG; the
+ * full-space solver and adc2_rayleigh apply the ADC(2)-x matrix.
+ * Errors: ADC2_ERR_ARG (NULL handle, unknown method), ADC2_ERR_OOM, ADC2_ERR_HIP.
+ */
+#define ADC2_METHOD_ADC2 0
+#define ADC2_METHOD_ADC2X 1
+ADC2_API adc2_status adc2_set_method(adc2_handle h, int method, void* stream);
+
+/*
  * adc2_rayleigh -- FP64 Rayleigh quotients and residual norms of k vectors:
  *   omega[i] = x_i^H M x_i / x_i^H x_i,  resnorm[i] = ||M x_i - omega_i x_i|| / ||x_i||
  * computed with an FP64 sigma build whatever the handle's precision (the

@@ -13,6 +13,7 @@ Functions mirror the C ABI names:
     adc2_davidson(h, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0,
                   guess=None, want_vectors=True, verbose=0) -> (omega, X, info)
     adc2_set_precision(h, prec)
+    adc2_set_method(h, method)
     adc2_rayleigh(h, X) -> (omega, resnorm)
     adc2_omega_backward(h, X, g_omega, dL=None, deps=None) -> (dL, deps)
     adc2_get_m11(h) -> complex128 tensor
@@ -45,6 +46,8 @@ ADC2_FP64 = 0
 ADC2_C64 = 1
 ADC2_BF16X3 = 2
 ADC2_MAX_ROOTS = 32
+ADC2_METHOD_ADC2 = 0
+ADC2_METHOD_ADC2X = 1
 ADC2_SOLVER_FULL = 0
 ADC2_SOLVER_FOLDED = 1
 ADC2_BATCH_ROUNDS = 0
@@ -65,7 +68,7 @@ EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_pr
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
            "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns", "adc2_transition",
-           "adc2_sigma_noalloc"]
+           "adc2_sigma_noalloc", "adc2_set_method"]
 
 
 class DavOpts(ctypes.Structure):
@@ -168,6 +171,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_davidson.argtypes = [vp, i, ctypes.POINTER(DavOpts), vp, ctypes.POINTER(d), vp,
                                   ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson.restype = i
+    lib.adc2_set_method.argtypes = [vp, i, vp]
+    lib.adc2_set_method.restype = i
     lib.adc2_set_precision.argtypes = [vp, i]
     lib.adc2_set_precision.restype = i
     lib.adc2_rayleigh.argtypes = [vp, i, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp]
@@ -425,6 +430,12 @@ def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess
 
 def adc2_set_precision(h: Handle, prec: int):
     _check(load().adc2_set_precision(h.ptr, prec), "adc2_set_precision")
+
+
+def adc2_set_method(h: Handle, method: int, stream=None):
+    """ADC2_METHOD_ADC2 (default) or ADC2_METHOD_ADC2X (first-order doubles
+    block; its integrals are formed on first selection)."""
+    _check(load().adc2_set_method(h.ptr, int(method), _stream_ptr(stream)), "adc2_set_method")
 
 
 def adc2_rayleigh(h: Handle, X, stream=None):

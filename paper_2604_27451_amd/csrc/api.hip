@@ -47,6 +47,12 @@ static void free_handle(adc2_handle h) {
   dfree(h, h->part);
   dfree(h, h->Zb);
   dfree(h, h->Tp);
+  dfree(h, h->Vpp);
+  dfree(h, h->Hh);
+  dfree(h, h->WvT);
+  dfree(h, h->WcT);
+  dfree(h, h->diagx);
+  dfree(h, h->Xw);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (int i = 0; i <= adc2_handle_s::NK; ++i)
@@ -317,6 +323,8 @@ adc2_status adc2_omega_backward(adc2_handle h, int nroots, const void* X, const 
     return fail(ADC2_ERR_ARG, "adc2_omega_backward: nroots must be in 1..ADC2_MAX_ROOTS");
   for (int k = 0; k < nroots; ++k)
     if (!std::isfinite(g_omega[k])) return fail(ADC2_ERR_ARG, "adc2_omega_backward: non-finite g_omega");
+  if (h->method != ADC2_METHOD_ADC2)
+    return fail(ADC2_ERR_ARG, "adc2_omega_backward: the adjoint covers the ADC(2) matrix only");
   return omega_backward(h, nroots, (const double2*)X, g_omega, (double2*)dL, deps, (hipStream_t)stream);
 }
 
@@ -329,7 +337,7 @@ adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream) {
 
 adc2_status adc2_get_diag(adc2_handle h, double* dst, void* stream) {
   if (!h || !dst) return fail(ADC2_ERR_ARG, "adc2_get_diag: bad arguments");
-  ADC2_HIP(hipMemcpyAsync(dst, h->diag, sizeof(double) * h->d.dim, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  ADC2_HIP(hipMemcpyAsync(dst, cur_diag(h), sizeof(double) * h->d.dim, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return ADC2_OK;
 }
 
@@ -463,6 +471,9 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   }
   if (opt && opt->solver == ADC2_SOLVER_FOLDED) {
     if (nroots <= 0 || nroots > ADC2_MAX_ROOTS) return fail(ADC2_ERR_ARG, "adc2_davidson: nroots must be in 1..32");
+    if (h->method != ADC2_METHOD_ADC2)
+      return fail(ADC2_ERR_ARG, "adc2_davidson: the folded solver needs the diagonal doubles block of ADC(2); "
+                                "use the full-space solver for ADC(2)-x");
     return fold_davidson(h, nroots, opt, guess, omega, Xout, info, (hipStream_t)stream);
   }
   if (opt && opt->solver != ADC2_SOLVER_FULL) return fail(ADC2_ERR_ARG, "adc2_davidson: unknown solver");
@@ -651,7 +662,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     DAV_TRY(hipMemcpyAsync(w.idx, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
     DAV_TRY(hipStreamSynchronize(st));   // act (pageable, loop-local) consumed before it is freed
     k_gather_theta<<<1, 64, 0, st>>>(w.theta, w.idx, na, w.thact);
-    if ((rc = dav_precondition(w.T, w.thact, h->diag, na, dim, st)) != ADC2_OK) return rc;
+    if ((rc = dav_precondition(w.T, w.thact, cur_diag(h), na, dim, st)) != ADC2_OK) return rc;
     int na_use = na;
     if (s + na > max_sub && keep_max >= k && keep_max < s) {
       const int keep = keep_max;

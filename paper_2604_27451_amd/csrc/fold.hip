@@ -404,6 +404,10 @@ static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
 
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
                           void* Xout, adc2_dav_info* info, hipStream_t st) {
+  if (h->method != ADC2_METHOD_ADC2) {
+    set_error("adc2_davidson (folded): needs the diagonal doubles block of ADC(2)");
+    return ADC2_ERR_ARG;
+  }
   if (opt && opt->follow) {
     set_error("adc2_davidson: root following is provided by the full-space solver only");
     return ADC2_ERR_ARG;

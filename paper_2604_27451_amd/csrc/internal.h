@@ -85,6 +85,15 @@ struct adc2_handle_s {
   int ysplit = 1;           // K-splits of the Y-build GEMM
   int ysplit_tuned = 0;     // K-split fixed by adc2_autotune (0: the size heuristic)
   int gemm3 = 0;            // heavy GEMMs: 0 = four-multiplication 128x128 (default), 1 = three-multiplication 128x64
+  // method: ADC2_METHOD_ADC2 or ADC2_METHOD_ADC2X (first-order doubles block, adc2x.hip)
+  int method = 0;
+  double2* Vpp = nullptr;   // ADC(2)-x: [(a<b)][(c<d)] <ab||cd>
+  double2* Hh = nullptr;    //           [(I,j)][(K,k)] <Kk||Ij>
+  double2* WvT = nullptr;   //           [(j,b)][(k,c)] <kb||cj>, k, j valence
+  double2* WcT = nullptr;   //           [(I,b)][(K,c)] <Kb||cI>, K, I core
+  double* diagx = nullptr;  //           diagonal of M with the first-order doubles block
+  double2* Xw = nullptr;    //           sigma work space: unpacked doubles (two layouts), ring products
+  int wsx_m = 0;
   // folded-solver preconditioner (host, built on first use): per singles (K,c) the coupling
   // column norm sum_d |M21_{d,(Kc)}|^2 and its |M21|^2-weighted mean doubles energy
   std::vector<double> pre_nu, pre_dbar;
@@ -151,6 +160,14 @@ adc2_status wbuild_pairs(adc2_handle h, const int2* dpairs, int npairs, double2*
 // i = g*a_inner + x (likewise B); gridDim.y = nsplit K-splits, C holds nsplit partials.
 adc2_status bgemm_kmajor(const double2* A, long a_gstride, long a_ld, int a_inner, const double2* B, long b_gstride,
                          long b_ld, int b_inner, int M, int N, int K, int nsplit, double2* C, hipStream_t st);
+
+// ---- ADC(2)-x (adc2x.hip) ----
+constexpr size_t ADC2X_MAX_BYTES = size_t(64) << 30;   // integral blocks of the first-order doubles block
+adc2_status build_adc2x(adc2_handle h, hipStream_t st);
+// sigma2 += (first-order doubles block) r2 for m full vectors (FP64)
+adc2_status adc2x_apply(adc2_handle h, int m, const double2* x, double2* s, hipStream_t st);
+// diagonal of M for the handle's method
+inline const double* cur_diag(adc2_handle h) { return h->method == ADC2_METHOD_ADC2X ? h->diagx : h->diag; }
 
 // ---- folded solver (fold.hip) ----
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,

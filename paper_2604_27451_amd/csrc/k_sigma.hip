@@ -1294,6 +1294,16 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
     }
   }
   if ((rc = mark(8)) != ADC2_OK) return rc;
+  // ADC(2)-x: the first-order doubles block (FP64), on whole sigma requests only
+  for (int q = 0; q < nreq; ++q) {
+    adc2_handle h = rq[q].h;
+    if (h->method != ADC2_METHOD_ADC2X) continue;
+    if (!sgl[q] || !dbl[q]) {
+      set_error("sigma: ADC(2)-x needs whole sigma products (partial products assume a diagonal doubles block)");
+      return ADC2_ERR_ARG;
+    }
+    if ((rc = adc2x_apply(h, rq[q].m, rq[q].xin, rq[q].sout, st)) != ADC2_OK) return rc;
+  }
   if (prof) {
     adc2_handle h = h0;
     const Dims& d = h->d;
@@ -1397,6 +1407,10 @@ extern "C" adc2_status adc2_sigma_noalloc(adc2_handle h, int m, const void* X, v
   }
   if (h->prec != ADC2_FP64) {
     set_error("adc2_sigma_noalloc: only the FP64 form (the handle is in a precision form)");
+    return ADC2_ERR_ARG;
+  }
+  if (h->method != ADC2_METHOD_ADC2) {
+    set_error("adc2_sigma_noalloc: only the ADC(2) matrix (the handle is set to ADC(2)-x)");
     return ADC2_ERR_ARG;
   }
   const WsPlan p = noalloc_plan(h, m);
