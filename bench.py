@@ -65,31 +65,68 @@ def f_sigma(nc, no, nv, naux):
     return 8.0 * (2.0 * nc * no * nv * nv * naux + 2.0 * nc * nv * nv * naux + (nc * nv) ** 2)
 
 
-def cpu_baseline(sysm, nj: int = 8):
+def host_info():
+    """The host the CPU baseline runs on: core count, CPU model, BLAS of the
+    libraries the oracle calls (torch for its contractions, numpy beside it)."""
+    import platform
+    import subprocess
+    import numpy as np
+    import torch
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    torch_blas = None
+    for tok in torch.__config__.show().replace(",", " ").split():
+        if tok.startswith("BLAS_INFO="):
+            torch_blas = tok.split("=", 1)[1]
+    np_blas = None
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        np_blas = f"{b.get('name')} {b.get('version', '')}".strip()
+    except Exception:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model or platform.processor(),
+            "torch_threads": torch.get_num_threads(), "torch_blas": torch_blas, "numpy_blas": np_blas}
+
+
+def cpu_baseline(L, eps, nc, no, nv, naux, nj: int, nvs: int):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
-    the sigma build (integral blocks + product) for one vector of this system
-    restricted to its first nj valence spinors."""
+    the sigma build (integral blocks + product) for one vector of the system
+    restricted to its first nj valence and first nvs virtual spinors (every
+    Cholesky vector kept).  L, eps may be host arrays or device tensors."""
     import numpy as np
     import torch
     from oracle import adc2 as O
     from synth import random_vectors
-    nc, no, nv, naux = sysm.nc, sysm.no, sysm.nv, sysm.naux
-    idx = np.r_[0:nc, nc:nc + nj, nc + no:nc + no + nv]
-    Ls = np.ascontiguousarray(sysm.L[:, idx][:, :, idx])
-    es = sysm.eps[idx]
+    idx = np.r_[0:nc, nc:nc + nj, nc + no:nc + no + nvs]
+    if isinstance(L, torch.Tensor):
+        it = torch.as_tensor(idx, device=L.device)
+        Ls = np.concatenate([L[p0:p0 + 250][:, it][:, :, it].cpu().numpy() for p0 in range(0, naux, 250)])
+        es = eps[it].cpu().numpy()
+    else:
+        Ls = np.ascontiguousarray(L[:, idx][:, :, idx])
+        es = eps[idx]
     t0 = time.perf_counter()
-    a = O.Adc2(Ls, es, nc, nj, nv)
+    a = O.Adc2(Ls, es, nc, nj, nvs)
     a.sigma_op()
     x = torch.from_numpy(random_vectors(11, 1, a.dim))
     a.sigma(x)
     dt = time.perf_counter() - t0
-    fl = f_sigma(nc, nj, nv, naux)
-    return {"value": fl / dt / 1e12, "unit": "complex TFLOP/s", "cores": torch.get_num_threads(),
+    fl = f_sigma(nc, nj, nvs, naux)
+    hi = host_info()
+    return {"value": fl / dt / 1e12, "unit": "complex TFLOP/s", "cores": hi["torch_threads"],
             "kind": "oracle",
-            "sample": f"oracle sigma (integral blocks + product) for 1 vector of the same system "
-                      f"restricted to its first {nj} valence spinors (nc={nc}, no={nj}, nv={nv}, "
+            "sample": f"oracle sigma (integral blocks + product) for 1 vector of the same system restricted "
+                      f"to its first {nj} valence and first {nvs} virtual spinors (nc={nc}, no={nj}, nv={nvs}, "
                       f"naux={naux}); {dt:.2f} s for {fl:.3e} algorithmic flops",
-            "seconds": dt}
+            "seconds": dt, "host": hi}
 
 
 def load_traffic(prec):
@@ -439,81 +476,19 @@ def run_fd(args, A, np, torch):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--nroots", type=int, default=0)
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--tol-mixed", type=float, default=1e-3)
-    ap.add_argument("--tol-c64", type=float, default=1e-5)
-    ap.add_argument("--max-iter", type=int, default=400)
-    ap.add_argument("--max-subspace", type=int, default=0, help="search-space limit (0: the solver's default)")
-    ap.add_argument("--nguess", type=int, default=0, help="guess vectors (0: the solver's default)")
-    ap.add_argument("--solver", choices=["folded", "full"], default="folded")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 leg of the precision form")
-    ap.add_argument("--no-refined", action="store_true",
-                    help="skip the FP64 solve started from split-BF16 vectors (FP64 roots through the precision form)")
-    ap.add_argument("--tol-refine", type=float, default=1e-4,
-                    help="split-BF16 tolerance before the FP64 continuation")
-    ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "fd", "peaks", "transition"], default="single",
-                    help="batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
-                         "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
-                         "one after the other; prints its own JSON line.  peaks: the device-rate "
-                         "microbenchmarks the rooflines are quoted against")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="batch workload: keep the size rule for the Y-build K-split instead of adc2_autotune")
-    ap.add_argument("--tol-batch", type=float, default=5e-5,
-                    help="complex64 residual tolerance of the batch workload (its largest system's noise floor "
-                         "is ~2e-5)")
-    ap.add_argument("--batch-systems", default="",
-                    help="comma-separated indices of the batch systems to run (default: all eight)")
-    ap.add_argument("--sigma-probe", action="store_true",
-                    help="short run for hardware counters: 3 FP64, 3 complex64 and 3 split-BF16 sigma "
-                         "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
-              "(sharding over the valence index is a design, not built)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_2604_27451_amd as A
-    from synth import CONFIGS, config_system
-
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    A.load()
-    if args.workload == "batch":
-        run_batch(args, A, np, torch)
-        return
-    if args.workload == "fd":
-        run_fd(args, A, np, torch)
-        return
-    if args.workload == "peaks":
-        run_peaks(args, A)
-        return
-    if args.workload == "transition":
-        run_transition(args, A, np, torch)
-        return
-    cfg = CONFIGS[args.config]
+def run_pipeline(args, A, np, torch, config=None, peaks=True, with_cpu=True):
+    """The whole hot path of one configuration as one step: setup, FP64
+    folded solve, adjoint, two-stage FP64 solve through split-BF16, split-BF16
+    and complex64 solves with FP64 polish.  Returns the JSON record."""
+    from synth import CONFIGS, config_inputs_device
+    config = config or args.config
+    cfg = CONFIGS[config]
     nroots = args.nroots or cfg["nroots"]
     solver = A.ADC2_SOLVER_FOLDED if args.solver == "folded" else A.ADC2_SOLVER_FULL
     t = time.time()
-    sysm = config_system(args.config)
-    print(f"[bench] generated {args.config} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
-    nc, no, nv, naux = sysm.nc, sysm.no, sysm.nv, sysm.naux
-    L = torch.from_numpy(sysm.L).cuda()
-    eps = torch.from_numpy(sysm.eps).cuda()
-    torch.cuda.synchronize()
+    L, eps = config_inputs_device(config)
+    print(f"[bench] generated {config} on the device in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    nc, no, nv, naux = cfg["nc"], cfg["no"], cfg["nv"], cfg["naux"]
 
     if args.sigma_probe:
         from synth import random_vectors
@@ -644,7 +619,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"CVS-ADC(2) {args.config}: nc={nc} no={no} nv={nv} naux={naux} complex128, "
+        "config": {"workload": f"CVS-ADC(2) {config}: nc={nc} no={no} nv={nv} naux={naux} complex128, "
                                f"{nroots} roots, {args.solver} solver, FP64 tol {args.tol:g}",
                    "nc": nc, "no": no, "nv": nv, "naux": naux, "nroots": nroots,
                    "dim": nc * nv + nc * no * nv * (nv - 1) // 2, "solver": args.solver},
@@ -718,6 +693,9 @@ def main():
                                        PEAK_FP32_MFMA)
         out["mixed_c64"]["tol"] = args.tol_c64
     # measured MFMA rates beside the published peaks (outside the timed steps)
+    if not peaks:
+        out["cpu_baseline"] = None
+        return out
     pk = measure_peaks(A, ["mfma_f64", "mfma_f64_rand"] +
                        (["mfma_bf16", "mfma_bf16_rand"] if "mixed" in out else []) +
                        (["mfma_f32"] if "mixed_c64" in out else []))
@@ -733,11 +711,327 @@ def main():
     if "mixed_c64" in out:
         out["mixed_c64"]["roofline"] = with_measured_peak(out["mixed_c64"]["roofline"], pk["mfma_f32"]["measured"])
     cpu = None
+    if with_cpu and not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(L, eps, nc, no, nv, naux, 8, nv)
+    out["cpu_baseline"] = cpu
+    return out
+
+
+FORMS = (("fp64", "ADC2_FP64", PEAK_FP64_MFMA, "complex128 operands, FP64 MFMA"),
+         ("c64", "ADC2_C64", PEAK_FP32_MFMA, "complex64 operands, FP32 MFMA, FP32 accumulation"),
+         ("bf16x3", "ADC2_BF16X3", PEAK_BF16X3,
+          "split-BF16 operands (hi + lo of each complex64 part), BF16 MFMA, FP32 accumulation"))
+
+
+def agg_kernel_stats(records):
+    agg = {}
+    for ks in records:
+        for k, v in ks.items():
+            if v["launches"] == 0:
+                continue
+            a = agg.setdefault(k, {"launches": 0, "ms": 0.0, "flops": 0.0})
+            for f in a:
+                a[f] += v[f]
+    return agg
+
+
+def oracle_leg_c1(A, np, torch, tol_mixed):
+    """Roots at c1 against the oracle itself: the oracle's Davidson (FP64,
+    CPU) beside the GPU's FP64 and split-BF16 folded solves."""
+    from oracle import adc2 as O
+    from synth import CONFIGS, config_system
+    c = CONFIGS["c1"]
+    s = config_system("c1")
+    k = c["nroots"]
+    t0 = time.perf_counter()
+    w_or, _, inf = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv).roots(k, tol=1e-9, max_iter=400)
+    t_or = time.perf_counter() - t0
+    h = A.adc2_setup(torch.from_numpy(s.L).cuda(), torch.from_numpy(s.eps).cuda(), s.nc, s.no, s.nv, s.naux)
+    w64, _, _ = A.adc2_davidson(h, k, tol=1e-9, solver=A.ADC2_SOLVER_FOLDED)
+    A.adc2_set_precision(h, A.ADC2_BF16X3)
+    wb, Xb, infb = A.adc2_davidson(h, k, tol=tol_mixed, solver=A.ADC2_SOLVER_FOLDED)
+    A.adc2_set_precision(h, A.ADC2_FP64)
+    wp, _ = A.adc2_rayleigh(h, Xb)
+    h.close()
+    wo = w_or.numpy()
+    return {"workload": f"c1: nc={s.nc} no={s.no} nv={s.nv} naux={s.naux}, {k} roots; oracle Davidson to 1e-9 "
+                        f"(converged {inf['converged']}, {t_or:.1f} s on the host)",
+            "fp64_abs_err_ha": [float(x) for x in np.array(w64) - wo],
+            "bf16x3_ev_err_raw": [float(x) for x in (np.array(wb) - wo) * HARTREE_EV],
+            "bf16x3_ev_err_polished": [float(x) for x in (np.array(wp) - wo) * HARTREE_EV],
+            "bf16x3_tol": tol_mixed}
+
+
+def run_headline(args, A, np, torch):
+    """The benchmark line: on the heavy-element-complex configuration (c3:
+    nc=6, no=120, nv=600, naux=3000, inputs resident in HBM) one step is one
+    sigma build of a block of 10 vectors in each of the three forms (FP64,
+    complex64, split-BF16), timed with HIP events on the launch stream; setup
+    (blocks, MP2, singles block, operand copies of both precision forms) is
+    outside the steps.  After the timed steps, once each: FP64 roots through
+    the precision form (two-stage solve) and split-BF16 roots with the FP64
+    polish, each from a fresh setup, with the per-root eV error; the roots at
+    c1 against the oracle itself; the whole path at c2; the CPU baseline."""
+    import argparse as _ap
+    from synth import CONFIGS, config_inputs_device
+    cfg = CONFIGS[args.config]
+    nc, no, nv, naux = cfg["nc"], cfg["no"], cfg["nv"], cfg["naux"]
+    nroots = args.nroots or cfg["nroots"]
+    m = nroots
+    fold = A.ADC2_SOLVER_FOLDED
+    t = time.time()
+    L, eps = config_inputs_device(args.config)
+    print(f"[bench] generated {args.config} on the device in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    dim = nc * nv + nc * no * nv * (nv - 1) // 2
+    if args.sigma_probe:
+        h = A.adc2_setup(L, eps, nc, no, nv, naux)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        X = torch.complex(torch.randn((m, dim), generator=g, device="cuda", dtype=torch.float64),
+                          torch.randn((m, dim), generator=g, device="cuda", dtype=torch.float64))
+        S = torch.empty_like(X)
+        for prec in (A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3):
+            A.adc2_set_precision(h, prec)
+            for _ in range(3):
+                A.adc2_sigma(h, X, S)
+        torch.cuda.synchronize()
+        src = torch.ones(2 ** 31 // 8, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        dst = src + 1.0          # calibration: reads 2 GiB, writes 2 GiB
+        torch.cuda.synchronize()
+        print(f"[bench] sigma probe done ({float(dst[5]):.1f})", file=sys.stderr, flush=True)
+        return
+    t0 = time.perf_counter()
+    h = A.adc2_setup(L, eps, nc, no, nv, naux)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(27451)
+    X = torch.complex(torch.randn((m, dim), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((m, dim), generator=g, device="cuda", dtype=torch.float64)) * (0.5 ** 0.5)
+    S = torch.empty_like(X)
+    for _, prec, _, _ in FORMS:          # operand copies and work spaces of every form (setup, untimed)
+        A.adc2_set_precision(h, getattr(A, prec))
+        A.adc2_sigma(h, X, S)
+    torch.cuda.synchronize()
+    print(f"[bench] setup {setup_s:.2f}s, operand copies built", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rec = {f[0]: {"ms": [], "ks": []} for f in FORMS}
+
+    def step(i, timed):
+        line = []
+        for tag, prec, _, _ in FORMS:
+            A.adc2_set_precision(h, getattr(A, prec))
+            A.adc2_profile(h, True)
+            e0.record()
+            A.adc2_sigma(h, X, S)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            ks = A.adc2_kernel_stats(h)
+            A.adc2_profile(h, False)
+            if timed:
+                rec[tag]["ms"].append(ms)
+                rec[tag]["ks"].append(ks)
+            line.append(f"{tag} {ms:.1f} ms")
+        print(f"[bench] step {i} ({'timed' if timed else 'warmup'}): " + ", ".join(line), file=sys.stderr,
+              flush=True)
+
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(i, True)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    A.adc2_set_precision(h, A.ADC2_FP64)
+    del X, S
+    h.close()
+    torch.cuda.empty_cache()
+
+    fl = f_sigma(nc, no, nv, naux) * m
+    sig = {}
+    for tag, prec, peak, what in FORMS:
+        ms = float(np.mean(rec[tag]["ms"]))
+        agg = agg_kernel_stats(rec[tag]["ks"])
+        sig[tag] = {"what": what, "ms_per_sigma": round(ms, 3), "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                    "frac_of_peak": round(fl / (ms * 1e-3) / 1e12 / peak, 4),
+                    "roofline": roofline_of(agg, peak, load_traffic(tag)),
+                    "kernels": {k: {"launches": v["launches"], "ms_per_launch": round(v["ms"] / v["launches"], 3),
+                                    "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
+                                for k, v in agg.items()}}
+    pk = measure_peaks(A, ["mfma_f64", "mfma_f64_rand", "mfma_f32", "mfma_bf16", "mfma_bf16_rand"])
+    sig["fp64"]["roofline"] = with_measured_peak(sig["fp64"]["roofline"], pk["mfma_f64"]["measured"])
+    sig["c64"]["roofline"] = with_measured_peak(sig["c64"]["roofline"], pk["mfma_f32"]["measured"])
+    sig["bf16x3"]["roofline"] = with_measured_peak(sig["bf16x3"]["roofline"], pk["mfma_bf16"]["measured"] * 8 / 24)
+    rnd = pk["mfma_bf16_rand"]["measured"] * 8.0 / 24.0
+    sig["bf16x3"]["roofline"]["peak_measured_random_operands"] = round(rnd, 2)
+    sig["bf16x3"]["roofline"]["frac_of_random_operands"] = round(sig["bf16x3"]["roofline"]["achieved"] / rnd, 4)
+
+    # ---- time to roots (outside the timed steps), each from a fresh setup ----
+    kw = dict(max_iter=args.max_iter, solver=fold, max_subspace=args.max_subspace or 32,
+              nguess=args.nguess or nroots, raise_on_noconv=False, verbose=1 if args.verbose else 0)
+    roots = {}
+    if not args.no_refined:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = A.adc2_setup(L, eps, nc, no, nv, naux)
+        wr, Xr, infr = A.adc2_davidson(h, nroots, tol=args.tol, mixed_tol=args.tol_refine, **kw)
+        torch.cuda.synchronize()
+        roots["fp64_via_bf16x3"] = {
+            "what": f"FP64 roots through the precision form: adc2_davidson with mixed_tol = {args.tol_refine:g} "
+                    f"(split-BF16 folded solve to {args.tol_refine:g}, then the FP64 folded solve to {args.tol:g} "
+                    "from its vectors), from adc2_setup to the roots on the host",
+            "time_to_roots_s": round(time.perf_counter() - t0, 3), "iterations": infr["iters"],
+            "converged": infr["converged"], "max_resnorm": max(infr["resnorm"]), "omega_ha": list(wr)}
+        print(f"[bench] FP64 roots through split-BF16: {roots['fp64_via_bf16x3']['time_to_roots_s']:.1f}s "
+              f"({infr['iters']} it, max|r| {max(infr['resnorm']):.1e})", file=sys.stderr, flush=True)
+        del Xr
+        h.close()
+    if not args.no_mixed:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = A.adc2_setup(L, eps, nc, no, nv, naux, prec=A.ADC2_BF16X3)
+        wb, Xb, infb = A.adc2_davidson(h, nroots, tol=args.tol_mixed, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        A.adc2_set_precision(h, A.ADC2_FP64)
+        wp, rn = A.adc2_rayleigh(h, Xb)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = {"what": f"split-BF16 folded solve to residual {args.tol_mixed:g} and the FP64 Rayleigh quotients of "
+                     "its vectors (adc2_rayleigh), from adc2_setup to the roots on the host",
+             "time_to_roots_s": round(t1 - t0, 3), "time_to_polished_roots_s": round(t2 - t0, 3),
+             "iterations": infb["iters"], "converged": infb["converged"], "max_resnorm": max(infb["resnorm"]),
+             "polished_resnorm_max": max(rn), "omega_ha": list(wb)}
+        if "fp64_via_bf16x3" in roots:
+            wref = np.array(roots["fp64_via_bf16x3"]["omega_ha"])
+            r["ev_err_raw"] = [float(x) for x in (np.array(wb) - wref) * HARTREE_EV]
+            r["ev_err_polished"] = [float(x) for x in (np.array(wp) - wref) * HARTREE_EV]
+            r["error_reference"] = "the FP64 roots above (GPU, residual <= tol; the oracle check is at c1)"
+        roots["bf16x3"] = r
+        print(f"[bench] split-BF16 roots: {t1 - t0:.1f}s ({infb['iters']} it), polish {t2 - t1:.1f}s",
+              file=sys.stderr, flush=True)
+        del Xb
+        h.close()
+    torch.cuda.empty_cache()
+    c1 = oracle_leg_c1(A, np, torch, args.tol_mixed)
+    print("[bench] c1 roots against the oracle: FP64 max |dw| "
+          f"{max(abs(x) for x in c1['fp64_abs_err_ha']):.1e} Ha, split-BF16 polished max "
+          f"{max(abs(x) for x in c1['bf16x3_ev_err_polished']):.1e} eV", file=sys.stderr, flush=True)
+    c2 = None
+    if not args.no_c2:
+        a2 = _ap.Namespace(**vars(args))
+        a2.steps, a2.warmup, a2.max_subspace, a2.nguess, a2.nroots = 1, 0, 0, 0, 0
+        c2 = run_pipeline(a2, A, np, torch, config="c2", peaks=False, with_cpu=False)
+    cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(sysm)
-    out["cpu_baseline"] = cpu
+        cpu = cpu_baseline(L, eps, nc, no, nv, naux, 4, 300)
+    out = {
+        "metric": METRIC,
+        "value": sig["fp64"]["tflops"],
+        "unit": "complex TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total / max(1, args.steps) * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"CVS-ADC(2) {args.config}: nc={nc} no={no} nv={nv} naux={naux}; one step = one "
+                               f"sigma build of {m} vectors in each of FP64, complex64 and split-BF16 "
+                               "(value: the FP64 one)",
+                   "nc": nc, "no": no, "nv": nv, "naux": naux, "m": m, "dim": dim},
+        "roofline": sig["fp64"]["roofline"],
+        "sigma": sig,
+        "setup_s": round(setup_s, 3),
+        "time_to_roots": roots,
+        "roots_vs_oracle_c1": c1,
+        "c2": c2,
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--nroots", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol-mixed", type=float, default=1e-3)
+    ap.add_argument("--tol-c64", type=float, default=1e-5)
+    ap.add_argument("--max-iter", type=int, default=400)
+    ap.add_argument("--max-subspace", type=int, default=0, help="search-space limit (0: the solver's default)")
+    ap.add_argument("--nguess", type=int, default=0, help="guess vectors (0: the solver's default)")
+    ap.add_argument("--solver", choices=["folded", "full"], default="folded")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 leg of the precision form")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the FP64 solve started from split-BF16 vectors (FP64 roots through the precision form)")
+    ap.add_argument("--tol-refine", type=float, default=1e-4,
+                    help="split-BF16 tolerance before the FP64 continuation")
+    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="headline: skip the whole-path leg at c2")
+    ap.add_argument("--workload", choices=["headline", "pipeline", "batch", "fd", "peaks", "transition"],
+                    default="headline",
+                    help="headline (default): sigma builds of the configuration in the three forms as the "
+                         "steps, then the time-to-roots legs; pipeline: the whole path of one configuration "
+                         "(setup, solves in every form, adjoint) as one step.  batch: the batching form (eight systems of uneven size, 16 roots each, complex64 "
+                         "contractions, FP64 subspace) solved with adc2_davidson_batch and, for comparison, "
+                         "one after the other; prints its own JSON line.  peaks: the device-rate "
+                         "microbenchmarks the rooflines are quoted against")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch workload: keep the size rule for the Y-build K-split instead of adc2_autotune")
+    ap.add_argument("--tol-batch", type=float, default=5e-5,
+                    help="complex64 residual tolerance of the batch workload (its largest system's noise floor "
+                         "is ~2e-5)")
+    ap.add_argument("--batch-systems", default="",
+                    help="comma-separated indices of the batch systems to run (default: all eight)")
+    ap.add_argument("--sigma-probe", action="store_true",
+                    help="short run for hardware counters: 3 FP64, 3 complex64 and 3 split-BF16 sigma "
+                         "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over the valence index is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2604_27451_amd as A
+    from synth import CONFIGS, config_system
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    A.load()
+    if args.workload == "batch":
+        run_batch(args, A, np, torch)
+        return
+    if args.workload == "fd":
+        run_fd(args, A, np, torch)
+        return
+    if args.workload == "peaks":
+        run_peaks(args, A)
+        return
+    if args.workload == "transition":
+        run_transition(args, A, np, torch)
+        return
+    if args.workload == "pipeline":
+        print(json.dumps(run_pipeline(args, A, np, torch, config=args.config)), flush=True)
+        return
+    run_headline(args, A, np, torch)
 
 
 if __name__ == "__main__":

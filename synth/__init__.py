@@ -80,6 +80,38 @@ def draw_cholesky(seed: int, naux: int, n: int, sigma: float,
     return out
 
 
+def draw_cholesky_device(seed: int, naux: int, n: int, sigma: float, device="cuda", threads: int = 16,
+                         chunk: int = 64):
+    """draw_cholesky straight into a device tensor [naux][n][n] (complex128):
+    the same per-P draws, made by a pool of host threads chunk by chunk and
+    copied to the device, so that no host array of the whole size is held."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    out = torch.empty((naux, n, n), dtype=torch.complex128, device=device)
+    host = torch.empty((chunk, n, n), dtype=torch.complex128).pin_memory()
+    hv = host.numpy()
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        for p0 in range(0, naux, chunk):
+            p1 = min(naux, p0 + chunk)
+
+            def one(P, p0=p0):
+                hv[P - p0] = draw_cholesky_P(seed, P, n, sigma)
+            list(ex.map(one, range(p0, p1)))
+            out[p0:p1].copy_(host[:p1 - p0])
+    torch.cuda.synchronize(device)
+    return out
+
+
+def config_inputs_device(name: str, device="cuda", threads: int = 16):
+    """(L, eps) of a configuration on the device, drawn as config_system draws
+    them (same values)."""
+    import torch
+    c = CONFIGS[name]
+    n = c["nc"] + c["no"] + c["nv"]
+    eps = torch.from_numpy(draw_eps(c["seed"], c["nc"], c["no"], c["nv"])).to(device)
+    return draw_cholesky_device(c["seed"], c["naux"], n, 0.05, device, threads), eps
+
+
 def make_system(nc: int, no: int, nv: int, naux: int, seed: int,
                 sigma: float = 0.05, core=EPS_CORE, val=EPS_VAL,
                 virt=EPS_VIRT, label: str = "") -> System:
