@@ -180,3 +180,21 @@ def test_element_mutants_are_caught():
     # the unmutated restatements agree (the mutants differ only by the slip)
     for I, a, J, b in entries[:20]:
         assert abs(_m11_element_mutant(L, e, sp, I, a, J, b, None) - complex(M[I, a, J, b])) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_m11_row_every_row(shape):
+    """m11_row (the row evaluator the full-size GPU tests compare whole rows
+    of M11 with) equals m11() on every row; without term (i) it differs only
+    on the J == I block, and there by term (i) itself (nonzero)."""
+    L, e, sp = _system(*shape)
+    M = O.m11(L, e, sp).reshape(sp.nc, sp.nv, sp.nc, sp.nv)
+    ti = O.m11_terms(L, e, sp)["m2i"]
+    scale = float(M.abs().max())
+    for I, a in itertools.product(range(sp.nc), range(sp.nv)):
+        r = O.m11_row(L, e, sp, I, a)
+        assert float((r - M[I, a]).abs().max()) < 1e-13 * scale
+        r0 = O.m11_row(L, e, sp, I, a, with_term_i=False)
+        d = r0 - M[I, a]
+        assert float((d + ti[I, a]).abs().max()) < 1e-13 * scale
+    assert float(ti.abs().max()) > 1e3 * 1e-13 * scale     # far above the comparison tolerance
