@@ -72,11 +72,21 @@ def draw_cholesky_P(seed: int, P: int, n: int, sigma: float) -> np.ndarray:
 
 
 def draw_cholesky(seed: int, naux: int, n: int, sigma: float,
-                  out: np.ndarray | None = None) -> np.ndarray:
+                  out: np.ndarray | None = None, threads: int = 16) -> np.ndarray:
+    """All slices L[P]; large draws are spread over a pool of host threads
+    (each slice has its own generator, so the values do not depend on it)."""
     if out is None:
         out = np.empty((naux, n, n), dtype=np.complex128)
-    for P in range(naux):
+
+    def one(P):
         out[P] = draw_cholesky_P(seed, P, n, sigma)
+    if threads > 1 and naux * n * n > (1 << 22):
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(naux)))
+    else:
+        for P in range(naux):
+            one(P)
     return out
 
 

@@ -121,3 +121,45 @@ def test_davidson_batch_reports_failing_system():
     assert len(w1) == 3
     for h in hs:
         h.close()
+
+
+def test_sigma_batch_full_size_c4():
+    """The batch workload at full size (eight systems, (no, nv) from (20,100)
+    to (80,400), naux = 4 nv), complex64 contractions as in the batching
+    form and FP64: the grouped sigma equals separate sigma builds bit for bit;
+    the largest system's (no=80, nv=400) entries against the oracle's
+    single-element evaluators (FP64 to 1e-10, complex64 to 3e-5)."""
+    systems = batch_systems(1.0)
+    hs = setup(systems, A.ADC2_C64)
+    xs = [dev(random_vectors(1200 + q, 4, h.dim)) for q, h in enumerate(hs)]
+    s = systems[1]
+    nc, no, nv = s.nc, s.no, s.nv
+    sp = O.Spaces(nc, no, nv)
+    Lt, et = torch.from_numpy(s.L), torch.from_numpy(s.eps)
+    xc = xs[1].cpu()
+    npair = nv * (nv - 1) // 2
+    pts = [(0, 0, 0, 1), (nc - 1, no - 1, nv - 2, nv - 1), (2, 40, 17, 333), (5, 7, 0, nv - 1)]
+    off = [nc * nv + (I * no + j) * npair + a * nv - a * (a + 1) // 2 + (b - a - 1) for I, j, a, b in pts]
+    dref = np.array([O.sigma2_element(Lt, et, sp, xc[v], *p) for v in (0, 3) for p in pts])
+    cpts = [(0, 0), (nc - 1, nv - 1)]
+    cref = np.array([O.sigma1_coupling_element(Lt, sp, xc[3], K, c) for K, c in cpts])
+    print("  oracle samples ready", flush=True)
+    for prec, tol in ((A.ADC2_C64, 3e-5), (A.ADC2_FP64, 1e-10)):
+        for h in hs:
+            A.adc2_set_precision(h, prec)
+        sb = A.adc2_sigma_batch(hs, xs)
+        for q, (h, x) in enumerate(zip(hs, xs)):
+            s1 = A.adc2_sigma(h, x)
+            torch.cuda.synchronize()
+            assert torch.equal(sb[q], s1), (prec, q)
+        S = sb[1].cpu()
+        got = np.array([complex(S[v, o_]) for v in (0, 3) for o_ in off])
+        ed = np.abs(got - dref).max() / np.abs(dref).max()
+        M11 = A.adc2_get_m11(hs[1]).cpu()
+        c1 = S[3, :nc * nv] - xc[3, :nc * nv] @ M11.T
+        gc = np.array([complex(c1[K * nv + c]) for K, c in cpts])
+        ec = np.abs(gc - cref).max() / np.abs(cref).max()
+        print(f"  prec {prec}: batched equal to separate; system 1 doubles {ed:.2e} coupling {ec:.2e}", flush=True)
+        assert ed < tol and ec < tol
+    for h in hs:
+        h.close()

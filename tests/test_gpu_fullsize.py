@@ -2,11 +2,14 @@
 one by one (oracle/adc2.py: m11_element, sigma2_element,
 sigma1_coupling_element).
 
-c2 (nc=6, no=60, nv=300, naux=1500) with m = 10 vectors, the block size of
-the benchmark's sigma builds, in every precision form; c3 (nc=6, no=120,
-nv=600, naux=3000) in FP64 with m = 2.  Sampled entries include the first
-and last pair (a, b) and the last core/valence indices, so that the ragged
-tails of every GEMM tile dimension are hit.
+c2 (nc=6, no=60, nv=300, naux=1500) and c3 (nc=6, no=120, nv=600,
+naux=3000) with m = 10 vectors, the block size of the benchmark's sigma
+builds, in every precision form.  Sampled entries include the first and last
+pair (a, b) and the last core/valence indices, so that the ragged tails of
+every GEMM tile dimension are hit.  Whole rows of M11 are compared with the
+oracle's row evaluator (m11_row): at c2 complete rows, at c3 the columns
+J != I of a row (the delta_IJ term would need every <kl||bc>, 5.7e9
+integrals, on the host).
 
 Singles entries of sigma are split into the singles block and the
 doubles-to-singles coupling: M11 is checked entry by entry against
@@ -47,7 +50,7 @@ def doubles_offset(nc, no, nv, I, j, a, b):
     return nc * nv + (I * no + j) * (nv * (nv - 1) // 2) + q
 
 
-def run_case(name, precs, m, n_d, n_s, n_m11, s_vecs=None):
+def run_case(name, precs, m, n_d, n_s, n_m11, s_vecs=None, rows=(), rows_offdiag=()):
     s = config_system(name)
     nc, no, nv = s.nc, s.no, s.nv
     sp = O.Spaces(nc, no, nv)
@@ -68,6 +71,18 @@ def run_case(name, precs, m, n_d, n_s, n_m11, s_vecs=None):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print(f"  M11 sampled rel err {err:.2e}", flush=True)
     assert err < 1e-10
+    Mr = M11.reshape(nc, nv, nc, nv)
+    for I, a in rows:
+        ref_r = O.m11_row(Lt, et, sp, I, a)
+        err = float((Mr[I, a] - ref_r).abs().max() / ref_r.abs().max())
+        print(f"  M11 row ({I},{a}) rel err {err:.2e}", flush=True)
+        assert err < 1e-10
+    for I, a in rows_offdiag:
+        ref_r = O.m11_row(Lt, et, sp, I, a, with_term_i=False)
+        keep = [J for J in range(nc) if J != I]
+        err = float((Mr[I, a, keep] - ref_r[keep]).abs().max() / ref_r[keep].abs().max())
+        print(f"  M11 row ({I},{a}), columns J != I, rel err {err:.2e}", flush=True)
+        assert err < 1e-10
     d_pts = doubles_samples(nc, no, nv, rng, n_d)
     s_pts = ([(0, 0), (nc - 1, nv - 1)] + [(int(rng.integers(nc)), int(rng.integers(nv))) for _ in range(n_s)])[:n_s]
     vecs = [0, m - 1]
@@ -94,10 +109,12 @@ def run_case(name, precs, m, n_d, n_s, n_m11, s_vecs=None):
 
 
 def test_c2_sampled_sigma_all_precisions():
-    run_case("c2", [A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3], 10, 12, 4, 5)
+    run_case("c2", [A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3], 10, 12, 4, 5, rows=[(5, 299)],
+             rows_offdiag=[(0, 0), (3, 150)])
 
 
-def test_c3_sampled_sigma_fp64():
+def test_c3_sampled_sigma_all_precisions():
     # the c3 evaluators are costly on the host (one coupling entry contracts
-    # nv^2 no naux = 1.3e11 terms): fewer samples, same kinds
-    run_case("c3", [A.ADC2_FP64], 2, 8, 2, 3)
+    # nv^2 no naux = 1.3e11 terms): fewer coupling samples, same kinds
+    run_case("c3", [A.ADC2_FP64, A.ADC2_C64, A.ADC2_BF16X3], 10, 16, 2, 3, s_vecs=[9],
+             rows_offdiag=[(5, 599)])

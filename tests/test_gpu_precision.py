@@ -113,3 +113,31 @@ def test_b3_roots_c1():
     assert info64["converged"]
     assert d_raw.max() < 1e-4          # eV; measured 6e-6 (eigenvalue error ~ residual^2)
     assert d_pol.max() < 1e-4
+
+
+@pytest.fixture(scope="module")
+def c1_oracle_roots():
+    s = config_system("c1")
+    o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    w, _, inf = o.roots(4, tol=1e-9, max_iter=300)
+    assert inf["converged"]
+    return s, w.numpy()
+
+
+@pytest.mark.parametrize("prec,tol", [(A.ADC2_C64, 1e-5), (A.ADC2_BF16X3, 1e-3)])
+def test_precision_roots_c1_vs_oracle(c1_oracle_roots, prec, tol):
+    """The precision form's roots against the FP64 oracle's own roots (not
+    the GPU's FP64 ones): within 1e-3 eV per root raw, and the FP64
+    Rayleigh quotients of its vectors within 1e-3 eV as well."""
+    s, w_or = c1_oracle_roots
+    print(f"[case] precision form {prec} c1 roots vs the oracle", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux, prec=prec)
+    w, X, inf = A.adc2_davidson(h, 4, tol=tol, solver=A.ADC2_SOLVER_FOLDED)
+    A.adc2_set_precision(h, A.ADC2_FP64)
+    wp, rn = A.adc2_rayleigh(h, X)
+    d_raw = (np.array(w) - w_or) * EV
+    d_pol = (np.array(wp) - w_or) * EV
+    print(f"  eV error raw {np.abs(d_raw).max():.2e}, polished {np.abs(d_pol).max():.2e}", flush=True)
+    assert inf["converged"]
+    assert np.abs(d_raw).max() < 1e-3 and np.abs(d_pol).max() < 1e-3
+    h.close()

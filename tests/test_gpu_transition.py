@@ -208,3 +208,32 @@ def test_transition_spin_selection_rule_larger():
     for g in dark:
         assert f[g].max() < 1e-18 * max(1.0, f.max())     # measured <= 3e-21
     assert max(f[g[0]] for g in bright) > 1e-6
+
+
+@pytest.mark.parametrize("shape,seed", [((1, 2, 5, 9), 61), ((2, 3, 6, 12), 62)])
+def test_transition_F_element_by_element(shape, seed):
+    """F itself, entry by entry: with unit vectors e_i as X (groups of at most
+    32, the entry point's limit) T_i = e_i^H F = F_i for each Cartesian
+    component; compared with the oracle's F through first and second order
+    (singles and doubles, every entry)."""
+    s = make_system(*shape, seed=seed)
+    sp = O.Spaces(s.nc, s.no, s.nv)
+    dip = dipole_integrals(seed, sp.n)
+    print(f"[case] transition F element by element {shape} dim={sp.dim}", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    L, e = O.as_c128(s.L), O.as_f64(s.eps)
+    dd = dev(dip)
+    for order, tol in ((1, 1e-12), (2, 1e-11)):
+        Fo = O.transition_moments(L, e, sp, dip, order=order).numpy()   # [3][dim]
+        Fg = np.zeros((3, sp.dim), dtype=np.complex128)
+        for i0 in range(0, sp.dim, 32):
+            k = min(32, sp.dim - i0)
+            E = torch.zeros((k, sp.dim), dtype=torch.complex128)
+            E[torch.arange(k), i0 + torch.arange(k)] = 1.0
+            T, _ = A.adc2_transition(h, dd, E.cuda(), [1.0] * k, order=order)
+            Fg[:, i0:i0 + k] = T.T
+        err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+        print(f"  order {order}: F max rel err {err:.2e} over {3 * sp.dim} entries", flush=True)
+        assert err < tol
+        assert np.abs(Fo[:, sp.n_singles:]).max() > 1e-3 * np.abs(Fo).max()   # the doubles of F are compared too
+    h.close()
