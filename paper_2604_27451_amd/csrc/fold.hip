@@ -48,106 +48,164 @@ namespace {
 constexpr int FMM = 128;    // Chebyshev moments stored (computed on demand, 8 at a time)
 constexpr int FGB = 16;     // Gram tile edge
 constexpr int FCH = 32;     // doubles per LDS chunk
-constexpr int FMB = 8;      // moments per workgroup
-constexpr int FTI = 32;     // largest row tile of the moment kernel
+constexpr int FMB = 8;      // moments are held in blocks of 8
 constexpr int FSMAX = 64;   // largest search space
 constexpr int FCLAMP = 25;  // iterations a projected root may stay at the expansion limit
 constexpr int FSTALL = 40;  // iterations without a 20% drop of the largest residual before giving up
 
 __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / b); }
 
-// Chebyshev moments of the new columns.  A workgroup owns ti rows (i) x qc
-// columns (j, qc <= 16, ti = min(32, 256 / qc)) and NB consecutive blocks of
-// FMB moments, so that each chunk of U is read once per row tile:
-//   part[((tile * nmb + mb) * nchb + chb)][mm][t] =
-//     sum over this block's chunks of conj(U_i[d]) T_{FMB mb + mm}(Dt_d) U_j[d],
-// t = (i - i0) * qc + (j - jc0), i < s, j < jc0 + qc, mb = NB * blockIdx.z + (0..NB-1).
-template <int NB>
-__global__ __launch_bounds__(256) void k_cheb_part(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
-                                                    int qc, int ti, const double* __restrict__ D, double c,
-                                                    double ih, int inv, double w0, int nchb, int nmb,
+// Chebyshev moments on the FP64 matrix cores.  The weights T_m(t_d) are
+// real, so with P_ij(d) = conj(U_i[d]) U_j[d]
+//   Re K_m[i][j] = sum_d Re P_ij(d) T_m(t_d),  Im K_m[i][j] = sum_d Im P_ij(d) T_m(t_d)
+// is a real GEMM: rows (pair, re|im), columns m, contraction over the doubles
+// d.  The pairs p = i qc + jq (i < s, jq < qc) are enumerated densely, 16 per
+// matrix-instruction row block; a wave owns RB row blocks, a workgroup 64 RB
+// pairs x 16 NCB moments and one slice of the doubles (split-K).  A fragments
+// are the products P formed in registers from the staged U rows (lane l:
+// pair 16 rb + l % 16, d = 4 kstep + l / 16), so P never touches LDS or HBM;
+// B fragments are T_m(t_d) of the staged chunk (cos(m arccos t_d) for the
+// first two m of the slice, the three-term recurrence after).  The next
+// chunk's U values are loaded into registers while the current chunk's
+// matrix instructions run.  Per 4 doubles a wave issues 2 RB NCB
+// v_mfma_f64_16x16x4_f64.
+//   part[((tile * nz + z) * nchb + chb)][pl * NM + mm] (complex),
+//   pl < 64 RB the pair within the tile, mm < NM = 16 NCB, moment m = z NM + mm.
+constexpr int MKC = 32;   // doubles per staged chunk
+constexpr int MPF = (FSMAX + FGB) * MKC / 256;   // staged complex values per thread and chunk (upper bound)
+template <int NCB, int RB>
+__global__ __launch_bounds__(256) void k_cheb_mfma(const double2* __restrict__ U, long ldu, long nd, int s, int jc0,
+                                                    int qc, const double* __restrict__ D, double c, double ih,
+                                                    int inv, double w0, int nchb, int nz,
                                                     double2* __restrict__ part) {
-  constexpr int NM = NB * FMB;
-  __shared__ double2 ui[FTI][FCH + 1];
-  __shared__ double2 uj[FGB][FCH + 1];
-  __shared__ double tm[NM][FCH];
-  const int tile = blockIdx.y;
-  const int mb0 = blockIdx.z * NB;
-  const int i0 = tile * ti;
-  const int tid = threadIdx.x;
-  const int ii = tid / qc, jj = tid - ii * qc;
-  const bool act = ii < ti;
-  double2 acc[NM];
+  constexpr int NM = 16 * NCB;
+  constexpr int TP = 64 * RB;   // pairs per workgroup
+  __shared__ double2 ui[FSMAX][MKC + 1];
+  __shared__ double2 uj[FGB][MKC + 1];
+  __shared__ double tb[MKC][NM + 1];
+  const int tile = blockIdx.y, z = blockIdx.z;
+  const int m0 = z * NM;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int jl = lane & 15, kq = lane >> 4;
+  const int npair = s * qc;
+  const int p0 = tile * TP;
+  const int ilo = p0 / qc, ihi = min(s - 1, (min(npair, p0 + TP) - 1) / qc);
+  const int nrow = ihi - ilo + 1;
+  const int nstage = (nrow + qc) * MKC;
+  // this lane's pair in each of its row blocks (a pair beyond the last reads zeros)
+  int pi_[RB], pj_[RB];
 #pragma unroll
-  for (int k = 0; k < NM; ++k) acc[k] = make_double2(0.0, 0.0);
-  const long nch = (nd + FCH - 1) / FCH;
-  const int nrow = ti + qc;
-  for (long ch = blockIdx.x; ch < nch; ch += nchb) {
-    const long e0 = ch * FCH;
+  for (int rb = 0; rb < RB; ++rb) {
+    const int p = p0 + (w * RB + rb) * 16 + jl;
+    pi_[rb] = p < npair ? p / qc - ilo : -1;
+    pj_[rb] = p < npair ? p % qc : 0;
+  }
+  d4 acc[RB][2][NCB];
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int b = 0; b < NCB; ++b) acc[a][q][b] = d4{0.0, 0.0, 0.0, 0.0};
+  const long nch = (nd + MKC - 1) / MKC;
+  // the next chunk's U values and doubles energy, loaded into registers ahead of use
+  double2 pf[MPF];
+  double dnext = 0.0;
+  auto load = [&](long ch) {
+    const long e0 = ch * MKC;
+#pragma unroll
+    for (int k = 0; k < MPF; ++k) {
+      const int t = tid + 256 * k;
+      double2 v = make_double2(0.0, 0.0);
+      if (t < nstage) {
+        const int row = t / MKC, e = t - row * MKC;
+        const long ge = e0 + e;
+        if (ge < nd) v = row < nrow ? U[(long)(ilo + row) * ldu + ge] : U[(long)(jc0 + row - nrow) * ldu + ge];
+      }
+      pf[k] = v;
+    }
+    if (tid < MKC) dnext = e0 + tid < nd ? D[e0 + tid] : 0.0;
+  };
+  long ch = blockIdx.x;
+  if (ch < nch) load(ch);
+  for (; ch < nch; ch += nchb) {
+    const long e0 = ch * MKC;
     __syncthreads();
-    for (int idx = tid; idx < nrow * FCH; idx += 256) {
-      const int row = idx / FCH, e = idx - row * FCH;
-      const long ge = e0 + e;
-      if (row < ti) {
-        const int i = i0 + row;
-        ui[row][e] = (i < s && ge < nd) ? U[(long)i * ldu + ge] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < MPF; ++k) {
+      const int t = tid + 256 * k;
+      if (t < nstage) {
+        const int row = t / MKC, e = t - row * MKC;
+        if (row < nrow) ui[row][e] = pf[k];
+        else uj[row - nrow][e] = pf[k];
+      }
+    }
+    if (tid < MKC) {   // T_m(t_d), m0 <= m < m0 + NM: two cosines, then the three-term recurrence
+      double tv[NM];
+      if (e0 + tid < nd) {
+        const double x = fmin(1.0, fmax(-1.0, ((inv ? 1.0 / (dnext - w0) : dnext) - c) * ih));
+        const double th = acos(x);
+        tv[0] = cos((double)m0 * th);
+        tv[1] = cos((double)(m0 + 1) * th);
+#pragma unroll
+        for (int q = 2; q < NM; ++q) tv[q] = 2.0 * x * tv[q - 1] - tv[q - 2];
       } else {
-        const int j = jc0 + row - ti;
-        uj[row - ti][e] = (ge < nd) ? U[(long)j * ldu + ge] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < NM; ++q) tv[q] = 0.0;
       }
-    }
-    if (tid < FCH) {   // T_m of this chunk's doubles energies
-      const long ge = e0 + tid;
-      const double t = ge < nd ? ((inv ? 1.0 / (D[ge] - w0) : D[ge]) - c) * ih : 0.0;
-      double t0 = 1.0, t1 = t;
-      const int m0 = mb0 * FMB;
-      for (int m = 0; m < m0 + NM; ++m) {
-        double tv;
-        if (m == 0) tv = 1.0;
-        else if (m == 1) tv = t;
-        else {
-          tv = 2.0 * t * t1 - t0;
-          t0 = t1;
-          t1 = tv;
-        }
-        if (m >= m0) tm[m - m0][tid] = ge < nd ? tv : 0.0;
-      }
+#pragma unroll
+      for (int q = 0; q < NM; ++q) tb[tid][q] = tv[q];
     }
     __syncthreads();
-    if (act) {
-      for (int e = 0; e < FCH; ++e) {
-        const double2 p = cdotc(ui[ii][e], uj[jj][e]);
+    if (ch + nchb < nch) load(ch + nchb);
 #pragma unroll
-        for (int k = 0; k < NM; ++k) {
-          const double tv = tm[k][e];
-          acc[k].x += tv * p.x;
-          acc[k].y += tv * p.y;
+    for (int ks = 0; ks < MKC / 4; ++ks) {
+      const int dl = ks * 4 + kq;
+      double bf[NCB];
+#pragma unroll
+      for (int b = 0; b < NCB; ++b) bf[b] = tb[dl][b * 16 + jl];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        double pr = 0.0, pim = 0.0;
+        if (pi_[rb] >= 0) {
+          const double2 u = ui[pi_[rb]][dl];
+          const double2 v = uj[pj_[rb]][dl];
+          pr = u.x * v.x + u.y * v.y;   // conj(u) v
+          pim = u.x * v.y - u.y * v.x;
+        }
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+          acc[rb][0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, bf[b], acc[rb][0][b], 0, 0, 0);
+          acc[rb][1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pim, bf[b], acc[rb][1][b], 0, 0, 0);
         }
       }
     }
   }
+  // accumulator (row = pair kq + 4 r of the block, column mm = 16 b + jl) -> this workgroup's partial
+  double2* out = part + ((long)(tile * nz + z) * nchb + blockIdx.x) * (TP * NM);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int mb = mb0 + b;
-    if (mb >= nmb) break;
-    double2* out = part + (((long)tile * nmb + mb) * nchb + blockIdx.x) * (FMB * 256);
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int k = 0; k < FMB; ++k) out[k * 256 + tid] = acc[b * FMB + k];
-  }
+    for (int b = 0; b < NCB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pl = (w * RB + rb) * 16 + kq + 4 * r, mm = b * 16 + jl;
+        out[(long)pl * NM + mm] = make_double2(acc[rb][0][b][r], acc[rb][1][b][r]);
+      }
 }
 
-// K[m][i][jq] = sum_chb part   for m < MM, i < s, jq < qc
-__global__ void k_cheb_reduce(const double2* __restrict__ part, int s, int qc, int ti, int nmb, int nchb, int MM,
-                              double2* __restrict__ K) {
+// K[m][i][jq] = sum_chb part of k_cheb_mfma   for m < MM, i < s, jq < qc
+__global__ void k_cheb_mfma_reduce(const double2* __restrict__ part, int s, int qc, int TP, int NM, int nz, int nchb,
+                                   int MM, double2* __restrict__ K) {
   const long total = (long)MM * s * qc;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int m = (int)(e / ((long)s * qc));
-    const int i = (int)((e / qc) % s), jq = (int)(e % qc);
-    const int tile = i / ti;
-    const int t = (i - tile * ti) * qc + jq;
-    const int mb = m / FMB, k = m % FMB;
+    const int p = (int)(e % ((long)s * qc));          // i * qc + jq
+    const int tile = p / TP, pl = p % TP;
+    const int z = m / NM, mm = m % NM;
+    const double2* src = part + (long)(tile * nz + z) * nchb * ((long)TP * NM) + (long)pl * NM + mm;
     double2 a = make_double2(0.0, 0.0);
-    for (int b = 0; b < nchb; ++b) a = cadd(a, part[(((long)tile * nmb + mb) * nchb + b) * (FMB * 256) + k * 256 + t]);
+    for (int b = 0; b < nchb; ++b) a = cadd(a, src[(long)b * TP * NM]);
     K[e] = a;
   }
 }
@@ -473,11 +531,9 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   double2 *Sb, *Tin, *X2, *Sx, *Kd, *part, *Yd, *Cd;
   double *omd, *mm;
   int nchb = (int)std::max<long>(1, std::min<long>(512, nd / 4096));
-  int cheb_nb = 2;          // 8-moment blocks per workgroup of the moment kernel (measured best at c2)
-  if (const char* v = getenv("ADC2_CHEB_NB")) cheb_nb = std::max(1, std::min(4, atoi(v)));
   if (const char* v = getenv("ADC2_CHEB_NCHB")) nchb = (int)std::max<long>(1, std::min<long>(1024, atol(v)));
   const int nmb = FMM / FMB;
-  const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;   // row tiles have >= 16 rows
+  const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;   // split-K partials of the moments
   FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
   FD_TRY(dalloc((void**)&Tin, sizeof(double2) * qmax * dim));
   FD_TRY(dalloc((void**)&X2, sizeof(double2) * k * dim));
@@ -629,22 +685,30 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     const auto tc0 = std::chrono::steady_clock::now();
     for (int c0 = j0; c0 < j0 + q; c0 += FGB) {
       const int qc = std::min(FGB, j0 + q - c0);
-      const int ti = std::min(FTI, 256 / qc);
-      const int ntile = (srows + ti - 1) / ti;
-      // up to four 8-moment blocks per workgroup (one read of U), more in further z-slices
-      const int nbw = std::min(cheb_nb, mblocks);
-      dim3 g(nchb, ntile, (mblocks + nbw - 1) / nbw);
-      switch (nbw) {
-        case 1: k_cheb_part<1><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
-        case 2: k_cheb_part<2><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
-        case 3: k_cheb_part<3><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
-        default: k_cheb_part<4><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, ti, Ddev, rmap.c, rmap.ih, rmap.inv, rmap.w0, nchb, mblocks, part); break;
-      }
-      ADC2_CHECK_LAUNCH();
       const int mm_ = mblocks * FMB;
       const long tot = (long)mm_ * srows * qc;
-      k_cheb_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, ti,
-                                                                                      mblocks, nchb, mm_, Kd);
+      // 16 or 32 moments per pass (z-slices for more); 128 or 256 pairs per workgroup
+      const int ncb = mm_ > 16 ? 2 : 1;
+      const int nm = 16 * ncb;
+      const int nz = (mm_ + nm - 1) / nm;
+      const int npair = srows * qc;
+      const int rb = npair > 128 ? 4 : 2;
+      const int tp = 64 * rb;
+      const int ntile = (npair + tp - 1) / tp;
+      int nch_m = (int)std::max<long>(1, std::min<long>(nchb, (nd + MKC - 1) / MKC));
+      while (nch_m > 1 && (long)ntile * nz * nch_m * tp * nm > part_len) nch_m /= 2;
+      dim3 g(nch_m, ntile, nz);
+#define CHEB_MFMA(NCB_, RB_)                                                                              \
+  k_cheb_mfma<NCB_, RB_><<<g, 256, 0, st>>>(Uro, dim, nd, srows, c0, qc, Ddev, rmap.c, rmap.ih, rmap.inv, \
+                                           rmap.w0, nch_m, nz, part)
+      if (ncb == 1 && rb == 4) CHEB_MFMA(1, 4);
+      else if (ncb == 1) CHEB_MFMA(1, 2);
+      else if (rb == 4) CHEB_MFMA(2, 4);
+      else CHEB_MFMA(2, 2);
+#undef CHEB_MFMA
+      ADC2_CHECK_LAUNCH();
+      k_cheb_mfma_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, tp,
+                                                                                            nm, nz, nch_m, mm_, Kd);
       ADC2_CHECK_LAUNCH();
       ADC2_HIP(hipMemcpyAsync(Kh, Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
       ADC2_HIP(hipStreamSynchronize(st));
