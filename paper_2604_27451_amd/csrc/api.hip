@@ -112,6 +112,48 @@ __global__ void k_gather_theta(const double* __restrict__ th, const int* __restr
   if (threadIdx.x < n) out[threadIdx.x] = th[idx[threadIdx.x]];
 }
 
+// Preconditioner of the full-space solver from the Schur complement of the
+// doubles block: the correction equation (theta - M) t = r with M22 ~ diag(D)
+// gives t2 = (theta - D)^-1 (r2 + M21 t1), and t1 from the singles block of
+// the folded operator, approximated by its diagonal
+//   t1_e = r1_e / (theta - d11_e - nu_e / (theta - Dbar_e))
+// (nu_e = |column e of M21|^2, Dbar_e its weighted mean doubles energy).
+// Step 1: t1 into T's singles, zero doubles (the sigma of (t1, 0) gives M21 t1).
+__global__ void k_schur_singles(double2* __restrict__ T, const double* __restrict__ theta, int k, long dim, long ns,
+                                const double* __restrict__ diag, const double* __restrict__ nu,
+                                const double* __restrict__ dbar) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < dim * k; e += (long)gridDim.x * blockDim.x) {
+    const int q = (int)(e / dim);
+    const long x = e % dim;
+    if (x >= ns) {
+      T[e] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double th = theta[q];
+    double den = th - diag[x];
+    const double gap = th - dbar[x];
+    if (nu[x] > 0.0 && fabs(gap) > 1e-12) den -= nu[x] / gap;
+    if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+    T[e] = make_double2(T[e].x / den, T[e].y / den);
+  }
+}
+
+// Step 2: t2 = (theta - D)^-1 (r2 + W2), r the residual of root idx[q], W = sigma of (t1, 0).
+__global__ void k_schur_doubles(double2* __restrict__ T, const double2* __restrict__ W,
+                                const double2* __restrict__ R, const int* __restrict__ idx,
+                                const double* __restrict__ theta, int k, long dim, long ns,
+                                const double* __restrict__ diag) {
+  const long nd = dim - ns;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nd * k; e += (long)gridDim.x * blockDim.x) {
+    const int q = (int)(e / nd);
+    const long x = ns + e % nd;
+    double den = theta[q] - diag[x];
+    if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+    const double2 r = R[(long)idx[q] * dim + x], wv = W[(long)q * dim + x];
+    T[(long)q * dim + x] = make_double2((r.x + wv.x) / den, (r.y + wv.y) / den);
+  }
+}
+
 }  // namespace adc2
 
 using namespace adc2;
@@ -384,11 +426,11 @@ struct DavWork {
   double2 *V = nullptr, *S = nullptr, *Xb = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr;
   double2 *Vn = nullptr, *Sn = nullptr, *Ref = nullptr, *P = nullptr;
   double2 *G = nullptr, *Z = nullptr, *Gt = nullptr, *Ut = nullptr, *Cc = nullptr, *scratch = nullptr;
-  double *theta = nullptr, *lam = nullptr, *npart = nullptr, *thact = nullptr;
+  double *theta = nullptr, *lam = nullptr, *npart = nullptr, *thact = nullptr, *pnu = nullptr, *pdb = nullptr;
   int *idx = nullptr, *count = nullptr;
   ~DavWork() {
     dfree(h, V); dfree(h, S); dfree(h, Xb); dfree(h, R); dfree(h, T); dfree(h, T2); dfree(h, Vn); dfree(h, Sn);
-    dfree(h, Ref); dfree(h, P);
+    dfree(h, Ref); dfree(h, P); dfree(h, pnu); dfree(h, pdb);
     dfree(h, G); dfree(h, Z); dfree(h, Gt); dfree(h, Ut); dfree(h, Cc); dfree(h, scratch);
     dfree(h, theta); dfree(h, lam); dfree(h, npart); dfree(h, thact); dfree(h, idx); dfree(h, count);
   }
@@ -500,6 +542,14 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     return fail(ADC2_ERR_ARG, "adc2_davidson: root following needs at least nroots guess vectors");
   const int keep_max = std::min(std::min(2 * k, 32), max_sub - k);
   const int nblk = dav_nblk(dim);
+  // preconditioner: the Schur form above (default), or the plain diagonal
+  bool schur = true;
+  if (const char* v = getenv("ADC2_FULL_PRECOND")) schur = strcmp(v, "diag") != 0;
+  hipStream_t st0 = (hipStream_t)stream;
+  if (schur) {
+    adc2_status r0 = build_fold_precond(h, st0);
+    if (r0 != ADC2_OK) return r0;
+  }
 
   DavWork w;
   w.h = h;
@@ -524,6 +574,13 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
   DAV_TRY(dmalloc(h, &w.thact, sizeof(double) * 32));
   DAV_TRY(dmalloc(h, &w.idx, sizeof(int) * LDG));
   DAV_TRY(dmalloc(h, &w.count, sizeof(int)));
+  if (schur) {
+    DAV_TRY(dmalloc(h, &w.pnu, sizeof(double) * d.ns));
+    DAV_TRY(dmalloc(h, &w.pdb, sizeof(double) * d.ns));
+    DAV_TRY(hipMemcpyAsync(w.pnu, h->pre_nu.data(), sizeof(double) * d.ns, hipMemcpyHostToDevice, st));
+    DAV_TRY(hipMemcpyAsync(w.pdb, h->pre_dbar.data(), sizeof(double) * d.ns, hipMemcpyHostToDevice, st));
+    DAV_TRY(hipStreamSynchronize(st));
+  }
   if (follow) {
     // reference vectors of the followed roots: the first nroots guess vectors as given
     DAV_TRY(dmalloc(h, &w.Ref, sizeof(double2) * k * dim));
@@ -533,6 +590,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
 
   double ms_sigma = 0.0;
   int n_sigma = 0;
+  long n_half = 0;   // half sigma products (one of the two heavy GEMMs) of the preconditioner
   auto run_sigma = [&](const double2* x, double2* s_out, int m) -> adc2_status {
     DAV_TRY(hipEventRecord(h->ev0, st));
     adc2_status r = sigma_call(h, m, x, s_out, SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN, st);
@@ -662,7 +720,25 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     DAV_TRY(hipMemcpyAsync(w.idx, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
     DAV_TRY(hipStreamSynchronize(st));   // act (pageable, loop-local) consumed before it is freed
     k_gather_theta<<<1, 64, 0, st>>>(w.theta, w.idx, na, w.thact);
-    if ((rc = dav_precondition(w.T, w.thact, cur_diag(h), na, dim, st)) != ADC2_OK) return rc;
+    if (schur) {
+      const unsigned gb = (unsigned)std::min<long>(16384, (dim * na + 255) / 256);
+      k_schur_singles<<<gb, 256, 0, st>>>(w.T, w.thact, na, dim, d.ns, cur_diag(h), w.pnu, w.pdb);
+      DAV_TRY(hipGetLastError());
+      // M21 t1: the singles-input half of a sigma (ADC(2)-x needs the whole product of (t1, 0))
+      const int parts = h->method == ADC2_METHOD_ADC2 ? SIGMA_SINGLES_IN : (SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN);
+      DAV_TRY(hipEventRecord(h->ev0, st));
+      if ((rc = sigma_call(h, na, w.T, w.T2, parts, st)) != ADC2_OK) return rc;
+      DAV_TRY(hipEventRecord(h->ev1, st));
+      DAV_TRY(hipEventSynchronize(h->ev1));
+      float ms = 0.f;
+      DAV_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      ms_sigma += ms;
+      n_half += parts == SIGMA_SINGLES_IN ? na : 2 * na;
+      k_schur_doubles<<<gb, 256, 0, st>>>(w.T, w.T2, w.R, w.idx, w.thact, na, dim, d.ns, cur_diag(h));
+      DAV_TRY(hipGetLastError());
+    } else if ((rc = dav_precondition(w.T, w.thact, cur_diag(h), na, dim, st)) != ADC2_OK) {
+      return rc;
+    }
     int na_use = na;
     if (s + na > max_sub && keep_max >= k && keep_max < s) {
       const int keep = keep_max;
@@ -703,7 +779,7 @@ adc2_status adc2_davidson(adc2_handle h, int nroots, const adc2_dav_opts* opt, c
     info->subspace = s;
     for (int j = 0; j < k; ++j) info->resnorm[j] = rn[j];
     info->ms_sigma = ms_sigma;
-    info->sigma_flops = sigma_flops_per_vector(d) * n_sigma;
+    info->sigma_flops = sigma_flops_per_vector(d) * (n_sigma + 0.5 * n_half);
     info->ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }

@@ -393,7 +393,7 @@ struct FoldRoot {
 // 128x128 FP64 GEMM per valence j, C[(a,c)][b] = sum_P L^P_ac L^P_bj; the
 // light columns -d_ac <Kb||Ij> + d_bc <Ka||Ij> from the stored <Ka||Ij>
 // (their interference with the main term is left out: this is a preconditioner).
-static adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
+adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
   if (!h->pre_nu.empty()) return ADC2_OK;
   const Dims& d = h->d;
   const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux, o = d.o;

@@ -170,6 +170,9 @@ adc2_status adc2x_apply(adc2_handle h, int m, const double2* x, double2* s, hipS
 inline const double* cur_diag(adc2_handle h) { return h->method == ADC2_METHOD_ADC2X ? h->diagx : h->diag; }
 
 // ---- folded solver (fold.hip) ----
+// per singles (K,c): nu = squared norm of column (K,c) of M21 and its |M21|^2-weighted
+// mean doubles energy, into h->pre_nu / h->pre_dbar (built once per handle)
+adc2_status build_fold_precond(adc2_handle h, hipStream_t st);
 adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const void* guess, double* omega,
                           void* Xout, adc2_dav_info* info, hipStream_t st);
 
