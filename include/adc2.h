@@ -200,13 +200,16 @@ ADC2_API adc2_status adc2_sigma_noalloc(adc2_handle h, int m, const void* X, voi
  * roots (the precision form's arithmetic never reaches them).  info sums
  * both stages; the handle is left in ADC2_FP64.  mixed_tol must exceed
  * tol (ADC2_ERR_ARG otherwise, and with root following).
- * Root following (opt->follow = 1, full-space solver): the root-specific
- * Davidson the paper uses to keep each root matched to its guess (Hirao and
- * Nakatsuji, cited in the Computational details).  Root j is, at every
- * iteration, the Ritz pair whose vector overlaps most (|<g_j|x>|^2) with
- * guess vector g_j, assigned greedily in decreasing order of overlap; omega
- * and X are then in guess order, not ascending.  Needs guess with at least
- * nroots vectors (ADC2_ERR_ARG otherwise, and with the folded solver).
+ * Root following (opt->follow = 1): the root-specific Davidson the paper
+ * uses to keep each root matched to its guess (Hirao and Nakatsuji, cited in
+ * the Computational details).  Root j is, at every iteration, the Ritz pair
+ * whose unit vector overlaps most (|<g_j|x>|^2 / |g_j|^2) with guess vector
+ * g_j, assigned greedily in decreasing order of overlap; omega and X are
+ * then in guess order, not ascending.  The folded solver solves every branch
+ * of its projected problem (one per search-space vector) and measures the
+ * overlap on the singles (the doubles of its Ritz vectors follow from their
+ * singles).
+ * Needs guess with at least nroots vectors (ADC2_ERR_ARG otherwise).
  * Returns ADC2_ERR_NOCONV (with the best omega/X/info written) when max_iter
  * is reached; ADC2_ERR_NONFINITE when the iteration produced NaN/Inf.
  * Synchronises the stream.

@@ -339,7 +339,7 @@ def adc2_davidson(h: Handle, nroots, tol=1e-8, max_iter=0, max_subspace=0, ngues
                   want_vectors=True, verbose=0, stream=None, raise_on_noconv=True, solver=ADC2_SOLVER_FULL,
                   follow=False, mixed_tol=0.0):
     """Eigenpairs of M.  follow=True: root j follows guess vector j (root-specific
-    Davidson; full-space solver; results in guess order).  mixed_tol > 0: solve
+    Davidson; either solver; results in guess order).  mixed_tol > 0: solve
     with split-BF16 sigma builds to mixed_tol first, then in FP64 to tol."""
     import torch
     opts = DavOpts(tol, max_iter, max_subspace, nguess, verbose, solver, 1 if follow else 0, float(mixed_tol))

@@ -381,6 +381,7 @@ struct FoldRoot {
                                  // 5 projected eigensolve did not converge
   int need = 0;
   int clamped = 0;               // consecutive iterations with status 1 (held at the expansion limit)
+  int branch = 0;                // eigenvalue index j of lambda_j(G(omega)) = omega this entry solves
 };
 
 }  // namespace
@@ -466,10 +467,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     set_error("adc2_davidson (folded): needs the diagonal doubles block of ADC(2)");
     return ADC2_ERR_ARG;
   }
-  if (opt && opt->follow) {
-    set_error("adc2_davidson: root following is provided by the full-space solver only");
-    return ADC2_ERR_ARG;
-  }
+  const bool follow = opt && opt->follow != 0;
   const Dims& dd = h->d;
   const long ns = dd.ns, nd = dd.nd, dim = dd.dim;
   const double tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
@@ -487,6 +485,14 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   int nguess = (opt && opt->nguess > 0) ? opt->nguess : (k <= 8 ? 2 * k : k);
   nguess = (int)std::min<long>(std::min(nguess, smax), ns);
   const int qmax = std::max(nguess, k);
+  if (follow && (!guess || nguess < k)) {
+    set_error("adc2_davidson: root following needs at least nroots guess vectors");
+    return ADC2_ERR_ARG;
+  }
+  // root following: every branch lambda_b(G(omega)) = omega of the search
+  // space (b < s; the b-th root below min D is branch b) is solved and root j
+  // is the one whose Ritz vector overlaps most with guess j
+  const int nbr = follow ? smax : k;
 
   // ---- device buffers ----
   std::vector<void*> owned;
@@ -801,10 +807,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   };
 
   // ---- initial space ----
+  std::vector<cplx> gref;   // singles of the followed guess vectors, as given
   {
     std::vector<cplx> T((size_t)nguess * ns, cplx(0.0, 0.0));
     if (guess) {
       FD_TRY(d2h_rows((const double2*)guess, nguess, T.data()));
+      if (follow) gref.assign(T.begin(), T.begin() + (size_t)k * ns);
     } else {
       std::vector<int> idx(ns);
       for (long i = 0; i < ns; ++i) idx[i] = (int)i;
@@ -827,7 +835,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     }
   }
 
-  std::vector<FoldRoot> roots(k);
+  std::vector<FoldRoot> roots(nbr);
+  for (int b = 0; b < nbr; ++b) roots[b].branch = b;
   std::vector<char> prov(k, 0);   // root held at the expansion limit this iteration
   std::vector<double> res(k, 1e300);
   bool have_omega = false, converged = false;
@@ -871,8 +880,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     // to min D than about 0.025 (min D - w0) are out of reach of this solver
     double hi0 = rmap.reach(1.05);
     double wlo = rmap.inv ? std::max(lo0, rmap.w0 + 0.1 * (Dmin - rmap.w0)) : lo0;   // lowest omega evaluated
-    auto solve_root = [&](int j) {
-      FoldRoot& R = roots[j];
+    auto solve_root = [&](int idx) {
+      FoldRoot& R = roots[idx];
+      const int j = R.branch;
+      if (j >= s) {   // fewer basis vectors than this branch index
+        R.status = 6;
+        return;
+      }
       double wv = have_omega ? R.omega : wlo;
       if (!(wv > wlo && wv < hi0)) wv = have_omega ? std::min(std::max(wv, wlo), hi0 - 1e-9 * std::fabs(hi0)) : wlo;
       double lo = wlo, hi = hi0;
@@ -962,13 +976,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     for (int attempt = 0; attempt < 4; ++attempt) {
       {
         std::vector<std::thread> th;
-        for (int j = 1; j < k; ++j) th.emplace_back(solve_root, j);
+        for (int j = 1; j < nbr; ++j) th.emplace_back(solve_root, j);
         solve_root(0);
         for (auto& t : th) t.join();
       }
       int need = 0;
       bool below = false;
-      for (int j = 0; j < k; ++j) {
+      for (int j = 0; j < nbr; ++j) {
         if (roots[j].status == 3) need = std::max(need, roots[j].need);
         if (roots[j].status == 4) below = true;
       }
@@ -986,6 +1000,56 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       // more Chebyshev moments: recompute them for the whole space
       mcomp = std::min(nmb, (need + FMB - 1) / FMB);
       FD_TRY(cheb_cols(s, 0, s, mcomp));
+    }
+    if (follow) {
+      // root j = the branch whose Ritz vector (x1 = V y, |x|^2 = 1 + |x2|^2)
+      // overlaps most with the singles of guess j, assigned greedily in
+      // decreasing order of overlap; the chosen entries move to the front
+      std::vector<cplx> pg((size_t)k * s);
+      std::vector<double> gn(k, 0.0);
+      par_for(k, [&](int j) {
+        const cplx* g = &gref[(size_t)j * ns];
+        for (long e = 0; e < ns; ++e) gn[j] += std::norm(g[e]);
+        for (int i = 0; i < s; ++i) {
+          const cplx* v = &Vs[(size_t)i * ns];
+          cplx a = 0.0;
+          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * g[e];
+          pg[(size_t)j * s + i] = a;
+        }
+      });
+      std::vector<double> ov((size_t)k * nbr, -1.0);
+      for (int b = 0; b < nbr; ++b) {
+        const FoldRoot& R = roots[b];
+        if ((R.status != 0 && R.status != 1) || (int)R.y.size() != s) continue;
+        for (int j = 0; j < k; ++j) {
+          cplx a = 0.0;
+          for (int i = 0; i < s; ++i) a += std::conj(pg[(size_t)j * s + i]) * R.y[i];
+          ov[(size_t)j * nbr + b] = std::norm(a) / ((1.0 + std::max(R.n2, 0.0)) * std::max(gn[j], 1e-300));
+        }
+      }
+      std::vector<int> sel(k, -1);
+      std::vector<char> used(nbr, 0);
+      for (int n = 0; n < k; ++n) {
+        int bj = -1, bb = -1;
+        double best = -2.0;
+        for (int j = 0; j < k; ++j) {
+          if (sel[j] >= 0) continue;
+          for (int b = 0; b < nbr; ++b)
+            if (!used[b] && ov[(size_t)j * nbr + b] > best) {
+              best = ov[(size_t)j * nbr + b];
+              bj = j;
+              bb = b;
+            }
+        }
+        sel[bj] = bb;
+        used[bb] = 1;
+      }
+      std::vector<FoldRoot> re;
+      re.reserve(nbr);
+      for (int j = 0; j < k; ++j) re.push_back(roots[sel[j]]);
+      for (int b = 0; b < nbr; ++b)
+        if (!used[b]) re.push_back(roots[b]);
+      roots.swap(re);
     }
     // A projected root that is not below the limit of the resolvent expansion
     // (status 1) is held there, as an unconverged Ritz pair of G at that
@@ -1174,7 +1238,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       };
       rot_mat(H11.data());
       for (int m = 0; m < FMB * mcomp; ++m) rot_mat(&K[(size_t)m * smax * smax]);
-      for (int j = 0; j < k; ++j) {
+      for (int j = 0; j < nbr; ++j) {
         roots[j].y.clear();
         roots[j].Z.clear();   // the basis changed: next solve starts cold
       }

@@ -95,5 +95,99 @@ def test_follow_argument_errors():
     g[0, 0] = 1
     g[1, 1] = 1
     with pytest.raises(A.Adc2Error):
-        A.adc2_davidson(h, 2, guess=g, follow=True, solver=A.ADC2_SOLVER_FOLDED)
+        A.adc2_davidson(h, 2, follow=True, solver=A.ADC2_SOLVER_FOLDED)     # no guess
+    with pytest.raises(A.Adc2Error):
+        A.adc2_davidson(h, 2, guess=g, nguess=1, follow=True, solver=A.ADC2_SOLVER_FOLDED)   # fewer than roots
+    h.close()
+
+
+# ---------------------------------------------------------------- folded solver
+FOLD = A.ADC2_SOLVER_FOLDED
+
+
+def strong_system():
+    """A system whose lowest 16 roots lie below min D (coupling sigma 0.3)."""
+    return make_system(2, 3, 8, 24, seed=305, sigma=0.3)
+
+
+def run_folded(s, refs, tol=1e-9):
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    g = dev(refs.numpy())
+    w, X, inf = A.adc2_davidson(h, refs.shape[0], tol=tol, guess=g, nguess=refs.shape[0], follow=True,
+                                solver=FOLD)
+    h.close()
+    return np.array(w), X.cpu(), inf
+
+
+def test_follow_folded_perturbed_eigenvectors():
+    """The folded solver follows roots by the overlap of its Ritz singles with
+    the guesses' singles (the doubles of a Ritz vector are a function of its
+    singles); targets are non-lowest states below min D."""
+    s = strong_system()
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    M = a.matrix()
+    w_all, v_all = torch.linalg.eigh(M)
+    Dmin = float(O.m22_diag(a.eps, a.sp).min())
+    pick = [4, 1, 9]
+    assert float(w_all[max(pick)]) < Dmin - 0.5
+    rng = np.random.default_rng(3)
+    noise = torch.from_numpy(rng.standard_normal((3, a.dim)) + 1j * rng.standard_normal((3, a.dim)))
+    noise = noise / torch.linalg.vector_norm(noise, dim=1, keepdim=True)
+    refs = v_all[:, pick].T + 0.25 * noise
+    w_ref, X_ref = O.roots_following(M, refs)
+    assert np.abs(w_ref.numpy() - w_all[pick].numpy()).max() < 1e-12
+    print(f"[case] folded follow perturbed eigenvectors {pick}", flush=True)
+    w, X, inf = run_folded(s, refs)
+    print(f"  gpu {w}  oracle {w_ref.numpy()}  its {inf['iters']}", flush=True)
+    assert inf["converged"]
+    assert np.abs(w - w_ref.numpy()).max() < 1e-9
+    ovl = (X.conj() @ X_ref).abs().diagonal()
+    assert (ovl - 1).abs().max().item() < 1e-8
+
+
+def test_follow_folded_cis_guesses():
+    s = strong_system()
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    sp = a.sp
+    M = a.matrix()
+    M1 = O.m11(a.L, a.eps, sp, order=1)
+    wc, vc = torch.linalg.eigh(M1)
+    pick = [0, 2, 5]
+    refs = torch.zeros(3, a.dim, dtype=O.C128)
+    refs[:, :sp.n_singles] = vc[:, pick].T
+    w_ref, _ = O.roots_following(M, refs)
+    print(f"[case] folded follow CIS states {pick}: oracle {w_ref.numpy()} margin {margin(M, refs, w_ref):.3f}",
+          flush=True)
+    assert not np.all(np.diff(w_ref.numpy()) > 0)      # not simply the lowest roots in order
+    w, X, inf = run_folded(s, refs)
+    print(f"  gpu {w}  its {inf['iters']}", flush=True)
+    assert inf["converged"]
+    assert np.abs(w - w_ref.numpy()).max() < 1e-9
+
+
+def test_follow_folded_equals_full_space_c1():
+    """At c1 (no explicit matrix on the host) the folded and the full-space
+    solvers follow the same CIS guesses to the same roots, each certified by
+    its FP64 residual."""
+    from synth import config_system
+    s = config_system("c1")
+    a = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    M1 = O.m11(a.L, a.eps, a.sp, order=1)
+    wc, vc = torch.linalg.eigh(M1)
+    pick = [0, 2, 5, 3]
+    refs = torch.zeros(len(pick), a.dim, dtype=O.C128)
+    refs[:, :a.sp.n_singles] = vc[:, pick].T
+    print(f"[case] follow c1 folded vs full space, CIS states {pick}", flush=True)
+    h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+    g = dev(refs.numpy())
+    wf, Xf, inf_f = A.adc2_davidson(h, len(pick), tol=1e-9, guess=g, nguess=len(pick), follow=True, solver=FOLD)
+    wa, Xa, inf_a = A.adc2_davidson(h, len(pick), tol=1e-9, guess=g, nguess=len(pick), follow=True,
+                                    max_iter=400)
+    print(f"  folded {np.round(wf, 9)} ({inf_f['iters']} it)  full {np.round(wa, 9)} ({inf_a['iters']} it)",
+          flush=True)
+    assert inf_f["converged"] and inf_a["converged"]
+    assert np.abs(np.array(wf) - np.array(wa)).max() < 1e-8
+    for X in (Xf, Xa):
+        wr, rn = A.adc2_rayleigh(h, X)
+        assert max(rn) < 1e-8
     h.close()
