@@ -297,18 +297,22 @@ __global__ void k_minmax(const double* __restrict__ D, long n, double* __restric
   }
 }
 
-// Main coupling term of the preconditioner for one valence j:
-//   nu[c] += sum_{a<b} |V_abc|^2,  mu[c] += sum_{a<b} |V_abc|^2 (e_a + e_b - e_j),
-//   V_abc = <ab||cj> = C[(a,c)][b] - C[(b,c)][a],  C[(x,c)][y] = (xc|yj).
-// One workgroup per c; 32x32 tile pairs (a-block <= b-block) through LDS so
-// that both C reads are coalesced.
-__global__ __launch_bounds__(256) void k_schur_red(const double2* __restrict__ C, int nv,
-                                                    const double* __restrict__ ev, double ej,
-                                                    double* __restrict__ nu, double* __restrict__ mu) {
-  __shared__ double2 t1[32][33];
-  __shared__ double2 t2[32][33];
+// Main coupling term of the preconditioner for one virtual c = c0 + cc and
+// one valence j (workgroup (cc, j)):
+//   part[j][c] = ( sum_{a<b} |V_ab|^2,  sum_{a<b} |V_ab|^2 (e_a + e_b - e_j) ),
+//   V_ab = <ab||cj> = Z[cc][j][a][b] - Z[cc][j][b][a],  Z[cc][j][x][y] = (x c|y j).
+// 32x32 tile pairs (a-block <= b-block) through LDS so that both Z reads are
+// coalesced.  Every (j, c) entry is written once: no clearing, and the sums
+// over j are taken afterwards in a fixed order.
+__global__ __launch_bounds__(256) void k_schur_red(const float2* __restrict__ Z, int no, int nv, int c0,
+                                                    const double* __restrict__ ev, const double* __restrict__ ej,
+                                                    double* __restrict__ part) {
+  __shared__ float2 t1[32][33];
+  __shared__ float2 t2[32][33];
   __shared__ double red[2][256];
-  const int c = blockIdx.x;
+  const int cc = blockIdx.x, j = blockIdx.y;
+  const float2* C = Z + ((long)cc * no + j) * nv * nv;
+  const double e_j = ej[j];
   const int tid = threadIdx.x;
   const int nb = (nv + 31) / 32;
   double s0 = 0.0, s1 = 0.0;
@@ -319,19 +323,20 @@ __global__ __launch_bounds__(256) void k_schur_red(const double2* __restrict__ C
       for (int e = tid; e < 1024; e += 256) {
         const int r = e / 32, q = e % 32;
         const int a = a0 + r, b = b0 + q;
-        t1[r][q] = (a < nv && b < nv) ? C[((long)a * nv + c) * nv + b] : make_double2(0.0, 0.0);
+        t1[r][q] = (a < nv && b < nv) ? C[(long)a * nv + b] : make_float2(0.f, 0.f);
         const int b2 = b0 + r, a2 = a0 + q;
-        t2[r][q] = (a2 < nv && b2 < nv) ? C[((long)b2 * nv + c) * nv + a2] : make_double2(0.0, 0.0);
+        t2[r][q] = (a2 < nv && b2 < nv) ? C[(long)b2 * nv + a2] : make_float2(0.f, 0.f);
       }
       __syncthreads();
       for (int e = tid; e < 1024; e += 256) {
         const int r = e / 32, q = e % 32;
         const int a = a0 + r, b = b0 + q;
         if (a < nv && b < nv && a < b) {
-          const double2 v = csub(t1[r][q], t2[q][r]);
-          const double w2 = v.x * v.x + v.y * v.y;
+          const double vx = (double)t1[r][q].x - (double)t2[q][r].x;
+          const double vy = (double)t1[r][q].y - (double)t2[q][r].y;
+          const double w2 = vx * vx + vy * vy;
           s0 += w2;
-          s1 += w2 * (ev[a] + ev[b] - ej);
+          s1 += w2 * (ev[a] + ev[b] - e_j);
         }
       }
     }
@@ -347,8 +352,9 @@ __global__ __launch_bounds__(256) void k_schur_red(const double2* __restrict__ C
     __syncthreads();
   }
   if (tid == 0) {
-    nu[c] += red[0][0];
-    mu[c] += red[1][0];
+    double* o = part + ((long)j * nv + c0 + cc) * 2;
+    o[0] = red[0][0];
+    o[1] = red[1][0];
   }
 }
 
@@ -390,44 +396,61 @@ struct FoldRoot {
 // doubles energy: per singles e = (K,c), nu_e = sum_d |M21_{d,e}|^2 and the
 // weighted mean Dbar_e = sum_d |M21_{d,e}|^2 D_d / nu_e, so that
 //   diag[M11 + M12 (omega - D)^-1 M21]_e ~ d11_e + nu_e / (omega - Dbar_e).
-// The dominant three-virtual column  <ab||cj> (same for every K) comes from one
-// 128x128 FP64 GEMM per valence j, C[(a,c)][b] = sum_P L^P_ac L^P_bj; the
-// light columns -d_ac <Kb||Ij> + d_bc <Ka||Ij> from the stored <Ka||Ij>
-// (their interference with the main term is left out: this is a preconditioner).
+// The dominant three-virtual column  <ab||cj> (same for every K) comes from
+// split-BF16 GEMMs over chunks of c, Z[cc][j][a][b] = sum_P L^P_{a,c} L^P_{b,j}
+// (8 nv^3 no naux flops in all, on the BF16 matrix cores; the ~1e-6 relative
+// error of the split form is immaterial for a preconditioner); the light
+// columns -d_ac <Kb||Ij> + d_bc <Ka||Ij> from the stored <Ka||Ij> (their
+// interference with the main term is left out: this is a preconditioner).
 adc2_status build_fold_precond(adc2_handle h, hipStream_t st) {
   if (!h->pre_nu.empty()) return ADC2_OK;
   const Dims& d = h->d;
   const int nc = d.nc, no = d.no, nv = d.nv, naux = d.naux, o = d.o;
-  const long nv2 = (long)nv * nv;
-  double2* C = nullptr;
-  double* nm = nullptr;
+  const long nvo = (long)no * nv;
+  // chunk of virtuals c per GEMM: Z (complex64, nck no nv^2) within about 2 GB
+  const int nck = (int)std::max<long>(1, std::min<long>(nv, (2L << 30) / (8L * nvo * nv)));
+  __bf16 *Ab = nullptr, *Bown = nullptr;
+  float2* Z = nullptr;
+  double* part = nullptr;
   std::vector<double> eps(d.n);
   std::vector<double2> Vt((size_t)nc * no * nc * nv);
-  std::vector<double> hnm(2 * nv);
-  hipError_t e = dmalloc(h, &C, sizeof(double2) * nv2 * nv);
-  if (e == hipSuccess) e = dmalloc(h, &nm, sizeof(double) * 2 * nv);
-  if (e == hipSuccess) e = hipMemsetAsync(nm, 0, sizeof(double) * 2 * nv, st);
+  std::vector<double> hpart((size_t)no * nv * 2);
+  hipError_t e = dmalloc(h, &Ab, split_bytes((long)nck * nv, naux));
+  if (e == hipSuccess) e = dmalloc(h, &Z, sizeof(float2) * nck * nvo * nv);
+  if (e == hipSuccess) e = dmalloc(h, &part, sizeof(double) * 2 * nvo);
+  if (e == hipSuccess && !h->LvB) e = dmalloc(h, &Bown, split_bytes(nvo, naux));
   if (e == hipSuccess) e = hipMemcpy(eps.data(), h->eps, sizeof(double) * d.n, hipMemcpyDeviceToHost);
   adc2_status rc = ADC2_OK;
-  for (int j = 0; j < no && e == hipSuccess && rc == ADC2_OK; ++j) {
-    // C[(a,c)][b] = sum_P Lvv[P][a][c] Lvo[nc+j][P][b]
-    rc = bgemm_kmajor(h->Lvv, 0, nv2, (int)nv2, h->Lvo + (long)(nc + j) * naux * nv, 0, nv, nv, (int)nv2, nv, naux,
-                      1, C, st);
+  const __bf16* LvB = h->LvB ? (const __bf16*)h->LvB : Bown;
+  if (e == hipSuccess && Bown) rc = pack_valence_b3(h, Bown, st);
+  for (int c0 = 0; c0 < nv && e == hipSuccess && rc == ADC2_OK; c0 += nck) {
+    const int nk = std::min(nck, nv - c0);
+    rc = schur_gemm_b3(h, c0, nk, LvB, Ab, Z, st);
     if (rc != ADC2_OK) break;
-    k_schur_red<<<nv, 256, 0, st>>>(C, nv, h->eps + o, eps[nc + j], nm, nm + nv);
+    k_schur_red<<<dim3(nk, no), 256, 0, st>>>(Z, no, nv, c0, h->eps + o, h->eps + nc, part);
     e = hipGetLastError();
   }
   if (e == hipSuccess && rc == ADC2_OK) e = hipStreamSynchronize(st);
-  if (e == hipSuccess && rc == ADC2_OK) e = hipMemcpy(hnm.data(), nm, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rc == ADC2_OK)
+    e = hipMemcpy(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost);
   if (e == hipSuccess && rc == ADC2_OK)
     e = hipMemcpy(Vt.data(), h->Vt, sizeof(double2) * Vt.size(), hipMemcpyDeviceToHost);
-  dfree(h, C);
-  dfree(h, nm);
+  dfree(h, Ab);
+  dfree(h, Bown);
+  dfree(h, Z);
+  dfree(h, part);
   if (rc != ADC2_OK) return rc;
   if (e != hipSuccess) {
-    set_error(std::string("adc2_davidson (folded): preconditioner: ") + hipGetErrorString(e));
+    set_error(std::string("adc2_davidson: preconditioner: ") + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
   }
+  // sums over j in a fixed order
+  std::vector<double> hnm(2 * nv, 0.0);
+  for (int j = 0; j < no; ++j)
+    for (int c = 0; c < nv; ++c) {
+      hnm[c] += hpart[((size_t)j * nv + c) * 2];
+      hnm[nv + c] += hpart[((size_t)j * nv + c) * 2 + 1];
+    }
   const double* ev = eps.data() + o;
   std::vector<double> nu((size_t)nc * nv), db((size_t)nc * nv);
   for (int K = 0; K < nc; ++K) {

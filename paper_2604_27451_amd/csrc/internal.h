@@ -147,6 +147,8 @@ adc2_status ybuild_sum(adc2_handle h, int m, hipStream_t st);
 adc2_status tau_from_w(double2* W, const int2* dpairs, int npairs, const double* eps, int o, int nv, hipStream_t st);
 // bytes of an R x K operand in the blocked split-BF16 layout
 long split_bytes(long R, long K);
+adc2_status pack_valence_b3(adc2_handle h, __bf16* dst, hipStream_t st);
+adc2_status schur_gemm_b3(adc2_handle h, int c0, int nck, const __bf16* LvB, __bf16* Ab, float2* Z, hipStream_t st);
 
 // ---- setup pieces reused by the adjoint (k_setup.hip) ----
 // W[p][a][c] = <ac||kl> for every occupied pair p = (k<l) in row-major pair order.

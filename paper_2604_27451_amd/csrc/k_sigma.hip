@@ -403,14 +403,16 @@ __device__ __forceinline__ void ygemm_b3_item(BigSmemB (&s)[2], const __bf16* __
   });
 }
 
-// Split a K-major complex64 operand (element (k, row) at src[g*gstride + x +
-// k*ld], row = g*inner + x < R, k < K) into the blocked split layout of
-// zgemmb.h (rows padded to 128, k to 32, padding zero).  Thread t of a block's
-// 512 owns row r = (t / 4) % 128 and the k-group stored in 16-byte slot t % 4
-// of that row, so every plane store of a wave covers 16 whole 64-byte rows
-// (1 KB contiguous); the source reads of a wave are 4 runs of 16 rows.
-__global__ void k_split_pack(const float2* __restrict__ src, long gstride, long ld, int inner, int R, int K,
-                             int nrt, int nkc, __bf16* __restrict__ dst) {
+// Split a K-major complex operand (element (k, row) at src[g*gstride +
+// x*xstride + k*ld], row = g*inner + x < R, k < K; complex64, or complex128
+// rounded to complex64 first) into the blocked split layout of zgemmb.h (rows
+// padded to 128, k to 32, padding zero).  Thread t of a block's 512 owns row
+// r = (t / 4) % 128 and the k-group stored in 16-byte slot t % 4 of that row,
+// so every plane store of a wave covers 16 whole 64-byte rows (1 KB
+// contiguous); with xstride 1 the source reads of a wave are 4 runs of 16 rows.
+template <class TS>
+__global__ void k_split_pack(const TS* __restrict__ src, long gstride, long xstride, long ld, int inner, int R,
+                             int K, int nrt, int nkc, __bf16* __restrict__ dst) {
   const long total = (long)nrt * nkc * 512;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int slot = (int)(t & 3), r = (int)((t >> 2) & 127);
@@ -421,10 +423,14 @@ __global__ void k_split_pack(const float2* __restrict__ src, long gstride, long 
     float re[8], im[8];
     if (row < R) {
       const int g = row / inner;
-      const float2* p = src + (long)g * gstride + (row - g * inner);
+      const TS* p = src + (long)g * gstride + (long)(row - g * inner) * xstride;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float2 v = k0 + e < K ? p[(long)(k0 + e) * ld] : make_float2(0.f, 0.f);
+        float2 v = make_float2(0.f, 0.f);
+        if (k0 + e < K) {
+          const TS w = p[(long)(k0 + e) * ld];
+          v = make_float2((float)w.x, (float)w.y);
+        }
         re[e] = v.x;
         im[e] = v.y;
       }
@@ -446,11 +452,13 @@ __global__ void k_split_pack(const float2* __restrict__ src, long gstride, long 
 
 long split_bytes(long R, long K) { return (long)cdiv(R, BT) * cdiv(K, BKB) * BLOCK_BYTES; }
 
-static adc2_status split_pack(const float2* src, long gstride, long ld, int inner, long R, long K, __bf16* dst,
-                              hipStream_t st) {
+template <class TS>
+static adc2_status split_pack(const TS* src, long gstride, long ld, int inner, long R, long K, __bf16* dst,
+                              hipStream_t st, long xstride = 1) {
   const int nrt = cdiv(R, BT), nkc = cdiv(K, BKB);
   const long total = (long)nrt * nkc * 512;
-  k_split_pack<<<grid_for(total, 256, 1L << 20), 256, 0, st>>>(src, gstride, ld, inner, (int)R, (int)K, nrt, nkc, dst);
+  k_split_pack<TS><<<grid_for(total, 256, 1L << 20), 256, 0, st>>>(src, gstride, xstride, ld, inner, (int)R, (int)K,
+                                                                    nrt, nkc, dst);
   ADC2_CHECK_LAUNCH();
   return ADC2_OK;
 }
@@ -898,6 +906,32 @@ adc2_status build_b3(adc2_handle h, hipStream_t st) {
   ADC2_HIP(dmalloc(h, &h->LvTB, split_bytes(R2, K2)));
   if ((rc = split_pack(h->Lv32, (long)d.naux * d.nv, d.nv, d.nv, R1, K1, (__bf16*)h->LvB, st)) != ADC2_OK) return rc;
   return split_pack(h->LvT32, 0, d.naux, d.naux, R2, K2, (__bf16*)h->LvTB, st);
+}
+
+// Split-BF16 operands and GEMM of the Schur preconditioner's three-virtual
+// column.  pack_valence_b3 writes the valence rows of L in the sigma2 B layout
+// (rows (j,b), K = P; the same bits as the handle's LvB).  schur_gemm_b3
+// packs, for virtuals c in [c0, c0 + nck), A rows (cc,a) with element
+// L^P_{a,c0+cc} (from Lvv[P][a][c]) into Ab and forms
+//   Z[cc][j][a][b] = sum_P L^P_{a,c0+cc} L^P_{b,j}     (all j, a, b)
+// on the sigma2 split-BF16 kernel.
+adc2_status pack_valence_b3(adc2_handle h, __bf16* dst, hipStream_t st) {
+  const Dims& d = h->d;
+  return split_pack(h->Lvo + (long)d.nc * d.naux * d.nv, (long)d.naux * d.nv, d.nv, d.nv, (long)d.no * d.nv, d.naux,
+                    dst, st);
+}
+
+adc2_status schur_gemm_b3(adc2_handle h, int c0, int nck, const __bf16* LvB, __bf16* Ab, float2* Z,
+                          hipStream_t st) {
+  const Dims& d = h->d;
+  const long R = (long)nck * d.nv;
+  // row (cc, a): group cc (stride 1 in Lvv), position a (stride nv), k = P (stride nv^2)
+  adc2_status rc = split_pack(h->Lvv + c0, 1, (long)d.nv * d.nv, d.nv, R, d.naux, Ab, st, (long)d.nv);
+  if (rc != ADC2_OK) return rc;
+  const long nblk = (long)cdiv(R, BT) * cdiv((long)d.no * d.nv, BT);
+  k_zsig2_b3<<<(unsigned)nblk, 512, 0, st>>>(Ab, LvB, (int)R, d.no, d.nv, d.naux, Z);
+  ADC2_CHECK_LAUNCH();
+  return ADC2_OK;
 }
 
 adc2_status ensure_ws_b3(adc2_handle h, int m) {
