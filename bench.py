@@ -47,16 +47,41 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
 # algorithmic complex flops (8 per complex multiply-add)
 PEAK_BF16X3 = 2500.0 * 8.0 / 24.0
 HARTREE_EV = 27.211386245988
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
-KERNEL_SOURCES = ["paper_2604_27451_amd/csrc/k_sigma.hip", "paper_2604_27451_amd/csrc/tile.h",
-                  "paper_2604_27451_amd/csrc/zgemm.h", "paper_2604_27451_amd/csrc/zgemm32.h", "paper_2604_27451_amd/csrc/zgemmb.h"]
+# hardware-counter traffic of the heavy sigma kernels, per configuration profiled
+TRAFFIC_FILES = {"c3": os.path.join(ROOT, "profiles", "traffic_c3.json")}
+CSRC = "paper_2604_27451_amd/csrc"
+# sources that define each heavy sigma kernel: its GEMM engine header(s) and its own definition
+KERNEL_DEFS = {("fp64", "ybuild"): (["zgemm.h", "tile.h"], "k_ygemm("),
+               ("fp64", "sigma2"): (["zgemm.h", "tile.h"], "k_zsig2("),
+               ("c64", "ybuild"): (["zgemm32.h", "zgemm.h"], "k_ygemm_c64("),
+               ("c64", "sigma2"): (["zgemm32.h", "zgemm.h"], "k_zsig2_c64("),
+               ("bf16x3", "ybuild"): (["zgemmb.h", "zgemm.h"], "k_ygemm_b3("),
+               ("bf16x3", "sigma2"): (["zgemmb.h", "zgemm.h"], "k_zsig2_b3(")}
 
 
-def kernel_hash() -> str:
+def _definition(text: str, name: str) -> str:
+    """Source text of the kernel whose declarator contains `name`: from the
+    line that starts its declaration (with a template line above it) to the
+    closing brace in column 0."""
+    i = text.index("void " + name)
+    start = text.rfind("\n", 0, i) + 1
+    prev = text.rfind("\n", 0, start - 1) + 1
+    if text[prev:start].startswith("template"):
+        start = prev
+    end = text.index("\n}\n", i) + 3
+    return text[start:end]
+
+
+def kernel_hash(prec: str, kernel: str) -> str:
+    """Hash of the sources of one heavy sigma kernel: hardware counters taken
+    on it stay valid exactly while this is unchanged."""
+    files, name = KERNEL_DEFS[(prec, kernel)]
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+    for f in files:
+        with open(os.path.join(ROOT, CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, CSRC, "k_sigma.hip")) as fh:
+        h.update(_definition(fh.read(), name).encode())
     return h.hexdigest()[:16]
 
 
@@ -116,38 +141,48 @@ def cpu_baseline(L, eps, nc, no, nv, naux, nj: int, nvs: int):
     t0 = time.perf_counter()
     a = O.Adc2(Ls, es, nc, nj, nvs)
     a.sigma_op()
+    t1 = time.perf_counter()
     x = torch.from_numpy(random_vectors(11, 1, a.dim))
     a.sigma(x)
-    dt = time.perf_counter() - t0
+    t2 = time.perf_counter()
+    dt = t2 - t0
     fl = f_sigma(nc, nj, nvs, naux)
     hi = host_info()
+    # value: a sigma build from the Cholesky vectors, as the GPU path does it on every call (it keeps
+    # no three-virtual integrals); product_only: the same flops over the product with the oracle's
+    # stored integral blocks alone (their construction amortised over many vectors)
     return {"value": fl / dt / 1e12, "unit": "complex TFLOP/s", "cores": hi["torch_threads"],
             "kind": "oracle",
-            "sample": f"oracle sigma (integral blocks + product) for 1 vector of the same system restricted "
-                      f"to its first {nj} valence and first {nvs} virtual spinors (nc={nc}, no={nj}, nv={nvs}, "
-                      f"naux={naux}); {dt:.2f} s for {fl:.3e} algorithmic flops",
-            "seconds": dt, "host": hi}
+            "sample": f"oracle sigma (integral blocks {t1 - t0:.2f} s + product {t2 - t1:.2f} s) for 1 vector of "
+                      f"the same system restricted to its first {nj} valence and first {nvs} virtual spinors "
+                      f"(nc={nc}, no={nj}, nv={nvs}, naux={naux}); {dt:.2f} s for {fl:.3e} algorithmic flops",
+            "seconds": dt, "integral_seconds": t1 - t0, "product_seconds": t2 - t1,
+            "product_only_value": fl / max(1e-9, t2 - t1) / 1e12, "host": hi}
 
 
-def load_traffic(prec):
-    """Calibrated HBM bytes per launch of the sigma kernels (m = 10 vectors)
-    from the committed hardware-counter profile, if it was taken on the
-    current kernel sources; {} otherwise."""
+def load_traffic(prec, config="c2"):
+    """Calibrated HBM bytes per launch of the heavy sigma kernels (m = 10
+    vectors) from the committed hardware-counter profile of the
+    configuration, for the kernels whose sources are unchanged since."""
+    if config not in TRAFFIC_FILES:
+        return {}
     try:
-        tr = json.load(open(TRAFFIC_FILE))
-    except Exception:
+        tr = json.load(open(TRAFFIC_FILES[config]))
+    except (OSError, ValueError):
         return {}
-    if tr.get("kernel_hash") != kernel_hash():
-        return {}
-    return tr.get("bytes_per_launch", {}).get(prec, {})
+    out = {}
+    for kern, rec in tr.get("kernels", {}).get(prec, {}).items():
+        if (prec, kern) in KERNEL_DEFS and rec.get("hash") == kernel_hash(prec, kern):
+            out[kern] = rec["bytes_per_launch"]
+    return out
 
 
-def roofline_of(stats, peak, traffic):
+def roofline_of(stats, peak, traffic, every_launch_m10=False):
     dom = max(stats, key=lambda k: stats[k]["ms"])
     d = stats[dom]
     # the counter profile is per launch of m = 10 vectors; in the folded solver every Y-build
     # launch has m = nroots = 10, the sigma2 launches have as many vectors as new directions
-    tb = traffic.get(dom) if dom == "ybuild" else None
+    tb = traffic.get(dom) if (dom == "ybuild" or every_launch_m10) else None
     per_flops = d["flops"] / max(1, d["launches"])
     per_ms = d["ms"] / max(1, d["launches"])
     achieved = per_flops / (per_ms * 1e-3) / 1e12 if per_ms > 0 else 0.0
@@ -603,7 +638,7 @@ def run_pipeline(args, A, np, torch, config=None, peaks=True, with_cpu=True):
 
     agg64 = agg_stats("ks64")
     value = tflops([r["info64"] for r in res])
-    roofline = roofline_of(agg64, PEAK_FP64_MFMA, load_traffic("fp64"))
+    roofline = roofline_of(agg64, PEAK_FP64_MFMA, load_traffic("fp64", config))
     last = res[-1]
     w64 = np.array(last["w64"])
     out = {
@@ -664,7 +699,7 @@ def run_pipeline(args, A, np, torch, config=None, peaks=True, with_cpu=True):
             "ev_err_raw": [float(x) for x in (wm - w64) * HARTREE_EV],
             "ev_err_polished": [float(x) for x in (wp - w64) * HARTREE_EV],
             "polished_resnorm": [float(x) for x in m["rn_polish"]],
-            "roofline": roofline_of(agg, peak, load_traffic(tag)),
+            "roofline": roofline_of(agg, peak, load_traffic({"b3": "bf16x3"}.get(tag, tag), config)),
             "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2),
                             "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
                         for k, v in agg.items()},
@@ -859,7 +894,7 @@ def run_headline(args, A, np, torch):
         agg = agg_kernel_stats(rec[tag]["ks"])
         sig[tag] = {"what": what, "ms_per_sigma": round(ms, 3), "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
                     "frac_of_peak": round(fl / (ms * 1e-3) / 1e12 / peak, 4),
-                    "roofline": roofline_of(agg, peak, load_traffic(tag)),
+                    "roofline": roofline_of(agg, peak, load_traffic(tag, args.config), every_launch_m10=True),
                     "kernels": {k: {"launches": v["launches"], "ms_per_launch": round(v["ms"] / v["launches"], 3),
                                     "tflops": round(v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12, 3)}
                                 for k, v in agg.items()}}
