@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadc2.so")
-SOURCES = ["api.hip", "k_setup.hip", "k_sigma.hip", "k_davidson.hip", "k_adjoint.hip", "fold.hip", "batch.hip", "peaks.hip", "tune.hip", "fns.hip", "transition.hip", "adc2x.hip"]
+SOURCES = ["api.hip", "k_setup.hip", "k_sigma.hip", "k_davidson.hip", "k_adjoint.hip", "fold.hip", "fold_la.hip", "batch.hip", "peaks.hip", "tune.hip", "fns.hip", "transition.hip", "adc2x.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -11,8 +11,8 @@
 // is expanded in Chebyshev polynomials of tau(D), an affine image of
 // 1/(D - w0) with w0 below the roots (or of D itself):
 //   (omega - D)^-1 = sum_m g_m(omega) T_m(tau(D)),
-// so that K_m = U^H T_m U is computed once per basis vector on the GPU and
-// G(omega) for any omega < min D costs only host arithmetic.  Each root j
+// so that K_m = U^H T_m U is computed once per basis vector and G(omega)
+// for any omega < min D costs only small matrix arithmetic.  Each root j
 // solves lambda_j(G(omega)) = omega by safeguarded Newton steps
 // (d lambda_j / d omega = -|x2|^2); the Newton update
 // (lambda + omega |x2|^2) / (1 + |x2|^2) is the Rayleigh quotient of the Ritz
@@ -25,23 +25,24 @@
 // by construction), so each iteration applies M21 to the new directions and
 // M12 to the Ritz doubles: one sigma build's worth of GEMMs per root, as in
 // the full-space solver, with the doubles never entering the search space.
+// All of the subspace work (the projected eigensolves, Gram-Schmidt, Ritz
+// vectors, residuals, restarts) runs in FP64 on the GPU (fold_la.hip); the
+// host reads status words and residual norms to steer the iteration.
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <thread>
 #include <vector>
 
+#include "fold_la.h"
 #include "hostla.h"
 #include "internal.h"
+#include "jacobi.h"
 #include "tile.h"
 
 namespace adc2 {
-
-using hostla::cplx;
 
 namespace {
 
@@ -358,38 +359,6 @@ __global__ __launch_bounds__(256) void k_schur_red(const float2* __restrict__ Z,
   }
 }
 
-// f(0..n-1) on up to 16 host threads
-template <class F>
-static void par_for(int n, F&& f) {
-  const int nt = std::min(n, (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
-  if (nt <= 1) {
-    for (int i = 0; i < n; ++i) f(i);
-    return;
-  }
-  std::atomic<int> next(0);
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&]() {
-      int i;
-      while ((i = next++) < n) f(i);
-    });
-  for (auto& x : th) x.join();
-}
-
-struct FoldRoot {
-  double omega = 0.0;            // evaluation point: x2 = (omega - D)^-1 U y
-  double rq = 0.0;               // Rayleigh quotient of that (x1, x2): (lambda + omega |x2|^2) / (1 + |x2|^2)
-  double n2 = 0.0;               // |x2|^2 for the unit-norm y
-  std::vector<cplx> y;           // eigenvector of G(omega) for this root
-  std::vector<cplx> Z;           // all eigenvectors of G(omega) (columns)
-  int status = 0;                // 0 ok, 1 root not below the doubles threshold, 2 expansion too long,
-                                 // 3 more moments needed (need), 4 below the shifted map's range,
-                                 // 5 projected eigensolve did not converge
-  int need = 0;
-  int clamped = 0;               // consecutive iterations with status 1 (held at the expansion limit)
-  int branch = 0;                // eigenvalue index j of lambda_j(G(omega)) = omega this entry solves
-};
-
 }  // namespace
 
 // Diagonal of the folded operator without the omega dependence of each
@@ -490,6 +459,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     set_error("adc2_davidson (folded): needs the diagonal doubles block of ADC(2)");
     return ADC2_ERR_ARG;
   }
+  static_assert(FSMAX == JMAX, "search space and subspace eigensolver sizes");
+  static_assert(FMM == FOLD_MM, "moment counts");
   const bool follow = opt && opt->follow != 0;
   const Dims& dd = h->d;
   const long ns = dd.ns, nd = dd.nd, dim = dd.dim;
@@ -500,14 +471,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   smax = std::min(smax, FSMAX);
   smax = std::max(smax, 2 * k);            // room for k Ritz vectors plus k new directions
   smax = (int)std::min<long>(smax, ns);
-  if (k > smax) {
+  if (k > smax || smax > FSMAX) {
     set_error("adc2_davidson (folded): nroots exceeds the singles dimension or the search-space limit");
     return ADC2_ERR_ARG;
   }
   const int keep_max = std::max(k, std::min(2 * k, smax - k));   // vectors kept at a restart
   int nguess = (opt && opt->nguess > 0) ? opt->nguess : (k <= 8 ? 2 * k : k);
   nguess = (int)std::min<long>(std::min(nguess, smax), ns);
-  const int qmax = std::max(nguess, k);
   if (follow && (!guess || nguess < k)) {
     set_error("adc2_davidson: root following needs at least nroots guess vectors");
     return ADC2_ERR_ARG;
@@ -519,14 +489,12 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
   // ---- device buffers ----
   std::vector<void*> owned;
-  std::vector<void*>* pinned_list = nullptr;
+  void* hsm = nullptr;   // pinned staging of the small host <-> device records
   auto release = [&]() {
     for (void* p : owned) dfree(h, p);
     owned.clear();
-    if (pinned_list) {
-      for (void* p : *pinned_list) hipHostFree(p);
-      pinned_list->clear();
-    }
+    if (hsm) hipHostFree(hsm);
+    hsm = nullptr;
   };
   auto dalloc = [&](void** p, size_t bytes) -> adc2_status {
     hipError_t e = dmalloc(h, p, std::max<size_t>(bytes, 16));
@@ -557,86 +525,94 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     }                                                                                     \
   } while (0)
 
-  double2 *Sb, *Tin, *X2, *Sx, *Kd, *part, *Yd, *Cd;
-  double *omd, *mm;
   int nchb = (int)std::max<long>(1, std::min<long>(512, nd / 4096));
   if (const char* v = getenv("ADC2_CHEB_NCHB")) nchb = (int)std::max<long>(1, std::min<long>(1024, atol(v)));
   const int nmb = FMM / FMB;
   const long part_len = (long)((FSMAX + FGB - 1) / FGB) * nmb * nchb * FMB * 256;   // split-K partials of the moments
+  const int nrb = fold_resid_blocks(ns);
+  // sigma rows: Sb = sigma of the basis (v, 0), singles part S1 and doubles part U = M21 v
+  double2 *Sb, *Tin, *X2, *Sx, *Kt, *part, *Yd, *Cd;
   FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
+  const int qmax = std::max(nguess, k);   // rows of one sigma input block (new directions never exceed it)
   FD_TRY(dalloc((void**)&Tin, sizeof(double2) * qmax * dim));
   FD_TRY(dalloc((void**)&X2, sizeof(double2) * k * dim));
   FD_TRY(dalloc((void**)&Sx, sizeof(double2) * k * dim));
-  FD_TRY(dalloc((void**)&Kd, sizeof(double2) * FMM * smax * FGB));
+  FD_TRY(dalloc((void**)&Kt, sizeof(double2) * FMM * smax * FGB));
   FD_TRY(dalloc((void**)&part, sizeof(double2) * part_len));
   FD_TRY(dalloc((void**)&Yd, sizeof(double2) * FSMAX * FSMAX));
   FD_TRY(dalloc((void**)&Cd, sizeof(double2) * FSMAX * FSMAX));
-  FD_TRY(dalloc((void**)&omd, sizeof(double) * 32));
+  // search-space state: singles basis V, S1, H11 = V^H S1, moments K_m, per-root eigenvectors
+  double2 *Vd, *S1d, *Hd, *Kall, *Td, *T2d, *Gw, *Cg, *Ybr, *Zbr, *X1d, *R1d, *PG, *gref, *gsc;
+  FD_TRY(dalloc((void**)&Vd, sizeof(double2) * FSMAX * ns));
+  FD_TRY(dalloc((void**)&S1d, sizeof(double2) * FSMAX * ns));
+  FD_TRY(dalloc((void**)&Hd, sizeof(double2) * JMAX * JMAX));
+  FD_TRY(dalloc((void**)&Kall, sizeof(double2) * FMM * JMAX * JMAX));
+  FD_TRY(dalloc((void**)&Td, sizeof(double2) * FSMAX * ns));
+  FD_TRY(dalloc((void**)&T2d, sizeof(double2) * FSMAX * ns));
+  FD_TRY(dalloc((void**)&Gw, sizeof(double2) * JMAX * JMAX));
+  FD_TRY(dalloc((void**)&Cg, sizeof(double2) * JMAX * JMAX));
+  FD_TRY(dalloc((void**)&Ybr, sizeof(double2) * nbr * JMAX));
+  FD_TRY(dalloc((void**)&Zbr, sizeof(double2) * nbr * JMAX * JMAX));
+  FD_TRY(dalloc((void**)&X1d, sizeof(double2) * k * ns));
+  FD_TRY(dalloc((void**)&R1d, sizeof(double2) * k * ns));
+  FD_TRY(dalloc((void**)&PG, sizeof(double2) * JMAX * k));
+  FD_TRY(dalloc((void**)&gref, sizeof(double2) * k * ns));
+  FD_TRY(dalloc((void**)&gsc, sizeof(double2) * 16L * dav_nblk(ns) * 256));
+  double *hw, *lam, *npart, *ov, *gnd, *omd, *scd, *pnu_d, *pdb_d, *mm;
+  FD_TRY(dalloc((void**)&hw, sizeof(double) * JMAX));
+  FD_TRY(dalloc((void**)&lam, sizeof(double) * JMAX));
+  FD_TRY(dalloc((void**)&npart, sizeof(double) * k * nrb));
+  FD_TRY(dalloc((void**)&ov, sizeof(double) * k * nbr));
+  FD_TRY(dalloc((void**)&gnd, sizeof(double) * k));
+  FD_TRY(dalloc((void**)&omd, sizeof(double) * FSMAX));
+  FD_TRY(dalloc((void**)&scd, sizeof(double) * FSMAX));
+  FD_TRY(dalloc((void**)&pnu_d, sizeof(double) * ns));
+  FD_TRY(dalloc((void**)&pdb_d, sizeof(double) * ns));
   FD_TRY(dalloc((void**)&mm, sizeof(double) * 2 * 256));
-  // Host <-> device traffic goes through pinned staging and contiguous device
-  // rows only; strided rows are gathered / scattered by k_rows_copy.
-  double2* Rowc;
-  FD_TRY(dalloc((void**)&Rowc, sizeof(double2) * qmax * ns));
-  std::vector<void*> pinned;
-  auto release_pinned = [&]() {
-    for (void* p : pinned) hipHostFree(p);
-    pinned.clear();
+  int *icount, *ibuf;
+  FD_TRY(dalloc((void**)&icount, sizeof(int) * 4));
+  FD_TRY(dalloc((void**)&ibuf, sizeof(int) * FSMAX));
+  FoldEntry* entd;
+  FoldResult* resd;
+  FoldBounds* bndd;
+  FD_TRY(dalloc((void**)&entd, sizeof(FoldEntry) * nbr));
+  FD_TRY(dalloc((void**)&resd, sizeof(FoldResult) * nbr));
+  FD_TRY(dalloc((void**)&bndd, sizeof(FoldBounds)));
+  const size_t hsm_bytes = std::max<size_t>(
+      {sizeof(double) * 512, sizeof(double) * k * nrb, sizeof(double) * k * nbr, sizeof(FoldEntry) * nbr,
+       sizeof(FoldResult) * nbr, sizeof(double2) * JMAX * JMAX, sizeof(double) * ns});
+  FD_HIP(hipHostMalloc(&hsm, hsm_bytes, hipHostMallocDefault));
+  // small records through the pinned staging block (each transfer completes before the block is reused)
+  auto up = [&](void* dst, const void* src, size_t bytes) -> adc2_status {
+    memcpy(hsm, src, bytes);
+    ADC2_HIP(hipMemcpyAsync(dst, hsm, bytes, hipMemcpyHostToDevice, st));
+    ADC2_HIP(hipStreamSynchronize(st));
+    return ADC2_OK;
   };
-  auto palloc = [&](void** p, size_t bytes) -> adc2_status {
-    hipError_t e = hipHostMalloc(p, std::max<size_t>(bytes, 16), hipHostMallocDefault);
-    if (e != hipSuccess) {
-      set_error(std::string("adc2_davidson (folded): hipHostMalloc: ") + hipGetErrorString(e));
-      return e == hipErrorOutOfMemory ? ADC2_ERR_OOM : ADC2_ERR_HIP;
+  auto down = [&](void* dst, const void* src, size_t bytes) -> adc2_status {
+    ADC2_HIP(hipMemcpyAsync(hsm, src, bytes, hipMemcpyDeviceToHost, st));
+    ADC2_HIP(hipStreamSynchronize(st));
+    memcpy(dst, hsm, bytes);
+    return ADC2_OK;
+  };
+  // out[j] (+)= alpha sum_i V[i] C[i][j] over rows of length n, in blocks of 32 columns
+  auto combine = [&](const double2* V, int s_, const double2* C, int ldc, int m, long n, double2* out, double alpha,
+                     bool acc) -> adc2_status {
+    for (int c0 = 0; c0 < m; c0 += 32) {
+      adc2_status r = dav_combine(V, s_, C + c0, ldc, std::min(32, m - c0), n, out + (long)c0 * n, alpha, acc, st);
+      if (r != ADC2_OK) return r;
     }
-    pinned.push_back(*p);
     return ADC2_OK;
   };
-  pinned_list = &pinned;
-  cplx *hRow, *hK, *hY;
-  double* hD;
-  {
-    adc2_status r = palloc((void**)&hRow, sizeof(cplx) * qmax * ns);
-    if (r == ADC2_OK) r = palloc((void**)&hK, sizeof(cplx) * FMM * smax * FGB);
-    if (r == ADC2_OK) r = palloc((void**)&hY, sizeof(cplx) * FSMAX * FSMAX);
-    if (r == ADC2_OK) r = palloc((void**)&hD, sizeof(double) * std::max<long>(512 + 32, ns));
-    if (r != ADC2_OK) {
-      release_pinned();
-      release();
-      return r;
-    }
-  }
-  const unsigned rgrid = (unsigned)std::min<long>(4096, ((long)qmax * ns + 255) / 256);
-  // host rows (q x ns) -> device rows with stride dim
-  auto h2d_rows = [&](const cplx* host, int q, double2* dst) -> adc2_status {
-    memcpy(hRow, host, sizeof(cplx) * q * ns);
-    ADC2_HIP(hipMemcpyAsync(Rowc, hRow, sizeof(double2) * q * ns, hipMemcpyHostToDevice, st));
-    k_rows_copy<<<rgrid, 256, 0, st>>>(Rowc, ns, dst, dim, q, ns);
-    ADC2_CHECK_LAUNCH();
-    ADC2_HIP(hipStreamSynchronize(st));
-    return ADC2_OK;
-  };
-  // device rows with stride dim (singles block) -> host rows (q x ns)
-  auto d2h_rows = [&](const double2* src, int q, cplx* host) -> adc2_status {
-    k_rows_copy<<<rgrid, 256, 0, st>>>(src, dim, Rowc, ns, q, ns);
-    ADC2_CHECK_LAUNCH();
-    ADC2_HIP(hipMemcpyAsync(hRow, Rowc, sizeof(double2) * q * ns, hipMemcpyDeviceToHost, st));
-    ADC2_HIP(hipStreamSynchronize(st));
-    memcpy(host, hRow, sizeof(cplx) * q * ns);
-    return ADC2_OK;
-  };
-  // small host array -> device, through pinned staging
-  auto h2d_small = [&](void* dst, const void* src, size_t bytes) -> adc2_status {
-    memcpy(hY, src, bytes);
-    ADC2_HIP(hipMemcpyAsync(dst, hY, bytes, hipMemcpyHostToDevice, st));
-    ADC2_HIP(hipStreamSynchronize(st));
-    return ADC2_OK;
-  };
+  const unsigned rgrid = (unsigned)std::min<long>(4096, ((long)FSMAX * ns + 255) / 256);
   const double* Ddev = h->diag + ns;       // doubles diagonal D
-  const double2* Uro = nullptr;            // doubles part of Sb rows
-  double2* Urw = Sb + ns;
-  Uro = Urw;
+  const double* d11d = h->diag;            // singles diagonal of M11
+  double2* Urw = Sb + ns;                  // doubles part of the Sb rows
+  const double2* Uro = Urw;
 
   FD_TRY(build_fold_precond(h, st));
+  FD_TRY(up(pnu_d, h->pre_nu.data(), sizeof(double) * ns));
+  FD_TRY(up(pdb_d, h->pre_dbar.data(), sizeof(double) * ns));
   const std::vector<double>& pnu = h->pre_nu;
   const std::vector<double>& pdb = h->pre_dbar;
 
@@ -644,12 +620,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   k_minmax<<<256, 256, 0, st>>>(Ddev, nd, mm);
   FD_HIP(hipGetLastError());
   std::vector<double> hm(512), d11(ns);
-  FD_HIP(hipMemcpyAsync(hD, mm, sizeof(double) * 512, hipMemcpyDeviceToHost, st));
-  FD_HIP(hipStreamSynchronize(st));
-  memcpy(hm.data(), hD, sizeof(double) * 512);
-  FD_HIP(hipMemcpyAsync(hD, h->diag, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
-  FD_HIP(hipStreamSynchronize(st));
-  memcpy(d11.data(), hD, sizeof(double) * ns);
+  FD_TRY(down(hm.data(), mm, sizeof(double) * 512));
+  FD_TRY(down(d11.data(), d11d, sizeof(double) * ns));
   double Dmin = 1e300, Dmax = -1e300;
   for (int b = 0; b < 256; ++b) {
     Dmin = std::min(Dmin, hm[2 * b]);
@@ -670,10 +642,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   }
   if (west < Dmin && std::isfinite(west))
     rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, west - std::max(1.0, 0.5 * (Dmin - west)));
+  auto fmap = [&]() { return FoldMap{rmap.inv ? 1 : 0, rmap.c, rmap.ih, rmap.w0}; };
 
-  // ---- host state ----
-  std::vector<cplx> Vs((size_t)smax * ns), S1((size_t)smax * ns), H11((size_t)smax * smax);
-  std::vector<cplx> K((size_t)FMM * smax * smax);
   int s = 0;
   long n21 = 0, n12 = 0;
   double ms_sigma = 0.0;
@@ -696,7 +666,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     hipEventDestroy(e1);
   };
 
-  // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 16 * mblocks
+  // Chebyshev moments K_m[i][j] for rows i < srows and columns [j0, j0 + q), m < 8 * mblocks
   // moment blocks held for every basis vector: with the shifted map, enough
   // for the root estimate plus two terms (more are added on demand)
   int mcomp = 3;
@@ -708,7 +678,6 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   if (verbose)
     fprintf(stderr, "[adc2 folded no=%d nv=%d] D in [%.6f, %.6f], root estimate %.6f, %s map w0 %.6f, %d moments\n",
             dd.no, dd.nv, Dmin, Dmax, west, rmap.inv ? "shifted-inverse" : "linear", rmap.w0, FMB * mcomp);
-  cplx* Kh = hK;
   double tm_cheb = 0.0;
   auto cheb_cols = [&](int srows, int j0, int q, int mblocks) -> adc2_status {
     const auto tc0 = std::chrono::steady_clock::now();
@@ -737,119 +706,87 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 #undef CHEB_MFMA
       ADC2_CHECK_LAUNCH();
       k_cheb_mfma_reduce<<<(unsigned)std::min<long>(4096, (tot + 255) / 256), 256, 0, st>>>(part, srows, qc, tp,
-                                                                                            nm, nz, nch_m, mm_, Kd);
+                                                                                            nm, nz, nch_m, mm_, Kt);
       ADC2_CHECK_LAUNCH();
-      ADC2_HIP(hipMemcpyAsync(Kh, Kd, sizeof(double2) * tot, hipMemcpyDeviceToHost, st));
-      ADC2_HIP(hipStreamSynchronize(st));
-      for (int m = 0; m < mm_; ++m)
-        for (int i = 0; i < srows; ++i)
-          for (int j = 0; j < qc; ++j) {
-            const cplx v = Kh[((size_t)m * srows + i) * qc + j];
-            K[((size_t)m * smax + i) * smax + c0 + j] = v;
-            K[((size_t)m * smax + c0 + j) * smax + i] = std::conj(v);
-          }
+      adc2_status r = fold_cheb_scatter(Kt, mm_, srows, c0, qc, Kall, st);
+      if (r != ADC2_OK) return r;
     }
+    if (verbose) ADC2_HIP(hipStreamSynchronize(st));
     tm_cheb += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
     return ADC2_OK;
   };
 
-  // append q orthonormal singles vectors T (host, q x ns): sigma of (v, 0), moments
-  auto add_vectors = [&](const std::vector<cplx>& T, int q) -> adc2_status {
-    adc2_status r = h2d_rows(T.data(), q, Tin);
-    if (r != ADC2_OK) return r;
-    r = sig_time(q, Tin, Sb + (long)s * dim, SIGMA_SINGLES_IN);
+  // append the q orthonormal singles vectors in rows 0..q-1 of Td: sigma of (v, 0), moments, H11 columns
+  auto add_vectors = [&](int q) -> adc2_status {
+    if (q > qmax) {
+      set_error("adc2_davidson (folded): more new directions than the input block holds");
+      return ADC2_ERR_ARG;
+    }
+    k_rows_copy<<<rgrid, 256, 0, st>>>(Td, ns, Tin, dim, q, ns);
+    ADC2_CHECK_LAUNCH();
+    adc2_status r = sig_time(q, Tin, Sb + (long)s * dim, SIGMA_SINGLES_IN);
     if (r != ADC2_OK) return r;
     n21 += q;
-    r = d2h_rows(Sb + (long)s * dim, q, S1.data() + (size_t)s * ns);
-    if (r != ADC2_OK) return r;
-    for (int j = 0; j < q; ++j)
-      std::copy(T.begin() + (size_t)j * ns, T.begin() + (size_t)(j + 1) * ns, Vs.begin() + (size_t)(s + j) * ns);
+    k_rows_copy<<<rgrid, 256, 0, st>>>(Sb + (long)s * dim, dim, S1d + (long)s * ns, ns, q, ns);
+    ADC2_CHECK_LAUNCH();
+    ADC2_HIP(hipMemcpyAsync(Vd + (long)s * ns, Td, sizeof(double2) * q * ns, hipMemcpyDeviceToDevice, st));
     const int snew = s + q;
-    r = cheb_cols(snew, s, q, mcomp);
-    if (r != ADC2_OK) return r;
-    par_for(snew, [&](int i) {
-      for (int j = s; j < snew; ++j) {
-        cplx a = 0.0;
-        const cplx* vi = &Vs[(size_t)i * ns];
-        const cplx* sj = &S1[(size_t)j * ns];
-        for (long e = 0; e < ns; ++e) a += std::conj(vi[e]) * sj[e];
-        H11[(size_t)i * smax + j] = a;
-      }
-    });
-    for (int i = 0; i < snew; ++i)
-      for (int j = s; j < snew; ++j) H11[(size_t)j * smax + i] = std::conj(H11[(size_t)i * smax + j]);
-    for (int j = s; j < snew; ++j) H11[(size_t)j * smax + j] = H11[(size_t)j * smax + j].real();
+    if ((r = cheb_cols(snew, s, q, mcomp)) != ADC2_OK) return r;
+    if ((r = dav_gram(Vd, snew, S1d + (long)s * ns, q, ns, Hd + s, JMAX, gsc, st)) != ADC2_OK) return r;
+    if ((r = fold_herm_fill(Hd, s, snew, st)) != ADC2_OK) return r;
     s = snew;
     return ADC2_OK;
   };
 
-  // orthonormalise rows of T against Vs[0..s) and among themselves; returns the kept count
-  auto orthonormalise = [&](std::vector<cplx>& T, int q) -> int {
-    std::vector<double> n0(q);
-    // against the space (two classical Gram-Schmidt passes, rows in parallel)
-    par_for(q, [&](int r) {
-      cplx* t = &T[(size_t)r * ns];
-      double a0 = 0.0;
-      for (long e = 0; e < ns; ++e) a0 += std::norm(t[e]);
-      n0[r] = std::sqrt(a0);
-      for (int pass = 0; pass < 2; ++pass) {
-        std::vector<cplx> a(s);
-        for (int i = 0; i < s; ++i) {
-          const cplx* v = &Vs[(size_t)i * ns];
-          cplx acc = 0.0;
-          for (long e = 0; e < ns; ++e) acc += std::conj(v[e]) * t[e];
-          a[i] = acc;
-        }
-        for (int i = 0; i < s; ++i) {
-          const cplx* v = &Vs[(size_t)i * ns];
-          for (long e = 0; e < ns; ++e) t[e] -= a[i] * v[e];
-        }
-      }
-    });
-    // among themselves (modified Gram-Schmidt, two passes)
-    int kept = 0;
-    for (int r = 0; r < q; ++r) {
-      cplx* t = &T[(size_t)r * ns];
-      if (!(n0[r] > 0.0) || !std::isfinite(n0[r])) continue;
-      for (int pass = 0; pass < 2; ++pass)
-        for (int i = 0; i < kept; ++i) {
-          const cplx* v = &T[(size_t)i * ns];
-          cplx a = 0.0;
-          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * t[e];
-          for (long e = 0; e < ns; ++e) t[e] -= a * v[e];
-        }
-      double n1 = 0.0;
-      for (long e = 0; e < ns; ++e) n1 += std::norm(t[e]);
-      n1 = std::sqrt(n1);
-      if (n1 <= 1e-10 * n0[r]) continue;
-      for (long e = 0; e < ns; ++e) t[e] /= n1;
-      if (kept != r) std::copy(t, t + ns, &T[(size_t)kept * ns]);
-      ++kept;
+  // orthonormalise rows 0..q-1 of Td against V[0..s) (two classical Gram-Schmidt passes, all rows at once)
+  // and among themselves (modified Gram-Schmidt, two passes, in row order); a row whose norm falls to
+  // 1e-10 of its initial norm is dropped; returns the kept count (rows 0..kept-1 of Td)
+  auto orthonormalise = [&](int q, int& kept) -> adc2_status {
+    kept = 0;
+    if (q <= 0) return ADC2_OK;
+    adc2_status r = fold_rownorm(Td, q, ns, lam, st);
+    if (r != ADC2_OK) return r;
+    for (int pass = 0; pass < 2 && s > 0; ++pass) {
+      if ((r = dav_gram(Vd, s, Td, q, ns, Cg, JMAX, gsc, st)) != ADC2_OK) return r;
+      if ((r = combine(Vd, s, Cg, JMAX, q, ns, Td, -1.0, true)) != ADC2_OK) return r;
     }
-    return kept;
+    if ((r = fold_mgs(Td, q, ns, lam, icount, st)) != ADC2_OK) return r;
+    return down(&kept, icount, sizeof(int));
   };
 
   // ---- initial space ----
-  std::vector<cplx> gref;   // singles of the followed guess vectors, as given
+  std::vector<double> gn(k, 0.0);
   {
-    std::vector<cplx> T((size_t)nguess * ns, cplx(0.0, 0.0));
     if (guess) {
-      FD_TRY(d2h_rows((const double2*)guess, nguess, T.data()));
-      if (follow) gref.assign(T.begin(), T.begin() + (size_t)k * ns);
+      k_rows_copy<<<rgrid, 256, 0, st>>>((const double2*)guess, dim, Td, ns, nguess, ns);
+      FD_HIP(hipGetLastError());
+      if (follow) {
+        // singles of the followed guess vectors, as given, and their squared norms
+        k_rows_copy<<<rgrid, 256, 0, st>>>((const double2*)guess, dim, gref, ns, k, ns);
+        FD_HIP(hipGetLastError());
+        FD_TRY(dav_gram(gref, k, gref, k, ns, Gw, JMAX, gsc, st));
+        std::vector<double2> g2((size_t)JMAX * JMAX);
+        FD_TRY(down(g2.data(), Gw, sizeof(double2) * JMAX * JMAX));
+        for (int j = 0; j < k; ++j) gn[j] = g2[(size_t)j * JMAX + j].x;
+        FD_TRY(up(gnd, gn.data(), sizeof(double) * k));
+      }
     } else {
       std::vector<int> idx(ns);
       for (long i = 0; i < ns; ++i) idx[i] = (int)i;
       std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d11[a] < d11[b]; });
-      for (int g = 0; g < nguess; ++g) T[(size_t)g * ns + idx[g]] = 1.0;
+      FD_TRY(up(ibuf, idx.data(), sizeof(int) * nguess));
+      FD_TRY(fold_unit(Td, nguess, ns, ibuf, st));
     }
-    const int q = orthonormalise(T, nguess);
+    int q = 0;
+    FD_TRY(orthonormalise(nguess, q));
     if (q < k) {
       cleanup_events();
+      hipStreamSynchronize(st);
       release();
       set_error("adc2_davidson (folded): the initial space has fewer vectors than roots");
       return ADC2_ERR_ARG;
     }
-    adc2_status r = add_vectors(T, q);
+    adc2_status r = add_vectors(q);
     if (r != ADC2_OK) {
       cleanup_events();
       hipStreamSynchronize(st);
@@ -858,18 +795,24 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     }
   }
 
-  std::vector<FoldRoot> roots(nbr);
-  for (int b = 0; b < nbr; ++b) roots[b].branch = b;
+  // projected roots (host side: the steering data; the vectors live in the device slots)
+  struct Root {
+    int branch = 0, slot = 0;   // eigenvalue index j of lambda_j(G(omega)) = omega; storage slot
+    int ysize = 0, zsize = 0;   // basis size of the vector / eigenvectors in the slot (0: none)
+    int status = 0, need = 0;
+    int clamped = 0;            // consecutive iterations with status 1 (held at the expansion limit)
+    double omega = 0.0, rq = 0.0, n2 = 0.0;
+  };
+  std::vector<Root> roots(nbr);
+  for (int b = 0; b < nbr; ++b) roots[b].branch = roots[b].slot = b;
   std::vector<char> prov(k, 0);   // root held at the expansion limit this iteration
-  std::vector<double> res(k, 1e300);
+  std::vector<double> res(k, 1e300), nrm(k, 1.0);
   bool have_omega = false, converged = false;
   int it = 0;
   // stagnation: the largest residual has not dropped below 0.8 of its best
   // value for FSTALL iterations (the precision form's noise floor)
   double best_rmax = 1e300;
   int best_it = 0;
-  std::vector<cplx> x1((size_t)k * ns), r1((size_t)k * ns), mx2((size_t)k * ns);
-  std::vector<double> nrm(k);
   const auto t_start = std::chrono::steady_clock::now();
   adc2_status final_rc = ADC2_OK;
   double tm_proj = 0.0, tm_res = 0.0, tm_new = 0.0;   // host-side phases (ms)
@@ -877,144 +820,51 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   auto ms_since = [](std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   };
+  std::vector<FoldEntry> ent(nbr);
+  std::vector<FoldResult> rres(nbr);
+  std::vector<double> hnp((size_t)k * nrb), hov((size_t)k * nbr);
+  std::vector<int> ib(FSMAX);
+  std::vector<double> hd(FSMAX);
 
   for (it = 1; it <= max_iter; ++it) {
-    // ---- projected nonlinear problem, one thread per root ----
+    // ---- projected nonlinear problem: one workgroup per root, lowest eigenvalue of H11 first ----
     const auto tp0 = now();
-    double lam_min;
-    {
-      std::vector<double> w(s);
-      std::vector<cplx> Z((size_t)s * s), Hs((size_t)s * s);
-      for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j) Hs[(size_t)i * s + j] = H11[(size_t)i * smax + j];
-      if (hostla::herm_eig(s, Hs.data(), w.data(), Z.data()) != 0) {
-        set_error("adc2_davidson (folded): the eigensolve of the projected singles block did not converge");
-        final_rc = ADC2_ERR_NOCONV;
-        break;
-      }
-      lam_min = w[0];
-    }
-    double T0 = 0.0;
-    for (int i = 0; i < s; ++i) T0 += K[(size_t)i * smax + i].real();
-    const double zb = 0.5 * (-(lam_min - Dmin) + std::sqrt((lam_min - Dmin) * (lam_min - Dmin) + 4.0 * std::max(T0, 0.0))) + 1.0;
-    const double lo0 = Dmin - zb;
+    FD_TRY(dav_heevj(Hd, s, JMAX, hw, Gw, JMAX, st));
     // a pole at |x| >= 1.05 has r = |x| - sqrt(x^2 - 1) < 0.73 and r^126 < 1e-17,
     // so at most 126 Chebyshev terms: with the shifted inverse, roots closer
     // to min D than about 0.025 (min D - w0) are out of reach of this solver
     double hi0 = rmap.reach(1.05);
-    double wlo = rmap.inv ? std::max(lo0, rmap.w0 + 0.1 * (Dmin - rmap.w0)) : lo0;   // lowest omega evaluated
-    auto solve_root = [&](int idx) {
-      FoldRoot& R = roots[idx];
-      const int j = R.branch;
-      if (j >= s) {   // fewer basis vectors than this branch index
-        R.status = 6;
-        return;
-      }
-      double wv = have_omega ? R.omega : wlo;
-      if (!(wv > wlo && wv < hi0)) wv = have_omega ? std::min(std::max(wv, wlo), hi0 - 1e-9 * std::fabs(hi0)) : wlo;
-      double lo = wlo, hi = hi0;
-      std::vector<double> b(FMM), e(FMM), w(s), gco(FMM), eco(FMM);
-      std::vector<cplx> G((size_t)s * s), Z((size_t)s * s), Zp;
-      // warm start from this root's last eigenvector basis, padded with the identity for the new vectors
-      const int zs = R.Z.empty() ? 0 : (int)std::lround(std::sqrt((double)R.Z.size()));
-      if (zs > 0 && zs <= s) {
-        Zp.assign((size_t)s * s, cplx(0.0, 0.0));
-        for (int i = 0; i < zs; ++i)
-          for (int l = 0; l < zs; ++l) Zp[(size_t)i * s + l] = R.Z[(size_t)i * zs + l];
-        for (int i = zs; i < s; ++i) Zp[(size_t)i * s + i] = 1.0;
-      }
-      R.status = 0;
-      for (int nit = 0; nit < 80; ++nit) {
-        // G = H11 + sum_m gco_m K_m,  |x2|^2 = y^H (sum_m eco_m K_m) y
-        const int M = rmap.coeffs(wv, FMM, b.data(), e.data(), gco.data(), eco.data());
-        if (M < 0) {
-          R.status = 2;
-          return;
-        }
-        if (M > FMB * mcomp) {
-          R.status = 3;
-          R.need = M;
-          return;
-        }
-        for (int i = 0; i < s; ++i)
-          for (int l = 0; l < s; ++l) {
-            cplx a = H11[(size_t)i * smax + l];
-            for (int m = 0; m < M; ++m) a += gco[m] * K[((size_t)m * smax + i) * smax + l];
-            G[(size_t)i * s + l] = a;
-          }
-        for (int i = 0; i < s; ++i) {
-          G[(size_t)i * s + i] = G[(size_t)i * s + i].real();
-          for (int l = i + 1; l < s; ++l) {
-            const cplx a = 0.5 * (G[(size_t)i * s + l] + std::conj(G[(size_t)l * s + i]));
-            G[(size_t)i * s + l] = a;
-            G[(size_t)l * s + i] = std::conj(a);
-          }
-        }
-        const int bad = Zp.empty() ? hostla::herm_eig(s, G.data(), w.data(), Z.data())
-                                   : hostla::herm_eig_warm(s, G.data(), Zp.data(), w.data(), Z.data());
-        if (bad != 0) {
-          R.status = 5;
-          return;
-        }
-        Zp = Z;
-        // |x2|^2 = y^H E y,  E = sum eco_m K_m
-        double n2 = 0.0;
-        {
-          std::vector<cplx> y(s);
-          for (int i = 0; i < s; ++i) y[i] = Z[(size_t)i * s + j];
-          cplx acc = 0.0;
-          for (int i = 0; i < s; ++i) {
-            cplx row = 0.0;
-            for (int l = 0; l < s; ++l) {
-              cplx kk = 0.0;
-              for (int m = 0; m < M; ++m) kk += eco[m] * K[((size_t)m * smax + i) * smax + l];
-              row += kk * y[l];
-            }
-            acc += std::conj(y[i]) * row;
-          }
-          n2 = acc.real();
-        }
-        const double f = w[j] - wv;
-        if (f > 0.0) lo = std::max(lo, wv);
-        else hi = std::min(hi, wv);
-        double wn = wv + f / (1.0 + std::max(n2, 0.0));
-        if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
-        // (wv, y) is an exact eigenpair of G(wv); its distance to the root is ~|wn - wv|, which only has
-        // to stay well below the residual tolerance of the outer iteration
-        const double wtol = std::min(1e-10, 1e-3 * tol) * std::max(1.0, std::fabs(wv));
-        const bool done = std::fabs(wn - wv) <= wtol || (hi - lo) <= 1e-15 * std::max(1.0, std::fabs(wv));
-        R.omega = wv;
-        R.rq = (w[j] + wv * std::max(n2, 0.0)) / (1.0 + std::max(n2, 0.0));
-        R.n2 = n2;
-        R.y.assign(s, 0.0);
-        for (int i = 0; i < s; ++i) R.y[i] = Z[(size_t)i * s + j];
-        R.Z = Z;
-        if (done) break;
-        wv = wn;
-      }
-      if (!(R.omega < hi0 - 1e-12 * std::fabs(hi0))) R.status = 1;
-      // the root lies below the lowest point the shifted map may evaluate
-      if (rmap.inv && wlo > lo0 && R.omega <= wlo + 1e-9 * std::max(1.0, std::fabs(wlo))) R.status = 4;
-    };
     for (int attempt = 0; attempt < 4; ++attempt) {
-      {
-        std::vector<std::thread> th;
-        for (int j = 1; j < nbr; ++j) th.emplace_back(solve_root, j);
-        solve_root(0);
-        for (auto& t : th) t.join();
+      for (int b = 0; b < nbr; ++b) {
+        const Root& R = roots[b];
+        ent[b] = FoldEntry{R.branch, R.slot, R.zsize, have_omega ? 1 : 0, R.omega};
       }
+      FD_TRY(up(entd, ent.data(), sizeof(FoldEntry) * nbr));
+      FD_TRY(fold_solve_launch(Hd, Kall, s, FMB * mcomp, fmap(), Dmin, hi0, tol, hw, entd, nbr, resd, Ybr, Zbr, bndd,
+                               st));
+      FD_TRY(down(rres.data(), resd, sizeof(FoldResult) * nbr));
       int need = 0;
       bool below = false;
-      for (int j = 0; j < nbr; ++j) {
-        if (roots[j].status == 3) need = std::max(need, roots[j].need);
-        if (roots[j].status == 4) below = true;
+      for (int b = 0; b < nbr; ++b) {
+        Root& R = roots[b];
+        const FoldResult& q = rres[b];
+        R.status = q.status;
+        R.need = q.need;
+        if (q.ysize == s) {
+          R.omega = q.omega;
+          R.rq = q.rq;
+          R.n2 = q.n2;
+          R.ysize = s;
+        }
+        if (q.zsize > 0) R.zsize = q.zsize;
+        if (R.status == 3) need = std::max(need, R.need);
+        if (R.status == 4) below = true;
       }
       if (below) {
         // a root below the shifted map's range: move the shift down (twice as
         // far from min D) and recompute the moments of the whole space
         rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, Dmin - 3.0 * (Dmin - rmap.w0));
         hi0 = rmap.reach(1.05);
-        wlo = std::max(lo0, rmap.w0 + 0.1 * (Dmin - rmap.w0));
         have_omega = false;
         FD_TRY(cheb_cols(s, 0, s, mcomp));
         continue;
@@ -1028,27 +878,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       // root j = the branch whose Ritz vector (x1 = V y, |x|^2 = 1 + |x2|^2)
       // overlaps most with the singles of guess j, assigned greedily in
       // decreasing order of overlap; the chosen entries move to the front
-      std::vector<cplx> pg((size_t)k * s);
-      std::vector<double> gn(k, 0.0);
-      par_for(k, [&](int j) {
-        const cplx* g = &gref[(size_t)j * ns];
-        for (long e = 0; e < ns; ++e) gn[j] += std::norm(g[e]);
-        for (int i = 0; i < s; ++i) {
-          const cplx* v = &Vs[(size_t)i * ns];
-          cplx a = 0.0;
-          for (long e = 0; e < ns; ++e) a += std::conj(v[e]) * g[e];
-          pg[(size_t)j * s + i] = a;
-        }
-      });
-      std::vector<double> ov((size_t)k * nbr, -1.0);
+      FD_TRY(dav_gram(Vd, s, gref, k, ns, PG, k, gsc, st));
+      FD_TRY(fold_overlap(PG, s, k, Ybr, entd, resd, nbr, gnd, ov, st));
+      FD_TRY(down(hov.data(), ov, sizeof(double) * k * nbr));
       for (int b = 0; b < nbr; ++b) {
-        const FoldRoot& R = roots[b];
-        if ((R.status != 0 && R.status != 1) || (int)R.y.size() != s) continue;
-        for (int j = 0; j < k; ++j) {
-          cplx a = 0.0;
-          for (int i = 0; i < s; ++i) a += std::conj(pg[(size_t)j * s + i]) * R.y[i];
-          ov[(size_t)j * nbr + b] = std::norm(a) / ((1.0 + std::max(R.n2, 0.0)) * std::max(gn[j], 1e-300));
-        }
+        const Root& R = roots[b];
+        if ((R.status != 0 && R.status != 1) || R.ysize != s)
+          for (int j = 0; j < k; ++j) hov[(size_t)j * nbr + b] = -1.0;
       }
       std::vector<int> sel(k, -1);
       std::vector<char> used(nbr, 0);
@@ -1058,8 +894,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         for (int j = 0; j < k; ++j) {
           if (sel[j] >= 0) continue;
           for (int b = 0; b < nbr; ++b)
-            if (!used[b] && ov[(size_t)j * nbr + b] > best) {
-              best = ov[(size_t)j * nbr + b];
+            if (!used[b] && hov[(size_t)j * nbr + b] > best) {
+              best = hov[(size_t)j * nbr + b];
               bj = j;
               bb = b;
             }
@@ -1067,7 +903,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         sel[bj] = bb;
         used[bb] = 1;
       }
-      std::vector<FoldRoot> re;
+      std::vector<Root> re;
       re.reserve(nbr);
       for (int j = 0; j < k; ++j) re.push_back(roots[sel[j]]);
       for (int b = 0; b < nbr; ++b)
@@ -1112,50 +948,32 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     const auto tr0 = now();
 
     // ---- Ritz vectors and residuals ----
-    std::vector<cplx> Yc((size_t)s * k);
-    std::vector<double> om(k);
     for (int j = 0; j < k; ++j) {
-      om[j] = roots[j].omega;
-      for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i];
+      ib[j] = roots[j].slot;
+      hd[j] = roots[j].omega;
       nrm[j] = std::sqrt(1.0 + std::max(roots[j].n2, 0.0));
     }
-    FD_TRY(h2d_small(Yd, Yc.data(), sizeof(double2) * s * k));
-    FD_TRY(h2d_small(omd, om.data(), sizeof(double) * k));
+    FD_TRY(up(ibuf, ib.data(), sizeof(int) * k));
+    FD_TRY(up(omd, hd.data(), sizeof(double) * k));
+    FD_TRY(fold_gather_y(Ybr, ibuf, nullptr, s, k, Yd, st));
     k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
                                                                                 X2 + ns, dim);
     FD_HIP(hipGetLastError());
     FD_TRY(sig_time(k, X2, Sx, SIGMA_DOUBLES_IN));
     n12 += k;
-    FD_TRY(d2h_rows(Sx, k, mx2.data()));
+    FD_TRY(fold_resid(Vd, S1d, s, ns, Yd, k, omd, Sx, dim, X1d, R1d, npart, st));
+    FD_TRY(down(hnp.data(), npart, sizeof(double) * k * nrb));
     double rmax = 0.0;
-    par_for(k, [&](int j) {
-      cplx* xj = &x1[(size_t)j * ns];
-      cplx* rj = &r1[(size_t)j * ns];
-      for (long e = 0; e < ns; ++e) {
-        xj[e] = 0.0;
-        rj[e] = mx2[(size_t)j * ns + e];
-      }
-      for (int i = 0; i < s; ++i) {
-        const cplx y = roots[j].y[i];
-        const cplx* v = &Vs[(size_t)i * ns];
-        const cplx* sv = &S1[(size_t)i * ns];
-        for (long e = 0; e < ns; ++e) {
-          xj[e] += y * v[e];
-          rj[e] += y * sv[e];
-        }
-      }
-      double rr = 0.0;
-      for (long e = 0; e < ns; ++e) {
-        rj[e] -= om[j] * xj[e];
-        rr += std::norm(rj[e]);
-      }
-      res[j] = std::sqrt(rr) / nrm[j];
-    });
-    for (int j = 0; j < k; ++j) rmax = std::max(rmax, res[j]);
+    for (int j = 0; j < k; ++j) {
+      double a = 0.0;
+      for (int b = 0; b < nrb; ++b) a += hnp[(size_t)j * nrb + b];
+      res[j] = std::sqrt(a) / nrm[j];
+      rmax = std::max(rmax, res[j]);
+    }
     tm_res += ms_since(tr0);
     if (verbose) {
       fprintf(stderr, "[adc2 folded no=%d nv=%d] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", dd.no, dd.nv, it,
-              s, rmax, om[0]);
+              s, rmax, roots[0].omega);
     }
     bool any_prov = false;
     for (int j = 0; j < k; ++j) any_prov = any_prov || prov[j];
@@ -1181,100 +999,45 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
 
     // ---- new directions: diagonal preconditioner on the singles ----
     const auto tn0 = now();
-    std::vector<cplx> T((size_t)k * ns);
     int q = 0;
     for (int j = 0; j < k; ++j) {
       if (res[j] <= tol && !prov[j]) continue;
-      cplx* t = &T[(size_t)q * ns];
-      for (long e = 0; e < ns; ++e) {
-        // approximate diagonal of the folded operator minus omega
-        double den = om[j] - d11[e];
-        const double gap = om[j] - pdb[e];
-        if (pnu[e] > 0.0 && std::fabs(gap) > 1e-12) den -= pnu[e] / gap;
-        if (std::fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
-        t[e] = r1[(size_t)j * ns + e] / den;
-      }
+      ib[q] = j;
+      hd[q] = roots[j].omega;
       ++q;
     }
+    FD_TRY(up(ibuf, ib.data(), sizeof(int) * q));
+    FD_TRY(up(scd, hd.data(), sizeof(double) * q));
+    FD_TRY(fold_newdir(R1d, ns, ibuf, scd, q, d11d, pnu_d, pdb_d, Td, st));
     // ---- restart: keep the Ritz singles of every root and the next ones of the highest root ----
     if (s + q > smax) {
       const int nk = std::min(keep_max, s);
-      std::vector<cplx> C((size_t)s * nk, 0.0);
-      for (int j = 0; j < k && j < nk; ++j)
-        for (int i = 0; i < s; ++i) C[(size_t)i * nk + j] = roots[j].y[i];
-      for (int c = k; c < nk; ++c)
-        for (int i = 0; i < s; ++i) C[(size_t)i * nk + c] = roots[k - 1].Z[(size_t)i * s + c];
-      // orthonormalise the columns of C (modified Gram-Schmidt, two passes)
+      for (int j = 0; j < k; ++j) ib[j] = roots[j].slot;
+      FD_TRY(up(ibuf, ib.data(), sizeof(int) * k));
+      FD_TRY(fold_restart_basis(Ybr, Zbr, ibuf, k, roots[k - 1].slot, s, nk, Cd, icount, st));
       int kc = 0;
-      for (int c = 0; c < nk; ++c) {
-        for (int pass = 0; pass < 2; ++pass)
-          for (int p = 0; p < kc; ++p) {
-            cplx a = 0.0;
-            for (int i = 0; i < s; ++i) a += std::conj(C[(size_t)i * nk + p]) * C[(size_t)i * nk + c];
-            for (int i = 0; i < s; ++i) C[(size_t)i * nk + c] -= a * C[(size_t)i * nk + p];
-          }
-        double nn = 0.0;
-        for (int i = 0; i < s; ++i) nn += std::norm(C[(size_t)i * nk + c]);
-        nn = std::sqrt(nn);
-        if (nn < 1e-8) continue;
-        for (int i = 0; i < s; ++i) C[(size_t)i * nk + kc] = C[(size_t)i * nk + c] / nn;
-        ++kc;
-      }
-      std::vector<cplx> Cc((size_t)s * kc);
-      for (int i = 0; i < s; ++i)
-        for (int c = 0; c < kc; ++c) Cc[(size_t)i * kc + c] = C[(size_t)i * nk + c];
-      FD_TRY(h2d_small(Cd, Cc.data(), sizeof(double2) * s * kc));
+      FD_TRY(down(&kc, icount, sizeof(int)));
+      // V, S1 (rows), H11 and every held K_m (C^H A C), the doubles parts U (in place)
+      FD_TRY(combine(Vd, s, Cd, kc, kc, ns, T2d, 1.0, false));
+      FD_HIP(hipMemcpyAsync(Vd, T2d, sizeof(double2) * kc * ns, hipMemcpyDeviceToDevice, st));
+      FD_TRY(combine(S1d, s, Cd, kc, kc, ns, T2d, 1.0, false));
+      FD_HIP(hipMemcpyAsync(S1d, T2d, sizeof(double2) * kc * ns, hipMemcpyDeviceToDevice, st));
+      FD_TRY(fold_rot_small(Hd, 0, 1, s, Cd, kc, st));
+      FD_TRY(fold_rot_small(Kall, (long)JMAX * JMAX, FMB * mcomp, s, Cd, kc, st));
       k_fold_rotate<<<(unsigned)((nd + 63) / 64), 256, 0, st>>>(Urw, dim, nd, s, Cd, kc);
       FD_HIP(hipGetLastError());
-      // Cc is pageable host memory local to this block: the copy must have
-      // consumed it before the block ends
-      FD_HIP(hipStreamSynchronize(st));
-      // host side: V, S1, H11, K
-      auto rot_rows = [&](std::vector<cplx>& A) {
-        std::vector<cplx> out((size_t)kc * ns, 0.0);
-        for (int c = 0; c < kc; ++c)
-          for (int i = 0; i < s; ++i) {
-            const cplx w = Cc[(size_t)i * kc + c];
-            if (w == cplx(0.0, 0.0)) continue;
-            for (long e = 0; e < ns; ++e) out[(size_t)c * ns + e] += w * A[(size_t)i * ns + e];
-          }
-        std::copy(out.begin(), out.end(), A.begin());
-      };
-      rot_rows(Vs);
-      rot_rows(S1);
-      auto rot_mat = [&](cplx* A) {   // A (s x s, ld smax) <- C^H A C
-        std::vector<cplx> T1((size_t)s * kc, 0.0), T2((size_t)kc * kc, 0.0);
-        for (int i = 0; i < s; ++i)
-          for (int c = 0; c < kc; ++c) {
-            cplx a = 0.0;
-            for (int l = 0; l < s; ++l) a += A[(size_t)i * smax + l] * Cc[(size_t)l * kc + c];
-            T1[(size_t)i * kc + c] = a;
-          }
-        for (int r = 0; r < kc; ++r)
-          for (int c = 0; c < kc; ++c) {
-            cplx a = 0.0;
-            for (int i = 0; i < s; ++i) a += std::conj(Cc[(size_t)i * kc + r]) * T1[(size_t)i * kc + c];
-            T2[(size_t)r * kc + c] = a;
-          }
-        for (int r = 0; r < kc; ++r)
-          for (int c = 0; c < kc; ++c) A[(size_t)r * smax + c] = T2[(size_t)r * kc + c];
-      };
-      rot_mat(H11.data());
-      for (int m = 0; m < FMB * mcomp; ++m) rot_mat(&K[(size_t)m * smax * smax]);
-      for (int j = 0; j < nbr; ++j) {
-        roots[j].y.clear();
-        roots[j].Z.clear();   // the basis changed: next solve starts cold
-      }
+      for (int j = 0; j < nbr; ++j) roots[j].ysize = roots[j].zsize = 0;   // the basis changed: next solve starts cold
       s = kc;
     }
-    const int qk = orthonormalise(T, q);
+    int qk = 0;
+    FD_TRY(orthonormalise(q, qk));
     if (qk == 0) {
       set_error("adc2_davidson (folded): no new search directions (stagnation)");
       final_rc = ADC2_ERR_NOCONV;
       break;
     }
     tm_new += ms_since(tn0);
-    FD_TRY(add_vectors(T, qk));
+    FD_TRY(add_vectors(qk));
   }
   if (verbose)
     fprintf(stderr,
@@ -1285,21 +1048,22 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   // ---- outputs ----
   if (final_rc == ADC2_OK || final_rc == ADC2_ERR_NOCONV) {
     for (int j = 0; j < k; ++j) omega[j] = roots[j].rq;
-    if (Xout && have_omega && !roots[0].y.empty() && (int)roots[0].y.size() == s) {
+    if (Xout && have_omega && roots[0].ysize == s) {
       double2* X = (double2*)Xout;
-      std::vector<cplx> Yc((size_t)s * k), xs((size_t)k * ns);
-      std::vector<double> om(k);
       for (int j = 0; j < k; ++j) {
-        om[j] = roots[j].omega;
-        for (int i = 0; i < s; ++i) Yc[(size_t)i * k + j] = roots[j].y[i] / nrm[j];
-        for (long e = 0; e < ns; ++e) xs[(size_t)j * ns + e] = x1[(size_t)j * ns + e] / nrm[j];
+        ib[j] = roots[j].slot;
+        hd[j] = roots[j].omega;
       }
-      FD_TRY(h2d_small(Yd, Yc.data(), sizeof(double2) * s * k));
-      FD_TRY(h2d_small(omd, om.data(), sizeof(double) * k));
+      std::vector<double> sc(k);
+      for (int j = 0; j < k; ++j) sc[j] = 1.0 / nrm[j];
+      FD_TRY(up(ibuf, ib.data(), sizeof(int) * k));
+      FD_TRY(up(omd, hd.data(), sizeof(double) * k));
+      FD_TRY(up(scd, sc.data(), sizeof(double) * k));
+      FD_TRY(fold_gather_y(Ybr, ibuf, scd, s, k, Yd, st));
       k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
                                                                                   X + ns, dim);
       FD_HIP(hipGetLastError());
-      FD_TRY(h2d_rows(xs.data(), k, X));
+      FD_TRY(fold_out_singles(X1d, ns, k, scd, X, dim, st));
     }
   }
   if (info) {

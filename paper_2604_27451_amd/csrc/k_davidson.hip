@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "jacobi.h"
 #include "tile.h"
 
 namespace adc2 {
@@ -277,175 +278,35 @@ adc2_status dav_unit_guess(double2* V, int g, long dim, const int* idx, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi for a complex Hermitian n x n matrix (n <= 64).
-// Reads the upper triangle of G (row-major, ldg), writes ascending
-// eigenvalues w[n] and eigenvectors as columns of Z (row-major, ldz).
-// Pair (p,q) rotation J = [[c, s e], [-s conj(e), c]], e = a_pq/|a_pq|,
-// t = sign(tau)/(|tau| + sqrt(1+tau^2)), tau = (a_qq - a_pp)/(2|a_pq|),
-// zeroes a_pq of J^H A J; all n/2 disjoint pairs of a round-robin round are
-// applied together.
+// Subspace eigensolve: the upper triangle of G (row-major, ldg) into LDS and
+// the parallel cyclic Jacobi of jacobi.h; ascending eigenvalues w[n] and
+// eigenvectors as columns of Z (row-major, ldz).
 // ---------------------------------------------------------------------------
-constexpr int JMAX = 64;
-
 __global__ __launch_bounds__(256) void k_heevj(const double2* __restrict__ G, int n, int ldg,
                                                 double* __restrict__ w, double2* __restrict__ Z, int ldz) {
-  __shared__ double ar[JMAX][JMAX];
-  __shared__ double ai[JMAX][JMAX];
-  __shared__ double2 zs[JMAX][JMAX];
-  __shared__ double rc[JMAX / 2], rs[JMAX / 2];
-  __shared__ double2 re[JMAX / 2];
-  __shared__ int rp[JMAX / 2], rq[JMAX / 2];
-  __shared__ double red[256];
-  __shared__ int done;
+  __shared__ JacobiSmem S;
   const int tid = threadIdx.x;
-  const int N = (n + 1) & ~1;   // even number of players (player n is a dummy if n is odd)
-  for (int e = tid; e < JMAX * JMAX; e += 256) {
-    const int i = e / JMAX, j = e % JMAX;
-    double x = 0, y = 0;
-    if (i < n && j < n) {
-      if (i <= j) {
-        const double2 g = G[(long)i * ldg + j];
-        x = g.x;
-        y = (i == j) ? 0.0 : g.y;
-      } else {
-        const double2 g = G[(long)j * ldg + i];
-        x = g.x;
-        y = -g.y;
-      }
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    double x, y;
+    if (i <= j) {
+      const double2 g = G[(long)i * ldg + j];
+      x = g.x;
+      y = (i == j) ? 0.0 : g.y;
+    } else {
+      const double2 g = G[(long)j * ldg + i];
+      x = g.x;
+      y = -g.y;
     }
-    ar[i][j] = x;
-    ai[i][j] = y;
-    zs[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    S.ar[i][j] = x;
+    S.ai[i][j] = y;
   }
   __syncthreads();
-  const int npair = N / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test: off-diagonal Frobenius norm vs full norm
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += 256) {
-      const int i = e / n, j = e % n;
-      const double v = ar[i][j] * ar[i][j] + ai[i][j] * ai[i][j];
-      tot += v;
-      if (i != j) off += v;
-    }
-    red[tid] = off;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) done = (offs <= 1e-30 * red[0] || offs == 0.0) ? 1 : 0;
-    __syncthreads();
-    if (done) break;
-    for (int round = 0; round < N - 1; ++round) {
-      if (tid < npair) {
-        // round-robin: player 0 fixed, players 1..N-1 rotate
-        int a, b;
-        if (tid == 0) {
-          a = 0;
-          b = 1 + (round % (N - 1));
-        } else {
-          a = 1 + ((round + tid) % (N - 1));
-          b = 1 + ((round + N - 1 - tid) % (N - 1));
-        }
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0, s = 0.0;
-        double2 ee = make_double2(1.0, 0.0);
-        if (q < n) {
-          const double br = ar[p][q], bi = ai[p][q];
-          const double mag = sqrt(br * br + bi * bi);
-          const double app = ar[p][p], aqq = ar[q][q];
-          if (mag > 1e-300 && mag > 1e-18 * (fabs(app) + fabs(aqq))) {
-            const double tau = (aqq - app) / (2.0 * mag);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            ee = make_double2(br / mag, bi / mag);
-          }
-        }
-        rp[tid] = p;
-        rq[tid] = q;
-        rc[tid] = c;
-        rs[tid] = s;
-        re[tid] = ee;
-      }
-      __syncthreads();
-      // column update A <- A J and Z <- Z J
-      for (int it = tid; it < npair * n; it += 256) {
-        const int pr = it / n, r = it % n;
-        const int p = rp[pr], q = rq[pr];
-        if (q >= n || rs[pr] == 0.0) continue;
-        const double c = rc[pr], s = rs[pr];
-        const double2 e = re[pr];
-        const double2 x = make_double2(ar[r][p], ai[r][p]);
-        const double2 y = make_double2(ar[r][q], ai[r][q]);
-        // new_p = c x - s conj(e) y ; new_q = s e x + c y
-        const double2 ny = cmul(cconj(e), y);
-        const double2 nx = cmul(e, x);
-        ar[r][p] = c * x.x - s * ny.x;
-        ai[r][p] = c * x.y - s * ny.y;
-        ar[r][q] = s * nx.x + c * y.x;
-        ai[r][q] = s * nx.y + c * y.y;
-        const double2 zx = zs[r][p], zy = zs[r][q];
-        const double2 zny = cmul(cconj(e), zy);
-        const double2 znx = cmul(e, zx);
-        zs[r][p] = make_double2(c * zx.x - s * zny.x, c * zx.y - s * zny.y);
-        zs[r][q] = make_double2(s * znx.x + c * zy.x, s * znx.y + c * zy.y);
-      }
-      __syncthreads();
-      // row update A <- J^H A : new_p = c x - s e y ; new_q = s conj(e) x + c y
-      for (int it = tid; it < npair * n; it += 256) {
-        const int pr = it / n, r = it % n;
-        const int p = rp[pr], q = rq[pr];
-        if (q >= n || rs[pr] == 0.0) continue;
-        const double c = rc[pr], s = rs[pr];
-        const double2 e = re[pr];
-        const double2 x = make_double2(ar[p][r], ai[p][r]);
-        const double2 y = make_double2(ar[q][r], ai[q][r]);
-        const double2 ey = cmul(e, y);
-        const double2 cx = cmul(cconj(e), x);
-        ar[p][r] = c * x.x - s * ey.x;
-        ai[p][r] = c * x.y - s * ey.y;
-        ar[q][r] = s * cx.x + c * y.x;
-        ai[q][r] = s * cx.y + c * y.y;
-      }
-      __syncthreads();
-      if (tid < npair) {
-        const int p = rp[tid], q = rq[tid];
-        if (q < n && rs[tid] != 0.0) {
-          ar[p][q] = ai[p][q] = ar[q][p] = ai[q][p] = 0.0;
-          ai[p][p] = ai[q][q] = 0.0;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // sort ascending (selection by one thread; n <= 64)
-  __shared__ int perm[JMAX];
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) perm[i] = i;
-    for (int i = 0; i < n; ++i) {
-      int best = i;
-      for (int j = i + 1; j < n; ++j)
-        if (ar[perm[j]][perm[j]] < ar[perm[best]][perm[best]]) best = j;
-      const int t = perm[i];
-      perm[i] = perm[best];
-      perm[best] = t;
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += 256) w[i] = ar[perm[i]][perm[i]];
+  jacobi_lds(S, n);
+  for (int i = tid; i < n; i += 256) w[i] = S.ar[S.perm[i]][S.perm[i]];
   for (int e = tid; e < n * n; e += 256) {
     const int r = e / n, c = e % n;
-    Z[(long)r * ldz + c] = zs[r][perm[c]];
+    Z[(long)r * ldz + c] = S.zs[r][S.perm[c]];
   }
 }
 
