@@ -642,7 +642,13 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   }
   if (west < Dmin && std::isfinite(west))
     rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, west - std::max(1.0, 0.5 * (Dmin - west)));
-  auto fmap = [&]() { return FoldMap{rmap.inv ? 1 : 0, rmap.c, rmap.ih, rmap.w0}; };
+  // Truncation of the resolvent expansion: to FP64 rounding for the FP64
+  // sigma; with the complex64 and split-BF16 contractions (relative sigma
+  // noise ~1e-7 and ~1e-6, residual tolerances 1e-3 .. 1e-5) 1e-10 is far
+  // below that noise and needs about 0.6 times the terms.
+  const double exp_tol = h->prec == ADC2_FP64 ? 1e-17 : 1e-10;
+  rmap.tol = exp_tol;
+  auto fmap = [&]() { return FoldMap{rmap.inv ? 1 : 0, rmap.c, rmap.ih, rmap.w0, rmap.tol}; };
 
   int s = 0;
   long n21 = 0, n12 = 0;
@@ -864,6 +870,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
         // a root below the shifted map's range: move the shift down (twice as
         // far from min D) and recompute the moments of the whole space
         rmap = hostla::ResolventMap::shifted_inverse(Dmin, Dmax, Dmin - 3.0 * (Dmin - rmap.w0));
+        rmap.tol = exp_tol;
         hi0 = rmap.reach(1.05);
         have_omega = false;
         FD_TRY(cheb_cols(s, 0, s, mcomp));

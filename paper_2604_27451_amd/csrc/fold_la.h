@@ -17,6 +17,7 @@ constexpr int FOLD_MM = 128;   // largest number of Chebyshev terms of the resol
 struct FoldMap {
   int inv;
   double c, ih, w0;
+  double tol;   // truncation of the expansion (terms until r^m < tol)
 };
 
 // One projected root to solve (host -> device): branch index, storage slot of

@@ -57,7 +57,7 @@ __device__ int fold_cheb_resolvent(double x, int mmax, double* b, double* e, dou
 
 __device__ int fold_coeffs(const FoldMap& r, double omega, int mmax, double* b, double* e, double* g, double* h) {
   if (!r.inv) {
-    const int M = fold_cheb_resolvent((omega - r.c) * r.ih, mmax, b, e, 1e-17);
+    const int M = fold_cheb_resolvent((omega - r.c) * r.ih, mmax, b, e, r.tol);
     for (int m = 0; m < M; ++m) {
       g[m] = b[m] * r.ih;
       h[m] = e[m] * r.ih * r.ih;
@@ -66,7 +66,7 @@ __device__ int fold_coeffs(const FoldMap& r, double omega, int mmax, double* b, 
   }
   if (!(omega > r.w0)) return -1;
   const double vs = 1.0 / (omega - r.w0);
-  const int M = fold_cheb_resolvent((vs - r.c) * r.ih, mmax, b, e, 1e-17 * fmin(1.0, r.c / vs));
+  const int M = fold_cheb_resolvent((vs - r.c) * r.ih, mmax, b, e, r.tol * fmin(1.0, r.c / vs));
   const double g1 = vs * vs * r.ih, h1 = 2.0 * vs * vs * vs * r.ih, h2 = vs * vs * vs * vs * r.ih * r.ih;
   for (int m = 0; m < M; ++m) {
     g[m] = -g1 * b[m];

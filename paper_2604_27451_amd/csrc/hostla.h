@@ -234,6 +234,7 @@ inline int cheb_resolvent(double x, int mmax, double* b, double* e, double tol =
 struct ResolventMap {
   bool inv = false;
   double c = 0.0, ih = 1.0, w0 = 0.0;   // tau = (v - c) * ih
+  double tol = 1e-17;                   // truncation: terms until r^m < tol (scaled for the shifted map)
 
   static ResolventMap linear(double Dmin, double Dmax) {
     ResolventMap r;
@@ -257,7 +258,7 @@ struct ResolventMap {
   // more than mmax are needed or omega is not below the interval
   int coeffs(double omega, int mmax, double* b, double* e, double* g, double* h) const {
     if (!inv) {
-      const int M = cheb_resolvent((omega - c) * ih, mmax, b, e);
+      const int M = cheb_resolvent((omega - c) * ih, mmax, b, e, tol);
       for (int m = 0; m < M; ++m) {
         g[m] = b[m] * ih;
         h[m] = e[m] * ih * ih;
@@ -267,7 +268,7 @@ struct ResolventMap {
     if (!(omega > w0)) return -1;
     const double vs = 1.0 / (omega - w0);
     // the truncated tail is scaled by v*^2 / hw relative to the linear case
-    const int M = cheb_resolvent((vs - c) * ih, mmax, b, e, 1e-17 * std::min(1.0, c / vs));
+    const int M = cheb_resolvent((vs - c) * ih, mmax, b, e, tol * std::min(1.0, c / vs));
     // (omega - D)^-1 = v* - (v*^2/hw) sum b T;  (omega - D)^-2 = v*^2 - 2 (v*^3/hw) sum b T + (v*^4/hw^2) sum e T
     const double g1 = vs * vs * ih, h1 = 2.0 * vs * vs * vs * ih, h2 = vs * vs * vs * vs * ih * ih;
     for (int m = 0; m < M; ++m) {
