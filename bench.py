@@ -910,7 +910,7 @@ def run_headline(args, A, np, torch):
     # The handle keeps its own blocks of L, so the input is released after
     # each setup (the solve's search space needs the room) and uploaded again
     # from a pinned host copy, untimed, before the next leg.
-    kw = dict(max_iter=args.max_iter, solver=fold, max_subspace=args.max_subspace or 48,
+    kw = dict(max_iter=args.max_iter, solver=fold, max_subspace=args.max_subspace,
               nguess=args.nguess or nroots, raise_on_noconv=False, verbose=1 if args.verbose else 0)
     Lhost = torch.empty(L.shape, dtype=L.dtype, pin_memory=True)
     Lhost.copy_(L)

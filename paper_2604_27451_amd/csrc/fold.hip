@@ -533,10 +533,15 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   // sigma rows: Sb = sigma of the basis (v, 0), singles part S1 and doubles part U = M21 v
   double2 *Sb, *Tin, *X2, *Sx, *Kt, *part, *Yd, *Cd;
   FD_TRY(dalloc((void**)&Sb, sizeof(double2) * smax * dim));
+  // One block of full-length rows serves three roles in disjoint parts: the
+  // singles of the new directions (input of the singles-in sigma, which does
+  // not read input doubles), the Ritz doubles x2 (input of the doubles-in
+  // sigma, which does not read input singles) and its output M12 x2 (singles
+  // only: the doubles-in sigma writes no output doubles).
   const int qmax = std::max(nguess, k);   // rows of one sigma input block (new directions never exceed it)
   FD_TRY(dalloc((void**)&Tin, sizeof(double2) * qmax * dim));
-  FD_TRY(dalloc((void**)&X2, sizeof(double2) * k * dim));
-  FD_TRY(dalloc((void**)&Sx, sizeof(double2) * k * dim));
+  X2 = Tin;
+  Sx = Tin;
   FD_TRY(dalloc((void**)&Kt, sizeof(double2) * FMM * smax * FGB));
   FD_TRY(dalloc((void**)&part, sizeof(double2) * part_len));
   FD_TRY(dalloc((void**)&Yd, sizeof(double2) * FSMAX * FSMAX));
