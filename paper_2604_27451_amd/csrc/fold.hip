@@ -639,10 +639,14 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   // a root falls below w0 + 0.1 (Dmin - w0).  The linear variable remains
   // for an estimate that is not below Dmin.
   hostla::ResolventMap rmap = hostla::ResolventMap::linear(Dmin, Dmax);
+  // per singles e, the lower root of omega = d11_e + nu_e / (omega - Dbar_e): the
+  // folded diagonal's estimate of the root that single e dominates
+  std::vector<double> rest(ns);
   double west = 1e300;
   for (long e = 0; e < ns; ++e) {
     const double a = d11[e], bb = pdb[e], nu = pnu[e];
     const double r = nu > 0.0 ? 0.5 * ((a + bb) - std::sqrt((a - bb) * (a - bb) + 4.0 * nu)) : a;
+    rest[e] = std::isfinite(r) ? r : 1e300;
     west = std::min(west, r);
   }
   if (west < Dmin && std::isfinite(west))
@@ -784,7 +788,8 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     } else {
       std::vector<int> idx(ns);
       for (long i = 0; i < ns; ++i) idx[i] = (int)i;
-      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d11[a] < d11[b]; });
+      // unit vectors on the singles of lowest folded-diagonal root estimate
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return rest[a] < rest[b]; });
       FD_TRY(up(ibuf, idx.data(), sizeof(int) * nguess));
       FD_TRY(fold_unit(Td, nguess, ns, ibuf, st));
     }
