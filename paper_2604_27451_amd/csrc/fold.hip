@@ -576,7 +576,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   FD_TRY(dalloc((void**)&mm, sizeof(double) * 2 * 256));
   int *icount, *ibuf;
   FD_TRY(dalloc((void**)&icount, sizeof(int) * 4));
-  FD_TRY(dalloc((void**)&ibuf, sizeof(int) * FSMAX));
+  FD_TRY(dalloc((void**)&ibuf, sizeof(int) * 2 * FSMAX));
   FoldEntry* entd;
   FoldResult* resd;
   FoldBounds* bndd;
@@ -823,6 +823,7 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
   for (int b = 0; b < nbr; ++b) roots[b].branch = roots[b].slot = b;
   std::vector<char> prov(k, 0);   // root held at the expansion limit this iteration
   std::vector<double> res(k, 1e300), nrm(k, 1.0);
+  bool res_valid = false;   // res holds an evaluation for every root
   bool have_omega = false, converged = false;
   int it = 0;
   // stagnation: the largest residual has not dropped below 0.8 of its best
@@ -965,32 +966,59 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
     const auto tr0 = now();
 
     // ---- Ritz vectors and residuals ----
+    // Residuals are evaluated for the roots not converged at their last
+    // evaluation (M12 x2, the expensive half, only for those); when all of
+    // those converge, the rest are evaluated at once with the same Ritz
+    // vectors, so convergence is always declared on a pass over every root.
+    // Root following re-selects roots each iteration: every root, always.
+    for (int j = 0; j < k; ++j) nrm[j] = std::sqrt(1.0 + std::max(roots[j].n2, 0.0));
+    auto eval_res = [&](const std::vector<int>& sel) -> adc2_status {
+      const int qa = (int)sel.size();
+      if (qa == 0) return ADC2_OK;
+      std::vector<int> sl(qa);
+      for (int c = 0; c < qa; ++c) {
+        sl[c] = roots[sel[c]].slot;
+        hd[c] = roots[sel[c]].omega;
+      }
+      adc2_status r = up(ibuf, sl.data(), sizeof(int) * qa);
+      if (r == ADC2_OK) r = up(ibuf + FSMAX, sel.data(), sizeof(int) * qa);
+      if (r == ADC2_OK) r = up(omd, hd.data(), sizeof(double) * qa);
+      if (r == ADC2_OK) r = fold_gather_y(Ybr, ibuf, nullptr, s, qa, Yd, st);
+      if (r != ADC2_OK) return r;
+      k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, qa, omd,
+                                                                                  Ddev, X2 + ns, dim);
+      ADC2_CHECK_LAUNCH();
+      if ((r = sig_time(qa, X2, Sx, SIGMA_DOUBLES_IN)) != ADC2_OK) return r;
+      n12 += qa;
+      if ((r = fold_resid(Vd, S1d, s, ns, Yd, qa, omd, Sx, dim, ibuf + FSMAX, X1d, R1d, npart, st)) != ADC2_OK)
+        return r;
+      if ((r = down(hnp.data(), npart, sizeof(double) * qa * nrb)) != ADC2_OK) return r;
+      for (int c = 0; c < qa; ++c) {
+        double a = 0.0;
+        for (int b = 0; b < nrb; ++b) a += hnp[(size_t)c * nrb + b];
+        res[sel[c]] = std::sqrt(a) / nrm[sel[c]];
+      }
+      return ADC2_OK;
+    };
+    std::vector<int> act, rest;
     for (int j = 0; j < k; ++j) {
-      ib[j] = roots[j].slot;
-      hd[j] = roots[j].omega;
-      nrm[j] = std::sqrt(1.0 + std::max(roots[j].n2, 0.0));
+      if (follow || !res_valid || res[j] > tol || prov[j]) act.push_back(j);
+      else rest.push_back(j);
     }
-    FD_TRY(up(ibuf, ib.data(), sizeof(int) * k));
-    FD_TRY(up(omd, hd.data(), sizeof(double) * k));
-    FD_TRY(fold_gather_y(Ybr, ibuf, nullptr, s, k, Yd, st));
-    k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
-                                                                                X2 + ns, dim);
-    FD_HIP(hipGetLastError());
-    FD_TRY(sig_time(k, X2, Sx, SIGMA_DOUBLES_IN));
-    n12 += k;
-    FD_TRY(fold_resid(Vd, S1d, s, ns, Yd, k, omd, Sx, dim, X1d, R1d, npart, st));
-    FD_TRY(down(hnp.data(), npart, sizeof(double) * k * nrb));
+    if (act.empty()) act.swap(rest);
+    FD_TRY(eval_res(act));
+    res_valid = true;
+    {
+      bool act_ok = true;
+      for (int j : act) act_ok = act_ok && res[j] <= tol && !prov[j];
+      if (act_ok && !rest.empty()) FD_TRY(eval_res(rest));   // certificate pass over the converged ones
+    }
     double rmax = 0.0;
-    for (int j = 0; j < k; ++j) {
-      double a = 0.0;
-      for (int b = 0; b < nrb; ++b) a += hnp[(size_t)j * nrb + b];
-      res[j] = std::sqrt(a) / nrm[j];
-      rmax = std::max(rmax, res[j]);
-    }
+    for (int j = 0; j < k; ++j) rmax = std::max(rmax, res[j]);
     tm_res += ms_since(tr0);
     if (verbose) {
-      fprintf(stderr, "[adc2 folded no=%d nv=%d] it %3d  space %2d  max|r| %.3e  omega0 %.12f\n", dd.no, dd.nv, it,
-              s, rmax, roots[0].omega);
+      fprintf(stderr, "[adc2 folded no=%d nv=%d] it %3d  space %2d  max|r| %.3e  omega0 %.12f  (%d evaluated)\n",
+              dd.no, dd.nv, it, s, rmax, roots[0].omega, (int)act.size());
     }
     bool any_prov = false;
     for (int j = 0; j < k; ++j) any_prov = any_prov || prov[j];
@@ -1080,7 +1108,10 @@ adc2_status fold_davidson(adc2_handle h, int k, const adc2_dav_opts* opt, const 
       k_fold_x2<<<(unsigned)std::min<long>(16384, (nd + 255) / 256), 256, 0, st>>>(Uro, dim, nd, s, Yd, k, omd, Ddev,
                                                                                   X + ns, dim);
       FD_HIP(hipGetLastError());
-      FD_TRY(fold_out_singles(X1d, ns, k, scd, X, dim, st));
+      // singles x1 / |x| = V y / |x| of the final Ritz vectors
+      FD_TRY(combine(Vd, s, Yd, k, k, ns, T2d, 1.0, false));
+      k_rows_copy<<<rgrid, 256, 0, st>>>(T2d, ns, X, dim, k, ns);
+      FD_HIP(hipGetLastError());
     }
   }
   if (info) {

@@ -47,7 +47,8 @@ adc2_status fold_gather_y(const double2* Ybr, const int* slot, const double* sca
                           hipStream_t st);
 int fold_resid_blocks(long ns);
 adc2_status fold_resid(const double2* V, const double2* S1, int s, long ns, const double2* Y, int q, const double* om,
-                       const double2* Sx, long ldx, double2* X1, double2* R1, double* npart, hipStream_t st);
+                       const double2* Sx, long ldx, const int* row, double2* X1, double2* R1, double* npart,
+                       hipStream_t st);
 adc2_status fold_newdir(const double2* R1, long ns, const int* root, const double* om, int q, const double* d11,
                         const double* pnu, const double* pdb, double2* T, hipStream_t st);
 adc2_status fold_unit(double2* T, int q, long ns, const int* idx, hipStream_t st);

@@ -322,16 +322,19 @@ __global__ void k_fold_gather_y(const double2* __restrict__ Ybr, const int* __re
   }
 }
 
-// x1[j] = V y_j,  r1[j] = S1 y_j + Sx[j] - om_j x1[j]  (Sx: the M12 x2 part, singles of rows with
-// stride ldx); npart[j][blk] = the block's share of |r1[j]|^2.  Grid (blocks over e, q roots).
+// For the c-th of q roots (grid (blocks over e, q)): x1 = V y_c, r1 = S1 y_c + Sx[c] - om_c x1 (Sx: the
+// M12 x2 part, singles of rows with stride ldx), written to row row[c] of X1 and R1 (row c without a
+// row list); npart[c][blk] = the block's share of |r1|^2.
 __global__ __launch_bounds__(256) void k_fold_resid(const double2* __restrict__ V, const double2* __restrict__ S1,
                                                      int s, long ns, const double2* __restrict__ Y, int q,
                                                      const double* __restrict__ om, const double2* __restrict__ Sx,
-                                                     long ldx, double2* __restrict__ X1, double2* __restrict__ R1,
+                                                     long ldx, const int* __restrict__ row,
+                                                     double2* __restrict__ X1, double2* __restrict__ R1,
                                                      double* __restrict__ npart) {
   __shared__ double2 yc[JMAX];
   __shared__ double red[256];
   const int j = blockIdx.y;
+  const long orow = row ? row[j] : j;
   for (int i = threadIdx.x; i < s; i += 256) yc[i] = Y[(long)i * q + j];
   __syncthreads();
   double acc = 0.0;
@@ -343,8 +346,8 @@ __global__ __launch_bounds__(256) void k_fold_resid(const double2* __restrict__ 
     }
     r.x -= om[j] * x.x;
     r.y -= om[j] * x.y;
-    X1[(long)j * ns + e] = x;
-    R1[(long)j * ns + e] = r;
+    X1[orow * ns + e] = x;
+    R1[orow * ns + e] = r;
     acc += r.x * r.x + r.y * r.y;
   }
   red[threadIdx.x] = acc;
@@ -622,9 +625,11 @@ adc2_status fold_gather_y(const double2* Ybr, const int* slot, const double* sca
 int fold_resid_blocks(long ns) { return (int)std::max<long>(1, std::min<long>(256, (ns + 1023) / 1024)); }
 
 adc2_status fold_resid(const double2* V, const double2* S1, int s, long ns, const double2* Y, int q, const double* om,
-                       const double2* Sx, long ldx, double2* X1, double2* R1, double* npart, hipStream_t st) {
+                       const double2* Sx, long ldx, const int* row, double2* X1, double2* R1, double* npart,
+                       hipStream_t st) {
+  if (q <= 0) return ADC2_OK;
   dim3 g(fold_resid_blocks(ns), q);
-  k_fold_resid<<<g, 256, 0, st>>>(V, S1, s, ns, Y, q, om, Sx, ldx, X1, R1, npart);
+  k_fold_resid<<<g, 256, 0, st>>>(V, S1, s, ns, Y, q, om, Sx, ldx, row, X1, R1, npart);
   ADC2_CHECK_LAUNCH();
   return ADC2_OK;
 }
