@@ -52,8 +52,6 @@ adc2_status fold_resid(const double2* V, const double2* S1, int s, long ns, cons
 adc2_status fold_newdir(const double2* R1, long ns, const int* root, const double* om, int q, const double* d11,
                         const double* pnu, const double* pdb, double2* T, hipStream_t st);
 adc2_status fold_unit(double2* T, int q, long ns, const int* idx, hipStream_t st);
-adc2_status fold_out_singles(const double2* X1, long ns, int q, const double* scale, double2* X, long ldx,
-                             hipStream_t st);
 adc2_status fold_herm_fill(double2* H, int s, int snew, hipStream_t st);
 adc2_status fold_cheb_scatter(const double2* Kt, int mm, int srows, int c0, int qc, double2* K, hipStream_t st);
 adc2_status fold_overlap(const double2* PG, int s, int k, const double2* Ybr, const FoldEntry* ent,

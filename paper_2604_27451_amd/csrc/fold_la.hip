@@ -379,17 +379,6 @@ __global__ void k_fold_newdir(const double2* __restrict__ R1, long ns, const int
   }
 }
 
-// X[c][e] = scale_c X1[c][e] for e < ns (rows of X with stride ldx): the singles of the returned vectors
-__global__ void k_fold_out_singles(const double2* __restrict__ X1, long ns, int q, const double* __restrict__ scale,
-                                   double2* __restrict__ X, long ldx) {
-  const long total = (long)q * ns;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / ns);
-    const long e = t - (long)c * ns;
-    X[(long)c * ldx + e] = cscale(X1[t], scale[c]);
-  }
-}
-
 // rows r < q of T (ld ns): unit vectors at idx[r]
 __global__ void k_fold_unit(double2* __restrict__ T, int q, long ns, const int* __restrict__ idx) {
   const long total = (long)q * ns;
@@ -639,14 +628,6 @@ adc2_status fold_newdir(const double2* R1, long ns, const int* root, const doubl
   const long total = (long)q * ns;
   k_fold_newdir<<<(unsigned)std::min<long>(4096, (total + 255) / 256), 256, 0, st>>>(R1, ns, root, om, q, d11, pnu,
                                                                                        pdb, T);
-  ADC2_CHECK_LAUNCH();
-  return ADC2_OK;
-}
-
-adc2_status fold_out_singles(const double2* X1, long ns, int q, const double* scale, double2* X, long ldx,
-                             hipStream_t st) {
-  const long total = (long)q * ns;
-  k_fold_out_singles<<<(unsigned)std::min<long>(4096, (total + 255) / 256), 256, 0, st>>>(X1, ns, q, scale, X, ldx);
   ADC2_CHECK_LAUNCH();
   return ADC2_OK;
 }
