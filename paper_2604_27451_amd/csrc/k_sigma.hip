@@ -718,7 +718,7 @@ __global__ __launch_bounds__(256) void k_light1(const TI* __restrict__ Rt, const
 // One workgroup per (g = (m,I,j), 32x32 tile pair ab <= bb); the mirror tile
 // is staged in LDS so that both reads of Z are coalesced.
 constexpr int PT = 32;
-constexpr int PK = 16;   // core spinors staged in LDS by the pack kernel
+constexpr int PK = 8;    // core spinors staged in LDS by the pack kernel (more read from global memory)
 template <class TZ>
 __global__ __launch_bounds__(256) void k_pack2(const TZ* __restrict__ Z, const double2* __restrict__ xin,
                                                 double2* __restrict__ sout, long dim, const double2* __restrict__ Vt,
