@@ -2,31 +2,38 @@
 """Benchmark: sigma-build complex TFLOP/s and time-to-N-roots of the CVS-ADC(2)
 hot path on one MI355X, FP64 and mixed precision side by side.
 
-One step = the whole hot path on one synthetic system already resident in
-HBM (nc=6, no=60, nv=300, naux=1500, complex128: the 3d-transition-metal-
-compound-sized configuration, 10 roots):
-  1. adc2_setup: Cholesky-block slicing, MP2 amplitudes, singles block (FP64)
-  2. FP64 roots: adc2_davidson, folded solver, residual tolerance 1e-8
-  3. adjoint: adc2_omega_backward for the 10 roots (unit weights)
-  4. mixed roots: split-BF16 heavy contractions on the BF16 MFMA (each
-     complex64 operand as hi + lo bf16, three products), folded solver to
-     residual 1e-3, then the FP64 Rayleigh quotients of those vectors
-     (adc2_rayleigh); the same with complex64 operands on the FP32 MFMA to
-     residual 1e-5 is reported as mixed_c64
-Every sigma build inside 2 and 4 is timed per kernel with HIP events on the
-stream it is launched on.
+Default (`--workload headline`): the heavy-element-complex-sized system
+nc=6, no=120, nv=600, naux=3000 (complex128, 10 roots, dim 129,387,600),
+drawn on the device and resident in HBM before anything is timed.
+
+One step = one sigma build of 10 vectors in each of FP64, complex64 (FP32
+MFMA) and split-BF16 (BF16 MFMA, hi + lo operands, three products), every
+kernel timed with HIP events on the stream it is launched on.  Once per
+invocation, outside the timed steps:
+  time_to_roots  from a fresh adc2_setup each (the input L released after
+                 it): FP64 roots through split-BF16 (adc2_davidson with
+                 mixed_tol = 1e-4, then FP64 to residual 1e-8), and
+                 split-BF16 roots to residual 1e-3 followed by their FP64
+                 Rayleigh quotients, with the eV error per root
+  roots_vs_oracle_c1  both forms against the CPU oracle's roots at
+                 nc=6, no=10, nv=40, naux=150
+  c2             the whole path at nc=6, no=60, nv=300, naux=1500: setup,
+                 FP64 folded solve, adjoint, two-stage solve, split-BF16 and
+                 complex64 solves with FP64 Rayleigh quotients
+  cpu_baseline   the CPU oracle timed on a bounded sample of the workload
 
 Printed JSON line:
   value          FP64 sigma-build complex TFLOP/s over the timed steps
                  (algorithmic flops, 8 per complex multiply-add, / HIP-event
                  time of the sigma builds)
-  ms_per_step    wall time of one step (1-4)
-  time_to_roots  FP64: setup + solve; mixed: setup + solve + FP64 polish
-  mixed          the same for the precision form, with |omega_mixed -
-                 omega_FP64| in eV per root (raw and after the FP64 polish)
-  roofline       the dominant FP64 sigma kernel: algorithmic flops per launch
-                 / mean launch time, against the FP64 matrix peak
-  cpu_baseline   the CPU oracle timed on a bounded sample of the same workload
+  ms_per_step    wall time of one step (three sigma builds)
+  roofline       the dominant FP64 sigma kernel (the Y-build): algorithmic
+                 flops per launch / mean launch time, against the FP64 matrix
+                 peak, with its hardware-counter HBM traffic per launch
+  sigma          per form: time, complex TFLOP/s, roofline record, per-kernel
+                 times
+Other workloads: pipeline (the whole path at one configuration), batch,
+fd, peaks, transition.
 """
 from __future__ import annotations
 
