@@ -141,13 +141,18 @@ __global__ __launch_bounds__(256) void k_cheb_mfma(const double2* __restrict__ U
         else uj[row - nrow][e] = pf[k];
       }
     }
-    if (tid < MKC) {   // T_m(t_d), m0 <= m < m0 + NM: two cosines, then the three-term recurrence
+    if (tid < MKC) {   // T_m(t_d), m0 <= m < m0 + NM: T_m0, T_m0+1, then the three-term recurrence
       double tv[NM];
       if (e0 + tid < nd) {
         const double x = fmin(1.0, fmax(-1.0, ((inv ? 1.0 / (dnext - w0) : dnext) - c) * ih));
-        const double th = acos(x);
-        tv[0] = cos((double)m0 * th);
-        tv[1] = cos((double)(m0 + 1) * th);
+        if (m0 == 0) {   // the first slice (every pass with at most NM moments): T_0 = 1, T_1 = x
+          tv[0] = 1.0;
+          tv[1] = x;
+        } else {
+          const double th = acos(x);
+          tv[0] = cos((double)m0 * th);
+          tv[1] = cos((double)(m0 + 1) * th);
+        }
 #pragma unroll
         for (int q = 2; q < NM; ++q) tv[q] = 2.0 * x * tv[q - 1] - tv[q - 2];
       } else {
