@@ -104,3 +104,38 @@ def test_folded_precision_form_c1():
     assert np.abs(np.array(w32) - w64).max() * ev < 1e-3
     assert np.abs(np.array(wp) - w64).max() < 1e-6
     h.close()
+
+
+def test_folded_restarts_and_single_root():
+    """Small search spaces force a restart every iteration or two (restart
+    basis, rotation of V, S1, H11, every moment matrix and U on the GPU);
+    one root and five roots against exact diagonalisation."""
+    s = make_system(2, 3, 8, 24, seed=305, sigma=0.3)
+    o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
+    M = o.matrix()
+    h = handle(s)
+    for k, smax in [(1, 2), (5, 10)]:
+        w_ex, _ = o.roots_exact(k)
+        w, X, info = A.adc2_davidson(h, k, tol=1e-10, max_subspace=smax, max_iter=400, solver=FOLD)
+        print(f"  k={k} smax={smax}: folded {np.round(w, 10)} exact {np.round(w_ex.numpy(), 10)} "
+              f"iters {info['iters']} space {info['subspace']}", flush=True)
+        assert info["converged"]
+        assert np.abs(np.array(w) - w_ex.numpy()).max() < 1e-9
+        Xc = X.cpu()
+        R = Xc @ M.T - torch.tensor(w, dtype=torch.float64)[:, None] * Xc
+        assert torch.linalg.vector_norm(R, dim=1).max().item() < 1e-8
+    h.close()
+
+
+def test_folded_deterministic_c1():
+    """Two folded solves of the same handle return the same roots and vectors
+    bit for bit (every reduction of the subspace algebra has a fixed order)."""
+    s = config_system("c1")
+    h = handle(s)
+    w1, X1, i1 = A.adc2_davidson(h, 4, tol=1e-9, solver=FOLD)
+    w2, X2, i2 = A.adc2_davidson(h, 4, tol=1e-9, solver=FOLD)
+    torch.cuda.synchronize()
+    assert i1["iters"] == i2["iters"]
+    assert list(w1) == list(w2)
+    assert torch.equal(X1, X2)
+    h.close()
