@@ -328,6 +328,16 @@ def run_batch(args, A, np, torch):
             A.adc2_autotune(h, nroots)
         return h
 
+    sig = batch_sigma_leg(A, torch, data, nroots, tuned, reps=args.batch_sigma_reps)
+    if args.batch_sigma_only:
+        print(json.dumps({"metric": "batched sigma of every system of the batch (m = " + str(nroots) + " each)",
+                          "value": sig["graph_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "c64 contractions", "data": "synthetic",
+                          "config": {"workload": "batching form: " + str(len(systems)) + " systems, nc=6, "
+                                     "(no, nv) = " + ", ".join(f"({s.no},{s.nv})" for s in systems) +
+                                     ", naux = 4 nv"},
+                          "sigma_launch": sig}), flush=True)
+        return
     # warm-up (untimed): one solve of the smallest system, so that no timed leg pays first-call costs
     qmin = min(range(len(data)), key=lambda q: systems[q].no * systems[q].nv ** 2)
     h = tuned(A.adc2_setup(*data[qmin], prec=A.ADC2_C64))
@@ -394,12 +404,57 @@ def run_batch(args, A, np, torch):
         "sequential_per_system_s": [round(r["s"], 3) for r in seq],
         "sequential_iterations": [r["info"]["iters"] for r in seq],
         "omega_ha_polished": [list(r["wp"]) for r in seq],
+        "sigma_launch": sig,
         "autotune": ({"m": nroots, "tune_s": round(sum(r["s"] for r in tune), 3),
                       "systems": [{"ysplit": r["ysplit"], "heuristic_ysplit": r["heuristic_ysplit"],
                                    "ms": {str(k): round(v, 3) for k, v in r["ms"].items()}} for r in tune]}
                      if tune else None),
     }
     print(json.dumps(out), flush=True)
+
+
+def batch_sigma_leg(A, torch, data, m, tuned, reps=20):
+    """One sigma product of m vectors for every system of the batch, timed
+    three ways on torch's current stream (HIP events, mean over reps): one
+    adc2_sigma per system, one adc2_sigma_batch (grouped heavy GEMMs), and the
+    replay of that batched launch sequence captured as a HIP graph
+    (adc2_graph_sigma_batch / adc2_graph_launch).  The replay's output is
+    checked against the eager batched product."""
+    hs = [tuned(h) for h in A.adc2_setup_batch(data, A.ADC2_C64)]
+    g = torch.Generator(device="cpu").manual_seed(77)
+    xs = [torch.randn(m, h.dim, dtype=torch.complex128, generator=g).cuda() for h in hs]
+    ss = [torch.empty_like(x) for x in xs]
+    graph = A.adc2_graph_sigma_batch(hs, xs)     # also the eager warm-up of every work space
+    for h, x, s_ in zip(hs, xs, ss):
+        A.adc2_sigma(h, x, s_)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    sep = timed(lambda: [A.adc2_sigma(h, x, s_) for h, x, s_ in zip(hs, xs, ss)])
+    bat = timed(lambda: A.adc2_sigma_batch(hs, xs, ss))
+    rep = timed(graph.launch)
+    eager = A.adc2_sigma_batch(hs, xs)
+    graph.launch()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(graph.S, eager))
+    graph.close()
+    for h in hs:
+        h.close()
+    out = {"m": m, "reps": reps, "separate_ms": round(sep, 3), "batched_ms": round(bat, 3),
+           "graph_ms": round(rep, 3), "graph_equals_batched": bool(same)}
+    print(f"[bench] batched sigma m={m}: separate {sep:.2f} ms, batched {bat:.2f} ms, graph replay {rep:.2f} ms "
+          f"(equal {same})", file=sys.stderr, flush=True)
+    return out
 
 
 def run_fd(args, A, np, torch):
@@ -1062,6 +1117,10 @@ def main():
                          "is ~2e-5)")
     ap.add_argument("--batch-systems", default="",
                     help="comma-separated indices of the batch systems to run (default: all eight)")
+    ap.add_argument("--batch-sigma-only", action="store_true",
+                    help="batch workload: time only the batched sigma (separate, batched, graph replay)")
+    ap.add_argument("--batch-sigma-reps", type=int, default=20,
+                    help="batch workload: repetitions of each timed batched-sigma variant")
     ap.add_argument("--sigma-probe", action="store_true",
                     help="short run for hardware counters: 3 FP64, 3 complex64 and 3 split-BF16 sigma "
                          "builds (m=10) and a 2 GiB read+write calibration kernel; prints no JSON")

@@ -353,6 +353,36 @@ ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nr
                                          int mode, double* omega, void* const* X, adc2_dav_info* info,
                                          void* stream);
 
+/*
+ * Graph-captured batched sigma (batching form): the whole launch sequence of
+ * one adc2_sigma_batch call (every phase of every system, the grouped heavy
+ * GEMMs included) recorded once as a HIP graph and replayed with one launch.
+ * A replay reads X_i and writes S_i at the device addresses given at capture,
+ * so a caller refills X_i in place between replays.
+ *
+ * adc2_graph_sigma_batch -- arguments as adc2_sigma_batch.  Runs the batched
+ *   sigma once eagerly on `stream` (so S_i = M_i X_i on return, and every
+ *   work space is sized), synchronises it, then captures the same sequence on
+ *   an internal stream and instantiates it into *out.  Per-kernel profiling
+ *   is suspended during the capture.  Errors: those of adc2_sigma_batch, and
+ *   ADC2_ERR_ARG for a handle in the ADC(2)-x method (its doubles block is
+ *   outside the captured sequence).
+ * adc2_graph_launch -- replays the graph on `stream` (asynchronous).  The
+ *   handles must still exist, and every one must still hold the work spaces,
+ *   operand copies, precision form, method and split counts the graph
+ *   recorded: a sigma call with a larger block, a change of precision,
+ *   method or autotuned split re-sizes them, and the launch then returns
+ *   ADC2_ERR_ARG (capture again) instead of replaying.  A replay shares the
+ *   handles' work spaces with every other sigma on them: calls that overlap
+ *   in time race.
+ * adc2_graph_destroy -- releases the graph (NULL is accepted).
+ */
+typedef struct adc2_graph_s* adc2_graph;
+ADC2_API adc2_status adc2_graph_sigma_batch(int nmol, const adc2_handle* hs, const int* m, const void* const* X,
+                                            void* const* S, void* stream, adc2_graph* out);
+ADC2_API adc2_status adc2_graph_launch(adc2_graph g, void* stream);
+ADC2_API adc2_status adc2_graph_destroy(adc2_graph g);
+
 /* Copy the dense singles block M11 (complex128 [nc*nv][nc*nv], row (I,a),
  * column (J,b)) into dev buffer dst.  Stream-ordered. */
 ADC2_API adc2_status adc2_get_m11(adc2_handle h, void* dst, void* stream);

@@ -68,7 +68,8 @@ EXPORTS = ["adc2_setup", "adc2_dim", "adc2_sigma", "adc2_davidson", "adc2_set_pr
            "adc2_rayleigh", "adc2_omega_backward", "adc2_get_m11", "adc2_get_diag", "adc2_mp2_energy", "adc2_profile",
            "adc2_kernel_stats", "adc2_destroy", "adc2_last_error", "adc2_setup_batch", "adc2_sigma_batch",
            "adc2_davidson_batch", "adc2_peak_probe", "adc2_autotune", "adc2_fns", "adc2_transition",
-           "adc2_sigma_noalloc", "adc2_set_method"]
+           "adc2_sigma_noalloc", "adc2_set_method", "adc2_graph_sigma_batch", "adc2_graph_launch",
+           "adc2_graph_destroy"]
 
 
 class DavOpts(ctypes.Structure):
@@ -194,6 +195,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc2_sigma_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp]
     lib.adc2_sigma_batch.restype = i
+    lib.adc2_graph_sigma_batch.argtypes = [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]
+    lib.adc2_graph_sigma_batch.restype = i
+    lib.adc2_graph_launch.argtypes = [vp, vp]
+    lib.adc2_graph_launch.restype = i
+    lib.adc2_graph_destroy.argtypes = [vp]
+    lib.adc2_graph_destroy.restype = i
     lib.adc2_davidson_batch.argtypes = [i, ctypes.POINTER(vp), i, ctypes.POINTER(DavOpts), i, ctypes.POINTER(d),
                                         ctypes.POINTER(vp), ctypes.POINTER(DavInfo), vp]
     lib.adc2_davidson_batch.restype = i
@@ -385,8 +393,7 @@ def adc2_setup_batch(systems, prec=ADC2_FP64, stream=None, alloc=None):
     return [Handle(ctypes.c_void_p(out[q]), *systems[q][2:6], alloc=al) for q in range(n)]
 
 
-def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):
-    """S_i = M_i X_i for every system of a batch in one batched launch sequence."""
+def _batch_args(hs, Xs, Ss):
     import torch
     n = len(hs)
     Xs = [X[None] if X.dim() == 1 else X for X in Xs]
@@ -404,8 +411,53 @@ def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):
         ms[q] = Xs[q].shape[0]
         xp[q] = Xs[q].data_ptr()
         sp[q] = Ss[q].data_ptr()
+    return n, hp, ms, xp, sp, Xs, Ss
+
+
+def adc2_sigma_batch(hs, Xs, Ss=None, stream=None):
+    """S_i = M_i X_i for every system of a batch in one batched launch sequence."""
+    n, hp, ms, xp, sp, Xs, Ss = _batch_args(hs, Xs, Ss)
     _check(load().adc2_sigma_batch(n, hp, ms, xp, sp, _stream_ptr(stream)), "adc2_sigma_batch")
     return Ss
+
+
+class SigmaGraph:
+    """A batched sigma captured as a HIP graph (adc2_graph_sigma_batch).
+    launch() replays it: it reads the X tensors and writes the S tensors it
+    was captured with (refill X in place between launches).  The tensors and
+    handles are kept alive as long as the graph."""
+
+    def __init__(self, ptr, hs, Xs, Ss):
+        self.ptr, self.hs, self.X, self.S = ptr, list(hs), Xs, Ss
+
+    def launch(self, stream=None):
+        if self.ptr is None:
+            raise Adc2Error(ADC2_ERR_ARG, "adc2_graph_launch: graph is closed")
+        if not all(h.ptr for h in self.hs):
+            raise Adc2Error(ADC2_ERR_ARG, "adc2_graph_launch: a handle of the graph was closed")
+        _check(load().adc2_graph_launch(self.ptr, _stream_ptr(stream)), "adc2_graph_launch")
+        return self.S
+
+    def close(self):
+        if self.ptr is not None:
+            load().adc2_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def adc2_graph_sigma_batch(hs, Xs, Ss=None, stream=None):
+    """Capture the batched sigma S_i = M_i X_i as a HIP graph; S holds the
+    eager result on return.  Returns a SigmaGraph."""
+    n, hp, ms, xp, sp, Xs, Ss = _batch_args(hs, Xs, Ss)
+    out = ctypes.c_void_p()
+    _check(load().adc2_graph_sigma_batch(n, hp, ms, xp, sp, _stream_ptr(stream), ctypes.byref(out)),
+           "adc2_graph_sigma_batch")
+    return SigmaGraph(out, hs, Xs, Ss)
 
 
 def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess=0, want_vectors=True,

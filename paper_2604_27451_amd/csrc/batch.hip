@@ -13,6 +13,13 @@
 // on the batch stream and releases the others.  In streams mode each solver
 // keeps its sigma builds on its own stream.  Every system sees exactly the
 // sigma results (and so the iterates) of a solve on its own.
+//
+// Graph-captured batched sigma: the launch sequence of one batched sigma is
+// recorded as a HIP graph (stream capture of sigma_multi, which makes no
+// allocation, memset or host synchronisation once the work spaces exist) and
+// replayed with one launch.  The graph holds the handles' buffer addresses,
+// so a replay first checks that each handle still has the state recorded at
+// capture.
 #include <condition_variable>
 #include <mutex>
 #include <string>
@@ -84,8 +91,58 @@ struct Rendezvous {
   }
 };
 
+// What the captured launch sequence of a handle depends on: its buffer
+// addresses, precision form, method and split counts.
+struct SigState {
+  int prec, method, gemm3, ysplit, nsplit;
+  const void* buf[18];
+  bool operator==(const SigState& o) const {
+    if (prec != o.prec || method != o.method || gemm3 != o.gemm3 || ysplit != o.ysplit || nsplit != o.nsplit)
+      return false;
+    for (int i = 0; i < 18; ++i)
+      if (buf[i] != o.buf[i]) return false;
+    return true;
+  }
+};
+
+SigState sig_state(adc2_handle h) {
+  SigState s;
+  s.prec = h->prec;
+  s.method = h->method;
+  s.gemm3 = h->gemm3;
+  s.ysplit = h->ysplit;
+  s.nsplit = h->nsplit;
+  const void* b[18] = {h->X,    h->Y,     h->Zb,  h->Tp,  h->part, h->XB,  h->RB, h->Lv32, h->LvT32,
+                       h->LvB,  h->LvTB,  h->LvT, h->Lvo, h->Lvv,  h->Vt,  h->eps, h->M11, nullptr};
+  for (int i = 0; i < 18; ++i) s.buf[i] = b[i];
+  return s;
+}
+
+// Requests of a batched sigma (shared argument checks of the batched entry points).
+adc2_status batch_requests(const char* who, int nmol, const adc2_handle* hs, const int* m, const void* const* X,
+                           void* const* S, std::vector<SigReq>& rq) {
+  if (nmol < 1 || !hs || !m || !X || !S) return bfail(ADC2_ERR_ARG, std::string(who) + ": bad arguments");
+  rq.resize(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    if (!hs[i] || !X[i] || !S[i] || m[i] < 1)
+      return bfail(ADC2_ERR_ARG, std::string(who) + ": system " + std::to_string(i) + ": NULL pointer or m < 1");
+    if (X[i] == S[i]) return bfail(ADC2_ERR_ARG, std::string(who) + ": S must not alias X");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return bfail(ADC2_ERR_ARG, std::string(who) + ": a handle appears twice");
+    rq[i] = SigReq{hs[i], m[i], (const double2*)X[i], (double2*)S[i], SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN};
+  }
+  return ADC2_OK;
+}
+
 }  // namespace
 }  // namespace adc2
+
+struct adc2_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<adc2_handle> hs;
+  std::vector<adc2::SigState> state;
+};
 
 using namespace adc2;
 
@@ -114,17 +171,95 @@ ADC2_API adc2_status adc2_setup_batch(int nmol, const adc2_mol* mols, int prec, 
 
 ADC2_API adc2_status adc2_sigma_batch(int nmol, const adc2_handle* hs, const int* m, const void* const* X,
                                       void* const* S, void* stream) {
-  if (nmol < 1 || !hs || !m || !X || !S) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: bad arguments");
-  std::vector<SigReq> rq(nmol);
-  for (int i = 0; i < nmol; ++i) {
-    if (!hs[i] || !X[i] || !S[i] || m[i] < 1)
-      return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: system " + std::to_string(i) + ": NULL pointer or m < 1");
-    if (X[i] == S[i]) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: S must not alias X");
-    for (int j = 0; j < i; ++j)
-      if (hs[j] == hs[i]) return bfail(ADC2_ERR_ARG, "adc2_sigma_batch: a handle appears twice");
-    rq[i] = SigReq{hs[i], m[i], (const double2*)X[i], (double2*)S[i], SIGMA_SINGLES_IN | SIGMA_DOUBLES_IN};
-  }
+  std::vector<SigReq> rq;
+  const adc2_status rc = batch_requests("adc2_sigma_batch", nmol, hs, m, X, S, rq);
+  if (rc != ADC2_OK) return rc;
   return sigma_multi(nmol, rq.data(), (hipStream_t)stream);
+}
+
+ADC2_API adc2_status adc2_graph_sigma_batch(int nmol, const adc2_handle* hs, const int* m, const void* const* X,
+                                            void* const* S, void* stream, adc2_graph* out) {
+  static const char* who = "adc2_graph_sigma_batch";
+  if (!out) return bfail(ADC2_ERR_ARG, std::string(who) + ": out is NULL");
+  *out = nullptr;
+  std::vector<SigReq> rq;
+  adc2_status rc = batch_requests(who, nmol, hs, m, X, S, rq);
+  if (rc != ADC2_OK) return rc;
+  for (int i = 0; i < nmol; ++i)
+    if (hs[i]->method != ADC2_METHOD_ADC2)
+      return bfail(ADC2_ERR_ARG, std::string(who) + ": system " + std::to_string(i) +
+                                     ": only the ADC(2) method is captured (the ADC(2)-x doubles block is not)");
+  // eager run: sizes every work space and operand copy, and gives S
+  hipStream_t us = (hipStream_t)stream;
+  if ((rc = sigma_multi(nmol, rq.data(), us)) != ADC2_OK) return rc;
+  {
+    const hipError_t e = hipStreamSynchronize(us);
+    if (e != hipSuccess) return bfail(ADC2_ERR_HIP, std::string(who) + ": " + hipGetErrorString(e));
+  }
+  auto* g = new adc2_graph_s;
+  g->hs.assign(hs, hs + nmol);
+  for (int i = 0; i < nmol; ++i) g->state.push_back(sig_state(hs[i]));
+  std::vector<int> prof(nmol);
+  for (int i = 0; i < nmol; ++i) {   // profiling records events and synchronises: off while capturing
+    prof[i] = hs[i]->profiling;
+    hs[i]->profiling = 0;
+  }
+  hipStream_t cs = nullptr;
+  std::string msg;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    rc = ADC2_ERR_HIP;
+    msg = std::string("stream capture: ") + hipGetErrorString(e);
+  } else {
+    rc = sigma_multi(nmol, rq.data(), cs);
+    if (rc != ADC2_OK) msg = adc2_last_error();
+    e = hipStreamEndCapture(cs, &g->graph);   // ends the capture on every path
+    if (rc == ADC2_OK && e != hipSuccess) {
+      rc = ADC2_ERR_HIP;
+      msg = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+    }
+  }
+  if (cs) hipStreamDestroy(cs);
+  for (int i = 0; i < nmol; ++i) hs[i]->profiling = prof[i];
+  for (int i = 0; rc == ADC2_OK && i < nmol; ++i)
+    if (!(sig_state(hs[i]) == g->state[i])) {
+      rc = ADC2_ERR_HIP;
+      msg = "a work space changed while capturing";
+    }
+  if (rc == ADC2_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      rc = ADC2_ERR_HIP;
+      msg = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+    }
+  }
+  if (rc != ADC2_OK) {
+    adc2_graph_destroy(g);
+    return bfail(rc, std::string(who) + ": " + msg);
+  }
+  *out = g;
+  return ADC2_OK;
+}
+
+ADC2_API adc2_status adc2_graph_launch(adc2_graph g, void* stream) {
+  if (!g || !g->exec) return bfail(ADC2_ERR_ARG, "adc2_graph_launch: NULL graph");
+  for (size_t i = 0; i < g->hs.size(); ++i)
+    if (!(sig_state(g->hs[i]) == g->state[i]))
+      return bfail(ADC2_ERR_ARG, "adc2_graph_launch: system " + std::to_string(i) +
+                                     ": its work spaces, precision form, method or splits changed since the "
+                                     "capture; capture the batch again");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return bfail(ADC2_ERR_HIP, std::string("adc2_graph_launch: ") + hipGetErrorString(e));
+  return ADC2_OK;
+}
+
+ADC2_API adc2_status adc2_graph_destroy(adc2_graph g) {
+  if (!g) return ADC2_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+  return ADC2_OK;
 }
 
 ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nroots, const adc2_dav_opts* opt,

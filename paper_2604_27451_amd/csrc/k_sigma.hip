@@ -470,7 +470,9 @@ __global__ __launch_bounds__(256) void k_zsig2_c64(const float2* __restrict__ X3
   zsig2_c64_item(s, X32, Lv32, rows, no, nv, naux, Z, xcd_remap(blockIdx.x, nt));
 }
 
-__global__ __launch_bounds__(256) void k_ygemm_c64(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
+// Two workgroups per CU: the accumulators then live in the unified register
+// file (no AGPR split) within 256 registers per lane.
+__global__ __launch_bounds__(256, 2) void k_ygemm_c64(const float2* __restrict__ LvT32, const float2* __restrict__ Rt32,
                                                     int rows, int no, int nv, int naux, double2* __restrict__ Y) {
   __shared__ BigSmemF s[2];
   const long nt = (long)((naux + BT - 1) / BT) * ((rows * nv + BT - 1) / BT);
@@ -493,11 +495,16 @@ __global__ __launch_bounds__(512) void k_ygemm_b3(const __bf16* __restrict__ LvT
 
 // ---------------------------------------------------------------------------
 // Grouped launches of the heavy GEMMs over several systems (batching form).
-// One job per system; its work items are (K-split, tile) pairs numbered from
-// w0.  The launch walks the concatenated item list [0, total): workgroup b
-// takes items b, b + gridDim.x, ...  Logical items are spread with xcd_remap
-// so that consecutive items of one system (which share operand panels) run on
-// one XCD; the ragged sizes of the systems only change the item table.
+// One job per system; its work items are (K-split, tile) pairs.  Job q owns
+// the slots [w0, w0 + npad) of the launch, npad = its item count rounded up
+// to a multiple of 8 and w0 a multiple of 8, so that slot w runs on XCD
+// w mod 8 and every job is spread evenly over the eight XCDs (the items of
+// different systems differ in K, hence in cost, by an order of magnitude:
+// an equal item count per XCD would leave some XCDs idle).  Within a job,
+// xcd_remap gives each XCD a contiguous run of items, which share operand
+// panels in its L2.  Jobs are ordered by decreasing cost per item, so the
+// tail of the launch is made of the cheapest items.  Workgroup b takes slots
+// b, b + gridDim.x, ... (gridDim.x a multiple of 8).
 constexpr int GMAX = 16;   // systems per grouped launch
 struct GemmJob {
   const void* A;     // Y-build: LvT32 (complex64) or LvTB (split);  sigma2: X32 or XB
@@ -505,7 +512,7 @@ struct GemmJob {
   void* C;           // Y (double2, nsplit partials) or Z (float2)
   int rows, no, nv, naux, nsplit;
   long ntile;        // output tiles of one K-split
-  long w0;           // first item
+  long w0;           // first slot (a multiple of 8)
 };
 struct GemmJobs {
   int n;
@@ -520,13 +527,20 @@ __device__ __forceinline__ int job_of(const GemmJobs& J, long item) {
   return q;
 }
 
+// Item of slot w of job g, or -1 for a padding slot.
+__device__ __forceinline__ long job_item(const GemmJob& g, long w) {
+  const long nit = g.ntile * g.nsplit;
+  const long item = xcd_remap(w - g.w0, (nit + 7) & ~7L);
+  return item < nit ? item : -1;
+}
+
 template <bool YBUILD>
-__global__ __launch_bounds__(256) void k_gemm_c64_grouped(const GemmJobs J) {
+__global__ __launch_bounds__(256, 2) void k_gemm_c64_grouped(const GemmJobs J) {
   __shared__ BigSmemF s[2];
   for (long w = blockIdx.x; w < J.total; w += gridDim.x) {
-    const long item = xcd_remap(w, J.total);
-    const GemmJob& g = J.j[job_of(J, item)];
-    const long loc = item - g.w0;
+    const GemmJob& g = J.j[job_of(J, w)];
+    const long loc = job_item(g, w);
+    if (loc < 0) continue;
     const int split = (int)(loc / g.ntile);
     const long lid = loc - (long)split * g.ntile;
     if (YBUILD)
@@ -541,9 +555,9 @@ template <bool YBUILD>
 __global__ __launch_bounds__(512) void k_gemm_b3_grouped(const GemmJobs J) {
   __shared__ BigSmemB s[2];
   for (long w = blockIdx.x; w < J.total; w += gridDim.x) {
-    const long item = xcd_remap(w, J.total);
-    const GemmJob& g = J.j[job_of(J, item)];
-    const long loc = item - g.w0;
+    const GemmJob& g = J.j[job_of(J, w)];
+    const long loc = job_item(g, w);
+    if (loc < 0) continue;
     const int split = (int)(loc / g.ntile);
     const long lid = loc - (long)split * g.ntile;
     if (YBUILD)
@@ -1102,7 +1116,7 @@ static adc2_status grouped_gemm(int nreq, const SigReq* rq, const std::vector<ch
   J.total = 0;
   auto flush = [&]() -> adc2_status {
     if (J.n == 0) return ADC2_OK;
-    const unsigned grid = (unsigned)std::min<long>(J.total, 1L << 20);
+    const unsigned grid = (unsigned)std::min<long>(J.total, 1L << 20);   // both multiples of 8
     if (prec == ADC2_BF16X3) {
       if (ybuild) k_gemm_b3_grouped<true><<<grid, 512, 0, st>>>(J);
       else k_gemm_b3_grouped<false><<<grid, 512, 0, st>>>(J);
@@ -1115,8 +1129,18 @@ static adc2_status grouped_gemm(int nreq, const SigReq* rq, const std::vector<ch
     J.total = 0;
     return ADC2_OK;
   };
+  // requests of this form, by decreasing K per item (ties: request order)
+  std::vector<std::pair<long, int>> order;
   for (int q = 0; q < nreq; ++q) {
     if (!use[q] || rq[q].h->prec != prec) continue;
+    const Dims& d = rq[q].h->d;
+    const long kpi = ybuild ? (long)d.no * d.nv / std::max(1, rq[q].h->ysplit) : (long)d.naux;
+    order.push_back({-kpi, q});
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<long, int>& a, const std::pair<long, int>& b) { return a.first < b.first; });
+  for (const auto& oq : order) {
+    const int q = oq.second;
     adc2_handle h = rq[q].h;
     const Dims& d = h->d;
     const int rows = rq[q].m * d.nc;
@@ -1140,7 +1164,7 @@ static adc2_status grouped_gemm(int nreq, const SigReq* rq, const std::vector<ch
       g.ntile = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
     }
     g.w0 = J.total;
-    J.total += g.ntile * g.nsplit;
+    J.total += (g.ntile * g.nsplit + 7) & ~7L;
     if (++J.n == GMAX) {
       adc2_status r = flush();
       if (r != ADC2_OK) return r;

@@ -125,6 +125,16 @@ def test_batch_argument_errors_without_gpu(lib):
     assert lib.adc2_davidson_batch(2, hs3, 2, None, 0, None, None, None, None) == A.ADC2_ERR_ARG
     assert lib.adc2_davidson_batch(2, hs3, 2, None, 7, om, None, None, None) == A.ADC2_ERR_ARG
     assert "mode" in A.adc2_last_error()
+    # graph capture of a batched sigma: the same checks, out[] cleared; NULL graphs
+    g = vp(72)
+    assert lib.adc2_graph_sigma_batch(2, hs3, ms, xs, ss, None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_graph_sigma_batch(2, hs, ms, xs, ss, None, ctypes.byref(g)) == A.ADC2_ERR_ARG
+    assert g.value is None
+    assert lib.adc2_graph_sigma_batch(2, hs2, ms, xs, ss, None, ctypes.byref(g)) == A.ADC2_ERR_ARG
+    assert "twice" in A.adc2_last_error()
+    assert lib.adc2_graph_sigma_batch(2, hs3, ms0, xs, ss, None, ctypes.byref(g)) == A.ADC2_ERR_ARG
+    assert lib.adc2_graph_launch(None, None) == A.ADC2_ERR_ARG
+    assert lib.adc2_graph_destroy(None) == A.ADC2_OK
 
 
 def test_one_hip_runtime_in_the_process():
