@@ -473,7 +473,7 @@ def adc2_davidson_batch(hs, nroots, tol=1e-8, max_iter=0, max_subspace=0, nguess
     hp = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in hs])
     xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs]) if want_vectors else None
     if mode is None:   # the faster of the two on the eight-system batch workload
-        mode = ADC2_BATCH_STREAMS
+        mode = ADC2_BATCH_ROUNDS
     st = load().adc2_davidson_batch(n, hp, nroots, ctypes.byref(opts), mode, omega, xp, infos, _stream_ptr(stream))
     _check(st, "adc2_davidson_batch")
     om = [list(omega[q * nroots:(q + 1) * nroots]) for q in range(n)]
