@@ -225,7 +225,8 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
     }
     h->alloc = *alloc;
   }
-  if (const char* v = getenv("ADC2_ZGEMM")) h->gemm3 = (strcmp(v, "3m") == 0) ? 1 : 0;
+  if (const char* v = getenv("ADC2_ZGEMM"))
+    h->zgemm = strcmp(v, "3m") == 0 ? ZGEMM_3M : strcmp(v, "big") == 0 ? ZGEMM_BIG : ZGEMM_MID;
 #define SETUP_TRY(call)                                                           \
   do {                                                                            \
     hipError_t e_ = (call);                                                       \

@@ -94,10 +94,10 @@ struct Rendezvous {
 // What the captured launch sequence of a handle depends on: its buffer
 // addresses, precision form, method and split counts.
 struct SigState {
-  int prec, method, gemm3, ysplit, nsplit;
+  int prec, method, zgemm, ysplit, nsplit;
   const void* buf[18];
   bool operator==(const SigState& o) const {
-    if (prec != o.prec || method != o.method || gemm3 != o.gemm3 || ysplit != o.ysplit || nsplit != o.nsplit)
+    if (prec != o.prec || method != o.method || zgemm != o.zgemm || ysplit != o.ysplit || nsplit != o.nsplit)
       return false;
     for (int i = 0; i < 18; ++i)
       if (buf[i] != o.buf[i]) return false;
@@ -109,7 +109,7 @@ SigState sig_state(adc2_handle h) {
   SigState s;
   s.prec = h->prec;
   s.method = h->method;
-  s.gemm3 = h->gemm3;
+  s.zgemm = h->zgemm;
   s.ysplit = h->ysplit;
   s.nsplit = h->nsplit;
   const void* b[18] = {h->X,    h->Y,     h->Zb,  h->Tp,  h->part, h->XB,  h->RB, h->Lv32, h->LvT32,

@@ -57,7 +57,7 @@ std::string tune_key(adc2_handle h, int m) {
   const Dims& d = h->d;
   std::ostringstream k;
   k << name << " nc=" << d.nc << " no=" << d.no << " nv=" << d.nv << " naux=" << d.naux << " m=" << m
-    << " prec=" << h->prec << " gemm3=" << h->gemm3;
+    << " prec=" << h->prec << " zgemm=" << h->zgemm;
   return k.str();
 }
 

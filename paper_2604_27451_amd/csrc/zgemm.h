@@ -182,6 +182,172 @@ __device__ __forceinline__ void big_tile_coords(long lid, int nbm, int nbn, int&
   bn = r / gsize;
 }
 
+
+// ---------------------------------------------------------------------------
+// Two-per-CU variant: 128 x 64 complex output tile per workgroup (4 waves as
+// 2 x 2, each a 64 x 32 quadrant of 4 x 2 blocks), chunks of 8 complex k.
+// The accumulators take 128 registers and the double-buffered LDS 48.5 KB,
+// so two workgroups share a CU and one's barrier and chunk turn-over run
+// under the other's MFMAs.  Each accumulator receives the same MFMAs in the
+// same k order as in the 128 x 128 engine, so the results are identical.
+// Sources: SrcGroupedK8<NS> (k-major, 8 k-rows per chunk, NS = rows / 32).
+// ---------------------------------------------------------------------------
+constexpr int MBK = 8;            // complex k per chunk
+constexpr int MTN = 64;           // tile columns
+constexpr int MLDN = MTN + 1;
+
+struct MidSmem {
+  double a_re[MBK][BLDP];
+  double a_im[MBK][BLDP];
+  double b_re[MBK][MLDN];
+  double b_im[MBK][MLDN];
+};
+
+// thread -> (k, i) of a k-major [8][32 NS] chunk: 32 consecutive lanes read
+// 32 consecutive i of one k row
+template <int NS, int LD>
+__device__ __forceinline__ void mid_stash(double (*re)[LD], double (*im)[LD], const RegsN<NS>& r, int tid) {
+  const int kk = tid >> 5, i0 = tid & 31;
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    re[kk][i0 + 32 * e] = r.v[e].x;
+    im[kk][i0 + 32 * e] = r.v[e].y;
+  }
+}
+
+struct MidAcc {
+  d4 re[4][2];
+  d4 im[4][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        re[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        im[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+  }
+};
+
+__device__ __forceinline__ void mid_mma(const MidSmem& s, MidAcc& acc, int wr, int wc, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < MBK; kg += 4) {
+    double ar[4], ai[4], br[2], bi[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ar[t] = s.a_re[kg + lk][wr + 16 * t + li];
+      ai[t] = s.a_im[kg + lk][wr + 16 * t + li];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      br[t] = s.b_re[kg + lk][wc + 16 * t + li];
+      bi[t] = s.b_im[kg + lk][wc + 16 * t + li];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc.im[a][b], 0, 0, 0);
+    // -Im(A) Im(B): the negation is the MFMA's own modifier on A (blgp bit 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], acc.re[a][b], 0, 0, 1);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc.im[a][b], 0, 0, 0);
+  }
+}
+
+// Double-buffered main loop over chunks [kc0, kc1), as big_mainloop.
+template <class SA, class SB>
+__device__ __forceinline__ void mid_mainloop(MidSmem (&s)[2], const SA& A, const SB& B, int kc0, int kc1,
+                                             MidAcc& acc) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 32;
+  if (kc0 >= kc1) return;
+  RegsN<4> ra;
+  RegsN<2> rb;
+  A.load(kc0, ra);
+  B.load(kc0, rb);
+  mid_stash<4, BLDP>(s[0].a_re, s[0].a_im, ra, tid);
+  mid_stash<2, MLDN>(s[0].b_re, s[0].b_im, rb, tid);
+  if (kc0 + 1 < kc1) {
+    A.load(kc0 + 1, ra);
+    B.load(kc0 + 1, rb);
+  }
+  __syncthreads();
+  for (int c = kc0; c < kc1; ++c) {
+    const int cur = (c - kc0) & 1;
+    if (c + 1 < kc1) {
+      mid_stash<4, BLDP>(s[cur ^ 1].a_re, s[cur ^ 1].a_im, ra, tid);
+      mid_stash<2, MLDN>(s[cur ^ 1].b_re, s[cur ^ 1].b_im, rb, tid);
+      if (c + 2 < kc1) {
+        A.load(c + 2, ra);
+        B.load(c + 2, rb);
+      }
+    }
+    mid_mma(s[cur], acc, wr, wc, lane);
+    __syncthreads();
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void mid_for_each(const MidAcc& acc, F&& f) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 32;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr + 16 * a + (lane >> 4) + 4 * r;
+        const int col = wc + 16 * b + (lane & 15);
+        f(row, col, make_double2(acc.re[a][b][r], acc.im[a][b][r]));
+      }
+}
+
+// k-major source for the two-per-CU engine: rows grouped as SrcGroupedK,
+// element (k, i) at base[g*gstride + a + k*ld], chunk of 8 k, NS = rows/32.
+template <int NS>
+struct SrcGroupedK8 {
+  const double2* base;
+  long gstride;
+  long ld;
+  int inner, nrows, nk;
+  long off[NS];
+  unsigned okmask;
+  int kk;
+  __device__ __forceinline__ void begin(int tid, int i0) {
+    kk = tid >> 5;
+    okmask = 0;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const int i = i0 + (tid & 31) + 32 * e;
+      const int g = i / inner;
+      off[e] = (long)g * gstride + (i - g * inner);
+      if (i < nrows) okmask |= 1u << e;
+    }
+  }
+  __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
+    const int k = kc * MBK + kk;
+    const long ko = (long)k * ld;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) r.v[e] = ((okmask >> e) & 1u) && k < nk ? base[off[e] + ko] : czero();
+  }
+};
 // ---------------------------------------------------------------------------
 // Three-multiplication variant (Gauss): for each 16x16 block
 //   T1 += Ar Br,  T2 += Ai Bi,  T3 += (Ar + Ai)(Br + Bi)
