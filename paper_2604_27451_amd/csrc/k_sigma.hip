@@ -749,6 +749,7 @@ __global__ __launch_bounds__(256) void k_light1(const TI* __restrict__ Rt, const
   const int I = mI % nc;
   const int c = cb * 256 + threadIdx.x;
   const bool cok = c < nv;
+  const int cs = cok ? c : 0;
   const long ld = (long)rows * nv;
   for (int K0 = 0; K0 < nc; K0 += 8) {
     double2 acc[8];
@@ -767,19 +768,25 @@ __global__ __launch_bounds__(256) void k_light1(const TI* __restrict__ Rt, const
         __syncthreads();
         const int dend = min(256, nv - dd0);
         int dd = 0;
-        for (; dd + 4 <= dend; dd += 4) {
-          double2 r[4];
+        // DU loads in flight per thread (16 for complex64 operands, where more loads
+        // in flight paid; 4 for complex128, where the registers would cost occupancy); a lane
+        // past the last column reads column 0 and its sums are never stored
+        constexpr int DU = sizeof(TI) == 8 ? 16 : 4;
+        for (; dd + DU <= dend; dd += DU) {
+          TI r[DU];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) r[u] = cok ? to_d2(R[(long)(dd0 + dd + u) * ld + c]) : czero();
+          for (int u = 0; u < DU; ++u) r[u] = R[(long)(dd0 + dd + u) * ld + cs];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < DU; ++u) {
+            const double2 x = to_d2(r[u]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd + u], r[u]));
+            for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd + u], x));
+          }
         }
         for (; dd < dend; ++dd) {
-          const double2 r = cok ? to_d2(R[(long)(dd0 + dd) * ld + c]) : czero();
+          const double2 x = to_d2(R[(long)(dd0 + dd) * ld + cs]);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd], r));
+          for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmul(vs[q][dd], x));
         }
       }
     }
