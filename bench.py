@@ -40,6 +40,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -276,11 +277,18 @@ def run_peaks(args, A):
 
 
 def heuristic_ysplit(s, m):
-    """The library's size rule for the Y-build K-split (used when no tuned
-    choice is set): enough splits for ~16 workgroups per CU, at most 8."""
-    bt = 128
-    ytiles = -(-s.naux // bt) * -(-(m * s.nc * s.nv) // bt)
-    return max(1, min(8, -(-(16 * 256) // ytiles)))
+    """The library's size rule for the Y-build K-split of a complex64 handle
+    (used when no tuned choice is set): the count 1..8 whose 128x128 tiles
+    fill whole rounds of the 512 workgroup slots best (two per CU), each
+    further split charged 0.2%."""
+    ytiles = -(-s.naux // 128) * -(-(m * s.nc * s.nv) // 128)
+    best, ys = None, 1
+    for c in range(1, 9):
+        rounds = ytiles * c / 512
+        cost = math.ceil(rounds) / rounds * (1.0 + 0.002 * (c - 1))
+        if best is None or cost < best:
+            best, ys = cost, c
+    return ys
 
 
 def run_batch(args, A, np, torch):

@@ -65,8 +65,9 @@ __host__ __device__ inline int cdf(long a, long b) { return (int)((a + b - 1) / 
 // pairs x 16 NCB moments and one slice of the doubles (split-K).  A fragments
 // are the products P formed in registers from the staged U rows (lane l:
 // pair 16 rb + l % 16, d = 4 kstep + l / 16), so P never touches LDS or HBM;
-// B fragments are T_m(t_d) of the staged chunk (cos(m arccos t_d) for the
-// first two m of the slice, the three-term recurrence after).  The next
+// B fragments are T_m(t_d) of the staged chunk (each thread forms NM/8
+// consecutive moments of one d: the first two from T_0 = 1, T_1 = t_d by the
+// doubling identities, the rest by the three-term recurrence).  The next
 // chunk's U values are loaded into registers while the current chunk's
 // matrix instructions run.  Per 4 doubles a wave issues 2 RB NCB
 // v_mfma_f64_16x16x4_f64.
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_cheb_mfma(const double2* __restrict__ U
 #pragma unroll
       for (int b = 0; b < NCB; ++b) acc[a][q][b] = d4{0.0, 0.0, 0.0, 0.0};
   const long nch = (nd + MKC - 1) / MKC;
-  // the next chunk's U values and doubles energy, loaded into registers ahead of use
+  // the next chunk's U values and doubles energies, loaded into registers ahead of use
   double2 pf[MPF];
   double dnext = 0.0;
   auto load = [&](long ch) {
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) void k_cheb_mfma(const double2* __restrict__ U
       }
       pf[k] = v;
     }
-    if (tid < MKC) dnext = e0 + tid < nd ? D[e0 + tid] : 0.0;
+    dnext = e0 + tid % MKC < nd ? D[e0 + tid % MKC] : 0.0;   // every thread: the energy of its weight column
   };
   long ch = blockIdx.x;
   if (ch < nch) load(ch);
@@ -141,26 +142,38 @@ __global__ __launch_bounds__(256) void k_cheb_mfma(const double2* __restrict__ U
         else uj[row - nrow][e] = pf[k];
       }
     }
-    if (tid < MKC) {   // T_m(t_d), m0 <= m < m0 + NM: T_m0, T_m0+1, then the three-term recurrence
-      double tv[NM];
-      if (e0 + tid < nd) {
-        const double x = fmin(1.0, fmax(-1.0, ((inv ? 1.0 / (dnext - w0) : dnext) - c) * ih));
-        if (m0 == 0) {   // the first slice (every pass with at most NM moments): T_0 = 1, T_1 = x
-          tv[0] = 1.0;
-          tv[1] = x;
-        } else {
-          const double th = acos(x);
-          tv[0] = cos((double)m0 * th);
-          tv[1] = cos((double)(m0 + 1) * th);
+    {  // T_m(t_d), m0 <= m < m0 + NM: thread (d, g) writes the NM/8 moments from n = m0 + g NM/8
+      constexpr int PER = NM / 8;
+      const int dl = tid % MKC, grp = tid / MKC;
+      const double dd = dnext;
+      double tv[PER];
+      if (e0 + dl < nd) {
+        const double x = fmin(1.0, fmax(-1.0, ((inv ? 1.0 / (dd - w0) : dd) - c) * ih));
+        // (T_n, T_n+1) from (T_0, T_1) = (1, x) by the doubling identities over the bits of n:
+        // T_2k = 2 T_k^2 - 1, T_2k+1 = 2 T_k T_k+1 - x, T_2k+2 = 2 T_k+1^2 - 1
+        const int n = m0 + grp * PER;
+        double a = 1.0, b = x;
+        for (int bit = 7; bit >= 0; --bit) {
+          if ((n >> bit) == 0) continue;
+          const double ab = 2.0 * a * b - x;
+          if ((n >> bit) & 1) {
+            a = ab;
+            b = 2.0 * b * b - 1.0;
+          } else {
+            b = ab;
+            a = 2.0 * a * a - 1.0;
+          }
         }
+        tv[0] = a;
+        tv[1] = b;
 #pragma unroll
-        for (int q = 2; q < NM; ++q) tv[q] = 2.0 * x * tv[q - 1] - tv[q - 2];
+        for (int q = 2; q < PER; ++q) tv[q] = 2.0 * x * tv[q - 1] - tv[q - 2];
       } else {
 #pragma unroll
-        for (int q = 0; q < NM; ++q) tv[q] = 0.0;
+        for (int q = 0; q < PER; ++q) tv[q] = 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < NM; ++q) tb[tid][q] = tv[q];
+      for (int q = 0; q < PER; ++q) tb[dl][grp * PER + q] = tv[q];
     }
     __syncthreads();
     if (ch + nchb < nch) load(ch + nchb);
