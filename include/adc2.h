@@ -476,18 +476,26 @@ ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double threshold, in
  * Autotuner of the sigma build's dominant GEMM, the Y-build (M12 half of the
  * sigma, Implementation section): its K-split count decides how many
  * workgroups a launch has against extra partial traffic and a summation
- * pass.  adc2_autotune times the Y-build of h's current precision form at
- * block size m for the K-splits 1, 2, 3, 4, 6, 8, 12, 16 (those whose partial
- * workspace stays under 8 GiB and that leave each split at least 64 of the
- * no*nv contraction indices), one warm-up and three timed launches each on
- * uniform random operands (the matrix cores run measurably faster on zeros), and
- * fixes the fastest for h (for every later block size too).  A choice already
- * made for the same (device, nc, no, nv, naux, m, form) in this process, or
- * listed in the text file named by the environment variable ADC2_TUNE_CACHE,
- * is reused without timing; new choices are appended to that file.
- * Results of sigma builds differ between K-splits only by rounding.
- * info (host, nullable) receives the choice, the candidates timed and their
- * best times in ms (ncand = 0 and from_cache = 1 for a cached choice).
+ * pass, and in the FP64 form its engine decides the tile shape (128 x 64 at
+ * two workgroups per CU, 128 x 128, or 128 x 64 three-multiplication).
+ * adc2_autotune times the Y-build of h's current precision form at block size
+ * m: in the FP64 form first each engine at its own size-rule K-split (unless
+ * the environment variable ADC2_ZGEMM fixes the engine), then, for the
+ * fastest engine (or the form's only one), the K-splits 1, 2, 3, 4, 6, 8, 12,
+ * 16 (those whose partial workspace stays under 8 GiB and that leave each
+ * split at least 64 of the no*nv contraction indices); one warm-up and three
+ * timed launches each on uniform random operands (the matrix cores run
+ * measurably faster on zeros).  It fixes the fastest engine and K-split for h
+ * (for every later block size too).  A choice already made for the same
+ * (device, nc, no, nv, naux, m, form) in this process, or listed in the text
+ * file named by the environment variable ADC2_TUNE_CACHE, is reused without
+ * timing; new choices are appended to that file.  Results of sigma builds
+ * differ between K-splits and engines only by rounding (the engines other than
+ * the three-multiplication one give identical results at equal K-splits).
+ * info (host, nullable) receives the choice, the K-splits timed and their
+ * best times in ms (ncand = 0 and from_cache = 1 for a cached choice), the
+ * chosen engine (zgemm: 0 = 128 x 128, 1 = three-multiplication, 2 = two
+ * per CU) and the engines timed with their best times.
  * Synchronises the stream; must not overlap other calls on h.  Errors:
  * ADC2_ERR_ARG (NULL handle, m out of 1..4096), ADC2_ERR_OOM, ADC2_ERR_HIP.
  */
@@ -497,6 +505,10 @@ typedef struct {
   int cand[8];
   double ms[8];
   int from_cache;
+  int zgemm;
+  int nengine;
+  int engine[4];
+  double engine_ms[4];
 } adc2_tune_info;
 ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_info* info, void* stream);
 

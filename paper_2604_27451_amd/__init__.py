@@ -81,7 +81,11 @@ class DavOpts(ctypes.Structure):
 
 class TuneInfo(ctypes.Structure):
     _fields_ = [("ysplit", ctypes.c_int), ("ncand", ctypes.c_int), ("cand", ctypes.c_int * 8),
-                ("ms", ctypes.c_double * 8), ("from_cache", ctypes.c_int)]
+                ("ms", ctypes.c_double * 8), ("from_cache", ctypes.c_int), ("zgemm", ctypes.c_int),
+                ("nengine", ctypes.c_int), ("engine", ctypes.c_int * 4), ("engine_ms", ctypes.c_double * 4)]
+
+
+ZGEMM_NAMES = {0: "128x128", 1: "128x64 three-multiplication", 2: "128x64 two per CU"}
 
 
 class Mol(ctypes.Structure):
@@ -650,12 +654,14 @@ def adc2_fns(h: Handle, L, threshold: float, stream=None):
 
 
 def adc2_autotune(h: Handle, m: int, stream=None) -> dict:
-    """Times the Y-build K-split candidates of h at block size m and fixes the
-    fastest; returns {"ysplit", "from_cache", "ms": {split: ms}}."""
+    """Times the Y-build candidates of h at block size m (in the FP64 form its
+    engines, then the K-splits of the fastest) and fixes the fastest; returns
+    {"ysplit", "zgemm", "from_cache", "ms": {split: ms}, "engines": {zgemm: ms}}."""
     info = TuneInfo()
     _check(load().adc2_autotune(h.ptr, m, ctypes.byref(info), _stream_ptr(stream)), "adc2_autotune")
-    return {"ysplit": info.ysplit, "from_cache": bool(info.from_cache),
-            "ms": {info.cand[c]: info.ms[c] for c in range(info.ncand)}}
+    return {"ysplit": info.ysplit, "zgemm": info.zgemm, "from_cache": bool(info.from_cache),
+            "ms": {info.cand[c]: info.ms[c] for c in range(info.ncand)},
+            "engines": {info.engine[e]: info.engine_ms[e] for e in range(info.nengine)}}
 
 
 def adc2_peak_probe(kind: int, nbytes: int = 0, reps: int = 5, stream=None) -> float:

@@ -144,6 +144,8 @@ adc2_status build_c64(adc2_handle h, hipStream_t st);
 adc2_status build_b3(adc2_handle h, hipStream_t st);
 adc2_status ensure_ws_b3(adc2_handle h, int m);
 adc2_status ensure_ws(adc2_handle h, int m);
+// K-split count of the Y-build by the size rule for h's form and engine at block size m
+int ysplit_rule(adc2_handle h, int m);
 adc2_status unpack_weighted(adc2_handle h, int m, const double2* xin, const double* wts, hipStream_t st);
 adc2_status ybuild_fp64(adc2_handle h, int m, hipStream_t st);
 // Y-build GEMM of one request in the handle's form (h->ysplit partials) and the partial sum

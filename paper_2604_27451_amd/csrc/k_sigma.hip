@@ -1040,27 +1040,35 @@ struct WsPlan {
 };
 
 // ys, ns > 0 impose the split counts instead of choosing them.
+// The Y-build's K-split count (1..8) whose tiles fill whole rounds of the
+// engine's workgroup slots best (the last round of a launch runs partly
+// empty), each further split charged 0.2% for its partial sum.
+int ysplit_rule(adc2_handle h, int m) {
+  const Dims& d = h->d;
+  const long rows = (long)m * d.nc;
+  const bool fp64 = h->prec == ADC2_FP64;
+  const int tn = fp64 && h->zgemm != ZGEMM_BIG ? BT3N : BT;
+  const long slots = 256L * ((fp64 && h->zgemm != ZGEMM_MID) || h->prec == ADC2_BF16X3 ? 1 : 2);
+  const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, tn);
+  int ys = 1;
+  double best = 0.0;
+  for (int c = 1; c <= 8; ++c) {
+    const double rounds = (double)(ytiles * c) / slots;
+    const double cost = std::ceil(rounds) / rounds * (1.0 + 0.002 * (c - 1));
+    if (c == 1 || cost < best) {
+      best = cost;
+      ys = c;
+    }
+  }
+  return ys;
+}
+
 static WsPlan ws_plan(adc2_handle h, int m, int ys = 0, int ns = 0) {
   const Dims& d = h->d;
   WsPlan p;
   const long rows = (long)m * d.nc;
   if (ys <= 0) {
-    // split the Y-build over K into the count (1..8) whose tiles fill whole rounds of the
-    // engine's workgroup slots best (the last round of a launch runs partly empty), each
-    // further split charged 0.2% for its partial sum
-    const bool fp64 = h->prec == ADC2_FP64;
-    const int tn = fp64 && h->zgemm != ZGEMM_BIG ? BT3N : BT;
-    const long slots = 256L * ((fp64 && h->zgemm != ZGEMM_MID) || h->prec == ADC2_BF16X3 ? 1 : 2);
-    const long ytiles = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, tn);
-    double best = 0.0;
-    for (int c = 1; c <= 8; ++c) {
-      const double rounds = (double)(ytiles * c) / slots;
-      const double cost = std::ceil(rounds) / rounds * (1.0 + 0.002 * (c - 1));
-      if (c == 1 || cost < best) {
-        best = cost;
-        ys = c;
-      }
-    }
+    ys = ysplit_rule(h, m);
     if (const char* v = getenv("ADC2_YSPLIT")) ys = std::max(1, std::min(16, atoi(v)));
     if (h->ysplit_tuned > 0) ys = h->ysplit_tuned;   // adc2_autotune's choice
   }

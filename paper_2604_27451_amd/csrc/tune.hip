@@ -2,12 +2,15 @@
 //
 // The Y-build contracts K = no*nv per output tile; its K-split (partials
 // summed afterwards) decides how many workgroups one launch has, against
-// the cost of the extra partial traffic and the summation.  The best split
-// depends on the system's shape, the block size and the precision form, so
-// adc2_autotune times every candidate on the device and keeps the fastest.
-// Choices are cached per (device, shape, block size, form) for the process
-// and, if ADC2_TUNE_CACHE names a file, across processes (one text line per
-// key, appended after each tuning).
+// the cost of the extra partial traffic and the summation.  In the FP64
+// form the tile shape is a choice too: three engines (128 x 64 at two
+// workgroups per CU, 128 x 128, 128 x 64 three-multiplication).  The best
+// choice depends on the system's shape, the block size and the precision
+// form, so adc2_autotune times the candidates on the device and keeps the
+// fastest: first each FP64 engine at its own size-rule K-split, then every
+// K-split of the fastest engine.  Choices are cached per (device, shape,
+// block size, form) for the process and, if ADC2_TUNE_CACHE names a file,
+// across processes (one text line per key, appended after each tuning).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -39,15 +42,20 @@ __global__ void k_fill_unit(T* __restrict__ p, size_t n, unsigned seed) {
 
 unsigned grid_fill(size_t n) { return (unsigned)std::max<size_t>(1, std::min<size_t>(8192, (n + 255) / 256)); }
 
+struct TuneChoice {
+  int engine;   // FP64 GEMM engine (ZGEMM_*), -1: the handle's own
+  int ysplit;
+};
 std::mutex tune_mu;
-std::map<std::string, int> tune_mem;   // key -> K-split
+std::map<std::string, TuneChoice> tune_mem;
 bool tune_file_read = false;
 
 const int CANDS[] = {1, 2, 3, 4, 6, 8, 12, 16};
 constexpr int NCAND = sizeof(CANDS) / sizeof(CANDS[0]);
 constexpr double YMAX_BYTES = 8.0 * (1 << 30);   // Y partial workspace limit for the search
 
-std::string tune_key(adc2_handle h, int m) {
+// search: the FP64 engine is part of the choice (else the handle's engine is part of the key)
+std::string tune_key(adc2_handle h, int m, bool search) {
   int dev = 0;
   hipDeviceProp_t p;
   std::string name = "gpu";
@@ -57,11 +65,13 @@ std::string tune_key(adc2_handle h, int m) {
   const Dims& d = h->d;
   std::ostringstream k;
   k << name << " nc=" << d.nc << " no=" << d.no << " nv=" << d.nv << " naux=" << d.naux << " m=" << m
-    << " prec=" << h->prec << " zgemm=" << h->zgemm;
+    << " prec=" << h->prec << " zgemm=";
+  if (search) k << "search";
+  else k << h->zgemm;
   return k.str();
 }
 
-// file lines: "<key> ysplit=<n>"
+// file lines: "<key>[ engine=<e>] ysplit=<n>"
 void read_cache_file() {
   if (tune_file_read) return;
   tune_file_read = true;
@@ -73,15 +83,25 @@ void read_cache_file() {
     const size_t p = line.rfind(" ysplit=");
     if (p == std::string::npos) continue;
     const int v = atoi(line.c_str() + p + 8);
-    if (v >= 1 && v <= 16) tune_mem[line.substr(0, p)] = v;
+    std::string head = line.substr(0, p);
+    int e = -1;
+    const size_t q = head.rfind(" engine=");
+    if (q != std::string::npos) {
+      e = atoi(head.c_str() + q + 8);
+      head = head.substr(0, q);
+    }
+    if (v >= 1 && v <= 16 && e >= -1 && e <= ZGEMM_MID) tune_mem[head] = TuneChoice{e, v};
   }
 }
 
-void append_cache_file(const std::string& key, int v) {
+void append_cache_file(const std::string& key, const TuneChoice& c) {
   const char* path = getenv("ADC2_TUNE_CACHE");
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " ysplit=" << v << "\n";
+  if (!f) return;
+  f << key;
+  if (c.engine >= 0) f << " engine=" << c.engine;
+  f << " ysplit=" << c.ysplit << "\n";
 }
 
 adc2_status tfail(adc2_status s, const std::string& m) {
@@ -101,15 +121,19 @@ extern "C" ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_in
   adc2_tune_info loc;
   adc2_tune_info& I = info ? *info : loc;
   memset(&I, 0, sizeof(I));
-  const std::string key = tune_key(h, m);
+  // the FP64 engine is searched unless the environment fixes it
+  const bool search = h->prec == ADC2_FP64 && !getenv("ADC2_ZGEMM");
+  const std::string key = tune_key(h, m, search);
   {
     std::lock_guard<std::mutex> lk(tune_mu);
     read_cache_file();
     auto it = tune_mem.find(key);
     if (it != tune_mem.end()) {
-      h->ysplit_tuned = it->second;
+      if (search && it->second.engine >= 0) h->zgemm = it->second.engine;
+      h->ysplit_tuned = it->second.ysplit;
       h->ws_m = 0;   // workspaces are re-sized for this split on the next sigma
-      I.ysplit = it->second;
+      I.ysplit = it->second.ysplit;
+      I.zgemm = h->zgemm;
       I.from_cache = 1;
       return ADC2_OK;
     }
@@ -126,17 +150,13 @@ extern "C" ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_in
     (void)hipEventDestroy(e0);
     return tfail(ADC2_ERR_HIP, "hipEventCreate");
   }
-  const int saved = h->ysplit_tuned;
-  int best = 0;
-  double best_ms = 1e300;
-  rc = ADC2_OK;
-  for (int c = 0; c < NCAND && rc == ADC2_OK; ++c) {
-    const int ys = CANDS[c];
-    if (ys > 1 && (ys * ybytes > YMAX_BYTES || (long)ys * 64 > kdim)) continue;
+  // best time of the Y-build (and its partial sum) with the handle's current engine at K-split ys
+  auto time_ybuild = [&](int ys, double& tmin) -> adc2_status {
     h->ysplit_tuned = ys;
     h->ws_m = 0;
-    if ((rc = ensure_ws(h, m)) != ADC2_OK) break;
-    if (h->prec == ADC2_BF16X3 && (rc = ensure_ws_b3(h, m)) != ADC2_OK) break;
+    adc2_status r = ensure_ws(h, m);
+    if (r == ADC2_OK && h->prec == ADC2_BF16X3) r = ensure_ws_b3(h, m);
+    if (r != ADC2_OK) return r;
     // data-like operands, uniform in [-1, 1): the matrix cores draw more power
     // on them than on zeros, and the power limit can hold the clock lower
     // (the split-BF16 Y-build at nc=6, no=60, nv=300 runs 40% longer on such
@@ -148,46 +168,75 @@ extern "C" ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_in
       const size_t nrb = (size_t)split_bytes((long)m * d.nc * d.nv, (long)d.no * d.nv) / 2;   // bf16 values
       k_fill_unit<__bf16><<<grid_fill(nrb), 256, 0, st>>>((__bf16*)h->RB, nrb, 0x85ebca6bu);
     }
-    if (hipGetLastError() != hipSuccess) {
-      rc = tfail(ADC2_ERR_HIP, "k_fill_unit");
-      break;
-    }
-    double tmin = 1e300;
-    for (int r = 0; r < 4 && rc == ADC2_OK; ++r) {   // one warm-up, three timed
-      if (hipEventRecord(e0, st) != hipSuccess) rc = tfail(ADC2_ERR_HIP, "hipEventRecord");
-      if (rc == ADC2_OK) rc = ybuild_launch(h, m, st);
-      if (rc == ADC2_OK) rc = ybuild_sum(h, m, st);
-      if (rc == ADC2_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-        rc = tfail(ADC2_ERR_HIP, "timing events");
+    if (hipGetLastError() != hipSuccess) return tfail(ADC2_ERR_HIP, "k_fill_unit");
+    tmin = 1e300;
+    for (int rep = 0; rep < 4; ++rep) {   // one warm-up, three timed
+      if (hipEventRecord(e0, st) != hipSuccess) return tfail(ADC2_ERR_HIP, "hipEventRecord");
+      if ((r = ybuild_launch(h, m, st)) != ADC2_OK || (r = ybuild_sum(h, m, st)) != ADC2_OK) return r;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return tfail(ADC2_ERR_HIP, "timing events");
       float ms = 0.f;
-      if (rc == ADC2_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = tfail(ADC2_ERR_HIP, "hipEventElapsedTime");
-      if (rc == ADC2_OK && r > 0) tmin = std::min(tmin, (double)ms);
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return tfail(ADC2_ERR_HIP, "hipEventElapsedTime");
+      if (rep > 0) tmin = std::min(tmin, (double)ms);
     }
-    if (rc != ADC2_OK) break;
+    return ADC2_OK;
+  };
+  const int saved_ys = h->ysplit_tuned, saved_engine = h->zgemm;
+  rc = ADC2_OK;
+  // stage 1 (FP64): each engine at its own size-rule K-split
+  if (search) {
+    const int engines[] = {ZGEMM_MID, ZGEMM_BIG, ZGEMM_3M};
+    double best_ms = 1e300;
+    int best_e = saved_engine;
+    for (int e : engines) {
+      h->zgemm = e;
+      double t = 0.0;
+      if ((rc = time_ybuild(ysplit_rule(h, m), t)) != ADC2_OK) break;
+      I.engine[I.nengine] = e;
+      I.engine_ms[I.nengine] = t;
+      ++I.nengine;
+      if (t < best_ms) {
+        best_ms = t;
+        best_e = e;
+      }
+    }
+    h->zgemm = best_e;
+  }
+  // stage 2: every K-split of the (chosen) engine
+  int best = 0;
+  double best_ms = 1e300;
+  for (int c = 0; c < NCAND && rc == ADC2_OK; ++c) {
+    const int ys = CANDS[c];
+    if (ys > 1 && (ys * ybytes > YMAX_BYTES || (long)ys * 64 > kdim)) continue;
+    double t = 0.0;
+    if ((rc = time_ybuild(ys, t)) != ADC2_OK) break;
     if (I.ncand < 8) {
       I.cand[I.ncand] = ys;
-      I.ms[I.ncand] = tmin;
+      I.ms[I.ncand] = t;
       ++I.ncand;
     }
-    if (tmin < best_ms) {
-      best_ms = tmin;
+    if (t < best_ms) {
+      best_ms = t;
       best = ys;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != ADC2_OK || best == 0) {
-    h->ysplit_tuned = saved;
+    h->ysplit_tuned = saved_ys;
+    h->zgemm = saved_engine;
     h->ws_m = 0;
     return rc != ADC2_OK ? rc : tfail(ADC2_ERR_ARG, "no K-split candidate fits");
   }
   h->ysplit_tuned = best;
   h->ws_m = 0;   // re-sized for the chosen split on the next sigma
   I.ysplit = best;
+  I.zgemm = h->zgemm;
   {
     std::lock_guard<std::mutex> lk(tune_mu);
-    tune_mem[key] = best;
-    append_cache_file(key, best);
+    const TuneChoice c{search ? h->zgemm : -1, best};
+    tune_mem[key] = c;
+    append_cache_file(key, c);
   }
   return ADC2_OK;
 }

@@ -1,10 +1,14 @@
-"""GPU checks of the autotuner (adc2_autotune).
+"""GPU checks of the autotuner (adc2_autotune) and of the FP64 GEMM engines
+it chooses between.
 
-The tuner times every Y-build K-split candidate of a handle and fixes the
-fastest; a sigma build after tuning must still match the oracle (the K-split
-only changes the summation order), a second handle of the same shape must
-take the choice from the cache without timing, and the choice must be
-written to the cache file named by ADC2_TUNE_CACHE.
+The tuner times the FP64 engines (tile shapes) at their size-rule K-splits,
+then every Y-build K-split candidate of the fastest (or of the form's only
+engine), and fixes the fastest; a sigma build after tuning must still match
+the oracle (engine and K-split only change the summation order), a second
+handle of the same shape must take the choice from the cache without timing,
+and the choice must be written to the cache file named by ADC2_TUNE_CACHE.
+The 128 x 128 and two-per-CU engines must give identical products at equal
+K-splits; the three-multiplication engine must match the oracle.
 """
 import os
 import re
@@ -35,10 +39,15 @@ def test_autotune_choice_keeps_sigma_and_is_cached(prec):
     h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux, prec=prec)
     x = dev(random_vectors(77, 3, h.dim))
     r = A.adc2_autotune(h, 3)
-    print(f"  choice {r['ysplit']} from {r['ms']}", flush=True)
+    print(f"  choice {r['ysplit']} from {r['ms']}; engine {r['zgemm']} from {r['engines']}", flush=True)
     assert not r["from_cache"]
     assert r["ysplit"] in r["ms"] and len(r["ms"]) >= 2
     assert r["ms"][r["ysplit"]] == min(r["ms"].values())
+    if prec == A.ADC2_FP64:
+        assert sorted(r["engines"]) == [0, 1, 2]
+        assert r["engines"][r["zgemm"]] == min(r["engines"].values())
+    else:
+        assert r["engines"] == {}
     S = A.adc2_sigma(h, x).cpu()
     o = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv)
     ref = o.sigma(x.cpu())
@@ -49,10 +58,13 @@ def test_autotune_choice_keeps_sigma_and_is_cached(prec):
     # same shape, same block size and form: the cached choice, no timing
     h2 = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux, prec=prec)
     r2 = A.adc2_autotune(h2, 3)
-    assert r2["from_cache"] and r2["ysplit"] == r["ysplit"] and r2["ms"] == {}
+    assert r2["from_cache"] and r2["ysplit"] == r["ysplit"] and r2["ms"] == {} and r2["zgemm"] == r["zgemm"]
     assert torch.equal(A.adc2_sigma(h2, x).cpu(), S)
     lines = open(CACHE).read().splitlines()
-    key = re.compile(rf"prec={prec} zgemm=\d+ ysplit={r['ysplit']}$")
+    if prec == A.ADC2_FP64:
+        key = re.compile(rf"prec=0 zgemm=search engine={r['zgemm']} ysplit={r['ysplit']}$")
+    else:
+        key = re.compile(rf"prec={prec} zgemm=\d+ ysplit={r['ysplit']}$")
     assert any(key.search(l) and "nv=40" in l for l in lines), lines
     h.close()
     h2.close()
@@ -64,3 +76,24 @@ def test_autotune_rejects_bad_arguments():
     with pytest.raises(A.Adc2Error):
         A.adc2_autotune(h, 0)
     h.close()
+
+
+def test_fp64_engines_equal_and_match_oracle(monkeypatch):
+    """Equal K-splits (forced): the 128 x 128 and the two-per-CU engines give
+    the same product bit for bit (same MFMAs in the same k order per output),
+    the three-multiplication engine matches the oracle."""
+    s = make_system(2, 7, 37, 110, seed=41)
+    x = dev(random_vectors(78, 3, s.nc * s.nv + s.nc * s.no * s.nv * (s.nv - 1) // 2))
+    ref = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv).sigma(x.cpu())
+    out = {}
+    monkeypatch.setenv("ADC2_YSPLIT", "3")
+    for eng in ("big", "mid", "3m"):
+        monkeypatch.setenv("ADC2_ZGEMM", eng)
+        print(f"[case] engine {eng} shape {(s.nc, s.no, s.nv, s.naux)} K-split 3", flush=True)
+        h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
+        out[eng] = A.adc2_sigma(h, x).cpu()
+        h.close()
+        err = ((out[eng] - ref).abs().max() / ref.abs().max()).item()
+        print(f"  vs oracle {err:.2e}", flush=True)
+        assert err < 1e-11
+    assert torch.equal(out["big"], out["mid"])
