@@ -59,8 +59,8 @@ HARTREE_EV = 27.211386245988
 TRAFFIC_FILES = {"c3": os.path.join(ROOT, "profiles", "traffic_c3.json")}
 CSRC = "paper_2604_27451_amd/csrc"
 # sources that define each heavy sigma kernel: its GEMM engine header(s) and its own definition
-KERNEL_DEFS = {("fp64", "ybuild"): (["zgemm.h", "tile.h"], "k_ygemm_mid("),
-               ("fp64", "sigma2"): (["zgemm.h", "tile.h"], "k_zsig2_mid("),
+KERNEL_DEFS = {("fp64", "ybuild"): (["zgemm.h", "tile.h"], "k_ygemm_wide("),
+               ("fp64", "sigma2"): (["zgemm.h", "tile.h"], "k_zsig2_wide("),
                ("c64", "ybuild"): (["zgemm32.h", "zgemm.h"], "k_ygemm_c64("),
                ("c64", "sigma2"): (["zgemm32.h", "zgemm.h"], "k_zsig2_c64("),
                ("bf16x3", "ybuild"): (["zgemmb.h", "zgemm.h"], "k_ygemm_b3("),

@@ -476,8 +476,9 @@ ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double threshold, in
  * Autotuner of the sigma build's dominant GEMM, the Y-build (M12 half of the
  * sigma, Implementation section): its K-split count decides how many
  * workgroups a launch has against extra partial traffic and a summation
- * pass, and in the FP64 form its engine decides the tile shape (128 x 64 at
- * two workgroups per CU, 128 x 128, or 128 x 64 three-multiplication).
+ * pass, and in the FP64 form its engine decides the tile shape (128 x 128 on
+ * eight waves, 128 x 64 at two workgroups per CU, 128 x 128 on four waves, or
+ * 128 x 64 three-multiplication).
  * adc2_autotune times the Y-build of h's current precision form at block size
  * m: in the FP64 form first each engine at its own size-rule K-split (unless
  * the environment variable ADC2_ZGEMM fixes the engine), then, for the
@@ -494,8 +495,9 @@ ADC2_API adc2_status adc2_fns(adc2_handle h, const void* L, double threshold, in
  * the three-multiplication one give identical results at equal K-splits).
  * info (host, nullable) receives the choice, the K-splits timed and their
  * best times in ms (ncand = 0 and from_cache = 1 for a cached choice), the
- * chosen engine (zgemm: 0 = 128 x 128, 1 = three-multiplication, 2 = two
- * per CU) and the engines timed with their best times.
+ * chosen engine (zgemm: 0 = 128 x 128 on four waves, 1 =
+ * three-multiplication, 2 = two per CU, 3 = 128 x 128 on eight waves) and the
+ * engines timed with their best times.
  * Synchronises the stream; must not overlap other calls on h.  Errors:
  * ADC2_ERR_ARG (NULL handle, m out of 1..4096), ADC2_ERR_OOM, ADC2_ERR_HIP.
  */

@@ -85,7 +85,8 @@ class TuneInfo(ctypes.Structure):
                 ("nengine", ctypes.c_int), ("engine", ctypes.c_int * 4), ("engine_ms", ctypes.c_double * 4)]
 
 
-ZGEMM_NAMES = {0: "128x128", 1: "128x64 three-multiplication", 2: "128x64 two per CU"}
+ZGEMM_NAMES = {0: "128x128 four waves", 1: "128x64 three-multiplication", 2: "128x64 two per CU",
+               3: "128x128 eight waves"}
 
 
 class Mol(ctypes.Structure):

@@ -226,7 +226,10 @@ adc2_status adc2_setup(const void* L, const double* eps, int nc, int no, int nv,
     h->alloc = *alloc;
   }
   if (const char* v = getenv("ADC2_ZGEMM"))
-    h->zgemm = strcmp(v, "3m") == 0 ? ZGEMM_3M : strcmp(v, "big") == 0 ? ZGEMM_BIG : ZGEMM_MID;
+    h->zgemm = strcmp(v, "3m") == 0    ? ZGEMM_3M
+               : strcmp(v, "big") == 0 ? ZGEMM_BIG
+               : strcmp(v, "mid") == 0 ? ZGEMM_MID
+                                       : ZGEMM_WIDE;
 #define SETUP_TRY(call)                                                           \
   do {                                                                            \
     hipError_t e_ = (call);                                                       \

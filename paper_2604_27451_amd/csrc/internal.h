@@ -34,11 +34,12 @@ inline hipError_t dmalloc(adc2_handle h, T** p, size_t bytes) {
 }
 
 // Sizes of one system.
-// Engines of the FP64 heavy GEMMs (zgemm.h): 128 x 128 four-multiplication,
-// 128 x 64 three-multiplication, 128 x 64 four-multiplication at two
-// workgroups per CU (the default).  Chosen per handle at setup
-// (environment ADC2_ZGEMM = big, 3m or mid).
-constexpr int ZGEMM_BIG = 0, ZGEMM_3M = 1, ZGEMM_MID = 2;
+// Engines of the FP64 heavy GEMMs (zgemm.h): 128 x 128 four-multiplication
+// on four waves, 128 x 64 three-multiplication, 128 x 64 four-multiplication
+// at two workgroups per CU, 128 x 128 four-multiplication on eight waves (the
+// default).  Chosen per handle at setup (environment ADC2_ZGEMM = big, 3m,
+// mid or wide) or by adc2_autotune.
+constexpr int ZGEMM_BIG = 0, ZGEMM_3M = 1, ZGEMM_MID = 2, ZGEMM_WIDE = 3;
 
 struct Dims {
   int nc, no, nv, naux;
@@ -90,7 +91,7 @@ struct adc2_handle_s {
   int nsplit = 0;
   int ysplit = 1;           // K-splits of the Y-build GEMM
   int ysplit_tuned = 0;     // K-split fixed by adc2_autotune (0: the size heuristic)
-  int zgemm = adc2::ZGEMM_MID;   // engine of the FP64 heavy GEMMs (ZGEMM_BIG, ZGEMM_3M or ZGEMM_MID)
+  int zgemm = adc2::ZGEMM_WIDE;  // engine of the FP64 heavy GEMMs (ZGEMM_*)
   // method: ADC2_METHOD_ADC2 or ADC2_METHOD_ADC2X (first-order doubles block, adc2x.hip)
   int method = 0;
   double2* Vpp = nullptr;   // ADC(2)-x: [(a<b)][(c<d)] <ab||cd>

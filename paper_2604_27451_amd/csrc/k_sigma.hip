@@ -344,6 +344,66 @@ __global__ __launch_bounds__(256, 2) void k_ygemm_mid(const double2* __restrict_
   });
 }
 
+// The same two contractions on the eight-wave engine (128 x 128 tiles, 16-k
+// chunks, two waves per SIMD).
+__global__ __launch_bounds__(512) void k_zsig2_wide(const double2* __restrict__ X, const double2* __restrict__ Lvo,
+                                                     int rows, int nc, int no, int nv, int naux,
+                                                     double2* __restrict__ Z) {
+  __shared__ BigSmem s[2];
+  const int ncols = no * nv;
+  const int nbm = (rows + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const long lds = (long)naux * nv;
+  SrcGroupedK8<4, BK> A{X, lds, nv, nv, rows, naux};
+  SrcGroupedK8<4, BK> B{Lvo + (long)nc * lds, lds, nv, nv, ncols, naux};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  MidAcc acc;
+  acc.zero();
+  wide_mainloop(s, A, B, 0, (naux + BK - 1) / BK, acc);
+  wide_for_each(acc, [&](int r, int c, double2 v) {
+    const int i = i0 + r, jc = j0 + c;
+    if (i < rows && jc < ncols) {
+      const int mI = i / nv, a = i - mI * nv;
+      const int j = jc / nv, b = jc - j * nv;
+      Z[(((long)mI * no + j) * nv + a) * nv + b] = v;
+    }
+  });
+}
+
+__global__ __launch_bounds__(512) void k_ygemm_wide(const double2* __restrict__ LvT, const double2* __restrict__ Rt,
+                                                     int rows, int no, int nv, int naux, double2* __restrict__ Y) {
+  __shared__ BigSmem s[2];
+  const int ncols = rows * nv;
+  const int nbm = (naux + BT - 1) / BT, nbn = (ncols + BT - 1) / BT;
+  const long lid = xcd_remap(blockIdx.x, (long)nbm * nbn);
+  int bm, bn;
+  big_tile_coords(lid, nbm, nbn, bm, bn);
+  const int i0 = bm * BT, j0 = bn * BT;
+  const int K = no * nv;
+  SrcGroupedK8<4, BK> A{LvT, 0, naux, naux, naux, K};
+  SrcGroupedK8<4, BK> B{Rt, 0, ncols, ncols, ncols, K};
+  A.begin(threadIdx.x, i0);
+  B.begin(threadIdx.x, j0);
+  const int nchunks = (K + BK - 1) / BK;
+  const int per = (nchunks + gridDim.y - 1) / gridDim.y;
+  const int kc0 = blockIdx.y * per, kc1 = min(nchunks, kc0 + per);
+  double2* Ys = Y + (long)blockIdx.y * ((long)rows * naux * nv);
+  MidAcc acc;
+  acc.zero();
+  wide_mainloop(s, A, B, kc0, kc1, acc);
+  wide_for_each(acc, [&](int r, int c, double2 v) {
+    const int P = i0 + r, col = j0 + c;
+    if (P < naux && col < ncols) {
+      const int mI = col / nv, cc = col - mI * nv;
+      Ys[((long)mI * naux + P) * nv + cc] = v;
+    }
+  });
+}
+
 // Precision form: the two heavy contractions on complex64 operands with the
 // FP32 MFMA and FP32 accumulation.  Each kernel body is an "item" (one output
 // tile and one K-split) so that the plain launches below and the grouped
@@ -1047,7 +1107,7 @@ int ysplit_rule(adc2_handle h, int m) {
   const Dims& d = h->d;
   const long rows = (long)m * d.nc;
   const bool fp64 = h->prec == ADC2_FP64;
-  const int tn = fp64 && h->zgemm != ZGEMM_BIG ? BT3N : BT;
+  const int tn = fp64 && h->zgemm != ZGEMM_BIG && h->zgemm != ZGEMM_WIDE ? BT3N : BT;
   const long slots = 256L * ((fp64 && h->zgemm != ZGEMM_MID) || h->prec == ADC2_BF16X3 ? 1 : 2);
   const long ytiles = (long)cdiv(d.naux, BT) * cdiv(rows * d.nv, tn);
   int ys = 1;
@@ -1175,9 +1235,12 @@ adc2_status ybuild_launch(adc2_handle h, int m, hipStream_t st) {
     else
       k_ygemm_c64<<<grid, 256, 0, st>>>(h->LvT32, (const float2*)h->Zb, rows, d.no, d.nv, d.naux, h->Y);
   } else {
-    const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, h->zgemm == ZGEMM_BIG ? BT : BT3N);
+    const bool wide_tile = h->zgemm == ZGEMM_BIG || h->zgemm == ZGEMM_WIDE;
+    const long nblk = (long)cdiv(d.naux, BT) * cdiv((long)rows * d.nv, wide_tile ? BT : BT3N);
     dim3 grid((unsigned)nblk, ys);
-    if (h->zgemm == ZGEMM_MID)
+    if (h->zgemm == ZGEMM_WIDE)
+      k_ygemm_wide<<<grid, 512, 0, st>>>(h->LvT, h->Zb, rows, d.no, d.nv, d.naux, h->Y);
+    else if (h->zgemm == ZGEMM_MID)
       k_ygemm_mid<<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.no, d.nv, d.naux, h->Y);
     else if (h->zgemm == ZGEMM_3M)
       k_ygemm<true><<<grid, 256, 0, st>>>(h->LvT, h->Zb, rows, d.nc, d.no, d.nv, d.naux, h->Y);
@@ -1388,6 +1451,9 @@ adc2_status sigma_multi(int nreq, const SigReq* rq, hipStream_t st) {
       else
         k_zsig2_c64<<<(unsigned)nblk, 256, 0, st>>>((const float2*)h->X, h->Lv32, rows * d.nv, d.no, d.nv, d.naux,
                                                       (float2*)h->Zb);
+    } else if (h->zgemm == ZGEMM_WIDE) {
+      const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, BT);
+      k_zsig2_wide<<<(unsigned)nblk, 512, 0, st>>>(h->X, h->Lvo, rows * d.nv, d.nc, d.no, d.nv, d.naux, h->Zb);
     } else if (h->zgemm == ZGEMM_MID) {
       const long nblk = (long)cdiv((long)rows * d.nv, BT) * cdiv((long)d.no * d.nv, MTN);
       k_zsig2_mid<<<(unsigned)nblk, 256, 0, st>>>(h->X, h->Lvo, rows * d.nv, d.nc, d.no, d.nv, d.naux, h->Zb);

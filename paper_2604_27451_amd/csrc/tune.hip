@@ -3,8 +3,9 @@
 // The Y-build contracts K = no*nv per output tile; its K-split (partials
 // summed afterwards) decides how many workgroups one launch has, against
 // the cost of the extra partial traffic and the summation.  In the FP64
-// form the tile shape is a choice too: three engines (128 x 64 at two
-// workgroups per CU, 128 x 128, 128 x 64 three-multiplication).  The best
+// form the tile shape is a choice too: four engines (128 x 128 on eight
+// waves, 128 x 64 at two workgroups per CU, 128 x 128 on four waves, 128 x 64
+// three-multiplication).  The best
 // choice depends on the system's shape, the block size and the precision
 // form, so adc2_autotune times the candidates on the device and keeps the
 // fastest: first each FP64 engine at its own size-rule K-split, then every
@@ -90,7 +91,7 @@ void read_cache_file() {
       e = atoi(head.c_str() + q + 8);
       head = head.substr(0, q);
     }
-    if (v >= 1 && v <= 16 && e >= -1 && e <= ZGEMM_MID) tune_mem[head] = TuneChoice{e, v};
+    if (v >= 1 && v <= 16 && e >= -1 && e <= ZGEMM_WIDE) tune_mem[head] = TuneChoice{e, v};
   }
 }
 
@@ -185,7 +186,7 @@ extern "C" ADC2_API adc2_status adc2_autotune(adc2_handle h, int m, adc2_tune_in
   rc = ADC2_OK;
   // stage 1 (FP64): each engine at its own size-rule K-split
   if (search) {
-    const int engines[] = {ZGEMM_MID, ZGEMM_BIG, ZGEMM_3M};
+    const int engines[] = {ZGEMM_WIDE, ZGEMM_MID, ZGEMM_BIG, ZGEMM_3M};
     double best_ms = 1e300;
     int best_e = saved_engine;
     for (int e : engines) {

@@ -319,9 +319,11 @@ __device__ __forceinline__ void mid_for_each(const MidAcc& acc, F&& f) {
       }
 }
 
-// k-major source for the two-per-CU engine: rows grouped as SrcGroupedK,
-// element (k, i) at base[g*gstride + a + k*ld], chunk of 8 k, NS = rows/32.
-template <int NS>
+// k-major source for the two-per-CU and eight-wave engines: rows grouped as
+// SrcGroupedK, element (k, i) at base[g*gstride + a + k*ld], chunks of CK k,
+// thread tid reads k = tid / 32 of the chunk and rows (tid % 32) + 32 e,
+// NS = rows / 32 (CK * 32 threads).
+template <int NS, int CK = MBK>
 struct SrcGroupedK8 {
   const double2* base;
   long gstride;
@@ -342,12 +344,106 @@ struct SrcGroupedK8 {
     }
   }
   __device__ __forceinline__ void load(int kc, RegsN<NS>& r) const {
-    const int k = kc * MBK + kk;
+    const int k = kc * CK + kk;
     const long ko = (long)k * ld;
 #pragma unroll
     for (int e = 0; e < NS; ++e) r.v[e] = ((okmask >> e) & 1u) && k < nk ? base[off[e] + ko] : czero();
   }
 };
+
+// ---------------------------------------------------------------------------
+// Eight-wave variant: the 128 x 128 tile and 16-k chunks of the big engine
+// (BigSmem, 132 KB) computed by 512 threads, each wave a 64 x 32 quadrant
+// (waves as 2 x 4), so two waves share each SIMD with 128 accumulation
+// registers each.  Same MFMAs per accumulator in the same k order as the
+// other engines.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wide_mma(const BigSmem& s, MidAcc& acc, int wr, int wc, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kg = 0; kg < BK; kg += 4) {
+    double ar[4], ai[4], br[2], bi[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ar[t] = s.a_re[kg + lk][wr + 16 * t + li];
+      ai[t] = s.a_im[kg + lk][wr + 16 * t + li];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      br[t] = s.b_re[kg + lk][wc + 16 * t + li];
+      bi[t] = s.b_im[kg + lk][wc + 16 * t + li];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc.im[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], acc.re[a][b], 0, 0, 1);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc.im[a][b], 0, 0, 0);
+  }
+}
+
+template <class SA, class SB>
+__device__ __forceinline__ void wide_mainloop(BigSmem (&s)[2], const SA& A, const SB& B, int kc0, int kc1,
+                                              MidAcc& acc) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 2) * 64, wc = (w & 3) * 32;
+  if (kc0 >= kc1) return;
+  RegsN<4> ra, rb;
+  A.load(kc0, ra);
+  B.load(kc0, rb);
+  mid_stash<4, BLDP>(s[0].a_re, s[0].a_im, ra, tid);
+  mid_stash<4, BLDP>(s[0].b_re, s[0].b_im, rb, tid);
+  if (kc0 + 1 < kc1) {
+    A.load(kc0 + 1, ra);
+    B.load(kc0 + 1, rb);
+  }
+  __syncthreads();
+  for (int c = kc0; c < kc1; ++c) {
+    const int cur = (c - kc0) & 1;
+    if (c + 1 < kc1) {
+      mid_stash<4, BLDP>(s[cur ^ 1].a_re, s[cur ^ 1].a_im, ra, tid);
+      mid_stash<4, BLDP>(s[cur ^ 1].b_re, s[cur ^ 1].b_im, rb, tid);
+      if (c + 2 < kc1) {
+        A.load(c + 2, ra);
+        B.load(c + 2, rb);
+      }
+    }
+    wide_mma(s[cur], acc, wr, wc, lane);
+    __syncthreads();
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void wide_for_each(const MidAcc& acc, F&& f) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 2) * 64, wc = (w & 3) * 32;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr + 16 * a + (lane >> 4) + 4 * r;
+        const int col = wc + 16 * b + (lane & 15);
+        f(row, col, make_double2(acc.re[a][b][r], acc.im[a][b][r]));
+      }
+}
 // ---------------------------------------------------------------------------
 // Three-multiplication variant (Gauss): for each 16x16 block
 //   T1 += Ar Br,  T2 += Ai Bi,  T3 += (Ar + Ai)(Br + Bi)

@@ -7,8 +7,8 @@ engine), and fixes the fastest; a sigma build after tuning must still match
 the oracle (engine and K-split only change the summation order), a second
 handle of the same shape must take the choice from the cache without timing,
 and the choice must be written to the cache file named by ADC2_TUNE_CACHE.
-The 128 x 128 and two-per-CU engines must give identical products at equal
-K-splits; the three-multiplication engine must match the oracle.
+The four-multiplication engines must give identical products at equal
+K-splits; every engine must match the oracle.
 """
 import os
 import re
@@ -44,7 +44,7 @@ def test_autotune_choice_keeps_sigma_and_is_cached(prec):
     assert r["ysplit"] in r["ms"] and len(r["ms"]) >= 2
     assert r["ms"][r["ysplit"]] == min(r["ms"].values())
     if prec == A.ADC2_FP64:
-        assert sorted(r["engines"]) == [0, 1, 2]
+        assert sorted(r["engines"]) == [0, 1, 2, 3]
         assert r["engines"][r["zgemm"]] == min(r["engines"].values())
     else:
         assert r["engines"] == {}
@@ -79,15 +79,16 @@ def test_autotune_rejects_bad_arguments():
 
 
 def test_fp64_engines_equal_and_match_oracle(monkeypatch):
-    """Equal K-splits (forced): the 128 x 128 and the two-per-CU engines give
-    the same product bit for bit (same MFMAs in the same k order per output),
-    the three-multiplication engine matches the oracle."""
+    """Equal K-splits (forced): the four-multiplication engines (128 x 128 on
+    four and on eight waves, 128 x 64 two per CU) give the same product bit
+    for bit (same MFMAs in the same k order per output), and every engine,
+    the three-multiplication one included, matches the oracle."""
     s = make_system(2, 7, 37, 110, seed=41)
     x = dev(random_vectors(78, 3, s.nc * s.nv + s.nc * s.no * s.nv * (s.nv - 1) // 2))
     ref = O.Adc2(s.L, s.eps, s.nc, s.no, s.nv).sigma(x.cpu())
     out = {}
     monkeypatch.setenv("ADC2_YSPLIT", "3")
-    for eng in ("big", "mid", "3m"):
+    for eng in ("big", "mid", "wide", "3m"):
         monkeypatch.setenv("ADC2_ZGEMM", eng)
         print(f"[case] engine {eng} shape {(s.nc, s.no, s.nv, s.naux)} K-split 3", flush=True)
         h = A.adc2_setup(dev(s.L), dev(s.eps), s.nc, s.no, s.nv, s.naux)
@@ -96,4 +97,4 @@ def test_fp64_engines_equal_and_match_oracle(monkeypatch):
         err = ((out[eng] - ref).abs().max() / ref.abs().max()).item()
         print(f"  vs oracle {err:.2e}", flush=True)
         assert err < 1e-11
-    assert torch.equal(out["big"], out["mid"])
+    assert torch.equal(out["big"], out["mid"]) and torch.equal(out["big"], out["wide"])
