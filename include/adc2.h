@@ -368,11 +368,12 @@ ADC2_API adc2_status adc2_davidson_batch(int nmol, const adc2_handle* hs, int nr
  *   ADC2_ERR_ARG for a handle in the ADC(2)-x method (its doubles block is
  *   outside the captured sequence).
  * adc2_graph_launch -- replays the graph on `stream` (asynchronous).  The
- *   handles must still exist, and every one must still hold the work spaces,
- *   operand copies, precision form, method and split counts the graph
- *   recorded: a sigma call with a larger block, a change of precision,
- *   method or autotuned split re-sizes them, and the launch then returns
- *   ADC2_ERR_ARG (capture again) instead of replaying.  A replay shares the
+ *   handles must still exist, and every one must still hold the work spaces
+ *   (addresses and capacities), operand copies, precision form, method,
+ *   engine and split counts the graph recorded: a sigma call with a larger
+ *   block, a change of precision or method, or adc2_autotune re-sizes or
+ *   changes them, and the launch then returns ADC2_ERR_ARG (capture again)
+ *   instead of replaying.  A replay shares the
  *   handles' work spaces with every other sigma on them: calls that overlap
  *   in time race.
  * adc2_graph_destroy -- releases the graph (NULL is accepted).

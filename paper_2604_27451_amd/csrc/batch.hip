@@ -92,12 +92,14 @@ struct Rendezvous {
 };
 
 // What the captured launch sequence of a handle depends on: its buffer
-// addresses, precision form, method and split counts.
+// addresses and capacities (a work space re-sized to fewer vectors can come
+// back at the same address), precision form, method and split counts.
 struct SigState {
-  int prec, method, zgemm, ysplit, nsplit;
+  int prec, method, zgemm, ysplit, nsplit, ws_m, wsb_m;
   const void* buf[18];
   bool operator==(const SigState& o) const {
-    if (prec != o.prec || method != o.method || zgemm != o.zgemm || ysplit != o.ysplit || nsplit != o.nsplit)
+    if (prec != o.prec || method != o.method || zgemm != o.zgemm || ysplit != o.ysplit || nsplit != o.nsplit ||
+        ws_m != o.ws_m || wsb_m != o.wsb_m)
       return false;
     for (int i = 0; i < 18; ++i)
       if (buf[i] != o.buf[i]) return false;
@@ -112,6 +114,8 @@ SigState sig_state(adc2_handle h) {
   s.zgemm = h->zgemm;
   s.ysplit = h->ysplit;
   s.nsplit = h->nsplit;
+  s.ws_m = h->ws_m;
+  s.wsb_m = h->wsb_m;
   const void* b[18] = {h->X,    h->Y,     h->Zb,  h->Tp,  h->part, h->XB,  h->RB, h->Lv32, h->LvT32,
                        h->LvB,  h->LvTB,  h->LvT, h->Lvo, h->Lvv,  h->Vt,  h->eps, h->M11, nullptr};
   for (int i = 0; i < 18; ++i) s.buf[i] = b[i];

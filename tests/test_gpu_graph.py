@@ -121,6 +121,13 @@ def test_graph_refuses_changed_workspaces_and_recaptures():
     for q in range(2):
         assert torch.equal(g2.S[q], eager[q]), q
     g2.close()
+    # the autotuner re-sizes the work spaces for a smaller block (they may come back at the
+    # same addresses): the graph of the larger block must not replay into them
+    g3 = A.adc2_graph_sigma_batch(hs, [dev(random_vectors(1800 + q, 3, h.dim)) for q, h in enumerate(hs)])
+    A.adc2_autotune(hs[1], 1)
+    with pytest.raises(A.Adc2Error, match="capture the batch again"):
+        g3.launch()
+    g3.close()
     # the ADC(2)-x method is not captured
     A.adc2_set_method(hs[0], A.ADC2_METHOD_ADC2X)
     with pytest.raises(A.Adc2Error, match="ADC\\(2\\)-x"):
