@@ -1,4 +1,4 @@
-// zgemm.h -- large-tile complex FP64 GEMM engine for gfx950.
+// zgemm.h -- large-tile complex FP64 GEMM engines for gfx950.
 //
 // C[i][j] = sum_k A(k, i) B(k, j) over a 128 x 128 complex output tile per
 // workgroup (256 threads = 4 waves, each wave a 64 x 64 quadrant made of
@@ -8,6 +8,10 @@
 // matrix-bound with one wave per SIMD.  Operands stream through LDS in
 // chunks of 16 complex k-values; the next chunk's global loads are issued
 // into registers before the current chunk's MFMAs.
+//
+// Variants below: the same tile on eight waves of 64 x 32 (wide_*, two
+// waves per SIMD; the sigma's default), 128 x 64 tiles at two workgroups per
+// CU (mid_*), and the three-multiplication 128 x 64 engine (big_*3).
 //
 // A source provides
 //   static constexpr int MAP;                      // KMAJOR or RMAJOR (tile.h)
