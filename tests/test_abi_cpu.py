@@ -201,3 +201,16 @@ def test_binding_rejects_wrong_shapes_before_any_call(monkeypatch):
         A.adc2_sigma(h, good)
     with pytest.raises(TypeError):
         A.adc2_transition(h, dip, good, [0.1, 0.2])
+
+
+def test_graph_wrapper_refuses_closed_handles_and_graphs():
+    """SigmaGraph.launch refuses, before any library call, a graph whose
+    handle was closed or that was itself closed."""
+    class Closed:
+        ptr = None
+    g = A.SigmaGraph(ctypes.c_void_p(4096), [Closed()], [], [])
+    with pytest.raises(A.Adc2Error, match="handle of the graph was closed"):
+        g.launch()
+    g.ptr = None   # never handed to the library: nothing to destroy
+    with pytest.raises(A.Adc2Error, match="graph is closed"):
+        g.launch()
